@@ -1,0 +1,167 @@
+/*
+ * mrpt2.h - C interface of the MI355X Epstein-Nesbet MRPT2 energy library.
+ *
+ * Computes the second-order energy of four-component multireference
+ * perturbation theory in the small-tensor-product distributed active space
+ * (STP-DAS) organisation (Majumder, Upadhyay, Beck, Oele, Li):
+ *
+ *   E2 = sum_{K in Q} |<K|H|Psi0>|^2 / (E0 - H_KK)          (eq. pt2, eq. pt2en)
+ *
+ * with the Epstein-Nesbet zeroth-order Hamiltonian (eq. zeroh: full H inside
+ * the primary space P, diagonal H_KK on the external space Q), P built from
+ * DAS configuration categories (Sec. 2.4), Q = every single and double
+ * excitation of P that is not in P (Sec. 2.3), frozen core folded into the
+ * one-electron operator and frozen virtuals removed (Sec. 2.5).
+ *
+ * Conventions (all arrays row-major; complex numbers interleaved (re, im)
+ * as pairs of doubles):
+ *  - Spinor order: frozen core | core | active (DAS subspaces in order) |
+ *    kept virtuals.  n = n_frozen_core + n_core + n_active + n_virt.
+ *    Frozen virtuals are never passed.
+ *  - H = sum h_pq a+_p a_q + 1/2 sum (pq|rs) a+_p a+_r a_s a_q with
+ *    (pq|rs) = sum_t weight[t] sum_L B_t[L,p,q] B_t[L,r,s]; h and every
+ *    B_t[L] must be Hermitian.  One factor set per two-electron operator
+ *    (Dirac-Coulomb, Gaunt, gauge), each with a real signed weight.
+ *  - Determinant phase: |D> = a+_{p1} ... a+_{pN} |0> with p1 < ... < pN.
+ *    The reference coefficient vector C follows the order returned by
+ *    mrpt2_plan_ref_strings.  Psi0 = C / ||C||; E0 is its Rayleigh quotient,
+ *    so C need not be normalised.
+ *  - All large arrays are device pointers owned by the caller.  The library
+ *    never allocates device memory: the caller provides a persistent region
+ *    (plan tables, uploaded once) and a workspace region (scratch).
+ *  - Every call returns a status; nothing aborts or throws across the ABI.
+ *
+ * Thread safety: a plan is immutable after mrpt2_plan; concurrent calls on
+ * one plan need separate workspaces.
+ */
+#ifndef MRPT2_H
+#define MRPT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRPT2_MAX_SUB 16
+#define MRPT2_MAX_SETS 4
+#define MRPT2_N_CLASS 9
+
+typedef enum {
+  MRPT2_OK = 0,
+  MRPT2_ERR_ARG = 1,          /* null pointer, bad count or value */
+  MRPT2_ERR_SHAPE = 2,        /* sizes inconsistent or beyond limits */
+  MRPT2_ERR_UNSUPPORTED = 3,  /* option not implemented */
+  MRPT2_ERR_WORKSPACE = 4,    /* persistent/workspace region too small */
+  MRPT2_ERR_HIP = 5,          /* a HIP runtime call failed */
+  MRPT2_ERR_NUMERIC = 6       /* non-finite input or a zero denominator */
+} mrpt2_status;
+
+typedef enum { MRPT2_FP64 = 0, MRPT2_MIXED = 1 } mrpt2_precision;
+
+/* Problem description (one instance).  Sec. 2.4: the primary space holds
+ * the active occupations whose per-subspace electron counts m_k satisfy
+ * sum m_k = n_act_elec and sum_k max(0, m_k - sub_base[k]) <= max_hops
+ * (max_hops >= n_act_elec gives a complete active space). */
+typedef struct {
+  int32_t n_frozen_core;            /* frozen core spinors (folded, Sec. 2.5) */
+  int32_t n_core;                   /* correlated core spinors */
+  int32_t n_virt;                   /* kept virtual spinors */
+  int32_t n_sub;                    /* DAS subspaces, 0..MRPT2_MAX_SUB (0: single
+                                       determinant reference) */
+  int32_t sub_size[MRPT2_MAX_SUB];  /* spinors per subspace */
+  int32_t sub_base[MRPT2_MAX_SUB];  /* base electron count per subspace */
+  int32_t max_hops;                 /* inter-subspace hop limit of P */
+  int32_t n_act_elec;               /* active electrons */
+  int32_t q_mode;                   /* 0: Q = all S+D not in P (Sec. 2.3);
+                                       1: only those with a core hole or a
+                                       virtual electron (Sec. 2.4 listing) */
+  int32_t n_sets;                   /* factor sets, 1..MRPT2_MAX_SETS */
+  int32_t rank[MRPT2_MAX_SETS];     /* Cholesky vectors per set */
+  double weight[MRPT2_MAX_SETS];    /* real signed weight per set */
+  int32_t precision;                /* mrpt2_precision */
+  double level_shift_b;             /* imaginary level shift b (Sec. 2.6);
+                                       must be 0 (eq. pt2 exactly) */
+} mrpt2_desc;
+
+/* Sizes and exact algorithmic work of one instance. */
+typedef struct {
+  int32_t n_orb;                    /* n (spinors passed in h, B) */
+  int32_t n_corr;                   /* correlated spinors */
+  int32_t n_chol;                   /* total Cholesky vectors */
+  int64_t n_ref;                    /* N_P */
+  int64_t n_ext;                    /* N_Q */
+  int64_t n_ext_class[MRPT2_N_CLASS];  /* per class, order (h,v) =
+      (2,2),(1,2),(0,2),(2,1),(1,1),(0,1),(2,0),(1,0),(0,0) */
+  int64_t n_strings_class[MRPT2_N_CLASS];
+  int64_t n_conn_class[MRPT2_N_CLASS];
+  double flop_integral;             /* algorithmic flops of the integral builds */
+  double flop_sigma;                /* algorithmic flops of the sigma contractions
+                                       (nonzero couplings only; the (2,2) class
+                                       has none) */
+  double bytes_factors;             /* bytes of all factor sets (one HBM pass) */
+} mrpt2_info;
+
+/* Inputs of one instance (device pointers). */
+typedef struct {
+  const double* h;                     /* complex [n][n] */
+  const double* B[MRPT2_MAX_SETS];     /* complex [rank_t][n][n] */
+  const double* c;                     /* complex [N_P], plan order */
+} mrpt2_inputs;
+
+typedef struct mrpt2_plan_s* mrpt2_plan_t;
+
+/* Build the plan for n_inst instances (host only; no device work).
+ * Enumerates the DAS categories, reference and external strings by
+ * excitation class (Sec. 2.4), excitation lists and the work decomposition.
+ * Errors: MRPT2_ERR_ARG for null pointers or n_inst < 1, MRPT2_ERR_SHAPE for
+ * inconsistent sizes (electrons vs subspaces, more than 64 active spinors,
+ * N_P >= 2^24), MRPT2_ERR_UNSUPPORTED for level_shift_b != 0 or an unknown
+ * precision.  On error *out is NULL. */
+mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out);
+
+/* Bytes of the persistent region (plan tables) and of the workspace needed by
+ * mrpt2_energy.  Both must be 256-byte aligned device allocations. */
+mrpt2_status mrpt2_plan_sizes(mrpt2_plan_t plan, size_t* persistent_bytes, size_t* workspace_bytes);
+
+/* Copy the plan tables to the caller's persistent region (async on stream;
+ * the host source stays valid for the life of the plan). */
+mrpt2_status mrpt2_plan_upload(mrpt2_plan_t plan, void* persistent, size_t bytes, hipStream_t stream);
+
+mrpt2_status mrpt2_plan_info(mrpt2_plan_t plan, int32_t inst, mrpt2_info* info);
+
+/* Active parts of the reference determinants, in the order C must follow:
+ * bit t of bits[i] set = active spinor t (0-based within the active block)
+ * occupied in reference determinant i.  bits has N_P entries (host). */
+mrpt2_status mrpt2_plan_ref_strings(mrpt2_plan_t plan, int32_t inst, uint64_t* bits);
+
+/* E2 for every instance.  in: n_inst input sets (host array of structs whose
+ * pointers are device pointers).  e2: device double[n_inst] (written).
+ * parts: optional device double[n_inst][12] = per-class E2 (class order as
+ * in mrpt2_info), then E0 - E_core (reference energy relative to the core
+ * energy), then ||C||^2.  Enqueued on stream; the call synchronises the
+ * stream once to read the device error flag.  Errors: MRPT2_ERR_WORKSPACE if
+ * the regions are too small or not uploaded, MRPT2_ERR_NUMERIC if an input
+ * is not finite or a denominator is zero (the energies are then not valid),
+ * MRPT2_ERR_HIP for launch or runtime failures. */
+mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in,
+                          const void* persistent, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream, double* e2, double* parts);
+
+/* Dense reference-space Hamiltonian minus the core energy,
+ * H_PP - E_core * 1, for instance inst (complex [N_P][N_P], device, written)
+ * - the matrix whose lowest eigenvector is the reference state.  Uses the
+ * same workspace as mrpt2_energy; c in `in` is not read. */
+mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
+                                         const void* persistent, void* workspace,
+                                         size_t workspace_bytes, hipStream_t stream, double* hpp);
+
+void mrpt2_plan_destroy(mrpt2_plan_t plan);
+const char* mrpt2_status_string(mrpt2_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

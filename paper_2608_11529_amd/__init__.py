@@ -1,0 +1,147 @@
+"""MI355X-native Epstein-Nesbet MRPT2 energy in the STP-DAS organisation.
+
+Python front end of libmrpt2.so.  PyTorch supplies device memory and the
+stream; every step of the energy runs in the library's HIP kernels.  The
+package fails loudly when the library is missing or no GPU is present: there
+is no CPU fallback.
+"""
+import ctypes
+
+import numpy as np
+
+from . import capi
+from .capi import CLASSES, Mrpt2Error  # noqa: F401
+
+
+def make_desc(n_frozen_core, n_core, n_virt, sub_sizes, sub_base, max_hops, n_act_elec,
+              sets, q_mode=0, precision=0, level_shift_b=0.0):
+    """Fill a descriptor.  sets = [(rank, weight), ...]."""
+    d = capi.Desc()
+    d.n_frozen_core = n_frozen_core
+    d.n_core = n_core
+    d.n_virt = n_virt
+    d.n_sub = len(sub_sizes)
+    for k, (s, b) in enumerate(zip(sub_sizes, sub_base)):
+        d.sub_size[k] = s
+        d.sub_base[k] = b
+    d.max_hops = max_hops
+    d.n_act_elec = n_act_elec
+    d.q_mode = q_mode
+    d.n_sets = len(sets)
+    for t, (r, w) in enumerate(sets):
+        d.rank[t] = r
+        d.weight[t] = w
+    d.precision = precision
+    d.level_shift_b = level_shift_b
+    return d
+
+
+def desc_of_problem(pb, precision=0, q_mode=None):
+    """Descriptor of a synth.problems.Problem."""
+    return make_desc(pb.n_fc, pb.n_c, pb.n_v, pb.sub_sizes, pb.base, min(pb.max_hops, 1 << 20),
+                     pb.n_elec, pb.sets, pb.q_mode if q_mode is None else q_mode, precision)
+
+
+class Plan:
+    """Host plan of one or more instances (no device work)."""
+
+    def __init__(self, descs):
+        if isinstance(descs, capi.Desc):
+            descs = [descs]
+        self.n_inst = len(descs)
+        arr = (capi.Desc * self.n_inst)(*descs)
+        self._descs = arr
+        h = ctypes.c_void_p()
+        capi.check(capi.lib().mrpt2_plan(arr, self.n_inst, ctypes.byref(h)), "mrpt2_plan")
+        self.handle = h
+        p, w = ctypes.c_size_t(), ctypes.c_size_t()
+        capi.check(capi.lib().mrpt2_plan_sizes(h, ctypes.byref(p), ctypes.byref(w)), "mrpt2_plan_sizes")
+        self.persistent_bytes = p.value
+        self.workspace_bytes = w.value
+
+    def info(self, inst=0):
+        inf = capi.Info()
+        capi.check(capi.lib().mrpt2_plan_info(self.handle, inst, ctypes.byref(inf)), "mrpt2_plan_info")
+        return inf
+
+    def ref_strings(self, inst=0):
+        n = self.info(inst).n_ref
+        out = np.zeros(n, dtype=np.uint64)
+        capi.check(capi.lib().mrpt2_plan_ref_strings(
+            self.handle, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "mrpt2_plan_ref_strings")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        try:
+            if h is not None and h.value:
+                capi.lib().mrpt2_plan_destroy(h)
+        except Exception:      # interpreter shutdown
+            pass
+        self.handle = None
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2608_11529_amd needs a ROCm GPU (gfx950); none is visible")
+    return torch
+
+
+class Engine:
+    """A plan with its device regions, bound to one GPU and stream."""
+
+    def __init__(self, plan, device="cuda:0", stream=None):
+        torch = _require_gpu()
+        self.torch = torch
+        self.plan = plan
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.persistent = torch.empty(max(plan.persistent_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+        capi.check(capi.lib().mrpt2_plan_upload(plan.handle, self.persistent.data_ptr(), plan.persistent_bytes,
+                                               self._sptr()), "mrpt2_plan_upload")
+        self.e2 = torch.zeros(plan.n_inst, dtype=torch.float64, device=self.device)
+        self.parts = torch.zeros((plan.n_inst, 12), dtype=torch.float64, device=self.device)
+
+    def _sptr(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _inputs(self, insts):
+        arr = (capi.Inputs * len(insts))()
+        keep = []
+        for i, (h, Bs, c) in enumerate(insts):
+            for x in [h, c, *Bs]:
+                if x is not None:
+                    if not x.is_contiguous() or x.device != self.device:
+                        raise ValueError("inputs must be contiguous tensors on the engine's device")
+                    keep.append(x)
+            arr[i].h = h.data_ptr()
+            for t, B in enumerate(Bs):
+                arr[i].B[t] = B.data_ptr()
+            arr[i].c = c.data_ptr() if c is not None else None
+        return arr, keep
+
+    def energy(self, insts, parts=True):
+        """insts: list of (h, [B_t], c) complex128 device tensors per
+        instance.  Returns the device tensor of E2 per instance (and the
+        per-class parts when parts=True)."""
+        arr, keep = self._inputs(insts)
+        code = capi.lib().mrpt2_energy(self.plan.handle, arr, self.persistent.data_ptr(),
+                                       self.workspace.data_ptr(), self.plan.workspace_bytes, self._sptr(),
+                                       self.e2.data_ptr(), self.parts.data_ptr() if parts else None)
+        capi.check(code, "mrpt2_energy")
+        del keep
+        return (self.e2, self.parts) if parts else self.e2
+
+    def reference_hamiltonian(self, h, Bs, inst=0):
+        torch = self.torch
+        n_p = self.plan.info(inst).n_ref
+        out = torch.empty((n_p, n_p), dtype=torch.complex128, device=self.device)
+        arr, keep = self._inputs([(h, Bs, None)])
+        code = capi.lib().mrpt2_reference_hamiltonian(self.plan.handle, inst, arr, self.persistent.data_ptr(),
+                                                      self.workspace.data_ptr(), self.plan.workspace_bytes,
+                                                      self._sptr(), out.data_ptr())
+        capi.check(code, "mrpt2_reference_hamiltonian")
+        del keep
+        return out

@@ -1,0 +1,117 @@
+"""ctypes binding of libmrpt2.so (argument marshalling only).
+
+Every function here forwards to the C interface declared in include/mrpt2.h;
+no arithmetic of the method runs in Python.  Device buffers are passed as
+raw pointers (torch tensors' data_ptr()), streams as raw HIP stream handles.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrpt2.so")
+
+MAX_SUB = 16
+MAX_SETS = 4
+N_CLASS = 9
+CLASSES = [(2, 2), (1, 2), (0, 2), (2, 1), (1, 1), (0, 1), (2, 0), (1, 0), (0, 0)]
+
+STATUS = {
+    0: "ok", 1: "invalid argument", 2: "inconsistent or unsupported sizes",
+    3: "unsupported option", 4: "persistent or workspace region too small",
+    5: "HIP runtime error", 6: "non-finite input or zero denominator",
+}
+
+
+class Mrpt2Error(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {STATUS.get(code, 'unknown')} (status {code})")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("n_frozen_core", ctypes.c_int32),
+        ("n_core", ctypes.c_int32),
+        ("n_virt", ctypes.c_int32),
+        ("n_sub", ctypes.c_int32),
+        ("sub_size", ctypes.c_int32 * MAX_SUB),
+        ("sub_base", ctypes.c_int32 * MAX_SUB),
+        ("max_hops", ctypes.c_int32),
+        ("n_act_elec", ctypes.c_int32),
+        ("q_mode", ctypes.c_int32),
+        ("n_sets", ctypes.c_int32),
+        ("rank", ctypes.c_int32 * MAX_SETS),
+        ("weight", ctypes.c_double * MAX_SETS),
+        ("precision", ctypes.c_int32),
+        ("level_shift_b", ctypes.c_double),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n_orb", ctypes.c_int32),
+        ("n_corr", ctypes.c_int32),
+        ("n_chol", ctypes.c_int32),
+        ("n_ref", ctypes.c_int64),
+        ("n_ext", ctypes.c_int64),
+        ("n_ext_class", ctypes.c_int64 * N_CLASS),
+        ("n_strings_class", ctypes.c_int64 * N_CLASS),
+        ("n_conn_class", ctypes.c_int64 * N_CLASS),
+        ("flop_integral", ctypes.c_double),
+        ("flop_sigma", ctypes.c_double),
+        ("bytes_factors", ctypes.c_double),
+    ]
+
+
+class Inputs(ctypes.Structure):
+    _fields_ = [
+        ("h", ctypes.c_void_p),
+        ("B", ctypes.c_void_p * MAX_SETS),
+        ("c", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmrpt2.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2608_11529_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int
+        L.mrpt2_plan.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, ctypes.POINTER(vp)]
+        L.mrpt2_plan.restype = st
+        L.mrpt2_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.mrpt2_plan_sizes.restype = st
+        L.mrpt2_plan_upload.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.mrpt2_plan_upload.restype = st
+        L.mrpt2_plan_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Info)]
+        L.mrpt2_plan_info.restype = st
+        L.mrpt2_plan_ref_strings.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+        L.mrpt2_plan_ref_strings.restype = st
+        L.mrpt2_energy.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp]
+        L.mrpt2_energy.restype = st
+        L.mrpt2_reference_hamiltonian.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Inputs), vp, vp,
+                                                  ctypes.c_size_t, vp, vp]
+        L.mrpt2_reference_hamiltonian.restype = st
+        L.mrpt2_plan_destroy.argtypes = [vp]
+        L.mrpt2_plan_destroy.restype = None
+        L.mrpt2_status_string.argtypes = [st]
+        L.mrpt2_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(code, where):
+    if code != 0:
+        raise Mrpt2Error(code, where)
+
+
+EXPORTED = [
+    "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
+    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_reference_hamiltonian",
+    "mrpt2_plan_destroy", "mrpt2_status_string",
+]

@@ -1,0 +1,96 @@
+// Device kernels of the MRPT2 energy (gfx950).
+//
+// Index conventions (n_fc frozen core, n_c core, n_a active, n_v virtual):
+//   global spinor g in [0, n): frozen core, core, active, virtual;
+//   correlated index pc = g - n_fc;
+//   occupied index xo in [0, n_o): core then active (n_o = n_c + n_a);
+//   active/virtual row index pr in [0, n_a + n_v): active then virtual.
+// Complex numbers are double2 (x = re, y = im).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrpt2 {
+
+// ---- complex helpers -------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+// Reciprocal: hardware estimate (about 2^-24 relative) refined by one
+// Newton-Raphson step, r1 = r0 (2 - d r0), giving relative error below 2^-47
+// with a one-sided bias, far under the energy tolerances used here.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ---- per-instance device view -------------------------------------------------
+struct Dev {
+  int n_fc, n_c, n_a, n_v, n_o, n_occ, n_corr, n, n_l, n_p;
+  int n_vt;
+  int64_t n_tp, n_pairs;
+  const double* sign;        // [n_l]
+  const double* scale;       // [n_l]
+  const uint64_t* pstrings;  // [n_p]
+  const int32_t* hole_pairs; // [C(n_c,2)][2]
+  const int32_t* tile_pairs; // [n_tp][2]
+  double* dg;                // [n_l][n]   scale * Re B[L][p][p]
+  double2* slab;             // [n_occ][n_corr][n_l]   scale * B[L][n_fc+pc][x]
+  double* W;                 // [n][n]
+  double* eps;               // [n_corr]
+  double2* f;                // [n_a+n_v][n_o]
+  double2* G;                // [n_o][n_a+n_v][n_o][n_a]
+  double2* A;                // [n_pairs][n_tp][64][64]
+  double2* hpp;              // [n_p][n_p]
+  double2* sigp;             // [n_p]
+  double* scal;              // [0] = E0 - E_core, [1] = ||C||^2
+  double* dsum;              // [n_l]
+  const double2* c;          // [n_p]
+};
+
+struct SetPtrs {
+  const double2* B[4];
+  int rank[4];
+  int l0[4];
+  int n_sets;
+};
+
+struct Pattern;
+
+struct ClassDev {
+  int h, v, n_pat;
+  int64_t n_str, n_rows, n_holes;
+  const uint64_t* strings;
+  const int32_t* conn_ptr;
+  const int32_t* conn;
+  const Pattern* pat;
+  double* T;     // [S]
+  double* Uc;    // [S][n_c]
+  double* Uv;    // [S][n_v]
+  double2* X;    // [n_pat][n_rows] (v < 2)
+  double* part;  // partial sums
+  int nsc;       // string chunks
+};
+
+struct PartList {
+  const double* p[9];
+  int64_t n[9];
+};
+
+__device__ __forceinline__ int64_t occ_pair(int x, int y, int n_o) {  // x < y
+  return (int64_t)x * n_o - (int64_t)x * (x + 1) / 2 + (y - x - 1);
+}
+
+__device__ __forceinline__ double2 Gv(const Dev& d, int xo, int pr, int yo, int qa) {
+  return d.G[(((int64_t)xo * (d.n_a + d.n_v) + pr) * d.n_o + yo) * d.n_a + qa];
+}
+
+}  // namespace mrpt2

@@ -1,0 +1,377 @@
+// Reference-space energy, per-string denominator tables, the sigma
+// contraction with the Epstein-Nesbet epilogue, and the reductions.
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace mrpt2 {
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// Sign of a_p or a+_p on string s (active bits below p).
+__device__ __forceinline__ int below_parity(uint64_t s, int p) { return popc64(s & ((1ull << p) - 1)) & 1; }
+
+// Active-space energy of string al relative to the core energy:
+// sum_{t in al} eps_t + sum_{t<u in al} W_tu.
+__device__ double act_energy(const Dev& d, uint64_t al) {
+  double e = 0.0;
+  uint64_t x = al;
+  while (x) {
+    const int t = __builtin_ctzll(x);
+    x &= x - 1;
+    const int gt = d.n_fc + d.n_c + t;
+    e += d.eps[d.n_c + t];
+    uint64_t y = x;
+    while (y) {
+      const int u = __builtin_ctzll(y);
+      y &= y - 1;
+      e += d.W[(int64_t)gt * d.n + d.n_fc + d.n_c + u];
+    }
+  }
+  return e;
+}
+
+// Dense reference-space Hamiltonian minus the core energy, by the
+// Slater-Condon rules within the active space (core and frozen core folded
+// into f).  Row i = bra, column j = ket.  grid (ceil(np/16), ceil(np/16)),
+// block (16, 16).
+__global__ void __launch_bounds__(256) k_hpp(Dev d, double2* __restrict__ out) {
+  const int j = blockIdx.x * 16 + threadIdx.x;
+  const int i = blockIdx.y * 16 + threadIdx.y;
+  if (i >= d.n_p || j >= d.n_p) return;
+  const uint64_t bi = d.pstrings[i], bj = d.pstrings[j];
+  const uint64_t cre = bi & ~bj, ann = bj & ~bi;
+  const int nd = popc64(cre);
+  double2 v = make_double2(0.0, 0.0);
+  const int nc = d.n_c;
+  if (nd == 0) {
+    v.x = act_energy(d, bi);
+  } else if (nd == 1) {
+    const int p = __builtin_ctzll(cre), q = __builtin_ctzll(ann);
+    // ket a_q then a+_p
+    int par = below_parity(bj, q);
+    const uint64_t mid = bj & ~(1ull << q);
+    par ^= below_parity(mid, p);
+    v = d.f[(int64_t)p * d.n_o + nc + q];
+    uint64_t x = mid;
+    while (x) {
+      const int w = __builtin_ctzll(x);
+      x &= x - 1;
+      v = cadd(v, csub(Gv(d, nc + q, p, nc + w, w), Gv(d, nc + w, p, nc + q, w)));
+    }
+    if (par) v = make_double2(-v.x, -v.y);
+  } else if (nd == 2) {
+    const int q1 = __builtin_ctzll(ann), q2 = 63 - __builtin_clzll(ann);
+    const int p1 = __builtin_ctzll(cre), p2 = 63 - __builtin_clzll(cre);
+    // ket a_q1, a_q2, a+_p1, a+_p2: value (p2 q1|p1 q2) - (p2 q2|p1 q1)
+    uint64_t s = bj;
+    int par = below_parity(s, q1);
+    s &= ~(1ull << q1);
+    par ^= below_parity(s, q2);
+    s &= ~(1ull << q2);
+    par ^= below_parity(s, p1);
+    s |= 1ull << p1;
+    par ^= below_parity(s, p2);
+    v = csub(Gv(d, nc + q1, p2, nc + q2, p1), Gv(d, nc + q2, p2, nc + q1, p1));
+    if (par) v = make_double2(-v.x, -v.y);
+  }
+  out[(int64_t)i * d.n_p + j] = v;
+}
+
+// sigma_P = H~ C, one wavefront per row.  grid (np), block 64.
+__global__ void __launch_bounds__(64) k_sigp(Dev d, const double2* __restrict__ hpp) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int j = lane; j < d.n_p; j += 64) acc = cfma(hpp[(int64_t)i * d.n_p + j], d.c[j], acc);
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_down(acc.x, off, 64);
+    acc.y += __shfl_down(acc.y, off, 64);
+  }
+  if (lane == 0) d.sigp[i] = acc;
+}
+
+// E0 - E_core = Re(C^H H~ C) / C^H C and ||C||^2.  One block, fixed order.
+__global__ void __launch_bounds__(256) k_e0(Dev d, int* flag) {
+  __shared__ double sn[256], sd[256];
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < d.n_p; i += 256) {
+    const double2 c = d.c[i], s = d.sigp[i];
+    num += c.x * s.x + c.y * s.y;
+    den += cabs2(c);
+  }
+  sn[threadIdx.x] = num;
+  sd[threadIdx.x] = den;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sn[threadIdx.x] += sn[threadIdx.x + o];
+      sd[threadIdx.x] += sd[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double e0 = sn[0] / sd[0];
+    if (!isfinite(e0) || !(sd[0] > 0.0)) *flag = 1;
+    d.scal[0] = e0;
+    d.scal[1] = sd[0];
+  }
+}
+
+// T[s] = (E0 - E_core) - E_act(alpha_s); Uc[s][c] = sum_{t in alpha_s} W_ct;
+// Uv[s][a] = sum_{t in alpha_s} W_at.  grid (S, ceil(max(n_c, n_v)/256)).
+__global__ void __launch_bounds__(256) k_class_tables(Dev d, ClassDev cd) {
+  const int64_t s = blockIdx.x;
+  const uint64_t al = cd.strings[s];
+  const int p = blockIdx.y * 256 + threadIdx.x;
+  if (blockIdx.y == 0 && threadIdx.x == 0) cd.T[s] = d.scal[0] - act_energy(d, al);
+  const int ga = d.n_fc + d.n_c;   // first active global index
+  if (cd.h > 0 && p < d.n_c) {
+    double u = 0.0;
+    uint64_t x = al;
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      u += d.W[(int64_t)(d.n_fc + p) * d.n + ga + t];
+    }
+    cd.Uc[s * d.n_c + p] = u;
+  }
+  if (cd.v > 0 && p < d.n_v) {
+    double u = 0.0;
+    uint64_t x = al;
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      u += d.W[(int64_t)(d.n_fc + d.n_o + p) * d.n + ga + t];
+    }
+    cd.Uv[s * d.n_v + p] = u;
+  }
+}
+
+// Row r of a class with v <= 1: holes index * n_v^v + virtual.
+__device__ __forceinline__ void decode_small_row(const Dev& d, const ClassDev& cd, int64_t r, int* c0,
+                                                 int* c1, int* a) {
+  int64_t hi = r;
+  *a = -1;
+  if (cd.v == 1) {
+    *a = (int)(r % d.n_v);
+    hi = r / d.n_v;
+  }
+  *c0 = -1;
+  *c1 = -1;
+  if (cd.h == 1) *c0 = (int)hi;
+  if (cd.h == 2) {
+    *c0 = d.hole_pairs[2 * hi];
+    *c1 = d.hole_pairs[2 * hi + 1];
+  }
+}
+
+// Coupling integrals of the classes with at most one virtual electron, per
+// pattern and row; the operator order of the plan fixes the integral slots:
+// rank-2 K = a+_p a+_r a_s a_q L gives (pq|rs) - (ps|rq) with q, s the
+// annihilations in order (core first) and r, p the creations in order
+// (active first, virtual last); rank-1 K = a+_p a_q L gives f_pq (one-body
+// pattern) or (pq|ww) - (pw|wq) (spectator w).  G(x;p;y;q) = (px|qy).
+// grid (ceil(rows/256), n_pat).
+__global__ void __launch_bounds__(256) k_xbuild(Dev d, ClassDev cd) {
+  const int64_t r = blockIdx.x * 256ll + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= cd.n_rows) return;
+  int c0, c1, a;
+  decode_small_row(d, cd, r, &c0, &c1, &a);
+  const Pattern pt = cd.pat[j];
+  const int nc = d.n_c, na = d.n_a;
+  double2 x = make_double2(0.0, 0.0);
+  // q = first annihilation (occupied index), p = last creation (act/virt row)
+  if (pt.kind == PAT_SINGLE) {
+    const int qo = (cd.h == 1) ? c0 : nc + pt.a0;
+    const int pr = (cd.v == 1) ? na + a : pt.r0;
+    x = d.f[(int64_t)pr * d.n_o + qo];
+  } else if (pt.kind == PAT_SPECT) {
+    const int qo = (cd.h == 1) ? c0 : nc + pt.a0;
+    const int pr = (cd.v == 1) ? na + a : pt.r0;
+    const int w = pt.w;
+    x = csub(Gv(d, qo, pr, nc + w, w), Gv(d, nc + w, pr, qo, w));
+  } else {
+    // annihilations in order
+    int q, s;
+    if (cd.h == 2) { q = c0; s = c1; }
+    else if (cd.h == 1) { q = c0; s = nc + pt.a0; }
+    else { q = nc + pt.a0; s = nc + pt.a1; }
+    // creations in order: active ascending then virtual; r first, p last
+    int rr, pr;
+    if (cd.v == 1) { rr = pt.r0; pr = na + a; }
+    else { rr = pt.r0; pr = pt.r1; }
+    x = csub(Gv(d, q, pr, s, rr), Gv(d, s, pr, q, rr));
+  }
+  cd.X[(int64_t)j * cd.n_rows + r] = x;
+}
+
+constexpr int SIG_THREADS = 256;
+
+// Sigma contraction and Epstein-Nesbet epilogue for one class:
+//   sigma[r, s] = sum_{(beta, j, sign) in list(s)} sign C_beta X[j, r]
+//   Delta = (E0 - E_core) - (H_KK - E_core)
+//         = T[s] + sum_{c in holes} (eps_c + Uc[s][c]) - sum_{a in virt} (eps_a + Uv[s][a])
+//           - W_cc' - W_ab + sum_{c, a} W_ca
+//   partial += |sigma|^2 / Delta   (divided by ||C||^2 at the end)
+// One thread per row, a chunk of strings per block.  grid (rb * nsc).
+template <int H, int V>
+__global__ void __launch_bounds__(SIG_THREADS) k_sigma(Dev d, ClassDev cd, int* flag) {
+  __shared__ double red[SIG_THREADS];
+  const int64_t rb = blockIdx.x / cd.nsc;
+  const int sc = blockIdx.x % cd.nsc;
+  const int64_t chunk = (cd.n_str + cd.nsc - 1) / cd.nsc;
+  const int64_t s_lo = sc * chunk;
+  const int64_t s_hi = min(cd.n_str, s_lo + chunk);
+  int64_t r = rb * SIG_THREADS + threadIdx.x;
+  bool valid = r < cd.n_rows;
+  if (!valid) r = cd.n_rows - 1;
+  int c0 = -1, c1 = -1, a = -1, b = -1;
+  int64_t rab = 0, hole = 0;
+  const int nc = d.n_c;
+  if (V == 2) {
+    const int64_t per = d.n_tp * 4096;
+    hole = r / per;
+    rab = r % per;
+    const int64_t tp = rab >> 12;
+    const int la = (int)((rab >> 6) & 63), lb = (int)(rab & 63);
+    a = d.tile_pairs[2 * tp] * 64 + la;
+    b = d.tile_pairs[2 * tp + 1] * 64 + lb;
+    if (!(a < b && b < d.n_v)) {
+      valid = false;            // padding or lower triangle: keep table reads in range
+      a = 0;
+      b = d.n_v > 1 ? 1 : 0;
+    }
+    if (H == 1) c0 = (int)hole;
+    if (H == 2) {
+      c0 = d.hole_pairs[2 * hole];
+      c1 = d.hole_pairs[2 * hole + 1];
+    }
+  } else {
+    decode_small_row(d, cd, r, &c0, &c1, &a);
+  }
+  // row constant
+  double qr = 0.0;
+  const int gfc = d.n_fc, gv = d.n_fc + d.n_o;
+  if (H >= 1) qr += d.eps[c0];
+  if (H == 2) qr += d.eps[c1] - d.W[(int64_t)(gfc + c0) * d.n + gfc + c1];
+  if (V >= 1) qr -= d.eps[d.n_o + a];
+  if (V == 2) qr -= d.eps[d.n_o + b] + d.W[(int64_t)(gv + a) * d.n + gv + b];
+  if (H >= 1 && V >= 1) {
+    qr += d.W[(int64_t)(gfc + c0) * d.n + gv + a];
+    if (V == 2) qr += d.W[(int64_t)(gfc + c0) * d.n + gv + b];
+    if (H == 2) {
+      qr += d.W[(int64_t)(gfc + c1) * d.n + gv + a];
+      if (V == 2) qr += d.W[(int64_t)(gfc + c1) * d.n + gv + b];
+    }
+  }
+  double acc = 0.0;
+  bool bad = false;
+  for (int64_t s = s_lo; s < s_hi; ++s) {
+    const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
+    double2 sig = make_double2(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const int32_t cb = cd.conn[2 * e];
+      const int j = cd.conn[2 * e + 1];
+      double2 cv = d.c[cb & 0x7fffffff];
+      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+      double2 xv;
+      if (V == 2) {
+        const Pattern pt = cd.pat[j];
+        int64_t pair;
+        if (H == 2) pair = occ_pair(c0, c1, d.n_o);
+        else if (H == 1) pair = occ_pair(c0, nc + pt.a0, d.n_o);
+        else pair = occ_pair(nc + pt.a0, nc + pt.a1, d.n_o);
+        xv = d.A[pair * d.n_tp * 4096 + rab];
+      } else {
+        xv = cd.X[(int64_t)j * cd.n_rows + r];
+      }
+      sig = cfma(cv, xv, sig);
+    }
+    double del = cd.T[s] + qr;
+    if (H >= 1) del += cd.Uc[s * nc + c0];
+    if (H == 2) del += cd.Uc[s * nc + c1];
+    if (V >= 1) del -= cd.Uv[s * d.n_v + a];
+    if (V == 2) del -= cd.Uv[s * d.n_v + b];
+    if (e1 > e0) {
+      const double t = cabs2(sig) * rcp_nr(del);
+      if (valid) {
+        if (!(del != 0.0) || !isfinite(t)) bad = true;
+        acc += t;
+      }
+    }
+  }
+  if (bad) *flag = 2;
+  red[threadIdx.x] = valid ? acc : 0.0;
+  __syncthreads();
+  for (int o = SIG_THREADS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cd.part[blockIdx.x] = red[0];
+}
+
+template __global__ void k_sigma<2, 2>(Dev, ClassDev, int*);
+template __global__ void k_sigma<1, 2>(Dev, ClassDev, int*);
+template __global__ void k_sigma<0, 2>(Dev, ClassDev, int*);
+template __global__ void k_sigma<2, 1>(Dev, ClassDev, int*);
+template __global__ void k_sigma<1, 1>(Dev, ClassDev, int*);
+template __global__ void k_sigma<0, 1>(Dev, ClassDev, int*);
+template __global__ void k_sigma<2, 0>(Dev, ClassDev, int*);
+template __global__ void k_sigma<1, 0>(Dev, ClassDev, int*);
+template __global__ void k_sigma<0, 0>(Dev, ClassDev, int*);
+
+// Per-class sum of partials (Neumaier-compensated, fixed order) divided by
+// ||C||^2; out[k] for k < 9, out[9] = E2, out[10] = E0 - E_core,
+// out[11] = ||C||^2; e2 receives E2.  One block.
+__global__ void __launch_bounds__(256) k_finish(Dev d, PartList pl, double* out, double* e2) {
+  __shared__ double ss[256], sc[256];
+  __shared__ double cls[MRPT2_N_CLASS];
+  for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+    double s = 0.0, comp = 0.0;
+    for (int64_t i = threadIdx.x; i < pl.n[k]; i += 256) {
+      const double x = pl.p[k][i];
+      const double t = s + x;
+      comp += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+      s = t;
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = comp;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) {
+        const double a = ss[threadIdx.x], b = ss[threadIdx.x + o];
+        const double t = a + b;
+        const double e = (fabs(a) >= fabs(b)) ? (a - t) + b : (b - t) + a;
+        ss[threadIdx.x] = t;
+        sc[threadIdx.x] += sc[threadIdx.x + o] + e;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cls[k] = (ss[0] + sc[0]) / d.scal[1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0, comp = 0.0;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const double x = cls[k];
+      const double t = s + x;
+      comp += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+      s = t;
+    }
+    const double tot = s + comp;
+    if (out) {
+      for (int k = 0; k < MRPT2_N_CLASS; ++k) out[k] = cls[k];
+      out[9] = tot;
+      out[10] = d.scal[0];
+      out[11] = d.scal[1];
+    }
+    *e2 = tot;
+  }
+}
+
+__global__ void k_clear_flag(int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+}  // namespace mrpt2

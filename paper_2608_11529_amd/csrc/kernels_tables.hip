@@ -1,0 +1,301 @@
+// One-pass tables over the Cholesky factors (frozen-core fold, core Fock
+// matrix, pair energies) and the complex FP64 MFMA integral builds.
+#include "kernels.hpp"
+
+namespace mrpt2 {
+
+// Slab of the factor columns of every occupied-type spinor x (frozen core,
+// core, active): slab[x][pc][L] = sqrt|w| B[L][n_fc + pc][x], and the scaled
+// diagonals dg[L][p] = sqrt|w| Re B[L][p][p].
+// grid (ceil(rank/64), n_corr), block 256.
+__global__ void __launch_bounds__(256) k_pack(Dev d, const double2* __restrict__ B, int l0, int rank) {
+  __shared__ double2 tile[64][17];
+  const int pc = blockIdx.y;
+  const int Lb = blockIdx.x * 64;
+  const int row = d.n_fc + pc;
+  for (int x0 = 0; x0 < d.n_occ; x0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int li = e >> 4, xi = e & 15;
+      const int L = Lb + li, x = x0 + xi;
+      double2 v = make_double2(0.0, 0.0);
+      if (L < rank && x < d.n_occ) v = B[((int64_t)L * d.n + row) * d.n + x];
+      tile[li][xi] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int xi = e >> 6, li = e & 63;
+      const int L = Lb + li, x = x0 + xi;
+      if (L < rank && x < d.n_occ) {
+        const double s = d.scale[l0 + L];
+        const double2 v = tile[li][xi];
+        d.slab[((int64_t)x * d.n_corr + pc) * d.n_l + l0 + L] = make_double2(s * v.x, s * v.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// grid (ceil(n/256), rank)
+__global__ void __launch_bounds__(256) k_diag(Dev d, const double2* __restrict__ B, int l0, int rank) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int L = blockIdx.y;
+  if (p >= d.n || L >= rank) return;
+  d.dg[(int64_t)(l0 + L) * d.n + p] = d.scale[l0 + L] * B[((int64_t)L * d.n + p) * d.n + p].x;
+}
+
+// Pair energies W_pq = (pp|qq) - (pq|qp) over all spinors, streaming every
+// factor once: (pq|qp) = sum_L w_L |B_pq|^2 for Hermitian B.
+// grid (ceil(n/256), n), block 256.  Sets flag on non-finite results.
+__global__ void __launch_bounds__(256) k_wpass(Dev d, SetPtrs sp, int* flag) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= d.n) return;
+  double coul = 0.0, exch = 0.0;
+  for (int t = 0; t < sp.n_sets; ++t) {
+    const double2* __restrict__ B = sp.B[t] + (int64_t)p * d.n + q;
+    const int64_t stride = (int64_t)d.n * d.n;
+    const int l0 = sp.l0[t];
+    const int rank = sp.rank[t];
+    int L = 0;
+    for (; L + 4 <= rank; L += 4) {
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = B[(int64_t)(L + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int Lg = l0 + L + u;
+        const double sg = d.sign[Lg], sc = d.scale[Lg];
+        exch = fma(sg * sc * sc, cabs2(v[u]), exch);
+        coul = fma(sg * d.dg[(int64_t)Lg * d.n + p], d.dg[(int64_t)Lg * d.n + q], coul);
+      }
+    }
+    for (; L < rank; ++L) {
+      const double2 v = B[(int64_t)L * stride];
+      const int Lg = l0 + L;
+      const double sg = d.sign[Lg], sc = d.scale[Lg];
+      exch = fma(sg * sc * sc, cabs2(v), exch);
+      coul = fma(sg * d.dg[(int64_t)Lg * d.n + p], d.dg[(int64_t)Lg * d.n + q], coul);
+    }
+  }
+  double w = (p == q) ? 0.0 : coul - exch;
+  if (!isfinite(w) || !isfinite(coul + exch)) {
+    *flag = 1;
+    w = 0.0;
+  }
+  d.W[(int64_t)p * d.n + q] = w;
+}
+
+// Orbital energies in the field of the frozen and correlated core:
+// eps_p = h_pp + sum_{j in core, j != p} W_pj (frozen core included).
+__global__ void __launch_bounds__(256) k_eps(Dev d, const double2* __restrict__ h, int* flag) {
+  const int pc = blockIdx.x * 256 + threadIdx.x;
+  if (pc >= d.n_corr) return;
+  const int g = d.n_fc + pc;
+  double e = h[(int64_t)g * d.n + g].x;
+  for (int j = 0; j < d.n_fc + d.n_c; ++j)
+    if (j != g) e += d.W[(int64_t)g * d.n + j];
+  if (!isfinite(e) || !isfinite(h[(int64_t)g * d.n + g].y)) *flag = 1;
+  d.eps[pc] = e;
+}
+
+// dsum[L] = sum over frozen and correlated core j of dg[L][j].
+__global__ void __launch_bounds__(256) k_dsum(Dev d) {
+  const int L = blockIdx.x * 256 + threadIdx.x;
+  if (L >= d.n_l) return;
+  double s = 0.0;
+  for (int j = 0; j < d.n_fc + d.n_c; ++j) s += d.dg[(int64_t)L * d.n + j];
+  d.dsum[L] = s;
+}
+
+// Core Fock matrix f_pq = h_pq + sum_{j in core} [(pq|jj) - (pj|jq)] for p
+// active or virtual and q core or active (frozen-core fold of Sec. 2 plus the
+// correlated core).  grid (n_o, n_a + n_v), one wavefront per entry.
+__global__ void __launch_bounds__(64) k_fock(Dev d, const double2* __restrict__ h) {
+  const int qo = blockIdx.x;
+  const int pr = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int pcorr = d.n_c + pr;
+  double2 acc = make_double2(0.0, 0.0);
+  const double2* Bq = d.slab + ((int64_t)(d.n_fc + qo) * d.n_corr + pcorr) * d.n_l;
+  for (int L = lane; L < d.n_l; L += 64) {
+    const double s = d.sign[L] * d.dsum[L];
+    acc.x = fma(s, Bq[L].x, acc.x);
+    acc.y = fma(s, Bq[L].y, acc.y);
+  }
+  for (int j = 0; j < d.n_fc + d.n_c; ++j) {
+    const double2* Bp = d.slab + ((int64_t)j * d.n_corr + pcorr) * d.n_l;
+    const double2* Bc = d.slab + ((int64_t)j * d.n_corr + qo) * d.n_l;
+    for (int L = lane; L < d.n_l; L += 64) {
+      const double s = d.sign[L];
+      const double2 a = Bp[L], b = Bc[L];   // B_pj and conj(B_jq) = B_qj
+      acc.x -= s * (a.x * b.x + a.y * b.y);
+      acc.y -= s * (a.y * b.x - a.x * b.y);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_down(acc.x, off, 64);
+    acc.y += __shfl_down(acc.y, off, 64);
+  }
+  if (lane == 0) {
+    const int gp = d.n_fc + pcorr, gq = d.n_fc + qo;
+    const double2 hv = h[(int64_t)gp * d.n + gq];
+    d.f[(int64_t)pr * d.n_o + qo] = make_double2(hv.x + acc.x, hv.y + acc.y);
+  }
+}
+
+// ---- complex FP64 MFMA tile: C[64][64] = sum_k a(r,k) b(c,k) ----------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int KC = 16;
+constexpr int KP = KC + 1;
+
+// v_mfma_f64_16x16x4f64 operand layout: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; the result D[i][j] sits in lane j + 16 (i%4), register i/4.
+// A complex product uses two real MFMAs per pair of complex k:
+//   Re += [ar, -ai] . [br; bi],   Im += [ai, ar] . [br; bi].
+template <class FA, class FB>
+__device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double2* sB,
+                                        d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int kq = lane >> 4;           // 0..3
+  const int kcl = kq >> 1, comp = kq & 1;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = tid; e < 64 * KC; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      const bool in = (k0 + kk) < K;
+      sA[r * KP + kk] = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
+      sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < KC; ks += 2) {
+      const int kc = ks + kcl;
+      double ar[2], ai[2], bb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double2 v = sA[(wr + i * 16 + (lane & 15)) * KP + kc];
+        ar[i] = comp ? -v.y : v.x;
+        ai[i] = comp ? v.x : v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double2 v = sB[(wc + j * 16 + (lane & 15)) * KP + kc];
+        bb[j] = comp ? v.y : v.x;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bb[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bb[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Row/column of accumulator element (i, j, reg) for this lane.
+__device__ __forceinline__ int acc_row(int i, int r) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  return (wv >> 1) * 32 + i * 16 + (lane >> 4) + 4 * r;
+}
+__device__ __forceinline__ int acc_col(int j) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  return (wv & 1) * 32 + j * 16 + (lane & 15);
+}
+
+// Antisymmetrised virtual-pair integrals for every occupied pair x < y
+// (core or active):  A[xy][a][b] = <ab||xy> = (ax|by) - (ay|bx)
+//   = sum_L w_L (B_ax B_by - B_ay B_bx),
+// one 64 x 64 tile (I, J), I <= J, of virtual pairs per block, K = 2 n_l.
+// grid (n_tp, n_pairs), block 256.
+__global__ void __launch_bounds__(256) k_abuild(Dev d) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int64_t tp = blockIdx.x;
+  int64_t pr = blockIdx.y;
+  int xo = 0;
+  while (pr >= d.n_o - 1 - xo) {
+    pr -= d.n_o - 1 - xo;
+    ++xo;
+  }
+  const int yo = xo + 1 + (int)pr;
+  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+  const int nl = d.n_l;
+  const double2* Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
+  const double2* Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
+  const double* sg = d.sign;
+  const int nv = d.n_v;
+  auto fa = [&](int r, int k) -> double2 {
+    const int a = I * 64 + r;
+    if (a >= nv) return make_double2(0.0, 0.0);
+    const int L = k < nl ? k : k - nl;
+    const double2 v = (k < nl ? Sx : Sy)[(int64_t)a * nl + L];
+    return make_double2(sg[L] * v.x, sg[L] * v.y);
+  };
+  auto fb = [&](int r, int k) -> double2 {
+    const int b = J * 64 + r;
+    if (b >= nv) return make_double2(0.0, 0.0);
+    if (k < nl) return Sy[(int64_t)b * nl + k];
+    const double2 v = Sx[(int64_t)b * nl + (k - nl)];
+    return make_double2(-v.x, -v.y);
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, 2 * nl, sA, sB, accR, accI);
+  double2* out = d.A + ((int64_t)blockIdx.y * d.n_tp + tp) * 4096;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[acc_row(i, r) * 64 + acc_col(j)] = make_double2(accR[i][j][r], accI[i][j][r]);
+}
+
+// Integrals with one active or virtual and one active spinor against two
+// occupied ones: G[x][p][y][q] = (px|qy), x, y core or active, p active or
+// virtual, q active.  One GEMM: rows (x, p), columns (y, q), K = n_l.
+// grid (ceil(N/64), ceil(M/64)), block 256.
+__global__ void __launch_bounds__(256) k_gbuild(Dev d) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int npr = d.n_a + d.n_v;
+  const int64_t M = (int64_t)d.n_o * npr;
+  const int64_t N = (int64_t)d.n_o * d.n_a;
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int nl = d.n_l;
+  const double* sg = d.sign;
+  auto fa = [&](int r, int k) -> double2 {
+    const int64_t m = m0 + r;
+    if (m >= M) return make_double2(0.0, 0.0);
+    const int xo = (int)(m / npr), p = (int)(m % npr);
+    const double2 v = d.slab[((int64_t)(d.n_fc + xo) * d.n_corr + d.n_c + p) * nl + k];
+    return make_double2(sg[k] * v.x, sg[k] * v.y);
+  };
+  auto fb = [&](int r, int k) -> double2 {
+    const int64_t nn = n0 + r;
+    if (nn >= N) return make_double2(0.0, 0.0);
+    const int yo = (int)(nn / d.n_a), q = (int)(nn % d.n_a);
+    return d.slab[((int64_t)(d.n_fc + yo) * d.n_corr + d.n_c + q) * nl + k];
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, nl, sA, sB, accR, accI);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + acc_row(i, r), nn = n0 + acc_col(j);
+        if (m < M && nn < N) d.G[m * N + nn] = make_double2(accR[i][j][r], accI[i][j][r]);
+      }
+}
+
+}  // namespace mrpt2

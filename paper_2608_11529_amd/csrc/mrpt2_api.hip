@@ -1,0 +1,282 @@
+// C interface: plan management and the launch sequence of one energy
+// evaluation (tables -> reference energy -> integral builds -> per-class
+// sigma contraction with the Epstein-Nesbet epilogue -> reductions).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.hpp"
+#include "mrpt2.h"
+#include "plan.hpp"
+
+#include "kernels_tables.hip"
+#include "kernels_energy.hip"
+
+struct mrpt2_plan_s {
+  mrpt2::Plan p;
+};
+
+using namespace mrpt2;
+
+namespace {
+
+#define HIPCHK(x)                                \
+  do {                                           \
+    if ((x) != hipSuccess) return MRPT2_ERR_HIP; \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_inputs* in) {
+  Dev d{};
+  d.n_fc = ip.n_fc;
+  d.n_c = ip.n_c;
+  d.n_a = ip.n_a;
+  d.n_v = ip.n_v;
+  d.n_o = ip.n_o;
+  d.n_occ = ip.n_occ;
+  d.n_corr = ip.n_corr;
+  d.n = ip.n;
+  d.n_l = ip.n_l;
+  d.n_p = (int)ip.pstrings.size();
+  d.n_vt = ip.n_vt;
+  d.n_tp = ip.n_tp;
+  d.n_pairs = ip.n_pairs;
+  const char* P = pers + ip.persistent_base;
+  char* W = work + ip.workspace_base;
+  d.sign = (const double*)(P + ip.off_sign);
+  d.scale = (const double*)(P + ip.off_scale);
+  d.pstrings = (const uint64_t*)(P + ip.off_pstrings);
+  d.hole_pairs = (const int32_t*)(P + ip.off_hole_pairs);
+  d.tile_pairs = (const int32_t*)(P + ip.off_tile_pairs);
+  d.dg = (double*)(W + ip.off_dg);
+  d.slab = (double2*)(W + ip.off_slab);
+  d.W = (double*)(W + ip.off_W);
+  d.eps = (double*)(W + ip.off_eps);
+  d.f = (double2*)(W + ip.off_f);
+  d.G = (double2*)(W + ip.off_G);
+  d.A = (double2*)(W + ip.off_A);
+  d.hpp = (double2*)(W + ip.off_hpp);
+  d.sigp = (double2*)(W + ip.off_sigp);
+  d.scal = (double*)(W + ip.off_scal);
+  d.dsum = (double*)(W + ip.off_dsum);
+  d.c = in ? (const double2*)in->c : nullptr;
+  return d;
+}
+
+ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work) {
+  const ClassPlan& cp = ip.cls[k];
+  const char* P = pers + ip.persistent_base;
+  char* W = work + ip.workspace_base;
+  ClassDev c{};
+  c.h = cp.h;
+  c.v = cp.v;
+  c.n_pat = (int)cp.patterns.size();
+  c.n_str = (int64_t)cp.strings.size();
+  c.n_rows = cp.n_rows;
+  c.n_holes = cp.n_holes;
+  c.strings = (const uint64_t*)(P + cp.off_strings);
+  c.conn_ptr = (const int32_t*)(P + cp.off_conn_ptr);
+  c.conn = (const int32_t*)(P + cp.off_conn);
+  c.pat = (const Pattern*)(P + cp.off_pat);
+  c.T = (double*)(W + cp.off_T);
+  c.Uc = (double*)(W + cp.off_Uc);
+  c.Uv = (double*)(W + cp.off_Uv);
+  c.X = (double2*)(W + cp.off_X);
+  c.part = (double*)(W + ip.off_part_class[k]);
+  const int64_t rb = cdiv(cp.n_rows, 256);
+  c.nsc = rb > 0 ? (int)(sigma_blocks(ip, k) / rb) : 1;
+  return c;
+}
+
+// Steps shared by the energy and the reference Hamiltonian: factor slabs,
+// pair energies, orbital energies, core Fock matrix, occupied integrals.
+mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipStream_t st, int* flag) {
+  SetPtrs sp{};
+  sp.n_sets = ip.d.n_sets;
+  int l0 = 0;
+  for (int t = 0; t < ip.d.n_sets; ++t) {
+    const int rank = ip.d.rank[t];
+    const double2* B = (const double2*)in->B[t];
+    if (rank > 0 && !B) return MRPT2_ERR_ARG;
+    sp.B[t] = B;
+    sp.rank[t] = rank;
+    sp.l0[t] = l0;
+    if (rank > 0) {
+      hipLaunchKernelGGL(k_pack, dim3(cdiv(rank, 64), ip.n_corr), dim3(256), 0, st, d, B, l0, rank);
+      hipLaunchKernelGGL(k_diag, dim3(cdiv(ip.n, 256), rank), dim3(256), 0, st, d, B, l0, rank);
+    }
+    l0 += rank;
+  }
+  hipLaunchKernelGGL(k_wpass, dim3(cdiv(ip.n, 256), ip.n), dim3(256), 0, st, d, sp, flag);
+  hipLaunchKernelGGL(k_eps, dim3(cdiv(ip.n_corr, 256)), dim3(256), 0, st, d, (const double2*)in->h, flag);
+  hipLaunchKernelGGL(k_dsum, dim3(cdiv(ip.n_l, 256)), dim3(256), 0, st, d);
+  if (ip.n_o > 0 && ip.n_a + ip.n_v > 0)
+    hipLaunchKernelGGL(k_fock, dim3(ip.n_o, ip.n_a + ip.n_v), dim3(64), 0, st, d, (const double2*)in->h);
+  if (ip.n_a > 0) {
+    const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
+    hipLaunchKernelGGL(k_gbuild, dim3(cdiv(N, 64), cdiv(M, 64)), dim3(256), 0, st, d);
+  }
+  HIPCHK(hipGetLastError());
+  return MRPT2_OK;
+}
+
+mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t wbytes) {
+  if (!pers || !work) return MRPT2_ERR_ARG;
+  if (wbytes < p.workspace_bytes) return MRPT2_ERR_WORKSPACE;
+  if (((uintptr_t)pers & 255) || ((uintptr_t)work & 255)) return MRPT2_ERR_ARG;
+  return MRPT2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out) {
+  if (!out) return MRPT2_ERR_ARG;
+  *out = nullptr;
+  mrpt2_plan_s* p = new (std::nothrow) mrpt2_plan_s();
+  if (!p) return MRPT2_ERR_ARG;
+  std::string err;
+  mrpt2_status st;
+  try {
+    st = build_plan(desc, n_inst, &p->p, &err);
+  } catch (...) {
+    st = MRPT2_ERR_SHAPE;
+  }
+  if (st != MRPT2_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_sizes(mrpt2_plan_t plan, size_t* pers, size_t* work) {
+  if (!plan || !pers || !work) return MRPT2_ERR_ARG;
+  *pers = plan->p.persistent_bytes;
+  *work = plan->p.workspace_bytes;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_upload(mrpt2_plan_t plan, void* pers, size_t bytes, hipStream_t st) {
+  if (!plan || !pers) return MRPT2_ERR_ARG;
+  if (bytes < plan->p.persistent_bytes) return MRPT2_ERR_WORKSPACE;
+  if ((uintptr_t)pers & 255) return MRPT2_ERR_ARG;
+  HIPCHK(hipMemcpyAsync(pers, plan->p.host_blob.data(), plan->p.persistent_bytes, hipMemcpyHostToDevice, st));
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_info(mrpt2_plan_t plan, int32_t inst, mrpt2_info* info) {
+  if (!plan || !info || inst < 0 || inst >= (int)plan->p.inst.size()) return MRPT2_ERR_ARG;
+  *info = plan->p.inst[inst].info;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_ref_strings(mrpt2_plan_t plan, int32_t inst, uint64_t* bits) {
+  if (!plan || !bits || inst < 0 || inst >= (int)plan->p.inst.size()) return MRPT2_ERR_ARG;
+  const auto& v = plan->p.inst[inst].pstrings;
+  std::memcpy(bits, v.data(), v.size() * 8);
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
+                          size_t workspace_bytes, hipStream_t st, double* e2, double* parts) {
+  if (!plan || !in || !e2) return MRPT2_ERR_ARG;
+  const Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  const char* pers = (const char*)persistent;
+  char* work = (char*)workspace;
+  int* flag = (int*)(work + P.off_flag);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
+  for (size_t ii = 0; ii < P.inst.size(); ++ii) {
+    const InstancePlan& ip = P.inst[ii];
+    const mrpt2_inputs* ini = in + ii;
+    if (!ini->h || !ini->c) return MRPT2_ERR_ARG;
+    Dev d = make_dev(ip, pers, work, ini);
+    s = tables(ip, ini, d, st, flag);
+    if (s != MRPT2_OK) return s;
+    const int np = (int)ip.pstrings.size();
+    hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, d.hpp);
+    hipLaunchKernelGGL(k_sigp, dim3(np), dim3(64), 0, st, d, (const double2*)d.hpp);
+    hipLaunchKernelGGL(k_e0, dim3(1), dim3(256), 0, st, d, flag);
+    if (ip.n_v >= 2 && ip.n_pairs > 0)
+      hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
+    PartList pl{};
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const ClassPlan& cp = ip.cls[k];
+      ClassDev cd = make_class(ip, k, pers, work);
+      pl.p[k] = cd.part;
+      pl.n[k] = 0;
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      const int mx = std::max(ip.n_c, ip.n_v);
+      hipLaunchKernelGGL(k_class_tables, dim3(cd.n_str, cdiv(std::max(mx, 1), 256)), dim3(256), 0, st, d, cd);
+      if (cp.v < 2)
+        hipLaunchKernelGGL(k_xbuild, dim3(cdiv(cp.n_rows, 256), cd.n_pat), dim3(256), 0, st, d, cd);
+      const int64_t nb = sigma_blocks(ip, k);
+      pl.n[k] = nb;
+      dim3 g(nb), b(256);
+      switch (k) {
+        case 0: hipLaunchKernelGGL((k_sigma<2, 2>), g, b, 0, st, d, cd, flag); break;
+        case 1: hipLaunchKernelGGL((k_sigma<1, 2>), g, b, 0, st, d, cd, flag); break;
+        case 2: hipLaunchKernelGGL((k_sigma<0, 2>), g, b, 0, st, d, cd, flag); break;
+        case 3: hipLaunchKernelGGL((k_sigma<2, 1>), g, b, 0, st, d, cd, flag); break;
+        case 4: hipLaunchKernelGGL((k_sigma<1, 1>), g, b, 0, st, d, cd, flag); break;
+        case 5: hipLaunchKernelGGL((k_sigma<0, 1>), g, b, 0, st, d, cd, flag); break;
+        case 6: hipLaunchKernelGGL((k_sigma<2, 0>), g, b, 0, st, d, cd, flag); break;
+        case 7: hipLaunchKernelGGL((k_sigma<1, 0>), g, b, 0, st, d, cd, flag); break;
+        default: hipLaunchKernelGGL((k_sigma<0, 0>), g, b, 0, st, d, cd, flag); break;
+      }
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, pl, parts ? parts + 12 * ii : nullptr, e2 + ii);
+    HIPCHK(hipGetLastError());
+  }
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+}
+
+mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
+                                         const void* persistent, void* workspace, size_t workspace_bytes,
+                                         hipStream_t st, double* hpp) {
+  if (!plan || !in || !hpp || inst < 0 || inst >= (int)plan->p.inst.size()) return MRPT2_ERR_ARG;
+  const Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  char* work = (char*)workspace;
+  int* flag = (int*)(work + P.off_flag);
+  const InstancePlan& ip = P.inst[inst];
+  if (!in->h) return MRPT2_ERR_ARG;
+  Dev d = make_dev(ip, (const char*)persistent, work, in);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
+  s = tables(ip, in, d, st, flag);
+  if (s != MRPT2_OK) return s;
+  const int np = (int)ip.pstrings.size();
+  hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, (double2*)hpp);
+  HIPCHK(hipGetLastError());
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+}
+
+void mrpt2_plan_destroy(mrpt2_plan_t plan) { delete plan; }
+
+const char* mrpt2_status_string(mrpt2_status s) {
+  switch (s) {
+    case MRPT2_OK: return "ok";
+    case MRPT2_ERR_ARG: return "invalid argument";
+    case MRPT2_ERR_SHAPE: return "inconsistent or unsupported sizes";
+    case MRPT2_ERR_UNSUPPORTED: return "unsupported option";
+    case MRPT2_ERR_WORKSPACE: return "persistent or workspace region too small";
+    case MRPT2_ERR_HIP: return "HIP runtime error";
+    case MRPT2_ERR_NUMERIC: return "non-finite input or zero denominator";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,465 @@
+// Host plan for the MRPT2 energy: STP-DAS categories and strings (Sec. 2.4),
+// external space by excitation class, excitation lists with fermionic signs,
+// and the device memory layout.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+namespace mrpt2 {
+namespace {
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t cur = 0;
+  size_t take(size_t bytes) {
+    size_t o = cur;
+    cur = align_up(cur + bytes);
+    return o;
+  }
+};
+
+// All electron counts m with sum m = ne and 0 <= m_k <= s_k, in lexicographic
+// order of (m_0, m_1, ...).
+void categories(const std::vector<int>& s, int ne, std::vector<std::vector<int>>* out) {
+  std::vector<int> m(s.size(), 0);
+  std::vector<int> suffix(s.size() + 1, 0);
+  for (int k = (int)s.size() - 1; k >= 0; --k) suffix[k] = suffix[k + 1] + s[k];
+  std::function<void(int, int)> rec = [&](int k, int left) {
+    if (k == (int)s.size()) {
+      if (left == 0) out->push_back(m);
+      return;
+    }
+    for (int x = 0; x <= std::min(s[k], left); ++x) {
+      if (left - x > suffix[k + 1]) continue;
+      m[k] = x;
+      rec(k + 1, left - x);
+    }
+  };
+  rec(0, ne);
+}
+
+// Strings of one category: product over subspaces of the combinations of m_k
+// spinors among s_k (lexicographic), the last subspace varying fastest.
+void category_strings(const std::vector<int>& s, const std::vector<int>& off,
+                      const std::vector<int>& m, std::vector<uint64_t>* out) {
+  std::vector<std::vector<uint64_t>> per(s.size());
+  for (size_t k = 0; k < s.size(); ++k) {
+    std::vector<int> c(m[k]);
+    for (int i = 0; i < m[k]; ++i) c[i] = i;
+    while (true) {
+      uint64_t b = 0;
+      for (int i = 0; i < m[k]; ++i) b |= 1ull << (off[k] + c[i]);
+      per[k].push_back(b);
+      int i = m[k] - 1;
+      while (i >= 0 && c[i] == s[k] - m[k] + i) --i;
+      if (i < 0) break;
+      ++c[i];
+      for (int j = i + 1; j < m[k]; ++j) c[j] = c[j - 1] + 1;
+    }
+  }
+  std::vector<size_t> idx(s.size(), 0);
+  while (true) {
+    uint64_t b = 0;
+    for (size_t k = 0; k < s.size(); ++k) b |= per[k][idx[k]];
+    out->push_back(b);
+    int k = (int)s.size() - 1;
+    while (k >= 0) {
+      if (++idx[k] < per[k].size()) break;
+      idx[k] = 0;
+      --k;
+    }
+    if (k < 0) break;
+  }
+}
+
+// Sign of applying the active operators to string beta (active bits only):
+// annihilations in `ann` order, then creations in `cre` order.  Each operator
+// on spinor p takes (-1)^(occupied active spinors below p).  Returns 0 when
+// the product vanishes; *res receives the resulting string.
+int op_sign(uint64_t beta, const int* ann, int na, const int* cre, int nc, uint64_t* res) {
+  int sgn = 1;
+  uint64_t d = beta;
+  for (int i = 0; i < na; ++i) {
+    uint64_t bit = 1ull << ann[i];
+    if (!(d & bit)) return 0;
+    if (popc(d & (bit - 1)) & 1) sgn = -sgn;
+    d &= ~bit;
+  }
+  for (int i = 0; i < nc; ++i) {
+    uint64_t bit = 1ull << cre[i];
+    if (d & bit) return 0;
+    if (popc(d & (bit - 1)) & 1) sgn = -sgn;
+    d |= bit;
+  }
+  *res = d;
+  return sgn;
+}
+
+std::vector<int> bits_of(uint64_t x) {
+  std::vector<int> b;
+  while (x) {
+    int p = __builtin_ctzll(x);
+    b.push_back(p);
+    x &= x - 1;
+  }
+  return b;
+}
+
+struct PatKey {
+  int32_t kind, a0, a1, r0, r1, w;
+  bool operator==(const PatKey& o) const {
+    return kind == o.kind && a0 == o.a0 && a1 == o.a1 && r0 == o.r0 && r1 == o.r1 && w == o.w;
+  }
+};
+struct PatHash {
+  size_t operator()(const PatKey& k) const {
+    return ((((size_t)k.kind * 131 + k.a0 + 1) * 131 + k.a1 + 1) * 131 + k.r0 + 1) * 131 * 131 +
+           (k.r1 + 1) * 131 + k.w + 1;
+  }
+};
+
+// Excitation lists of one class.  For external active string alpha and a
+// reference string beta = (alpha - R) + A:
+//   rank-2 patterns: |R| = 2 - v active creations, |A| = 2 - h annihilations;
+//   rank-1 patterns (h <= 1, v <= 1): |R| = 1 - v, |A| = 1 - h, as a one-body
+//   pattern and one spectator pattern per w in alpha - R.
+// Operator order (fixes the sign and the integral slots): core annihilations
+// ascending, active annihilations ascending (then w for a spectator), active
+// creations (w first for a spectator) ascending, virtual creations descending.
+void build_class(InstancePlan& ip, ClassPlan& cp) {
+  const int h = cp.h, v = cp.v;
+  std::unordered_map<PatKey, int, PatHash> pid;
+  auto get_pid = [&](const PatKey& k) {
+    auto it = pid.find(k);
+    if (it != pid.end()) return it->second;
+    int id = (int)cp.patterns.size();
+    pid.emplace(k, id);
+    cp.patterns.push_back(Pattern{k.kind, k.a0, k.a1, k.r0, k.r1, k.w, 0, 0});
+    return id;
+  };
+  // fixed pattern order for the dense classes: patterns indexed by their
+  // orbitals so that the integral layouts are regular
+  cp.conn_ptr.assign(cp.strings.size() + 1, 0);
+  const int n_a = ip.n_a;
+  const uint64_t amask = (n_a == 64) ? ~0ull : ((1ull << n_a) - 1);
+  for (size_t s = 0; s < cp.strings.size(); ++s) {
+    const uint64_t al = cp.strings[s];
+    const std::vector<int> occ = bits_of(al);
+    const std::vector<int> fre = bits_of(amask & ~al);
+    for (int rank = 1; rank <= 2; ++rank) {
+      const int nr = rank - v, na = rank - h;
+      if (nr < 0 || na < 0) continue;
+      // subsets R of occ of size nr, A of fre of size na
+      std::vector<int> R(nr), A(na);
+      std::function<void(int, int)> recA;
+      std::function<void(int, int)> recR = [&](int i0, int k) {
+        if (k == nr) {
+          recA(0, 0);
+          return;
+        }
+        for (int i = i0; i < (int)occ.size(); ++i) {
+          R[k] = occ[i];
+          recR(i + 1, k + 1);
+        }
+      };
+      recA = [&](int i0, int k) {
+        if (k < na) {
+          for (int i = i0; i < (int)fre.size(); ++i) {
+            A[k] = fre[i];
+            recA(i + 1, k + 1);
+          }
+          return;
+        }
+        uint64_t beta = al;
+        for (int x : R) beta &= ~(1ull << x);
+        for (int x : A) beta |= 1ull << x;
+        auto it = ip.pindex.find(beta);
+        if (it == ip.pindex.end()) return;
+        const int32_t bidx = it->second;
+        auto emit = [&](int kind, int w) {
+          int ann[3], cre[3], nan = 0, ncr = 0;
+          for (int x : A) ann[nan++] = x;
+          if (kind == PAT_SPECT) {
+            ann[nan++] = w;
+            cre[ncr++] = w;
+          }
+          for (int x : R) cre[ncr++] = x;
+          uint64_t res = 0;
+          int sg = op_sign(beta, ann, nan, cre, ncr, &res);
+          if (sg == 0 || res != al) return;
+          PatKey key{kind, na > 0 ? A[0] : -1, na > 1 ? A[1] : -1, nr > 0 ? R[0] : -1,
+                     nr > 1 ? R[1] : -1, kind == PAT_SPECT ? w : -1};
+          int id = get_pid(key);
+          cp.conn.push_back(bidx | (sg < 0 ? (int32_t)0x80000000 : 0));
+          cp.conn.push_back(id);
+        };
+        if (rank == 2) {
+          emit(PAT_DOUBLE, -1);
+        } else {
+          emit(PAT_SINGLE, -1);
+          for (int w : occ) {
+            bool inR = false;
+            for (int x : R) inR |= (x == w);
+            if (!inR) emit(PAT_SPECT, w);
+          }
+        }
+      };
+      recR(0, 0);
+    }
+    cp.conn_ptr[s + 1] = (int32_t)(cp.conn.size() / 2);
+  }
+  cp.n_conn = (int64_t)(cp.conn.size() / 2);
+}
+
+}  // namespace
+
+int64_t sigma_blocks(const InstancePlan& ip, int k) {
+  const ClassPlan& cp = ip.cls[k];
+  if (cp.strings.empty() || cp.n_rows == 0) return 0;
+  const int64_t rb = (cp.n_rows + 255) / 256;
+  int64_t nsc = std::max<int64_t>(1, std::min<int64_t>((int64_t)cp.strings.size(), (8192 + rb - 1) / rb));
+  return rb * nsc;
+}
+
+mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string* err) {
+  if (!dd || n_inst < 1 || !out) {
+    *err = "null argument or n_inst < 1";
+    return MRPT2_ERR_ARG;
+  }
+  out->inst.clear();
+  out->inst.resize(n_inst);
+  size_t pers = 0, work = 0;
+  for (int ii = 0; ii < n_inst; ++ii) {
+    const mrpt2_desc& d = dd[ii];
+    InstancePlan& ip = out->inst[ii];
+    ip.d = d;
+    if (d.n_sub < 0 || d.n_sub > MRPT2_MAX_SUB || d.n_sets < 1 || d.n_sets > MRPT2_MAX_SETS ||
+        d.n_frozen_core < 0 || d.n_core < 0 || d.n_virt < 0 || d.n_act_elec < 0 || d.max_hops < 0 ||
+        (d.q_mode != 0 && d.q_mode != 1)) {
+      *err = "descriptor field out of range";
+      return MRPT2_ERR_ARG;
+    }
+    if (d.precision != MRPT2_FP64 && d.precision != MRPT2_MIXED) {
+      *err = "unknown precision";
+      return MRPT2_ERR_UNSUPPORTED;
+    }
+    if (d.level_shift_b != 0.0) {
+      *err = "level shift not supported";
+      return MRPT2_ERR_UNSUPPORTED;
+    }
+    ip.n_fc = d.n_frozen_core;
+    ip.n_c = d.n_core;
+    ip.n_v = d.n_virt;
+    ip.n_e = d.n_act_elec;
+    ip.n_a = 0;
+    std::vector<int> ss, off;
+    int basesum = 0;
+    for (int k = 0; k < d.n_sub; ++k) {
+      if (d.sub_size[k] < 1 || d.sub_base[k] < 0 || d.sub_base[k] > d.sub_size[k]) {
+        *err = "bad subspace size or base occupation";
+        return MRPT2_ERR_SHAPE;
+      }
+      off.push_back(ip.n_a);
+      ss.push_back(d.sub_size[k]);
+      ip.n_a += d.sub_size[k];
+      basesum += d.sub_base[k];
+    }
+    if (ip.n_a > kMaxAct || ip.n_e > ip.n_a || basesum != ip.n_e) {
+      *err = "active space inconsistent (electrons, base occupations or > 64 spinors)";
+      return MRPT2_ERR_SHAPE;
+    }
+    ip.n_l = 0;
+    for (int t = 0; t < d.n_sets; ++t) {
+      if (d.rank[t] < 0 || !std::isfinite(d.weight[t])) {
+        *err = "bad factor set";
+        return MRPT2_ERR_ARG;
+      }
+      for (int l = 0; l < d.rank[t]; ++l) {
+        ip.set_sign.push_back(d.weight[t] < 0 ? -1.0 : 1.0);
+        ip.set_scale.push_back(std::sqrt(std::fabs(d.weight[t])));
+      }
+      ip.n_l += d.rank[t];
+    }
+    if (ip.n_l < 1) {
+      *err = "no Cholesky vectors";
+      return MRPT2_ERR_SHAPE;
+    }
+    ip.n_o = ip.n_c + ip.n_a;
+    ip.n_occ = ip.n_fc + ip.n_o;
+    ip.n_corr = ip.n_o + ip.n_v;
+    ip.n = ip.n_fc + ip.n_corr;
+    // primary space (Sec. 2.4)
+    std::vector<std::vector<int>> cats;
+    categories(ss, ip.n_e, &cats);
+    for (auto& m : cats) {
+      int hops = 0;
+      for (int k = 0; k < d.n_sub; ++k) hops += std::max(0, m[k] - d.sub_base[k]);
+      if (hops <= d.max_hops) ip.pcats.push_back(m);
+    }
+    for (auto& m : ip.pcats) category_strings(ss, off, m, &ip.pstrings);
+    if (ip.pstrings.empty() || ip.pstrings.size() >= (1u << 24)) {
+      *err = "reference space empty or too large";
+      return MRPT2_ERR_SHAPE;
+    }
+    for (size_t i = 0; i < ip.pstrings.size(); ++i) ip.pindex[ip.pstrings[i]] = (int32_t)i;
+    // external space by class: level = v + min over P categories of the
+    // surplus sum_k max(0, m_k - m'_k) must not exceed 2
+    int64_t n_ext = 0;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      cp.h = kClassH[k];
+      cp.v = kClassV[k];
+      const int ne = ip.n_e + cp.h - cp.v;
+      if (ne < 0 || ne > ip.n_a || cp.h > ip.n_c || cp.v > ip.n_v) continue;
+      if (cp.h == 0 && cp.v == 0 && d.q_mode == 1) continue;
+      std::vector<std::vector<int>> cc;
+      categories(ss, ne, &cc);
+      for (auto& m : cc) {
+        int best = 1 << 30;
+        bool inP = false;
+        for (auto& mp : ip.pcats) {
+          int sur = 0;
+          for (int q = 0; q < d.n_sub; ++q) sur += std::max(0, m[q] - mp[q]);
+          best = std::min(best, sur);
+          if (m == mp) inP = true;
+        }
+        if (cp.v + best > 2) continue;
+        if (cp.h == 0 && cp.v == 0 && inP) continue;
+        category_strings(ss, off, m, &cp.strings);
+      }
+      cp.n_holes = binom(ip.n_c, cp.h);
+      cp.n_ext = cp.n_holes * binom(ip.n_v, cp.v) * (int64_t)cp.strings.size();
+      n_ext += cp.n_ext;
+      if (!cp.strings.empty()) build_class(ip, cp);
+    }
+    // tiles of virtual pairs
+    ip.n_vt = (ip.n_v + kTile - 1) / kTile;
+    for (int I = 0; I < ip.n_vt; ++I)
+      for (int J = I; J < ip.n_vt; ++J) {
+        ip.tile_pairs.push_back(I);
+        ip.tile_pairs.push_back(J);
+      }
+    ip.n_tp = (int64_t)ip.tile_pairs.size() / 2;
+    for (int c = 0; c < ip.n_c; ++c)
+      for (int c2 = c + 1; c2 < ip.n_c; ++c2) {
+        ip.hole_pairs.push_back(c);
+        ip.hole_pairs.push_back(c2);
+      }
+    ip.n_pairs = (int64_t)ip.n_o * (ip.n_o - 1) / 2;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      if (cp.v == 2) cp.n_rows = cp.n_holes * ip.n_tp * kTile * kTile;
+      else if (cp.v == 1) cp.n_rows = cp.n_holes * ip.n_v;
+      else cp.n_rows = cp.n_holes;
+      if (cp.strings.empty()) cp.n_rows = 0;
+    }
+    // ---- persistent layout (plan tables) ----
+    Layout P;
+    ip.off_pstrings = P.take(ip.pstrings.size() * 8);
+    ip.off_hole_pairs = P.take(std::max<size_t>(ip.hole_pairs.size(), 2) * 4);
+    ip.off_tile_pairs = P.take(std::max<size_t>(ip.tile_pairs.size(), 2) * 4);
+    ip.off_sign = P.take(ip.n_l * 8);
+    ip.off_scale = P.take(ip.n_l * 8);
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      cp.off_strings = P.take(cp.strings.size() * 8);
+      cp.off_conn_ptr = P.take(cp.conn_ptr.size() * 4);
+      cp.off_conn = P.take(cp.conn.size() * 4);
+      cp.off_pat = P.take(cp.patterns.size() * sizeof(Pattern));
+    }
+    ip.persistent_bytes = P.cur;
+    ip.host_blob.assign(ip.persistent_bytes, 0);
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+      if (bytes) std::memcpy(ip.host_blob.data() + o, src, bytes);
+    };
+    put(ip.off_pstrings, ip.pstrings.data(), ip.pstrings.size() * 8);
+    put(ip.off_hole_pairs, ip.hole_pairs.data(), ip.hole_pairs.size() * 4);
+    put(ip.off_tile_pairs, ip.tile_pairs.data(), ip.tile_pairs.size() * 4);
+    put(ip.off_sign, ip.set_sign.data(), ip.n_l * 8);
+    put(ip.off_scale, ip.set_scale.data(), ip.n_l * 8);
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      put(cp.off_strings, cp.strings.data(), cp.strings.size() * 8);
+      put(cp.off_conn_ptr, cp.conn_ptr.data(), cp.conn_ptr.size() * 4);
+      put(cp.off_conn, cp.conn.data(), cp.conn.size() * 4);
+      put(cp.off_pat, cp.patterns.data(), cp.patterns.size() * sizeof(Pattern));
+    }
+    // ---- workspace layout ----
+    Layout W;
+    const size_t NP = ip.pstrings.size();
+    ip.off_dg = W.take((size_t)ip.n_l * ip.n * 8);
+    ip.off_slab = W.take((size_t)ip.n_occ * ip.n_corr * ip.n_l * 16);
+    ip.off_W = W.take((size_t)ip.n * ip.n * 8);
+    ip.off_eps = W.take((size_t)ip.n * 8);
+    ip.off_f = W.take((size_t)(ip.n_a + ip.n_v) * ip.n_o * 16);
+    ip.off_G = W.take((size_t)ip.n_o * (ip.n_a + ip.n_v) * ip.n_o * std::max(ip.n_a, 1) * 16);
+    ip.off_A = W.take(ip.n_v >= 2 ? (size_t)ip.n_pairs * ip.n_tp * kTile * kTile * 16 : 0);
+    ip.off_hpp = W.take(NP * NP * 16);
+    ip.off_sigp = W.take(NP * 16);
+    ip.off_scal = W.take(16 * 8);
+    ip.off_dsum = W.take((size_t)ip.n_l * 8);
+    ip.n_part = 0;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      const size_t S = cp.strings.size();
+      cp.off_T = W.take(S * 8);
+      cp.off_Uc = W.take(cp.h > 0 ? S * ip.n_c * 8 : 0);
+      cp.off_Uv = W.take(cp.v > 0 ? S * ip.n_v * 8 : 0);
+      cp.off_X = W.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
+      ip.n_part_class[k] = sigma_blocks(ip, k);
+      ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
+    }
+    ip.workspace_bytes = W.cur;
+    // info
+    mrpt2_info& inf = ip.info;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.n_orb = ip.n;
+    inf.n_corr = ip.n_corr;
+    inf.n_chol = ip.n_l;
+    inf.n_ref = (int64_t)NP;
+    inf.n_ext = n_ext;
+    double fs = 0;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const ClassPlan& cp = ip.cls[k];
+      inf.n_ext_class[k] = cp.n_ext;
+      inf.n_strings_class[k] = (int64_t)cp.strings.size();
+      inf.n_conn_class[k] = cp.n_conn;
+      // complex multiply-adds of the sigma contraction: one per coupling and
+      // external determinant (nonzero couplings only); the double core ->
+      // virtual class has no contraction (sigma = integral x coefficient)
+      if (k != 0) fs += 8.0 * (double)cp.n_conn * (double)cp.n_holes * (double)binom(ip.n_v, cp.v);
+    }
+    inf.flop_sigma = fs;
+    const double nv = ip.n_v, nl = ip.n_l;
+    inf.flop_integral = 8.0 * (double)ip.n_pairs * nv * (nv - 1) * nl +
+                        8.0 * (double)ip.n_o * (ip.n_a + ip.n_v) * ip.n_o * ip.n_a * nl;
+    inf.bytes_factors = 16.0 * nl * ip.n * ip.n;
+    ip.persistent_base = pers;
+    ip.workspace_base = work;
+    pers = align_up(pers + ip.persistent_bytes);
+    work = align_up(work + ip.workspace_bytes);
+  }
+  out->off_flag = work;
+  work = align_up(work + 256);
+  out->persistent_bytes = pers;
+  out->workspace_bytes = work;
+  out->host_blob.assign(pers, 0);
+  for (auto& ip : out->inst)
+    std::memcpy(out->host_blob.data() + ip.persistent_base, ip.host_blob.data(), ip.persistent_bytes);
+  return MRPT2_OK;
+}
+
+}  // namespace mrpt2

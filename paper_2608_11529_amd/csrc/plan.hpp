@@ -1,0 +1,95 @@
+// Host-side plan: STP-DAS string spaces, excitation lists and the device
+// memory layout of one MRPT2 energy evaluation.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mrpt2.h"
+
+namespace mrpt2 {
+
+constexpr int kTile = 64;           // virtual tile edge of the pair-integral blocks
+constexpr int kMaxAct = 64;         // active spinors fit one 64-bit string
+
+// Excitation classes, indexed as in mrpt2_info.
+constexpr int kClassH[MRPT2_N_CLASS] = {2, 1, 0, 2, 1, 0, 2, 1, 0};
+constexpr int kClassV[MRPT2_N_CLASS] = {2, 2, 2, 1, 1, 1, 0, 0, 0};
+
+// Pattern kinds: how the active part of an external string is reached from a
+// reference string, and which integral multiplies the coefficient.
+enum PatKind : int32_t {
+  PAT_DOUBLE = 0,   // rank-2: active annihilations A, creations R
+  PAT_SINGLE = 1,   // rank-1 one-body part (f^core)
+  PAT_SPECT = 2     // rank-1 two-body part with spectator w
+};
+
+// One pattern: up to two active annihilations (a0 < a1), up to two active
+// creations (r0 < r1), a spectator w.  -1 marks an unused slot.
+struct Pattern {
+  int32_t kind, a0, a1, r0, r1, w, pad0, pad1;
+};
+
+struct ClassPlan {
+  int h = 0, v = 0;
+  std::vector<uint64_t> strings;       // active strings of external dets
+  std::vector<Pattern> patterns;
+  std::vector<int32_t> conn_ptr;       // CSR over strings
+  std::vector<int32_t> conn;           // pairs (beta | sign<<31, pattern id)
+  int64_t n_holes = 0;                 // C(n_c, h)
+  int64_t n_rows = 0;                  // rows of the sigma matrix (holes x virtual tuples)
+  int64_t n_ext = 0;                   // exact determinant count
+  int64_t n_conn = 0;
+  // device offsets (bytes) within the instance's persistent region
+  size_t off_strings = 0, off_conn_ptr = 0, off_conn = 0, off_pat = 0;
+  // device offsets within the instance's workspace
+  size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0;
+};
+
+struct InstancePlan {
+  mrpt2_desc d{};
+  int n_fc = 0, n_c = 0, n_a = 0, n_v = 0, n_e = 0;
+  int n = 0, n_corr = 0, n_o = 0, n_occ = 0, n_l = 0;
+  int n_vt = 0;                       // virtual tiles
+  int64_t n_tp = 0;                   // virtual tile pairs I <= J
+  int64_t n_pairs = 0;                // occupied pairs x < y (core + active)
+  std::vector<std::vector<int>> pcats;
+  std::vector<uint64_t> pstrings;
+  std::unordered_map<uint64_t, int32_t> pindex;
+  ClassPlan cls[MRPT2_N_CLASS];
+  std::vector<int32_t> hole_pairs;    // (c, c') for c < c'
+  std::vector<int32_t> tile_pairs;    // (I, J) for I <= J
+  std::vector<double> set_sign;       // per Cholesky vector: sign of its weight
+  std::vector<double> set_scale;      // per Cholesky vector: sqrt|weight|
+  // persistent layout
+  size_t off_pstrings = 0, off_hole_pairs = 0, off_tile_pairs = 0, off_sign = 0, off_scale = 0;
+  size_t persistent_bytes = 0, persistent_base = 0;
+  // workspace layout
+  size_t off_dg = 0, off_slab = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
+  size_t off_hpp = 0, off_sigp = 0, off_scal = 0, off_dsum = 0, off_part = 0;
+  size_t workspace_bytes = 0, workspace_base = 0;
+  int64_t n_part = 0;                 // partial-sum slots
+  size_t off_part_class[MRPT2_N_CLASS]{};
+  int64_t n_part_class[MRPT2_N_CLASS]{};
+  mrpt2_info info{};
+  std::vector<char> host_blob;        // persistent region image
+};
+
+struct Plan {
+  std::vector<InstancePlan> inst;
+  size_t persistent_bytes = 0;
+  size_t workspace_bytes = 0;
+  size_t off_flag = 0;                // device error flag in the workspace
+  std::vector<char> host_blob;
+};
+
+// Builds the plan; returns MRPT2_OK or an error with a message in *err.
+mrpt2_status build_plan(const mrpt2_desc* d, int n_inst, Plan* out, std::string* err);
+
+// Number of rows per string chunk and the blocks used by the sparse-sigma
+// kernel of class k (shared by plan and launcher so the partial-sum slots
+// match the launch).
+int64_t sigma_blocks(const InstancePlan& ip, int k);
+
+}  // namespace mrpt2

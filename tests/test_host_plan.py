@@ -1,0 +1,105 @@
+"""Host-side checks of the C library (no GPU): it loads, exports every
+symbol the header declares, and its plan (reference strings, external-space
+counts per class, argument validation) agrees with the oracle's own
+enumeration."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth.problems as SP
+from oracle import counting, run
+
+from helpers import CLASSES, SMALL, problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def lib_module():
+    import paper_2608_11529_amd as M
+    return M
+
+
+def test_library_exports_header_symbols():
+    M = lib_module()
+    L = M.capi.lib()
+    with open(os.path.join(ROOT, "include", "mrpt2.h")) as f:
+        hdr = f.read()
+    names = set(re.findall(r"^\s*(?:mrpt2_status|void|const char\*)\s+(mrpt2_\w+)\s*\(", hdr, re.M))
+    assert names == set(M.capi.EXPORTED), names
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+@pytest.mark.parametrize("name", list(SMALL) + ["c0", "c1", "c2"])
+def test_plan_matches_oracle_enumeration(name):
+    M = lib_module()
+    pb = problem(name)
+    plan = M.Plan(M.desc_of_problem(pb))
+    inf = plan.info()
+    sp = run.space_of(pb)
+    cnt = counting.external_count(sp, 0)
+    for k, cl in enumerate(CLASSES):
+        assert inf.n_ext_class[k] == cnt[cl], (cl, inf.n_ext_class[k], cnt[cl])
+    assert inf.n_ext == sum(cnt.values())
+    if len(sp.p_strings()) < 20000:
+        bits = plan.ref_strings()
+        assert sorted(int(b) << pb.n_c for b in bits) == sp.p_strings()
+    for k, cl in enumerate(CLASSES):
+        assert inf.n_strings_class[k] == len(sp.class_strings(*cl, 0)) or inf.n_ext_class[k] == 0
+
+
+def test_plan_q_mode_1():
+    M = lib_module()
+    pb = problem("s_das")
+    plan = M.Plan(M.desc_of_problem(pb, q_mode=1))
+    cnt = counting.external_count(run.space_of(pb), 1)
+    assert plan.info().n_ext == sum(cnt.values())
+    assert plan.info().n_ext_class[8] == 0
+
+
+def test_reference_order_is_category_blocked():
+    """STP-DAS addressing (Sec. 2.4): reference strings are grouped by
+    category, each category a tensor product of per-subspace strings."""
+    M = lib_module()
+    pb = SP.config("c1")
+    bits = M.Plan(M.desc_of_problem(pb)).ref_strings()
+    sp = run.space_of(pb)
+    cats = [sp.category(int(b) << pb.n_c) for b in bits]
+    seen = []
+    for c in cats:
+        if not seen or seen[-1] != c:
+            assert c not in seen, "category appears in two blocks"
+            seen.append(c)
+    assert set(seen) == set(sp.p_categories())
+
+
+def test_table3_counts_through_the_plan():
+    """The plan's class rule reproduces the paper's printed nDets for Ne
+    (Table 3): 4 core, CAS(6e,8o), 108 virtual spinors."""
+    M = lib_module()
+    d = M.make_desc(0, 4, 108, [8], [6], 6, 6, [(1, 1.0)])
+    assert M.Plan(d).info().n_ext == 2692802
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n_sub", 17, 1), ("n_sets", 0, 1), ("q_mode", 2, 1), ("precision", 7, 3),
+    ("level_shift_b", 0.05, 3), ("n_act_elec", 9, 2),
+])
+def test_plan_rejects_bad_descriptors(field, value, code):
+    M = lib_module()
+    d = M.desc_of_problem(problem("s_cas"))
+    setattr(d, field, value)
+    with pytest.raises(M.Mrpt2Error) as ei:
+        M.Plan(d)
+    assert ei.value.code == code
+
+
+def test_null_arguments_return_status():
+    M = lib_module()
+    L = M.capi.lib()
+    assert L.mrpt2_plan(None, 1, ctypes.byref(ctypes.c_void_p())) == 1
+    assert L.mrpt2_plan_sizes(None, None, None) == 1
+    assert L.mrpt2_energy(None, None, None, None, 0, None, None, None) == 1
+    assert L.mrpt2_status_string(6) == b"non-finite input or zero denominator"
