@@ -150,6 +150,17 @@ mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in,
                           const void* persistent, void* workspace, size_t workspace_bytes,
                           hipStream_t stream, double* e2, double* parts);
 
+/* mrpt2_energy with its stages timed by HIP events recorded on `stream`.
+ * stage_ms (host float[23], milliseconds summed over instances):
+ * [0] factor tables (slabs, pair energies, orbital energies, core Fock),
+ * [1] occupied-integral build, [2] reference energy, [3] virtual-pair
+ * integral build, [4 + k] sigma contraction and epilogue of class k,
+ * [13 + k] denominator tables and couplings of class k, [22] reduction.
+ * Same errors as mrpt2_energy; MRPT2_ERR_ARG if stage_ms is NULL. */
+mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in,
+                                const void* persistent, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream, double* e2, double* parts, float* stage_ms);
+
 /* Dense reference-space Hamiltonian minus the core energy,
  * H_PP - E_core * 1, for instance inst (complex [N_P][N_P], device, written)
  * - the matrix whose lowest eigenvector is the reference state.  Uses the

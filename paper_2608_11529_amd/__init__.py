@@ -134,6 +134,17 @@ class Engine:
         del keep
         return (self.e2, self.parts) if parts else self.e2
 
+    def energy_timed(self, insts):
+        """energy() with per-stage milliseconds (dict over capi.STAGES)."""
+        arr, keep = self._inputs(insts)
+        ms = (ctypes.c_float * capi.N_STAGE)()
+        code = capi.lib().mrpt2_energy_timed(self.plan.handle, arr, self.persistent.data_ptr(),
+                                             self.workspace.data_ptr(), self.plan.workspace_bytes, self._sptr(),
+                                             self.e2.data_ptr(), self.parts.data_ptr(), ms)
+        capi.check(code, "mrpt2_energy_timed")
+        del keep
+        return self.e2, self.parts, dict(zip(capi.STAGES, list(ms)))
+
     def reference_hamiltonian(self, h, Bs, inst=0):
         torch = self.torch
         n_p = self.plan.info(inst).n_ref

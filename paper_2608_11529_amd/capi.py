@@ -14,6 +14,9 @@ MAX_SUB = 16
 MAX_SETS = 4
 N_CLASS = 9
 CLASSES = [(2, 2), (1, 2), (0, 2), (2, 1), (1, 1), (0, 1), (2, 0), (1, 0), (0, 0)]
+N_STAGE = 23
+STAGES = (["factor_tables", "occupied_integrals", "reference_energy", "pair_integrals"]
+          + ["sigma_%d%d" % c for c in CLASSES] + ["prep_%d%d" % c for c in CLASSES] + ["reduce"])
 
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "inconsistent or unsupported sizes",
@@ -94,6 +97,9 @@ def lib():
         L.mrpt2_plan_ref_strings.restype = st
         L.mrpt2_energy.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp]
         L.mrpt2_energy.restype = st
+        L.mrpt2_energy_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp,
+                                         ctypes.POINTER(ctypes.c_float)]
+        L.mrpt2_energy_timed.restype = st
         L.mrpt2_reference_hamiltonian.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Inputs), vp, vp,
                                                   ctypes.c_size_t, vp, vp]
         L.mrpt2_reference_hamiltonian.restype = st
@@ -112,6 +118,6 @@ def check(code, where):
 
 EXPORTED = [
     "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
-    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_reference_hamiltonian",
+    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string",
 ]

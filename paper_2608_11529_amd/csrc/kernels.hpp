@@ -78,6 +78,8 @@ struct ClassDev {
   double2* X;    // [n_pat][n_rows] (v < 2)
   double* part;  // partial sums
   int nsc;       // string chunks
+  double2* D;    // [S][n_pat] dense coefficients (classes with few patterns)
+  uint32_t* mask;  // [S] nonzero patterns per string
 };
 
 struct PartList {

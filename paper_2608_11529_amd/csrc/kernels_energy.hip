@@ -321,6 +321,270 @@ template __global__ void k_sigma<2, 0>(Dev, ClassDev, int*);
 template __global__ void k_sigma<1, 0>(Dev, ClassDev, int*);
 template __global__ void k_sigma<0, 0>(Dev, ClassDev, int*);
 
+// Class (2,2): K = core - {c, c'} + alpha + {a, b}, alpha in P.  Its only
+// connected reference determinant is core + alpha, so
+//   sigma_K = <ab||cc'> C_alpha  and  |sigma_K|^2 = |<ab||cc'>|^2 |C_alpha|^2,
+// and the class is a sum over (c<c', a<b) of |<ab||cc'>|^2 times
+// S_ab = sum_alpha |C_alpha|^2 / Delta(a, b, alpha), with
+//   Delta = G(alpha) + Y_a(alpha) + Y_b(alpha) - W_ab,
+//   G = T(alpha) + eps_c + Uc_c(alpha) + eps_c' + Uc_c'(alpha) - W_cc',
+//   Y_a = -eps_a - Uv_a(alpha) + W_ca + W_c'a.
+// Pure FP64 vector work: each thread owns a 4 x 4 block of (a, b) of a
+// 64 x 64 tile and walks alpha four at a time, merging the four fractions
+// c1/d1 + ... + c4/d4 into one numerator and denominator so that a single
+// reciprocal serves four determinants.
+// grid (n_tp, C(n_c, 2)), block 256.
+constexpr int AC22 = 32;
+
+__global__ void __launch_bounds__(256) k_e22(Dev d, ClassDev cd, int* flag) {
+  __shared__ double sYa[AC22][64];
+  __shared__ double sYb[AC22][64];
+  __shared__ double sG[AC22];
+  __shared__ double sCw[AC22];
+  __shared__ double ya0[64], yb0[64];
+  __shared__ double red[256];
+  const int tp = blockIdx.x, hp = blockIdx.y;
+  const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
+  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+  const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
+  const int nv = d.n_v, nc = d.n_c;
+  const int64_t gfc = d.n_fc, gv = d.n_fc + d.n_o;
+  const double* __restrict__ W = d.W;
+  if (tid < 64) {
+    const int a = I * 64 + tid;
+    ya0[tid] = (a < nv) ? -d.eps[d.n_o + a] + W[(gfc + c0) * d.n + gv + a] + W[(gfc + c1) * d.n + gv + a] : -1.0;
+  } else if (tid < 128) {
+    const int b = J * 64 + tid - 64;
+    yb0[tid - 64] = (b < nv) ? -d.eps[d.n_o + b] + W[(gfc + c0) * d.n + gv + b] + W[(gfc + c1) * d.n + gv + b] : -1.0;
+  }
+  const double gconst = d.eps[c0] + d.eps[c1] - W[(gfc + c0) * d.n + gfc + c1];
+  double wab[4][4], acc[4][4];
+  bool ok[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
+      ok[i][j] = (a < b) && (b < nv);
+      wab[i][j] = ok[i][j] ? W[(gv + a) * d.n + gv + b] : 0.0;
+      acc[i][j] = 0.0;
+    }
+  const int np = d.n_p;
+  const double* __restrict__ Uv = cd.Uv;
+  const double* __restrict__ Uc = cd.Uc;
+  for (int a0 = 0; a0 < np; a0 += AC22) {
+    __syncthreads();
+    for (int e = tid; e < AC22 * 64; e += 256) {
+      const int al = e >> 6, l = e & 63;
+      const int s = a0 + al;
+      const int a = I * 64 + l, b = J * 64 + l;
+      double ya = ya0[l], yb = yb0[l];
+      if (s < np) {
+        if (a < nv) ya -= Uv[(int64_t)s * nv + a];
+        if (b < nv) yb -= Uv[(int64_t)s * nv + b];
+      }
+      sYa[al][l] = ya;
+      sYb[al][l] = yb;
+    }
+    if (tid < AC22) {
+      const int s = a0 + tid;
+      if (s < np) {
+        sG[tid] = cd.T[s] + Uc[(int64_t)s * nc + c0] + Uc[(int64_t)s * nc + c1] + gconst;
+        sCw[tid] = cabs2(d.c[s]);
+      } else {
+        sG[tid] = 1e30;   // padding: vanishing weight, harmless denominator
+        sCw[tid] = 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int al = 0; al < AC22; al += 4) {
+      double g[4], cw[4], za[4][4], yb[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        g[k] = sG[al + k];
+        cw[k] = sCw[al + k];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) za[i][k] = g[k] + sYa[al + k][ta + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double d0 = (za[i][0] + yb[j][0]) - wab[i][j];
+          const double d1 = (za[i][1] + yb[j][1]) - wab[i][j];
+          const double d2 = (za[i][2] + yb[j][2]) - wab[i][j];
+          const double d3 = (za[i][3] + yb[j][3]) - wab[i][j];
+          const double n01 = fma(cw[0], d1, cw[1] * d0);
+          const double q01 = d0 * d1;
+          const double n23 = fma(cw[2], d3, cw[3] * d2);
+          const double q23 = d2 * d3;
+          const double num = fma(n01, q23, n23 * q01);
+          const double den = q01 * q23;
+          acc[i][j] = fma(num, rcp_nr(den), acc[i][j]);
+        }
+    }
+  }
+  // weights |<ab||cc'>|^2 from the pair-integral tile
+  const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+  double sum = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (ok[i][j]) {
+        const double t = cabs2(Ablk[(ta + 16 * i) * 64 + tb + 16 * j]) * acc[i][j];
+        if (!isfinite(t)) bad = true;
+        sum += t;
+      }
+    }
+  if (bad) *flag = 2;
+  red[tid] = sum;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) cd.part[(int64_t)hp * d.n_tp + tp] = red[0];
+}
+
+// Dense coefficients of a class with few patterns: D[s][j] = sum of sign C_beta
+// over the excitation list of string s with pattern j, and the bit mask of the
+// patterns present.  grid (ceil(S / 256)).
+__global__ void __launch_bounds__(256) k_dense_coef(Dev d, ClassDev cd) {
+  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+  if (s >= cd.n_str) return;
+  const int J = cd.n_pat;
+  double2* row = cd.D + s * J;
+  for (int j = 0; j < J; ++j) row[j] = make_double2(0.0, 0.0);
+  uint32_t m = 0;
+  for (int e = cd.conn_ptr[s]; e < cd.conn_ptr[s + 1]; ++e) {
+    const int32_t cb = cd.conn[2 * e];
+    const int j = cd.conn[2 * e + 1];
+    double2 cv = d.c[cb & 0x7fffffff];
+    if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+    row[j] = cadd(row[j], cv);
+    m |= 1u << j;
+  }
+  cd.mask[s] = m;
+}
+
+// Class (1,2): K = core - {c} + alpha' + {a, b}, reached from
+// L = core + alpha' + {t} by a_c a_t -> a+_b a+_a:
+//   sigma_K = sum_t <ab||ct> D[alpha'][t],
+//   Delta   = T + eps_c + Uc_c - eps_a - Uv_a - eps_b - Uv_b - W_ab + W_ca + W_cb.
+// One thread per (a, b) of a 16 x 16 sub-tile of a 64 x 64 virtual tile pair,
+// the couplings <ab||ct> of its row in registers; strings are walked in
+// chunks staged in LDS, patterns present in a string selected by a
+// wave-uniform mask, and four fractions |sigma|^2 / Delta merged per
+// reciprocal.  grid (16 n_tp, n_c), block 256.
+constexpr int SC12 = 32;
+
+template <int MJ>
+__global__ void __launch_bounds__(256) k_e12(Dev d, ClassDev cd, int* flag) {
+  __shared__ double sUa[SC12][16];
+  __shared__ double sUb[SC12][16];
+  __shared__ double sG[SC12];
+  __shared__ double2 sD[SC12][MJ];
+  __shared__ uint32_t sM[SC12];
+  __shared__ double red[256];
+  const int tp = blockIdx.x >> 4, sub = blockIdx.x & 15;
+  const int sa = sub >> 2, sb = sub & 3;
+  const int c = blockIdx.y;
+  const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+  if (I == Jt && sa > sb) {                    // block entirely below the diagonal
+    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + blockIdx.x] = 0.0;
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int la = sa * 16 + (tid >> 4), lb = sb * 16 + (tid & 15);
+  const int nv = d.n_v, nc = d.n_c;
+  int a = I * 64 + la, b = Jt * 64 + lb;
+  const bool valid = (a < b) && (b < nv);
+  if (!valid) {
+    a = 0;
+    b = nv > 1 ? 1 : 0;
+  }
+  const int J = cd.n_pat;
+  const int64_t gfc = d.n_fc, gv = d.n_fc + d.n_o;
+  const double* __restrict__ W = d.W;
+  const double rowc = -d.eps[d.n_o + a] - d.eps[d.n_o + b] - W[(gv + a) * d.n + gv + b] +
+                      W[(gfc + c) * d.n + gv + a] + W[(gfc + c) * d.n + gv + b];
+  double2 X[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j) {
+    X[j] = make_double2(0.0, 0.0);
+    if (j < J) {
+      const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
+      X[j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
+    }
+  }
+  const double epsc = d.eps[c];
+  const int64_t S = cd.n_str;
+  double acc = 0.0;
+  for (int64_t s0 = 0; s0 < S; s0 += SC12) {
+    __syncthreads();
+    for (int e = tid; e < SC12 * 16; e += 256) {
+      const int sl = e >> 4, l = e & 15;
+      const int64_t s = s0 + sl;
+      const int aa = I * 64 + sa * 16 + l, bb = Jt * 64 + sb * 16 + l;
+      sUa[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
+      sUb[sl][l] = (s < S && bb < nv) ? cd.Uv[s * nv + bb] : 0.0;
+    }
+    for (int e = tid; e < SC12 * MJ; e += 256) {
+      const int sl = e / MJ, j = e % MJ;
+      const int64_t s = s0 + sl;
+      sD[sl][j] = (s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
+    }
+    if (tid < SC12) {
+      const int64_t s = s0 + tid;
+      sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : 1e30;
+      sM[tid] = (s < S) ? cd.mask[s] : 0u;
+    }
+    __syncthreads();
+    const int ia = la - sa * 16, ib = lb - sb * 16;
+#pragma unroll 1
+    for (int sl = 0; sl < SC12; sl += 4) {
+      double w[4], dd[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t m = sM[sl + k];
+        double2 sg = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+          if (m & (1u << j)) sg = cfma(sD[sl + k][j], X[j], sg);
+        w[k] = cabs2(sg);
+        dd[k] = (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib];
+      }
+      const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
+      const double q01 = dd[0] * dd[1];
+      const double n23 = fma(w[2], dd[3], w[3] * dd[2]);
+      const double q23 = dd[2] * dd[3];
+      acc = fma(fma(n01, q23, n23 * q01), rcp_nr(q01 * q23), acc);
+    }
+  }
+  if (valid && !isfinite(acc)) *flag = 2;
+  red[tid] = valid ? acc : 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + blockIdx.x] = red[0];
+}
+
+template __global__ void k_e12<8>(Dev, ClassDev, int*);
+template __global__ void k_e12<16>(Dev, ClassDev, int*);
+template __global__ void k_e12<24>(Dev, ClassDev, int*);
+template __global__ void k_e12<32>(Dev, ClassDev, int*);
+
 // Per-class sum of partials (Neumaier-compensated, fixed order) divided by
 // ||C||^2; out[k] for k < 9, out[9] = E2, out[10] = E0 - E_core,
 // out[11] = ||C||^2; e2 receives E2.  One block.

@@ -85,6 +85,8 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.Uc = (double*)(W + cp.off_Uc);
   c.Uv = (double*)(W + cp.off_Uv);
   c.X = (double2*)(W + cp.off_X);
+  c.D = (double2*)(W + cp.off_D);
+  c.mask = (uint32_t*)(W + cp.off_mask);
   c.part = (double*)(W + ip.off_part_class[k]);
   const int64_t rb = cdiv(cp.n_rows, 256);
   c.nsc = rb > 0 ? (int)(sigma_blocks(ip, k) / rb) : 1;
@@ -93,7 +95,36 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
 
 // Steps shared by the energy and the reference Hamiltonian: factor slabs,
 // pair energies, orbital energies, core Fock matrix, occupied integrals.
-mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipStream_t st, int* flag) {
+// Timing slots of mrpt2_energy_timed (milliseconds, summed over instances).
+enum {
+  ST_TABLES = 0, ST_GBUILD = 1, ST_REF = 2, ST_ABUILD = 3, ST_SIGMA0 = 4,       // 4..12 sigma per class
+  ST_PREP0 = 13,                                                               // 13..21 class tables + couplings
+  ST_FINISH = 22, ST_N = 23
+};
+
+struct Timer {
+  hipEvent_t ev[2 * ST_N * 8];
+  int slot[ST_N * 8];
+  int n = 0;
+  bool on = false;
+  hipStream_t st;
+  int open_slot = -1;
+  void begin(int s) {
+    if (!on || n >= ST_N * 8) return;
+    slot[n] = s;
+    hipEventRecord(ev[2 * n], st);
+    open_slot = n;
+  }
+  void end() {
+    if (!on || open_slot < 0) return;
+    hipEventRecord(ev[2 * open_slot + 1], st);
+    ++n;
+    open_slot = -1;
+  }
+};
+
+mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipStream_t st, int* flag,
+                    Timer* tm) {
   SetPtrs sp{};
   sp.n_sets = ip.d.n_sets;
   int l0 = 0;
@@ -115,10 +146,13 @@ mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipS
   hipLaunchKernelGGL(k_dsum, dim3(cdiv(ip.n_l, 256)), dim3(256), 0, st, d);
   if (ip.n_o > 0 && ip.n_a + ip.n_v > 0)
     hipLaunchKernelGGL(k_fock, dim3(ip.n_o, ip.n_a + ip.n_v), dim3(64), 0, st, d, (const double2*)in->h);
+  tm->end();
+  tm->begin(ST_GBUILD);
   if (ip.n_a > 0) {
     const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
     hipLaunchKernelGGL(k_gbuild, dim3(cdiv(N, 64), cdiv(M, 64)), dim3(256), 0, st, d);
   }
+  tm->end();
   HIPCHK(hipGetLastError());
   return MRPT2_OK;
 }
@@ -128,6 +162,96 @@ mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t w
   if (wbytes < p.workspace_bytes) return MRPT2_ERR_WORKSPACE;
   if (((uintptr_t)pers & 255) || ((uintptr_t)work & 255)) return MRPT2_ERR_ARG;
   return MRPT2_OK;
+}
+
+mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
+                        size_t workspace_bytes, hipStream_t st, double* e2, double* parts, Timer& tm) {
+  if (!plan || !in || !e2) return MRPT2_ERR_ARG;
+  const Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  const char* pers = (const char*)persistent;
+  char* work = (char*)workspace;
+  int* flag = (int*)(work + P.off_flag);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
+  for (size_t ii = 0; ii < P.inst.size(); ++ii) {
+    const InstancePlan& ip = P.inst[ii];
+    const mrpt2_inputs* ini = in + ii;
+    if (!ini->h || !ini->c) return MRPT2_ERR_ARG;
+    Dev d = make_dev(ip, pers, work, ini);
+    tm.begin(ST_TABLES);
+    s = tables(ip, ini, d, st, flag, &tm);
+    if (s != MRPT2_OK) return s;
+    const int np = (int)ip.pstrings.size();
+    tm.begin(ST_REF);
+    hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, d.hpp);
+    hipLaunchKernelGGL(k_sigp, dim3(np), dim3(64), 0, st, d, (const double2*)d.hpp);
+    hipLaunchKernelGGL(k_e0, dim3(1), dim3(256), 0, st, d, flag);
+    tm.end();
+    if (ip.n_v >= 2 && ip.n_pairs > 0) {
+      tm.begin(ST_ABUILD);
+      hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
+      tm.end();
+    }
+    PartList pl{};
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const ClassPlan& cp = ip.cls[k];
+      ClassDev cd = make_class(ip, k, pers, work);
+      pl.p[k] = cd.part;
+      pl.n[k] = 0;
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      const int mx = std::max(ip.n_c, ip.n_v);
+      tm.begin(ST_PREP0 + k);
+      hipLaunchKernelGGL(k_class_tables, dim3(cd.n_str, cdiv(std::max(mx, 1), 256)), dim3(256), 0, st, d, cd);
+      if (cp.v < 2 && cd.n_pat > 0)
+        hipLaunchKernelGGL(k_xbuild, dim3(cdiv(cp.n_rows, 256), cd.n_pat), dim3(256), 0, st, d, cd);
+      tm.end();
+      const int64_t nb = sigma_blocks(ip, k);
+      pl.n[k] = nb;
+      dim3 g(nb), b(256);
+      tm.begin(ST_SIGMA0 + k);
+      if (k == 0) {
+        // dedicated vector kernel: one block per (virtual tile pair, core pair)
+        pl.n[k] = ip.n_tp * cp.n_holes;
+        hipLaunchKernelGGL(k_e22, dim3(ip.n_tp, cp.n_holes), dim3(256), 0, st, d, cd, flag);
+        tm.end();
+        continue;
+      }
+      if (k == 1 && cp.dense_coef) {
+        // one core hole, two virtual electrons: coefficients densified per
+        // string, couplings held in registers; one block per (tile pair, core)
+        hipLaunchKernelGGL(k_dense_coef, dim3(cdiv(cd.n_str, 256)), dim3(256), 0, st, d, cd);
+        pl.n[k] = ip.n_tp * 16 * cp.n_holes;
+        const dim3 g12(ip.n_tp * 16, cp.n_holes);
+        if (cd.n_pat <= 8) hipLaunchKernelGGL((k_e12<8>), g12, dim3(256), 0, st, d, cd, flag);
+        else if (cd.n_pat <= 16) hipLaunchKernelGGL((k_e12<16>), g12, dim3(256), 0, st, d, cd, flag);
+        else if (cd.n_pat <= 24) hipLaunchKernelGGL((k_e12<24>), g12, dim3(256), 0, st, d, cd, flag);
+        else hipLaunchKernelGGL((k_e12<32>), g12, dim3(256), 0, st, d, cd, flag);
+        tm.end();
+        continue;
+      }
+      switch (k) {
+        case 0: hipLaunchKernelGGL((k_sigma<2, 2>), g, b, 0, st, d, cd, flag); break;
+        case 1: hipLaunchKernelGGL((k_sigma<1, 2>), g, b, 0, st, d, cd, flag); break;
+        case 2: hipLaunchKernelGGL((k_sigma<0, 2>), g, b, 0, st, d, cd, flag); break;
+        case 3: hipLaunchKernelGGL((k_sigma<2, 1>), g, b, 0, st, d, cd, flag); break;
+        case 4: hipLaunchKernelGGL((k_sigma<1, 1>), g, b, 0, st, d, cd, flag); break;
+        case 5: hipLaunchKernelGGL((k_sigma<0, 1>), g, b, 0, st, d, cd, flag); break;
+        case 6: hipLaunchKernelGGL((k_sigma<2, 0>), g, b, 0, st, d, cd, flag); break;
+        case 7: hipLaunchKernelGGL((k_sigma<1, 0>), g, b, 0, st, d, cd, flag); break;
+        default: hipLaunchKernelGGL((k_sigma<0, 0>), g, b, 0, st, d, cd, flag); break;
+      }
+      tm.end();
+    }
+    tm.begin(ST_FINISH);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, pl, parts ? parts + 12 * ii : nullptr, e2 + ii);
+    tm.end();
+    HIPCHK(hipGetLastError());
+  }
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
 }
 
 }  // namespace
@@ -184,60 +308,31 @@ mrpt2_status mrpt2_plan_ref_strings(mrpt2_plan_t plan, int32_t inst, uint64_t* b
 
 mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
                           size_t workspace_bytes, hipStream_t st, double* e2, double* parts) {
-  if (!plan || !in || !e2) return MRPT2_ERR_ARG;
-  const Plan& P = plan->p;
-  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
-  if (s != MRPT2_OK) return s;
-  const char* pers = (const char*)persistent;
-  char* work = (char*)workspace;
-  int* flag = (int*)(work + P.off_flag);
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
-  for (size_t ii = 0; ii < P.inst.size(); ++ii) {
-    const InstancePlan& ip = P.inst[ii];
-    const mrpt2_inputs* ini = in + ii;
-    if (!ini->h || !ini->c) return MRPT2_ERR_ARG;
-    Dev d = make_dev(ip, pers, work, ini);
-    s = tables(ip, ini, d, st, flag);
-    if (s != MRPT2_OK) return s;
-    const int np = (int)ip.pstrings.size();
-    hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, d.hpp);
-    hipLaunchKernelGGL(k_sigp, dim3(np), dim3(64), 0, st, d, (const double2*)d.hpp);
-    hipLaunchKernelGGL(k_e0, dim3(1), dim3(256), 0, st, d, flag);
-    if (ip.n_v >= 2 && ip.n_pairs > 0)
-      hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
-    PartList pl{};
-    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-      const ClassPlan& cp = ip.cls[k];
-      ClassDev cd = make_class(ip, k, pers, work);
-      pl.p[k] = cd.part;
-      pl.n[k] = 0;
-      if (cp.strings.empty() || cp.n_rows == 0) continue;
-      const int mx = std::max(ip.n_c, ip.n_v);
-      hipLaunchKernelGGL(k_class_tables, dim3(cd.n_str, cdiv(std::max(mx, 1), 256)), dim3(256), 0, st, d, cd);
-      if (cp.v < 2)
-        hipLaunchKernelGGL(k_xbuild, dim3(cdiv(cp.n_rows, 256), cd.n_pat), dim3(256), 0, st, d, cd);
-      const int64_t nb = sigma_blocks(ip, k);
-      pl.n[k] = nb;
-      dim3 g(nb), b(256);
-      switch (k) {
-        case 0: hipLaunchKernelGGL((k_sigma<2, 2>), g, b, 0, st, d, cd, flag); break;
-        case 1: hipLaunchKernelGGL((k_sigma<1, 2>), g, b, 0, st, d, cd, flag); break;
-        case 2: hipLaunchKernelGGL((k_sigma<0, 2>), g, b, 0, st, d, cd, flag); break;
-        case 3: hipLaunchKernelGGL((k_sigma<2, 1>), g, b, 0, st, d, cd, flag); break;
-        case 4: hipLaunchKernelGGL((k_sigma<1, 1>), g, b, 0, st, d, cd, flag); break;
-        case 5: hipLaunchKernelGGL((k_sigma<0, 1>), g, b, 0, st, d, cd, flag); break;
-        case 6: hipLaunchKernelGGL((k_sigma<2, 0>), g, b, 0, st, d, cd, flag); break;
-        case 7: hipLaunchKernelGGL((k_sigma<1, 0>), g, b, 0, st, d, cd, flag); break;
-        default: hipLaunchKernelGGL((k_sigma<0, 0>), g, b, 0, st, d, cd, flag); break;
-      }
+  Timer tm;
+  tm.on = false;
+  return run_energy(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+}
+
+mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                void* workspace, size_t workspace_bytes, hipStream_t st, double* e2,
+                                double* parts, float* stage_ms) {
+  if (!stage_ms) return MRPT2_ERR_ARG;
+  Timer tm;
+  tm.on = true;
+  tm.st = st;
+  const int nev = 2 * ST_N * 8;
+  for (int i = 0; i < nev; ++i)
+    if (hipEventCreate(&tm.ev[i]) != hipSuccess) return MRPT2_ERR_HIP;
+  mrpt2_status s = run_energy(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+  for (int i = 0; i < ST_N; ++i) stage_ms[i] = 0.0f;
+  if (s == MRPT2_OK || s == MRPT2_ERR_NUMERIC) {
+    for (int i = 0; i < tm.n; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]) == hipSuccess) stage_ms[tm.slot[i]] += ms;
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, pl, parts ? parts + 12 * ii : nullptr, e2 + ii);
-    HIPCHK(hipGetLastError());
   }
-  int hflag = 0;
-  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+  for (int i = 0; i < nev; ++i) hipEventDestroy(tm.ev[i]);
+  return s;
 }
 
 mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
@@ -253,7 +348,8 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
   if (!in->h) return MRPT2_ERR_ARG;
   Dev d = make_dev(ip, (const char*)persistent, work, in);
   hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
-  s = tables(ip, in, d, st, flag);
+  Timer tm;
+  s = tables(ip, in, d, st, flag, &tm);
   if (s != MRPT2_OK) return s;
   const int np = (int)ip.pstrings.size();
   hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, (double2*)hpp);

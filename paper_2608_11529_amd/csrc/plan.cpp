@@ -345,6 +345,11 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       n_ext += cp.n_ext;
       if (!cp.strings.empty()) build_class(ip, cp);
     }
+    // the (2,2) class walks the reference strings themselves
+    if (!ip.cls[0].strings.empty() && ip.cls[0].strings != ip.pstrings) {
+      *err = "internal: (2,2) strings differ from the reference strings";
+      return MRPT2_ERR_SHAPE;
+    }
     // tiles of virtual pairs
     ip.n_vt = (ip.n_v + kTile - 1) / kTile;
     for (int I = 0; I < ip.n_vt; ++I)
@@ -419,6 +424,9 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.off_Uc = W.take(cp.h > 0 ? S * ip.n_c * 8 : 0);
       cp.off_Uv = W.take(cp.v > 0 ? S * ip.n_v * 8 : 0);
       cp.off_X = W.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
+      cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
+      cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
+      cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
       ip.n_part_class[k] = sigma_blocks(ip, k);
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
     }

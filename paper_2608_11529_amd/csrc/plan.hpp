@@ -12,6 +12,7 @@ namespace mrpt2 {
 
 constexpr int kTile = 64;           // virtual tile edge of the pair-integral blocks
 constexpr int kMaxAct = 64;         // active spinors fit one 64-bit string
+constexpr int kMaxDenseJ = 32;      // patterns held in registers by the dense-coefficient kernels
 
 // Excitation classes, indexed as in mrpt2_info.
 constexpr int kClassH[MRPT2_N_CLASS] = {2, 1, 0, 2, 1, 0, 2, 1, 0};
@@ -44,7 +45,8 @@ struct ClassPlan {
   // device offsets (bytes) within the instance's persistent region
   size_t off_strings = 0, off_conn_ptr = 0, off_conn = 0, off_pat = 0;
   // device offsets within the instance's workspace
-  size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0;
+  size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
+  bool dense_coef = false;             // coefficients as a dense [S][n_pat] table + masks
 };
 
 struct InstancePlan {

@@ -196,6 +196,27 @@ def factor_slice(pb: Problem, t: int, l0: int, l1: int, device="cpu") -> torch.T
     return out
 
 
+def factor_rows(pb: Problem, t: int, l0: int, l1: int, idx, device="cpu") -> torch.Tensor:
+    """B[t][L][idx][:, idx] for L in [l0, l1): the same entries as
+    factor_slice, generated only on the spinor subset idx (global indices)."""
+    g = torch.as_tensor(list(idx), dtype=torch.int64, device=device)
+    lo = torch.minimum(g[:, None], g[None, :])
+    hi = torch.maximum(g[:, None], g[None, :])
+    pidx = lo * STRIDE + hi
+    upper = (g[:, None] < g[None, :])
+    diag = (g[:, None] == g[None, :])
+    decay = torch.exp(-(g[:, None] - g[None, :]).abs().to(torch.float64) / 8.0)
+    m = len(idx)
+    out = torch.empty((l1 - l0, m, m), dtype=torch.complex128, device=device)
+    s_off = 0.1 / math.sqrt(2.0)
+    for L in range(l0, l1):
+        z0, z1 = rng.normal_pair(rng.stream_key(pb.seed, 100 + t, L), pidx)
+        re = torch.where(diag, 0.1 * z0, s_off * z0) * decay
+        im = torch.where(diag, torch.zeros_like(z1), torch.where(upper, s_off * z1, -s_off * z1)) * decay
+        out[L - l0] = torch.complex(re, im)
+    return out
+
+
 def factors(pb: Problem, device="cpu"):
     """All factor sets: list of complex128 [rank_t, n, n]."""
     return [factor_slice(pb, t, 0, r, device) for t, (r, _) in enumerate(pb.sets)]

@@ -66,5 +66,80 @@ def test_reference_energy_relative_to_core():
     assert abs(parts[10] - (E0_o - ecore)) < 1e-10
 
 
+def golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "%s_oracle.json" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_c1_matches_oracle_golden():
+    """Config c1 in full (1.25e9 external determinants, DAS with one hop,
+    Dirac-Coulomb + Gaunt) against the oracle's stored per-class values."""
+    import torch
+    import paper_2608_11529_amd as M
+    g = golden("c1")
+    pb = SP.config("c1")
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine(plan)
+    c_o = np.array(g["c_re"]) + 1j * np.array(g["c_im"])
+    c = to_plan_order(c_o, g["p_strings"], plan.ref_strings(), pb.n_c)
+    dev = eng.device
+    h, Bs = SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)]
+    print("[gpu] c1", flush=True)
+    e2, parts = eng.energy([(h, Bs, torch.from_numpy(np.ascontiguousarray(c)).to(dev))])
+    parts = parts[0].cpu().numpy()
+    for k, cl in enumerate(CLASSES):
+        ref = g["parts"]["%d%d" % cl]
+        assert abs(parts[k] - ref) <= TOL, (cl, parts[k], ref)
+    assert abs(float(e2[0]) - g["E2"]) <= TOL
+
+
+def test_bitwise_repeatable():
+    """Fixed-order reductions: two evaluations agree bit for bit."""
+    import torch
+    import paper_2608_11529_amd as M
+    pb = problem("s_tiles")
+    parts_o, E0_o, c_o, P_o = oracle_reference("s_tiles")
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine(plan)
+    dev = eng.device
+    c = torch.from_numpy(np.ascontiguousarray(to_plan_order(c_o, P_o, plan.ref_strings(), pb.n_c))).to(dev)
+    h, Bs = SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)]
+    a = eng.energy([(h, Bs, c)])[1].clone()
+    b = eng.energy([(h, Bs, c)])[1].clone()
+    assert torch.equal(a, b)
+
+
+def test_nonfinite_input_is_reported():
+    import torch
+    import paper_2608_11529_amd as M
+    pb = problem("s_cas")
+    parts_o, E0_o, c_o, P_o = oracle_reference("s_cas")
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine(plan)
+    dev = eng.device
+    c = torch.from_numpy(np.ascontiguousarray(to_plan_order(c_o, P_o, plan.ref_strings(), pb.n_c))).to(dev)
+    h, Bs = SP.one_body(pb).to(dev), [B.to(dev).clone() for B in SP.factors(pb)]
+    Bs[0][3, 2, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(M.Mrpt2Error) as ei:
+        eng.energy([(h, Bs, c)])
+    assert ei.value.code == 6
+
+
+def test_workspace_too_small_is_reported():
+    import ctypes
+    import paper_2608_11529_amd as M
+    pb = problem("s_cas")
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine(plan)
+    L = M.capi.lib()
+    arr = (M.capi.Inputs * 1)()
+    code = L.mrpt2_energy(plan.handle, arr, eng.persistent.data_ptr(), eng.workspace.data_ptr(),
+                          plan.workspace_bytes - 1, eng._sptr(), eng.e2.data_ptr(), None)
+    assert code == 4
+
+
 if __name__ == "__main__":
     sys.exit(pytest.main([__file__, "-v"]))
