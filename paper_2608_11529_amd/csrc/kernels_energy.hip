@@ -553,14 +553,21 @@ __global__ void __launch_bounds__(256) k_e12(Dev d, ClassDev cd, int* flag) {
 #pragma unroll 1
     for (int sl = 0; sl < SC12; sl += 4) {
       double w[4], dd[4];
+      double2 sg[4];
+      // strings are ordered by pattern mask, so the union of four masks is
+      // usually a single mask; absent couplings carry zero coefficients
+      const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < MJ; ++j)
+        if (um & (1u << j)) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
+        }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t m = sM[sl + k];
-        double2 sg = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < MJ; ++j)
-          if (m & (1u << j)) sg = cfma(sD[sl + k][j], X[j], sg);
-        w[k] = cabs2(sg);
+        w[k] = cabs2(sg[k]);
         dd[k] = (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib];
       }
       const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
@@ -584,6 +591,71 @@ template __global__ void k_e12<8>(Dev, ClassDev, int*);
 template __global__ void k_e12<16>(Dev, ClassDev, int*);
 template __global__ void k_e12<24>(Dev, ClassDev, int*);
 template __global__ void k_e12<32>(Dev, ClassDev, int*);
+
+// Class (0,2): K = core + alpha'' + {a, b}, reached from
+// L = core + alpha'' + {t, w} by a_t a_w -> a+_b a+_a:
+//   sigma_K = sum_{t<w} <ab||tw> sign C_L,
+//   Delta   = T - eps_a - Uv_a - eps_b - Uv_b - W_ab.
+// 32 rows (fixed a, 32 consecutive b) per block with the couplings of every
+// pattern staged in LDS; eight interleaved string streams per block walk the
+// excitation lists.  grid (128 n_tp), block 256, dynamic LDS n_pat * 512 B.
+__global__ void __launch_bounds__(256) k_e02(Dev d, ClassDev cd, int* flag) {
+  extern __shared__ double2 sX[];
+  __shared__ double red[256];
+  const int64_t bid = blockIdx.x;
+  const int64_t tp = bid >> 7;
+  const int la = (int)((bid >> 1) & 63), half = (int)(bid & 1);
+  const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+  const int nv = d.n_v, nc = d.n_c;
+  const int a0 = I * 64 + la;
+  const int bmax = Jt * 64 + half * 32 + 31;
+  if (a0 >= nv || a0 >= bmax) {               // no valid (a, b) in this block
+    if (threadIdx.x == 0) cd.part[bid] = 0.0;
+    return;
+  }
+  const int tid = threadIdx.x, rl = tid & 31, sgp = tid >> 5;
+  const int J = cd.n_pat;
+  for (int e = tid; e < J * 32; e += 256) {
+    const int j = e >> 5, r = e & 31;
+    const Pattern pt = cd.pat[j];
+    const int64_t pr = occ_pair(nc + pt.a0, nc + pt.a1, d.n_o);
+    sX[e] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + half * 32 + r];
+  }
+  __syncthreads();
+  int a = a0, b = Jt * 64 + half * 32 + rl;
+  const bool valid = (a < b) && (b < nv);
+  if (!valid) {
+    a = 0;
+    b = nv > 1 ? 1 : 0;
+  }
+  const int64_t gv = d.n_fc + d.n_o;
+  const double rowc = -d.eps[d.n_o + a] - d.eps[d.n_o + b] - d.W[(gv + a) * d.n + gv + b];
+  const int64_t S = cd.n_str;
+  double acc = 0.0;
+  for (int64_t s = sgp; s < S; s += 8) {
+    const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
+    double2 sig = make_double2(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const int32_t cb = cd.conn[2 * e];
+      const int j = cd.conn[2 * e + 1];
+      double2 cv = d.c[cb & 0x7fffffff];
+      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+      sig = cfma(cv, sX[j * 32 + rl], sig);
+    }
+    if (e1 > e0) {
+      const double del = cd.T[s] + rowc - cd.Uv[s * nv + a] - cd.Uv[s * nv + b];
+      acc = fma(cabs2(sig), rcp_nr(del), acc);
+    }
+  }
+  if (valid && !isfinite(acc)) *flag = 2;
+  red[tid] = valid ? acc : 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) cd.part[bid] = red[0];
+}
 
 // Per-class sum of partials (Neumaier-compensated, fixed order) divided by
 // ||C||^2; out[k] for k < 9, out[9] = E2, out[10] = E0 - E_core,

@@ -157,6 +157,14 @@ mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipS
   return MRPT2_OK;
 }
 
+// The (0,2) kernel keeps the couplings of 32 rows for every pattern in LDS.
+constexpr size_t kE02MaxLds = 150 * 1024;
+bool e02_fits(int n_pat) {
+  if (n_pat <= 0 || (size_t)n_pat * 512 > kE02MaxLds) return false;
+  return hipFuncSetAttribute((const void*)k_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kE02MaxLds) == hipSuccess;
+}
+
 mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t wbytes) {
   if (!pers || !work) return MRPT2_ERR_ARG;
   if (wbytes < p.workspace_bytes) return MRPT2_ERR_WORKSPACE;
@@ -227,6 +235,13 @@ mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* p
         else if (cd.n_pat <= 16) hipLaunchKernelGGL((k_e12<16>), g12, dim3(256), 0, st, d, cd, flag);
         else if (cd.n_pat <= 24) hipLaunchKernelGGL((k_e12<24>), g12, dim3(256), 0, st, d, cd, flag);
         else hipLaunchKernelGGL((k_e12<32>), g12, dim3(256), 0, st, d, cd, flag);
+        tm.end();
+        continue;
+      }
+      if (k == 2 && e02_fits(cd.n_pat)) {
+        // no core hole, two virtual electrons: couplings of a 32-row block in LDS
+        pl.n[k] = ip.n_tp * 128;
+        hipLaunchKernelGGL(k_e02, dim3(ip.n_tp * 128), dim3(256), (size_t)cd.n_pat * 512, st, d, cd, flag);
         tm.end();
         continue;
       }

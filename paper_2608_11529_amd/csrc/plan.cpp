@@ -224,6 +224,29 @@ void build_class(InstancePlan& ip, ClassPlan& cp) {
   cp.n_conn = (int64_t)(cp.conn.size() / 2);
 }
 
+// Reorder the strings of a class so that strings coupling to the same set of
+// active orbitals (same annihilated-orbital pattern set) are adjacent; the
+// register-resident coupling kernels then walk runs of identical masks.
+void sort_by_pattern_mask(InstancePlan& ip, ClassPlan& cp) {
+  const size_t S = cp.strings.size();
+  std::vector<uint64_t> key(S, 0);
+  for (size_t s = 0; s < S; ++s)
+    for (int e = cp.conn_ptr[s]; e < cp.conn_ptr[s + 1]; ++e) {
+      const Pattern& p = cp.patterns[cp.conn[2 * e + 1]];
+      if (p.a0 >= 0) key[s] |= 1ull << p.a0;
+    }
+  std::vector<size_t> ord(S);
+  for (size_t s = 0; s < S; ++s) ord[s] = s;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+  std::vector<uint64_t> sorted(S);
+  for (size_t s = 0; s < S; ++s) sorted[s] = cp.strings[ord[s]];
+  cp.strings.swap(sorted);
+  cp.patterns.clear();
+  cp.conn.clear();
+  cp.conn_ptr.clear();
+  build_class(ip, cp);
+}
+
 }  // namespace
 
 int64_t sigma_blocks(const InstancePlan& ip, int k) {
@@ -344,6 +367,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.n_ext = cp.n_holes * binom(ip.n_v, cp.v) * (int64_t)cp.strings.size();
       n_ext += cp.n_ext;
       if (!cp.strings.empty()) build_class(ip, cp);
+      if (k == 1 && !cp.strings.empty() && cp.patterns.size() <= (size_t)kMaxDenseJ)
+        sort_by_pattern_mask(ip, cp);
     }
     // the (2,2) class walks the reference strings themselves
     if (!ip.cls[0].strings.empty() && ip.cls[0].strings != ip.pstrings) {
@@ -427,7 +452,12 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
       cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
-      ip.n_part_class[k] = sigma_blocks(ip, k);
+      // partial-sum slots: the generic kernel's blocks or the dedicated
+      // kernels' grids ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per
+      // tile pair x core; (0,2): 128 half-rows per tile pair)
+      int64_t special = 0;
+      if (S && cp.v == 2) special = (k == 0) ? ip.n_tp * cp.n_holes : (k == 1) ? ip.n_tp * 16 * cp.n_holes : ip.n_tp * 128;
+      ip.n_part_class[k] = std::max(sigma_blocks(ip, k), special);
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
     }
     ip.workspace_bytes = W.cur;
