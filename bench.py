@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK = 78.6e12       # FLOP/s, dense FP64 matrix
 FP64_VALU_PEAK = 78.6e12       # FLOP/s, FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
+FP32_MFMA_PEAK = 157.3e12      # FLOP/s, dense FP32 matrix
 HBM_PEAK = 8.0e12              # B/s
 
 
@@ -95,6 +96,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,58 +116,62 @@ def main():
     Bs = SP.factors(pb, dev)
     torch.cuda.synchronize()
     print("[bench] inputs %s generated on GPU in %.1f s" % (args.config, time.time() - t), file=sys.stderr, flush=True)
-    plan = M.Plan(M.desc_of_problem(pb))
-    info = plan.info()
-    eng = M.Engine(plan, dev)
-    c, e0 = ground_state(eng, h, Bs)
+    prec = {"mixed": 1, "fp64": 0}
+    plans = {p: M.Plan(M.desc_of_problem(pb, precision=prec[p])) for p in ("fp64", "mixed")}
+    info = plans["fp64"].info()
+    engs = {p: M.Engine(plans[p], dev) for p in plans}
+    c, e0 = ground_state(engs["fp64"], h, Bs)
     print("[bench] plan ready, N_P=%d N_Q=%d, reference state E0-Ecore=%.6f" % (info.n_ref, info.n_ext, e0),
           file=sys.stderr, flush=True)
     insts = [(h, Bs, c)]
-    for _ in range(args.warmup):
-        eng.energy(insts)
-    torch.cuda.synchronize()
-    stage_sum = {}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e2, parts, ms = eng.energy_timed(insts)
-        for k, v in ms.items():
-            stage_sum[k] = stage_sum.get(k, 0.0) + v
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    stage = {k: v / args.steps for k, v in stage_sum.items()}
-    e2v = float(e2[0].item())
-    print("[bench] %d steps, %.1f ms/step, E2=%.12f" % (args.steps, ms_per_step, e2v), file=sys.stderr, flush=True)
-    print("[bench] stages (ms): " + json.dumps({k: round(v, 3) for k, v in stage.items() if v > 0}),
-          file=sys.stderr, flush=True)
+    res = {}
+    for p in (args.precision, "fp64" if args.precision == "mixed" else "mixed"):
+        eng = engs[p]
+        for _ in range(args.warmup):
+            eng.energy(insts)
+        torch.cuda.synchronize()
+        stage_sum = {}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e2, parts, ms = eng.energy_timed(insts)
+            for k, v in ms.items():
+                stage_sum[k] = stage_sum.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res[p] = {"ms": (t1 - t0) * 1000.0 / args.steps,
+                  "stage": {k: v / args.steps for k, v in stage_sum.items()},
+                  "e2": float(e2[0].item()), "parts": parts[0].cpu().tolist()}
+        print("[bench] %s: %d steps, %.1f ms/step, E2=%.12f" % (p, args.steps, res[p]["ms"], res[p]["e2"]),
+              file=sys.stderr, flush=True)
+        print("[bench] %s stages (ms): " % p + json.dumps({k: round(v, 3) for k, v in res[p]["stage"].items() if v > 0}),
+              file=sys.stderr, flush=True)
+    head = res[args.precision]
+    stage = head["stage"]
+    ms_per_step = head["ms"]
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel of the headline path
     dom = max(stage, key=lambda k: stage[k])
     n_v, n_l = pb.n_v, pb.n_l
     n_o = pb.n_c + pb.n_a
     if dom == "pair_integrals":
         flop = 8.0 * (n_o * (n_o - 1) // 2) * n_v * (n_v - 1) * n_l
         ach = flop / (stage[dom] * 1e-3)
-        roof = {"kernel": "k_abuild (virtual-pair integrals, complex FP64 MFMA)", "bound": "mfma",
-                "achieved": ach / 1e12, "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": ach / FP64_MFMA_PEAK, "traffic": None}
+        peak = FP32_MFMA_PEAK if args.precision == "mixed" else FP64_MFMA_PEAK
+        roof = {"kernel": "k_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
+                          % ("_f32" if args.precision == "mixed" else "", "FP32" if args.precision == "mixed" else "FP64"),
+                "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None}
     elif dom == "sigma_22":
-        # per external determinant of class (2,2): denominator 3 adds, one
-        # division (counted as one reciprocal + 2 Newton FMAs) and one FMA
-        # accumulation: 6 FP64 vector operations = algorithmic work
         ops = 6.0 * info.n_ext_class[0]
         ach = ops / (stage[dom] * 1e-3)
-        peak = FP64_VALU_PEAK / 2.0   # operations (an FMA is one operation)
+        peak = FP64_VALU_PEAK / 2.0
         roof = {"kernel": "k_e22 (class (2,2) denominators and sums, FP64 vector)", "bound": "alu",
                 "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Top/s",
                 "frac": ach / peak, "traffic": None}
     else:
         k = M.CLASSES.index(tuple(int(x) for x in dom.split("_")[1])) if dom.startswith("sigma_") else None
         if k is not None:
-            conn = info.n_conn_class[k]
-            holes = math.comb(pb.n_c, M.CLASSES[k][0])
-            virt = math.comb(n_v, M.CLASSES[k][1])
-            flop = 8.0 * conn * holes * virt
+            flop = 8.0 * info.n_conn_class[k] * math.comb(pb.n_c, M.CLASSES[k][0]) * math.comb(n_v, M.CLASSES[k][1])
             ach = flop / (stage[dom] * 1e-3)
             roof = {"kernel": "sigma contraction of class %s (complex FP64, nonzero couplings)" % dom[-2:],
                     "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
@@ -174,7 +180,7 @@ def main():
             roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
                     "frac": None, "traffic": None}
     roof["ms_per_launch"] = stage[dom]
-
+    other = "fp64" if args.precision == "mixed" else "mixed"
     out = {
         "metric": "external dets/sec + E2 evals/sec (mixed vs FP64, |dE2| Eh), 1 MI355X",
         "value": info.n_ext / (ms_per_step * 1e-3),
@@ -182,20 +188,25 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32-mfma+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
         "config": {"workload": "%s: n_fc=%d n_core=%d n_act=%d (%s, %d e, base %s, hops<=%d) n_virt=%d "
                                "n_chol=%d (sets %s); N_P=%d N_Q=%d"
                                % (args.config, pb.n_fc, pb.n_c, pb.n_a, "x".join(map(str, pb.sub_sizes)),
                                   pb.n_elec, pb.base, min(pb.max_hops, 99), n_v, n_l, pb.sets,
                                   info.n_ref, info.n_ext),
-                   "precision": "fp64", "n_ext": info.n_ext, "n_ref": info.n_ref},
+                   "precision": args.precision, "n_ext": info.n_ext, "n_ref": info.n_ref},
         "e2_evals_per_s": 1000.0 / ms_per_step,
-        "e2": e2v,
+        "e2": head["e2"],
+        "compare": {"precision": other, "value": info.n_ext / (res[other]["ms"] * 1e-3),
+                    "ms_per_step": res[other]["ms"], "e2": res[other]["e2"],
+                    "abs_dE2_mixed_vs_fp64": abs(res["mixed"]["e2"] - res["fp64"]["e2"]),
+                    "abs_dE2_per_class": [abs(x - y) for x, y in zip(res["mixed"]["parts"][:9], res["fp64"]["parts"][:9])]},
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        del Bs, h, eng
+        del Bs, h, engs, eng
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)

@@ -259,6 +259,136 @@ __global__ void __launch_bounds__(256) k_abuild(Dev d) {
         out[acc_row(i, r) * 64 + acc_col(j)] = make_double2(accR[i][j][r], accI[i][j][r]);
 }
 
+// ---- mixed precision: complex FP32 MFMA with FP64 carry ---------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int KC32 = 32;            // complex k per stage
+constexpr int KP32 = KC32 + 1;
+
+// v_mfma_f32_16x16x4f32: lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// result D[i][j] sits in lane j + 16 (i/4), register i%4.  Products and the
+// sums over one stage (KC32 complex k) are FP32; every stage's partial sums
+// are added into FP64 accumulators, so the FP32 rounding of a sum grows
+// with the stage length only.  Operands are rounded to FP32 once when they
+// are staged.
+template <class FA, class FB>
+__device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, float2* sB,
+                                            double (&accR)[2][2][4], double (&accI)[2][2][4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accR[i][j][r] = 0.0;
+        accI[i][j][r] = 0.0;
+      }
+  const int kq = lane >> 4;
+  const int kcl = kq >> 1, comp = kq & 1;
+  for (int k0 = 0; k0 < K; k0 += KC32) {
+    for (int e = tid; e < 64 * KC32; e += 256) {
+      const int r = e / KC32, kk = e % KC32;
+      const bool in = (k0 + kk) < K;
+      const double2 a = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
+      const double2 b = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
+      sA[r * KP32 + kk] = make_float2((float)a.x, (float)a.y);
+      sB[r * KP32 + kk] = make_float2((float)b.x, (float)b.y);
+    }
+    __syncthreads();
+    f4 pR[2][2], pI[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        pR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        pI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll 4
+    for (int ks = 0; ks < KC32; ks += 2) {
+      const int kc = ks + kcl;
+      float ar[2], ai[2], bb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float2 v = sA[(wr + i * 16 + (lane & 15)) * KP32 + kc];
+        ar[i] = comp ? -v.y : v.x;
+        ai[i] = comp ? v.x : v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float2 v = sB[(wc + j * 16 + (lane & 15)) * KP32 + kc];
+        bb[j] = comp ? v.y : v.x;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          pR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bb[j], pR[i][j], 0, 0, 0);
+          pI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bb[j], pI[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accR[i][j][r] += (double)pR[i][j][r];
+          accI[i][j][r] += (double)pI[i][j][r];
+        }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int acc_row_f32(int i, int r) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  return (wv >> 1) * 32 + i * 16 + 4 * (lane >> 4) + r;
+}
+
+// Mixed-precision form of k_abuild (same operands, same output layout).
+__global__ void __launch_bounds__(256) k_abuild_f32(Dev d) {
+  __shared__ float2 sA[64 * KP32];
+  __shared__ float2 sB[64 * KP32];
+  const int64_t tp = blockIdx.x;
+  int64_t pr = blockIdx.y;
+  int xo = 0;
+  while (pr >= d.n_o - 1 - xo) {
+    pr -= d.n_o - 1 - xo;
+    ++xo;
+  }
+  const int yo = xo + 1 + (int)pr;
+  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+  const int nl = d.n_l;
+  const double2* Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
+  const double2* Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
+  const double* sg = d.sign;
+  const int nv = d.n_v;
+  auto fa = [&](int r, int k) -> double2 {
+    const int a = I * 64 + r;
+    if (a >= nv) return make_double2(0.0, 0.0);
+    const int L = k < nl ? k : k - nl;
+    const double2 v = (k < nl ? Sx : Sy)[(int64_t)a * nl + L];
+    return make_double2(sg[L] * v.x, sg[L] * v.y);
+  };
+  auto fb = [&](int r, int k) -> double2 {
+    const int b = J * 64 + r;
+    if (b >= nv) return make_double2(0.0, 0.0);
+    if (k < nl) return Sy[(int64_t)b * nl + k];
+    const double2 v = Sx[(int64_t)b * nl + (k - nl)];
+    return make_double2(-v.x, -v.y);
+  };
+  double accR[2][2][4], accI[2][2][4];
+  cgemm64_f32(fa, fb, 2 * nl, sA, sB, accR, accI);
+  double2* out = d.A + ((int64_t)blockIdx.y * d.n_tp + tp) * 4096;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[acc_row_f32(i, r) * 64 + acc_col(j)] = make_double2(accR[i][j][r], accI[i][j][r]);
+}
+
 // Integrals with one active or virtual and one active spinor against two
 // occupied ones: G[x][p][y][q] = (px|qy), x, y core or active, p active or
 // virtual, q active.  One GEMM: rows (x, p), columns (y, q), K = n_l.

@@ -198,7 +198,10 @@ mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* p
     tm.end();
     if (ip.n_v >= 2 && ip.n_pairs > 0) {
       tm.begin(ST_ABUILD);
-      hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
+      if (ip.d.precision == MRPT2_MIXED)
+        hipLaunchKernelGGL(k_abuild_f32, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
+      else
+        hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
       tm.end();
     }
     PartList pl{};

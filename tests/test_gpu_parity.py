@@ -96,6 +96,43 @@ def test_c1_matches_oracle_golden():
     assert abs(float(e2[0]) - g["E2"]) <= TOL
 
 
+def test_c1_mixed_precision_within_tolerance():
+    """FP32-MFMA pair integrals with FP64 denominators and sums: within
+    1e-6 Eh of the oracle on c1, class by class."""
+    import torch
+    import paper_2608_11529_amd as M
+    g = golden("c1")
+    pb = SP.config("c1")
+    plan = M.Plan(M.desc_of_problem(pb, precision=1))
+    eng = M.Engine(plan)
+    c_o = np.array(g["c_re"]) + 1j * np.array(g["c_im"])
+    c = to_plan_order(c_o, g["p_strings"], plan.ref_strings(), pb.n_c)
+    dev = eng.device
+    h, Bs = SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)]
+    print("[gpu] c1 mixed", flush=True)
+    e2, parts = eng.energy([(h, Bs, torch.from_numpy(np.ascontiguousarray(c)).to(dev))])
+    parts = parts[0].cpu().numpy()
+    for k, cl in enumerate(CLASSES):
+        ref = g["parts"]["%d%d" % cl]
+        assert abs(parts[k] - ref) <= 1e-6, (cl, parts[k], ref)
+    assert abs(float(e2[0]) - g["E2"]) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["s_tiles", "s_fc"])
+def test_mixed_precision_small(name):
+    e2_64, parts_64, parts_o, _ = gpu_energy(name)
+    import torch
+    import paper_2608_11529_amd as M
+    pb = problem(name)
+    parts_o, E0_o, c_o, P_o = oracle_reference(name)
+    plan = M.Plan(M.desc_of_problem(pb, precision=1))
+    eng = M.Engine(plan)
+    dev = eng.device
+    c = torch.from_numpy(np.ascontiguousarray(to_plan_order(c_o, P_o, plan.ref_strings(), pb.n_c))).to(dev)
+    e2, parts = eng.energy([(SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)], c)])
+    assert abs(float(e2[0]) - e2_total(parts_o)) <= 1e-6
+
+
 def test_bitwise_repeatable():
     """Fixed-order reductions: two evaluations agree bit for bit."""
     import torch
