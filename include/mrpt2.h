@@ -169,6 +169,36 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
                                          const void* persistent, void* workspace,
                                          size_t workspace_bytes, hipStream_t stream, double* hpp);
 
+/* Work decomposition of one excitation class: mrpt2_energy writes one
+ * partial sum per block, sum over the block's external determinants of
+ * |sigma_K|^2 / (E0 - H_KK) (not yet divided by ||C||^2).  A block covers
+ * either (kind 0) the core holes `hole[0..n_holes)`, lowest virtual in
+ * [a_lo, a_hi), second virtual in [b_lo, b_hi) (b > a; two-virtual classes),
+ * or (kind 1) the rows [row_lo, row_hi) with row = hole_index * n_virt^v + a
+ * (hole_index in lexicographic order of the hole sets), and in both cases the
+ * class strings [s_lo, s_hi) in mrpt2_plan_class_strings order.  Virtual
+ * indices are 0-based within the kept virtuals, core indices within the
+ * correlated core.  For checking sampled parts of a large sum. */
+typedef struct {
+  int32_t kind;
+  int32_t n_holes;
+  int32_t hole[2];
+  int32_t a_lo, a_hi, b_lo, b_hi;
+  int64_t row_lo, row_hi;
+  int64_t s_lo, s_hi;
+} mrpt2_block;
+
+mrpt2_status mrpt2_plan_class_blocks(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t* n_blocks);
+mrpt2_status mrpt2_plan_class_block(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t block,
+                                    mrpt2_block* out);
+/* Active strings of the external determinants of class cls (host, in the
+ * order the blocks refer to; same bit convention as the reference strings). */
+mrpt2_status mrpt2_plan_class_strings(mrpt2_plan_t plan, int32_t inst, int32_t cls, uint64_t* bits);
+/* Copy the block partial sums of class cls from the last mrpt2_energy on
+ * this workspace to host memory (n_blocks doubles); synchronises stream. */
+mrpt2_status mrpt2_class_partials(mrpt2_plan_t plan, int32_t inst, int32_t cls, const void* workspace,
+                                  hipStream_t stream, double* out);
+
 void mrpt2_plan_destroy(mrpt2_plan_t plan);
 const char* mrpt2_status_string(mrpt2_status s);
 

@@ -50,14 +50,28 @@ class ClassOracle:
         self.V = np.arange(n_c + n_a, n)
         self.hd = np.real(np.diag(self.h)).astype(np.float64)
         self.W = integrals.pair_energies(self.Bs, self.ws)
-        self.gOOOO = integrals.eri_block(self.Bs, self.ws, self.O, self.O, self.O, self.O)
-        self.gVOOO = integrals.eri_block(self.Bs, self.ws, self.V, self.O, self.O, self.O)
+        self._goooo = None
+        self._gvooo = None
         self._gvv = {}
         self.P = space.p_strings()
         self.pidx = {a: i for i, a in enumerate(self.P)}
         self.core = space.core_mask
 
     # -- integrals ----------------------------------------------------------
+    @property
+    def gOOOO(self):
+        """(pq|rs) over core and active spinors (computed on first use)."""
+        if self._goooo is None:
+            self._goooo = integrals.eri_block(self.Bs, self.ws, self.O, self.O, self.O, self.O)
+        return self._goooo
+
+    @property
+    def gVOOO(self):
+        """(a x|y z), a virtual, x, y, z core or active (computed on first use)."""
+        if self._gvooo is None:
+            self._gvooo = integrals.eri_block(self.Bs, self.ws, self.V, self.O, self.O, self.O)
+        return self._gvooo
+
     def g_occ(self, p, q, r, s):
         return self.gOOOO[p, q, r, s]
 
@@ -87,11 +101,13 @@ class ClassOracle:
         return float(self.hd[occ].sum() + 0.5 * self.W[np.ix_(occ, occ)].sum())
 
     # -- main ------------------------------------------------------------------
-    def e2(self, C, q_mode=0, E0=None, core_sets=None, va=None, vb=None, classes=None):
+    def e2(self, C, q_mode=0, E0=None, core_sets=None, va=None, vb=None, classes=None, strings=None):
         """Per-class E2 parts (dict) and E0.  core_sets: allowed core-hole
         tuples (sorted, correlated core indices); va / vb: (lo, hi) ranges of
         virtual positions (0-based within the virtual block) for the lowest
-        and the second virtual spinor of K."""
+        and the second virtual spinor of K; strings: allowed active strings
+        of K (bit masks in this space's positions)."""
+        self.strings_filter = None if strings is None else set(int(x) for x in strings)
         C = np.asarray(C, dtype=np.complex128)
         if E0 is None:
             _, E0 = self.reference(C)
@@ -120,6 +136,12 @@ class ClassOracle:
         for Hc in combinations(range(self.sp.n_c), h):
             if self.core_sets is None or tuple(Hc) in self.core_sets:
                 yield Hc
+
+    def _cls_strings(self, h, v, q_mode):
+        out = self.sp.class_strings(h, v, q_mode)
+        if self.strings_filter is not None:
+            out = [a for a in out if a in self.strings_filter]
+        return out
 
     def _rep(self, v):
         return [int(x) for x in self.V[:v]]
@@ -152,6 +174,8 @@ class ClassOracle:
         for c, c2 in self._holes(2):
             X = self.g_vv(c, c2) - self.g_vv(c2, c)            # (ac|bc') - (ac'|bc)
             for i, al in enumerate(self.P):
+                if self.strings_filter is not None and al not in self.strings_filter:
+                    continue
                 L = self.core | al
                 D0 = L & ~(1 << c) & ~(1 << c2)
                 K = D0 | (1 << a0) | (1 << b0)
@@ -165,7 +189,7 @@ class ClassOracle:
         a0, b0 = self._rep(2)
         acts = bits(self.sp.act_mask)
         for (c,) in self._holes(1):
-            for al in self.sp.class_strings(1, 2, q_mode):
+            for al in self._cls_strings(1, 2, q_mode):
                 D0 = (self.core & ~(1 << c)) | al
                 K = D0 | (1 << a0) | (1 << b0)
                 sig = 0.0
@@ -187,7 +211,7 @@ class ClassOracle:
         terms = []
         a0, b0 = self._rep(2)
         acts = bits(self.sp.act_mask)
-        for al in self.sp.class_strings(0, 2, q_mode):
+        for al in self._cls_strings(0, 2, q_mode):
             D0 = self.core | al
             K = D0 | (1 << a0) | (1 << b0)
             sig = 0.0
@@ -208,7 +232,7 @@ class ClassOracle:
         terms = []
         (a0,) = self._rep(1)
         for c, c2 in self._holes(2):
-            for al in self.sp.class_strings(2, 1, q_mode):
+            for al in self._cls_strings(2, 1, q_mode):
                 D0 = (self.core & ~(1 << c) & ~(1 << c2)) | al
                 K = D0 | (1 << a0)
                 sig = 0.0
@@ -230,7 +254,7 @@ class ClassOracle:
         (a0,) = self._rep(1)
         acts = bits(self.sp.act_mask)
         for (c,) in self._holes(1):
-            for al in self.sp.class_strings(1, 1, q_mode):
+            for al in self._cls_strings(1, 1, q_mode):
                 D0 = (self.core & ~(1 << c)) | al
                 K = D0 | (1 << a0)
                 sig = 0.0
@@ -262,7 +286,7 @@ class ClassOracle:
         terms = []
         (a0,) = self._rep(1)
         acts = bits(self.sp.act_mask)
-        for al in self.sp.class_strings(0, 1, q_mode):
+        for al in self._cls_strings(0, 1, q_mode):
             D0 = self.core | al
             K = D0 | (1 << a0)
             sig = 0.0
@@ -299,7 +323,7 @@ class ClassOracle:
             core_k = self.core
             for c in Hc:
                 core_k &= ~(1 << c)
-            for al in self.sp.class_strings(h, 0, q_mode):
+            for al in self._cls_strings(h, 0, q_mode):
                 K = core_k | al
                 occ_a = bits(al)
                 free = [t for t in acts if not al >> t & 1]

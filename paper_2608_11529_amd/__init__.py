@@ -71,6 +71,26 @@ class Plan:
             self.handle, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "mrpt2_plan_ref_strings")
         return out
 
+    def class_blocks(self, cls, inst=0):
+        """Block descriptions (capi.Block) of class cls's partial sums."""
+        n = ctypes.c_int64()
+        capi.check(capi.lib().mrpt2_plan_class_blocks(self.handle, inst, cls, ctypes.byref(n)),
+                   "mrpt2_plan_class_blocks")
+        return n.value
+
+    def class_block(self, cls, b, inst=0):
+        out = capi.Block()
+        capi.check(capi.lib().mrpt2_plan_class_block(self.handle, inst, cls, b, ctypes.byref(out)),
+                   "mrpt2_plan_class_block")
+        return out
+
+    def class_strings(self, cls, inst=0):
+        n = self.info(inst).n_strings_class[cls]
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        capi.check(capi.lib().mrpt2_plan_class_strings(
+            self.handle, inst, cls, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), "mrpt2_plan_class_strings")
+        return out[:n]
+
     def __del__(self):
         h = getattr(self, "handle", None)
         try:
@@ -144,6 +164,17 @@ class Engine:
         capi.check(code, "mrpt2_energy_timed")
         del keep
         return self.e2, self.parts, dict(zip(capi.STAGES, list(ms)))
+
+    def class_partials(self, cls, inst=0):
+        """Block partial sums of class cls from the last energy() (host numpy,
+        not divided by ||C||^2)."""
+        n = self.plan.class_blocks(cls, inst)
+        out = np.zeros(max(n, 1))
+        capi.check(capi.lib().mrpt2_class_partials(self.plan.handle, inst, cls, self.workspace.data_ptr(),
+                                                   self._sptr(),
+                                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                   "mrpt2_class_partials")
+        return out[:n]
 
     def reference_hamiltonian(self, h, Bs, inst=0):
         torch = self.torch

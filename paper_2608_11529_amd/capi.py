@@ -74,6 +74,18 @@ class Inputs(ctypes.Structure):
     ]
 
 
+class Block(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("n_holes", ctypes.c_int32),
+        ("hole", ctypes.c_int32 * 2),
+        ("a_lo", ctypes.c_int32), ("a_hi", ctypes.c_int32),
+        ("b_lo", ctypes.c_int32), ("b_hi", ctypes.c_int32),
+        ("row_lo", ctypes.c_int64), ("row_hi", ctypes.c_int64),
+        ("s_lo", ctypes.c_int64), ("s_hi", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -103,6 +115,15 @@ def lib():
         L.mrpt2_reference_hamiltonian.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Inputs), vp, vp,
                                                   ctypes.c_size_t, vp, vp]
         L.mrpt2_reference_hamiltonian.restype = st
+        L.mrpt2_plan_class_blocks.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+        L.mrpt2_plan_class_blocks.restype = st
+        L.mrpt2_plan_class_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.POINTER(Block)]
+        L.mrpt2_plan_class_block.restype = st
+        L.mrpt2_plan_class_strings.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+        L.mrpt2_plan_class_strings.restype = st
+        L.mrpt2_class_partials.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.mrpt2_class_partials.restype = st
         L.mrpt2_plan_destroy.argtypes = [vp]
         L.mrpt2_plan_destroy.restype = None
         L.mrpt2_status_string.argtypes = [st]
@@ -119,5 +140,6 @@ def check(code, where):
 EXPORTED = [
     "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
     "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
-    "mrpt2_plan_destroy", "mrpt2_status_string",
+    "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
+    "mrpt2_plan_class_strings", "mrpt2_class_partials",
 ]

@@ -157,14 +157,6 @@ mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipS
   return MRPT2_OK;
 }
 
-// The (0,2) kernel keeps the couplings of 32 rows for every pattern in LDS.
-constexpr size_t kE02MaxLds = 150 * 1024;
-bool e02_fits(int n_pat) {
-  if (n_pat <= 0 || (size_t)n_pat * 512 > kE02MaxLds) return false;
-  return hipFuncSetAttribute((const void*)k_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)kE02MaxLds) == hipSuccess;
-}
-
 mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t wbytes) {
   if (!pers || !work) return MRPT2_ERR_ARG;
   if (wbytes < p.workspace_bytes) return MRPT2_ERR_WORKSPACE;
@@ -221,18 +213,17 @@ mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* p
       pl.n[k] = nb;
       dim3 g(nb), b(256);
       tm.begin(ST_SIGMA0 + k);
-      if (k == 0) {
+      pl.n[k] = cp.n_blocks;
+      if (cp.kernel == KERN_E22) {
         // dedicated vector kernel: one block per (virtual tile pair, core pair)
-        pl.n[k] = ip.n_tp * cp.n_holes;
         hipLaunchKernelGGL(k_e22, dim3(ip.n_tp, cp.n_holes), dim3(256), 0, st, d, cd, flag);
         tm.end();
         continue;
       }
-      if (k == 1 && cp.dense_coef) {
+      if (cp.kernel == KERN_E12) {
         // one core hole, two virtual electrons: coefficients densified per
         // string, couplings held in registers; one block per (tile pair, core)
         hipLaunchKernelGGL(k_dense_coef, dim3(cdiv(cd.n_str, 256)), dim3(256), 0, st, d, cd);
-        pl.n[k] = ip.n_tp * 16 * cp.n_holes;
         const dim3 g12(ip.n_tp * 16, cp.n_holes);
         if (cd.n_pat <= 8) hipLaunchKernelGGL((k_e12<8>), g12, dim3(256), 0, st, d, cd, flag);
         else if (cd.n_pat <= 16) hipLaunchKernelGGL((k_e12<16>), g12, dim3(256), 0, st, d, cd, flag);
@@ -241,9 +232,11 @@ mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* p
         tm.end();
         continue;
       }
-      if (k == 2 && e02_fits(cd.n_pat)) {
+      if (cp.kernel == KERN_E02) {
         // no core hole, two virtual electrons: couplings of a 32-row block in LDS
-        pl.n[k] = ip.n_tp * 128;
+        if (hipFuncSetAttribute((const void*)k_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kE02MaxLds) != hipSuccess)
+          return MRPT2_ERR_HIP;
         hipLaunchKernelGGL(k_e02, dim3(ip.n_tp * 128), dim3(256), (size_t)cd.n_pat * 512, st, d, cd, flag);
         tm.end();
         continue;
@@ -376,6 +369,47 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
   HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_class_blocks(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t* n_blocks) {
+  if (!plan || !n_blocks || inst < 0 || inst >= (int)plan->p.inst.size() || cls < 0 || cls >= MRPT2_N_CLASS)
+    return MRPT2_ERR_ARG;
+  const ClassPlan& cp = plan->p.inst[inst].cls[cls];
+  *n_blocks = (cp.strings.empty() || cp.n_rows == 0) ? 0 : cp.n_blocks;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_class_block(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t block,
+                                    mrpt2_block* out) {
+  int64_t nb = 0;
+  mrpt2_status s = mrpt2_plan_class_blocks(plan, inst, cls, &nb);
+  if (s != MRPT2_OK) return s;
+  if (!out || block < 0 || block >= nb) return MRPT2_ERR_ARG;
+  class_block(plan->p.inst[inst], cls, block, out);
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_plan_class_strings(mrpt2_plan_t plan, int32_t inst, int32_t cls, uint64_t* bits) {
+  if (!plan || !bits || inst < 0 || inst >= (int)plan->p.inst.size() || cls < 0 || cls >= MRPT2_N_CLASS)
+    return MRPT2_ERR_ARG;
+  const auto& v = plan->p.inst[inst].cls[cls].strings;
+  if (!v.empty()) std::memcpy(bits, v.data(), v.size() * 8);
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_class_partials(mrpt2_plan_t plan, int32_t inst, int32_t cls, const void* workspace,
+                                  hipStream_t st, double* out) {
+  int64_t nb = 0;
+  mrpt2_status s = mrpt2_plan_class_blocks(plan, inst, cls, &nb);
+  if (s != MRPT2_OK) return s;
+  if (!workspace || !out) return MRPT2_ERR_ARG;
+  const InstancePlan& ip = plan->p.inst[inst];
+  const char* src = (const char*)workspace + ip.workspace_base + ip.off_part_class[cls];
+  if (nb > 0) {
+    HIPCHK(hipMemcpyAsync(out, src, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return MRPT2_OK;
 }
 
 void mrpt2_plan_destroy(mrpt2_plan_t plan) { delete plan; }

@@ -257,6 +257,72 @@ int64_t sigma_blocks(const InstancePlan& ip, int k) {
   return rb * nsc;
 }
 
+void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
+  const ClassPlan& cp = ip.cls[k];
+  std::memset(o, 0, sizeof(*o));
+  const int64_t S = (int64_t)cp.strings.size();
+  o->s_lo = 0;
+  o->s_hi = S;
+  auto set_holes = [&](int64_t hidx) {
+    o->n_holes = cp.h;
+    if (cp.h == 1) o->hole[0] = (int)hidx;
+    if (cp.h == 2) {
+      o->hole[0] = ip.hole_pairs[2 * hidx];
+      o->hole[1] = ip.hole_pairs[2 * hidx + 1];
+    }
+  };
+  auto clampv = [&](int x) { return std::min(std::max(x, 0), ip.n_v); };
+  o->kind = 0;
+  if (cp.kernel == KERN_E22) {
+    const int64_t hp = b / ip.n_tp, tp = b % ip.n_tp;
+    set_holes(hp);
+    const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
+    o->a_lo = clampv(I * 64); o->a_hi = clampv(I * 64 + 64);
+    o->b_lo = clampv(J * 64); o->b_hi = clampv(J * 64 + 64);
+    return;
+  }
+  if (cp.kernel == KERN_E12) {
+    const int64_t c = b / (ip.n_tp * 16), r = b % (ip.n_tp * 16);
+    const int64_t tp = r / 16;
+    const int sub = (int)(r % 16), sa = sub >> 2, sb = sub & 3;
+    set_holes(c);
+    const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
+    o->a_lo = clampv(I * 64 + sa * 16); o->a_hi = clampv(I * 64 + sa * 16 + 16);
+    o->b_lo = clampv(J * 64 + sb * 16); o->b_hi = clampv(J * 64 + sb * 16 + 16);
+    return;
+  }
+  if (cp.kernel == KERN_E02) {
+    const int64_t tp = b >> 7;
+    const int la = (int)((b >> 1) & 63), half = (int)(b & 1);
+    set_holes(0);
+    const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
+    o->a_lo = clampv(I * 64 + la); o->a_hi = clampv(I * 64 + la + 1);
+    o->b_lo = clampv(J * 64 + half * 32); o->b_hi = clampv(J * 64 + half * 32 + 32);
+    return;
+  }
+  // generic kernel: rows x string chunk
+  const int64_t rb = (cp.n_rows + 255) / 256;
+  const int64_t nsc = rb > 0 ? sigma_blocks(ip, k) / rb : 1;
+  const int64_t rbi = b / nsc, sc = b % nsc;
+  const int64_t chunk = (S + nsc - 1) / nsc;
+  o->s_lo = std::min(S, sc * chunk);
+  o->s_hi = std::min(S, o->s_lo + chunk);
+  const int64_t r0 = rbi * 256, r1 = std::min(cp.n_rows, r0 + 256);
+  if (cp.v == 2) {
+    const int64_t per = ip.n_tp * 4096;
+    const int64_t hole = r0 / per, rab = r0 % per, tp = rab >> 12;
+    const int la = (int)((rab >> 6) & 63);
+    set_holes(hole);
+    const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
+    o->a_lo = clampv(I * 64 + la); o->a_hi = clampv(I * 64 + la + 4);
+    o->b_lo = clampv(J * 64); o->b_hi = clampv(J * 64 + 64);
+    return;
+  }
+  o->kind = 1;
+  o->row_lo = r0;
+  o->row_hi = r1;
+}
+
 mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string* err) {
   if (!dd || n_inst < 1 || !out) {
     *err = "null argument or n_inst < 1";
@@ -452,12 +518,20 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
       cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
-      // partial-sum slots: the generic kernel's blocks or the dedicated
-      // kernels' grids ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per
-      // tile pair x core; (0,2): 128 half-rows per tile pair)
-      int64_t special = 0;
-      if (S && cp.v == 2) special = (k == 0) ? ip.n_tp * cp.n_holes : (k == 1) ? ip.n_tp * 16 * cp.n_holes : ip.n_tp * 128;
-      ip.n_part_class[k] = std::max(sigma_blocks(ip, k), special);
+      // kernel choice and partial-sum blocks: the dedicated kernels' grids
+      // ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per tile pair x
+      // core; (0,2): 128 half-rows per tile pair) or the generic kernel's
+      cp.kernel = KERN_GENERIC;
+      if (S && cp.n_rows > 0) {
+        if (k == 0) cp.kernel = KERN_E22;
+        else if (k == 1 && cp.dense_coef) cp.kernel = KERN_E12;
+        else if (k == 2 && !cp.patterns.empty() && cp.patterns.size() * 512 <= kE02MaxLds) cp.kernel = KERN_E02;
+      }
+      cp.n_blocks = (cp.kernel == KERN_E22)   ? ip.n_tp * cp.n_holes
+                    : (cp.kernel == KERN_E12) ? ip.n_tp * 16 * cp.n_holes
+                    : (cp.kernel == KERN_E02) ? ip.n_tp * 128
+                                              : sigma_blocks(ip, k);
+      ip.n_part_class[k] = cp.n_blocks;
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
     }
     ip.workspace_bytes = W.cur;

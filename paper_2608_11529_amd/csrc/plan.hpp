@@ -47,6 +47,8 @@ struct ClassPlan {
   // device offsets within the instance's workspace
   size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
   bool dense_coef = false;             // coefficients as a dense [S][n_pat] table + masks
+  int kernel = 0;                      // KERN_* below
+  int64_t n_blocks = 0;                // partial sums written by the class's kernel
 };
 
 struct InstancePlan {
@@ -85,6 +87,13 @@ struct Plan {
   size_t off_flag = 0;                // device error flag in the workspace
   std::vector<char> host_blob;
 };
+
+// Kernel that evaluates a class.
+enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3 };
+constexpr size_t kE02MaxLds = 150 * 1024;   // LDS bytes of the (0,2) kernel's coupling block
+
+// Description of partial-sum block b of class k (see mrpt2_block).
+void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* out);
 
 // Builds the plan; returns MRPT2_OK or an error with a message in *err.
 mrpt2_status build_plan(const mrpt2_desc* d, int n_inst, Plan* out, std::string* err);

@@ -1,0 +1,120 @@
+"""Sampled parity at full size (c2, c4), in the launch configuration the
+benchmark times: the library's per-block partial sums (each a restricted sum
+of |sigma_K|^2 / (E0 - H_KK) over the external determinants of one work
+block, see mrpt2_block) against the CPU oracle on the same restriction, plus
+E0 of the full reference space.  The oracle works on the sub-problem of
+frozen core + core + active + the block's virtual spinors, which holds every
+term of those determinants.  Reference vector and oracle E0:
+tests/golden/<name>_sampled_ref.json (oracle-only)."""
+import json
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import synth.problems as SP
+from oracle import run
+from oracle.classes import ClassOracle
+from oracle.space import ActiveSpace
+
+from helpers import CLASSES, to_plan_order
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def reference(name):
+    with open(os.path.join(HERE, "golden", "%s_sampled_ref.json" % name)) as f:
+        return json.load(f)
+
+
+def oracle_block_sum(pb, h_full_idx, cl, c_sorted, e0_rel, holes_list, vsets, strings):
+    """Oracle E2 restricted to the given hole tuples, virtual ranges and
+    strings.  vsets: list of (hole tuple, a-range, b-range or None)."""
+    n_occ = pb.n_fc + pb.n_c + pb.n_a
+    vs = sorted(set(v for _, ar, br in vsets for v in list(ar) + (list(br) if br is not None else [])))
+    idx = list(range(n_occ)) + [n_occ + v for v in vs]
+    h = h_full_idx(idx)
+    Bs = [SP.factor_rows(pb, t, 0, r, idx).numpy() for t, (r, _) in enumerate(pb.sets)]
+    ws = SP.weights(pb)
+    hfc, Bc = run.correlated_inputs(h, Bs, ws, pb.n_fc)
+    sp = ActiveSpace(pb.n_c, pb.sub_sizes, pb.n_elec, pb.base, pb.max_hops, len(vs))
+    co = ClassOracle(sp, hfc, Bc, ws)
+    e0 = e0_rel + co.energy_of(co.core)
+    pos = {v: i for i, v in enumerate(vs)}
+    tot = 0.0
+    for hole, ar, br in vsets:
+        va = (pos[ar[0]], pos[ar[-1]] + 1) if len(ar) else (0, 0)
+        vb = (pos[br[0]], pos[br[-1]] + 1) if br is not None and len(br) else None
+        parts, _ = co.e2(c_sorted, 0, E0=e0, core_sets=[hole], va=va, vb=vb, classes=[cl], strings=strings)
+        tot += parts[cl]
+    return tot
+
+
+@pytest.mark.parametrize("name,per_class", [("c2", 3), ("c4", 1)])
+def test_sampled_blocks_match_oracle(name, per_class):
+    import torch
+    import paper_2608_11529_amd as M
+    ref = reference(name)
+    pb = SP.config(name)
+    plan = M.Plan(M.desc_of_problem(pb))
+    bits = plan.ref_strings()
+    P_sorted = sorted(int(b) << pb.n_c for b in bits)
+    seed, stream, scale = ref["noise"]
+    c = scale * SP.complex_normal(seed, stream, (len(P_sorted),)).numpy()
+    c[P_sorted.index(ref["beta"])] += 1.0
+    eng = M.Engine(plan)
+    dev = eng.device
+    print("[gpu] %s sampled: generating inputs" % name, flush=True)
+    h = SP.one_body(pb, dev)
+    Bs = SP.factors(pb, dev)
+    cd = torch.from_numpy(np.ascontiguousarray(to_plan_order(c, P_sorted, bits, pb.n_c))).to(dev)
+    e2, parts = eng.energy([(h, Bs, cd)])
+    parts = parts[0].cpu().numpy()
+    del Bs
+    torch.cuda.empty_cache()
+    assert abs(parts[10] - ref["E0_minus_Ecore"]) < 1e-9, (parts[10], ref["E0_minus_Ecore"])
+    norm = parts[11]
+    h_cpu = SP.one_body(pb).numpy()
+    rng = np.random.default_rng(11)
+    checked = 0
+    for k, cl in enumerate(CLASSES):
+        nb = plan.class_blocks(k)
+        if nb == 0:
+            continue
+        partials = eng.class_partials(k)
+        assert np.all(np.isfinite(partials))
+        strings_all = plan.class_strings(k)
+        cand = [b for b in rng.permutation(nb)[: 40 * per_class]]
+        done = 0
+        for b in cand:
+            blk = plan.class_block(k, int(b))
+            s_sel = [int(x) << pb.n_c for x in strings_all[blk.s_lo:blk.s_hi]]
+            h_, v_ = cl
+            if blk.kind == 0:
+                holes = tuple(blk.hole[i] for i in range(blk.n_holes))
+                ar = list(range(blk.a_lo, blk.a_hi))
+                br = list(range(blk.b_lo, blk.b_hi)) if v_ == 2 else None
+                if not ar or (br is not None and (not br or br[-1] <= ar[0])):
+                    assert partials[b] == 0.0
+                    continue
+                vsets = [(holes, ar, br)]
+            else:
+                hole_sets = list(combinations(range(pb.n_c), h_))
+                nv = pb.n_v if v_ == 1 else 1
+                groups = {}
+                for r in range(blk.row_lo, blk.row_hi):
+                    groups.setdefault(r // nv, []).append(r % nv)
+                vsets = [(hole_sets[hi], sorted(a) if v_ == 1 else [], None) for hi, a in groups.items()]
+            print("[gpu] %s class %s block %d" % (name, cl, b), flush=True)
+            want = oracle_block_sum(pb, lambda idx: h_cpu[np.ix_(idx, idx)], cl, c, ref["E0_minus_Ecore"],
+                                    None, vsets, s_sel)
+            got = partials[b] / norm
+            assert abs(got - want) <= 1e-10 + 1e-9 * abs(want), (name, cl, int(b), got, want)
+            done += 1
+            checked += 1
+            if done >= per_class:
+                break
+    assert checked >= 6
