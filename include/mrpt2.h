@@ -150,6 +150,23 @@ mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in,
                           const void* persistent, void* workspace, size_t workspace_bytes,
                           hipStream_t stream, double* e2, double* parts);
 
+/* mrpt2_energy without its final synchronisation: every step (a small
+ * host-to-device copy of the instance descriptors from library-owned pinned
+ * memory, then one batched launch per stage covering all instances) is
+ * enqueued on `stream`, so the call can be captured into a HIP graph and
+ * replayed.  Replays reuse the descriptors of the captured call (same input
+ * and output pointers).  The device error flag stays in the workspace; read
+ * it with mrpt2_check.  Two asynchronous calls with different inputs on one
+ * plan must be separated by a stream synchronisation (they share the pinned
+ * descriptor buffer). */
+mrpt2_status mrpt2_energy_async(mrpt2_plan_t plan, const mrpt2_inputs* in,
+                                const void* persistent, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream, double* e2, double* parts);
+
+/* Synchronise `stream` and report the error flag of the last evaluation on
+ * this workspace: MRPT2_OK or MRPT2_ERR_NUMERIC. */
+mrpt2_status mrpt2_check(mrpt2_plan_t plan, const void* workspace, hipStream_t stream);
+
 /* mrpt2_energy with its stages timed by HIP events recorded on `stream`.
  * stage_ms (host float[23], milliseconds summed over instances):
  * [0] factor tables (slabs, pair energies, orbital energies, core Fock),

@@ -154,6 +154,23 @@ class Engine:
         del keep
         return (self.e2, self.parts) if parts else self.e2
 
+    def energy_async(self, insts, stream=None):
+        """Enqueue an evaluation without synchronising (capturable in a HIP
+        graph).  The input tensors must stay alive until it has run; call
+        check() to read the error flag."""
+        arr, keep = self._inputs(insts)
+        s = ctypes.c_void_p((stream or self.stream).cuda_stream)
+        code = capi.lib().mrpt2_energy_async(self.plan.handle, arr, self.persistent.data_ptr(),
+                                             self.workspace.data_ptr(), self.plan.workspace_bytes, s,
+                                             self.e2.data_ptr(), self.parts.data_ptr())
+        capi.check(code, "mrpt2_energy_async")
+        self._keep = keep
+        return self.e2, self.parts
+
+    def check(self, stream=None):
+        s = ctypes.c_void_p((stream or self.stream).cuda_stream)
+        capi.check(capi.lib().mrpt2_check(self.plan.handle, self.workspace.data_ptr(), s), "mrpt2_check")
+
     def energy_timed(self, insts):
         """energy() with per-stage milliseconds (dict over capi.STAGES)."""
         arr, keep = self._inputs(insts)

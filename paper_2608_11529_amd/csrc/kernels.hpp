@@ -33,6 +33,13 @@ __device__ __forceinline__ double rcp_nr(double d) {
 }
 
 // ---- per-instance device view -------------------------------------------------
+struct SetPtrs {
+  const double2* B[4];
+  int rank[4];
+  int l0[4];
+  int n_sets;
+};
+
 struct Dev {
   int n_fc, n_c, n_a, n_v, n_o, n_occ, n_corr, n, n_l, n_p;
   int n_vt;
@@ -53,14 +60,13 @@ struct Dev {
   double2* sigp;             // [n_p]
   double* scal;              // [0] = E0 - E_core, [1] = ||C||^2
   double* dsum;              // [n_l]
+  // inputs and outputs of the current call
+  const double2* h;          // [n][n]
   const double2* c;          // [n_p]
-};
-
-struct SetPtrs {
-  const double2* B[4];
-  int rank[4];
-  int l0[4];
-  int n_sets;
+  SetPtrs sets;              // factor sets
+  double* out_parts;         // [12] or null
+  double* out_e2;            // [1]
+  double2* out_hpp;          // reference-Hamiltonian output (or null)
 };
 
 struct Pattern;
@@ -77,15 +83,41 @@ struct ClassDev {
   double* Uv;    // [S][n_v]
   double2* X;    // [n_pat][n_rows] (v < 2)
   double* part;  // partial sums
+  int64_t n_part;  // partial sums written by the class's kernel
   int nsc;       // string chunks
   double2* D;    // [S][n_pat] dense coefficients (classes with few patterns)
   uint32_t* mask;  // [S] nonzero patterns per string
 };
 
-struct PartList {
-  const double* p[9];
-  int64_t n[9];
+// Everything a kernel needs about one instance (uploaded once per call).
+// Descriptors sit kInstStride bytes apart in device memory.
+struct Inst {
+  Dev d;
+  ClassDev cls[9];
 };
+constexpr size_t kInstStride = 4096;
+
+__device__ __forceinline__ const Inst& inst_at(const Inst* base, int i) {
+  return *reinterpret_cast<const Inst*>(reinterpret_cast<const char*>(base) + (size_t)i * kInstStride);
+}
+
+// One instance's share of a batched launch: its grid (gx x gy blocks) starts
+// at flat block blk0 of the launch; arg is kernel specific (factor set).
+struct Job {
+  int32_t inst, gx, gy, arg;
+  int64_t blk0;
+};
+
+// Job of flat block b: the last job whose first block is <= b.
+__device__ __forceinline__ int find_job(const Job* __restrict__ jobs, int n, int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ int64_t occ_pair(int x, int y, int n_o) {  // x < y
   return (int64_t)x * n_o - (int64_t)x * (x + 1) / 2 + (y - x - 1);

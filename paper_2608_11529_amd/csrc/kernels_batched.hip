@@ -1,0 +1,105 @@
+// Batched launch wrappers: one launch covers every instance of a plan.  Each
+// flat block finds its job (instance, grid, argument) in the plan's job
+// table, rebuilds its block coordinates within that instance's grid, and runs
+// the kernel body on the instance's descriptor.
+#include "kernels.hpp"
+
+namespace mrpt2 {
+
+#define MRPT2_JOB                                                                              \
+  const int job_ = find_job(jobs, njobs, (int64_t)blockIdx.x);                                 \
+  const Job jb = jobs[job_];                                                                   \
+  const int64_t lb_ = (int64_t)blockIdx.x - jb.blk0;                                           \
+  const uint3 bid = make_uint3((uint32_t)(lb_ % jb.gx), (uint32_t)(lb_ / jb.gx), 0u);         \
+  const Inst& I = inst_at(insts, jb.inst);
+
+#define MRPT2_ARGS const Inst* __restrict__ insts, const Job* __restrict__ jobs, int njobs, int* flag, int karg
+
+__global__ void __launch_bounds__(256) k_b_pack(MRPT2_ARGS) {
+  MRPT2_JOB
+  pack_body(I.d, jb.arg, bid);
+}
+__global__ void __launch_bounds__(256) k_b_diag(MRPT2_ARGS) {
+  MRPT2_JOB
+  diag_body(I.d, jb.arg, bid);
+}
+__global__ void __launch_bounds__(256) k_b_wpass(MRPT2_ARGS) {
+  MRPT2_JOB
+  wpass_body(I.d, flag, bid);
+}
+__global__ void __launch_bounds__(256) k_b_eps(MRPT2_ARGS) {
+  MRPT2_JOB
+  eps_body(I.d, flag, bid);
+}
+__global__ void __launch_bounds__(256) k_b_dsum(MRPT2_ARGS) {
+  MRPT2_JOB
+  dsum_body(I.d, bid);
+}
+__global__ void __launch_bounds__(64) k_b_fock(MRPT2_ARGS) {
+  MRPT2_JOB
+  fock_body(I.d, bid);
+}
+__global__ void __launch_bounds__(256) k_b_gbuild(MRPT2_ARGS) {
+  MRPT2_JOB
+  gbuild_body(I.d, bid);
+}
+__global__ void __launch_bounds__(256) k_b_hpp(MRPT2_ARGS) {
+  MRPT2_JOB
+  hpp_body(I.d, karg ? I.d.out_hpp : I.d.hpp, bid);
+}
+__global__ void __launch_bounds__(64) k_b_sigp(MRPT2_ARGS) {
+  MRPT2_JOB
+  sigp_body(I.d, bid);
+}
+__global__ void __launch_bounds__(256) k_b_e0(MRPT2_ARGS) {
+  MRPT2_JOB
+  (void)bid;
+  e0_body(I.d, flag);
+}
+__global__ void __launch_bounds__(256) k_b_abuild(MRPT2_ARGS) {
+  MRPT2_JOB
+  abuild_body(I.d, bid);
+}
+__global__ void __launch_bounds__(256) k_b_abuild_f32(MRPT2_ARGS) {
+  MRPT2_JOB
+  abuild_f32_body(I.d, bid);
+}
+__global__ void __launch_bounds__(256) k_b_class_tables(MRPT2_ARGS) {
+  MRPT2_JOB
+  class_tables_body(I.d, I.cls[jb.arg], bid);
+}
+__global__ void __launch_bounds__(256) k_b_xbuild(MRPT2_ARGS) {
+  MRPT2_JOB
+  xbuild_body(I.d, I.cls[jb.arg], bid);
+}
+__global__ void __launch_bounds__(256) k_b_dense_coef(MRPT2_ARGS) {
+  MRPT2_JOB
+  dense_coef_body(I.d, I.cls[jb.arg], bid);
+}
+__global__ void __launch_bounds__(256) k_b_e22(MRPT2_ARGS) {
+  MRPT2_JOB
+  e22_body(I.d, I.cls[0], flag, bid);
+}
+template <int MJ>
+__global__ void __launch_bounds__(256) k_b_e12(MRPT2_ARGS) {
+  MRPT2_JOB
+  e12_body<MJ>(I.d, I.cls[1], flag, bid);
+}
+__global__ void __launch_bounds__(256) k_b_e02(MRPT2_ARGS) {
+  MRPT2_JOB
+  e02_body(I.d, I.cls[2], flag, bid);
+}
+template <int H, int V, int K>
+__global__ void __launch_bounds__(SIG_THREADS) k_b_sigma(MRPT2_ARGS) {
+  MRPT2_JOB
+  sigma_body<H, V>(I.d, I.cls[K], flag, bid);
+}
+__global__ void __launch_bounds__(256) k_b_finish(MRPT2_ARGS) {
+  MRPT2_JOB
+  (void)bid;
+  finish_body(I.d, I.cls);
+}
+
+#undef MRPT2_JOB
+
+}  // namespace mrpt2

@@ -34,9 +34,9 @@ __device__ double act_energy(const Dev& d, uint64_t al) {
 // Slater-Condon rules within the active space (core and frozen core folded
 // into f).  Row i = bra, column j = ket.  grid (ceil(np/16), ceil(np/16)),
 // block (16, 16).
-__global__ void __launch_bounds__(256) k_hpp(Dev d, double2* __restrict__ out) {
-  const int j = blockIdx.x * 16 + threadIdx.x;
-  const int i = blockIdx.y * 16 + threadIdx.y;
+__device__ __forceinline__ void hpp_body(const Dev& d, double2* __restrict__ out, const uint3 bid) {
+  const int j = bid.x * 16 + (threadIdx.x & 15);
+  const int i = bid.y * 16 + (threadIdx.x >> 4);
   if (i >= d.n_p || j >= d.n_p) return;
   const uint64_t bi = d.pstrings[i], bj = d.pstrings[j];
   const uint64_t cre = bi & ~bj, ann = bj & ~bi;
@@ -78,8 +78,9 @@ __global__ void __launch_bounds__(256) k_hpp(Dev d, double2* __restrict__ out) {
 }
 
 // sigma_P = H~ C, one wavefront per row.  grid (np), block 64.
-__global__ void __launch_bounds__(64) k_sigp(Dev d, const double2* __restrict__ hpp) {
-  const int i = blockIdx.x;
+__device__ __forceinline__ void sigp_body(const Dev& d, const uint3 bid) {
+  const double2* __restrict__ hpp = d.hpp;
+  const int i = bid.x;
   const int lane = threadIdx.x;
   double2 acc = make_double2(0.0, 0.0);
   for (int j = lane; j < d.n_p; j += 64) acc = cfma(hpp[(int64_t)i * d.n_p + j], d.c[j], acc);
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(64) k_sigp(Dev d, const double2* __restrict__ 
 }
 
 // E0 - E_core = Re(C^H H~ C) / C^H C and ||C||^2.  One block, fixed order.
-__global__ void __launch_bounds__(256) k_e0(Dev d, int* flag) {
+__device__ __forceinline__ void e0_body(const Dev& d, int* flag) {
   __shared__ double sn[256], sd[256];
   double num = 0.0, den = 0.0;
   for (int i = threadIdx.x; i < d.n_p; i += 256) {
@@ -119,11 +120,11 @@ __global__ void __launch_bounds__(256) k_e0(Dev d, int* flag) {
 
 // T[s] = (E0 - E_core) - E_act(alpha_s); Uc[s][c] = sum_{t in alpha_s} W_ct;
 // Uv[s][a] = sum_{t in alpha_s} W_at.  grid (S, ceil(max(n_c, n_v)/256)).
-__global__ void __launch_bounds__(256) k_class_tables(Dev d, ClassDev cd) {
-  const int64_t s = blockIdx.x;
+__device__ __forceinline__ void class_tables_body(const Dev& d, const ClassDev& cd, const uint3 bid) {
+  const int64_t s = bid.x;
   const uint64_t al = cd.strings[s];
-  const int p = blockIdx.y * 256 + threadIdx.x;
-  if (blockIdx.y == 0 && threadIdx.x == 0) cd.T[s] = d.scal[0] - act_energy(d, al);
+  const int p = bid.y * 256 + threadIdx.x;
+  if (bid.y == 0 && threadIdx.x == 0) cd.T[s] = d.scal[0] - act_energy(d, al);
   const int ga = d.n_fc + d.n_c;   // first active global index
   if (cd.h > 0 && p < d.n_c) {
     double u = 0.0;
@@ -172,9 +173,9 @@ __device__ __forceinline__ void decode_small_row(const Dev& d, const ClassDev& c
 // (active first, virtual last); rank-1 K = a+_p a_q L gives f_pq (one-body
 // pattern) or (pq|ww) - (pw|wq) (spectator w).  G(x;p;y;q) = (px|qy).
 // grid (ceil(rows/256), n_pat).
-__global__ void __launch_bounds__(256) k_xbuild(Dev d, ClassDev cd) {
-  const int64_t r = blockIdx.x * 256ll + threadIdx.x;
-  const int j = blockIdx.y;
+__device__ __forceinline__ void xbuild_body(const Dev& d, const ClassDev& cd, const uint3 bid) {
+  const int64_t r = bid.x * 256ll + threadIdx.x;
+  const int j = bid.y;
   if (r >= cd.n_rows) return;
   int c0, c1, a;
   decode_small_row(d, cd, r, &c0, &c1, &a);
@@ -216,10 +217,10 @@ constexpr int SIG_THREADS = 256;
 //   partial += |sigma|^2 / Delta   (divided by ||C||^2 at the end)
 // One thread per row, a chunk of strings per block.  grid (rb * nsc).
 template <int H, int V>
-__global__ void __launch_bounds__(SIG_THREADS) k_sigma(Dev d, ClassDev cd, int* flag) {
+__device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double red[SIG_THREADS];
-  const int64_t rb = blockIdx.x / cd.nsc;
-  const int sc = blockIdx.x % cd.nsc;
+  const int64_t rb = bid.x / cd.nsc;
+  const int sc = bid.x % cd.nsc;
   const int64_t chunk = (cd.n_str + cd.nsc - 1) / cd.nsc;
   const int64_t s_lo = sc * chunk;
   const int64_t s_hi = min(cd.n_str, s_lo + chunk);
@@ -308,18 +309,9 @@ __global__ void __launch_bounds__(SIG_THREADS) k_sigma(Dev d, ClassDev cd, int* 
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) cd.part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) cd.part[bid.x] = red[0];
 }
 
-template __global__ void k_sigma<2, 2>(Dev, ClassDev, int*);
-template __global__ void k_sigma<1, 2>(Dev, ClassDev, int*);
-template __global__ void k_sigma<0, 2>(Dev, ClassDev, int*);
-template __global__ void k_sigma<2, 1>(Dev, ClassDev, int*);
-template __global__ void k_sigma<1, 1>(Dev, ClassDev, int*);
-template __global__ void k_sigma<0, 1>(Dev, ClassDev, int*);
-template __global__ void k_sigma<2, 0>(Dev, ClassDev, int*);
-template __global__ void k_sigma<1, 0>(Dev, ClassDev, int*);
-template __global__ void k_sigma<0, 0>(Dev, ClassDev, int*);
 
 // Class (2,2): K = core - {c, c'} + alpha + {a, b}, alpha in P.  Its only
 // connected reference determinant is core + alpha, so
@@ -336,14 +328,14 @@ template __global__ void k_sigma<0, 0>(Dev, ClassDev, int*);
 // grid (n_tp, C(n_c, 2)), block 256.
 constexpr int AC22 = 32;
 
-__global__ void __launch_bounds__(256) k_e22(Dev d, ClassDev cd, int* flag) {
+__device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sYa[AC22][64];
   __shared__ double sYb[AC22][64];
   __shared__ double sG[AC22];
   __shared__ double sCw[AC22];
   __shared__ double ya0[64], yb0[64];
   __shared__ double red[256];
-  const int tp = blockIdx.x, hp = blockIdx.y;
+  const int tp = bid.x, hp = bid.y;
   const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
   const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
   const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
@@ -458,8 +450,8 @@ __global__ void __launch_bounds__(256) k_e22(Dev d, ClassDev cd, int* flag) {
 // Dense coefficients of a class with few patterns: D[s][j] = sum of sign C_beta
 // over the excitation list of string s with pattern j, and the bit mask of the
 // patterns present.  grid (ceil(S / 256)).
-__global__ void __launch_bounds__(256) k_dense_coef(Dev d, ClassDev cd) {
-  const int64_t s = blockIdx.x * 256ll + threadIdx.x;
+__device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd, const uint3 bid) {
+  const int64_t s = bid.x * 256ll + threadIdx.x;
   if (s >= cd.n_str) return;
   const int J = cd.n_pat;
   double2* row = cd.D + s * J;
@@ -488,19 +480,19 @@ __global__ void __launch_bounds__(256) k_dense_coef(Dev d, ClassDev cd) {
 constexpr int SC12 = 32;
 
 template <int MJ>
-__global__ void __launch_bounds__(256) k_e12(Dev d, ClassDev cd, int* flag) {
+__device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sUa[SC12][16];
   __shared__ double sUb[SC12][16];
   __shared__ double sG[SC12];
   __shared__ double2 sD[SC12][MJ];
   __shared__ uint32_t sM[SC12];
   __shared__ double red[256];
-  const int tp = blockIdx.x >> 4, sub = blockIdx.x & 15;
+  const int tp = bid.x >> 4, sub = bid.x & 15;
   const int sa = sub >> 2, sb = sub & 3;
-  const int c = blockIdx.y;
+  const int c = bid.y;
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
   if (I == Jt && sa > sb) {                    // block entirely below the diagonal
-    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + blockIdx.x] = 0.0;
+    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + bid.x] = 0.0;
     return;
   }
   const int tid = threadIdx.x;
@@ -584,13 +576,9 @@ __global__ void __launch_bounds__(256) k_e12(Dev d, ClassDev cd, int* flag) {
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + blockIdx.x] = red[0];
+  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + bid.x] = red[0];
 }
 
-template __global__ void k_e12<8>(Dev, ClassDev, int*);
-template __global__ void k_e12<16>(Dev, ClassDev, int*);
-template __global__ void k_e12<24>(Dev, ClassDev, int*);
-template __global__ void k_e12<32>(Dev, ClassDev, int*);
 
 // Class (0,2): K = core + alpha'' + {a, b}, reached from
 // L = core + alpha'' + {t, w} by a_t a_w -> a+_b a+_a:
@@ -599,18 +587,18 @@ template __global__ void k_e12<32>(Dev, ClassDev, int*);
 // 32 rows (fixed a, 32 consecutive b) per block with the couplings of every
 // pattern staged in LDS; eight interleaved string streams per block walk the
 // excitation lists.  grid (128 n_tp), block 256, dynamic LDS n_pat * 512 B.
-__global__ void __launch_bounds__(256) k_e02(Dev d, ClassDev cd, int* flag) {
+__device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   extern __shared__ double2 sX[];
   __shared__ double red[256];
-  const int64_t bid = blockIdx.x;
-  const int64_t tp = bid >> 7;
-  const int la = (int)((bid >> 1) & 63), half = (int)(bid & 1);
+  const int64_t blk = bid.x;
+  const int64_t tp = blk >> 7;
+  const int la = (int)((blk >> 1) & 63), half = (int)(blk & 1);
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
   const int nv = d.n_v, nc = d.n_c;
   const int a0 = I * 64 + la;
   const int bmax = Jt * 64 + half * 32 + 31;
   if (a0 >= nv || a0 >= bmax) {               // no valid (a, b) in this block
-    if (threadIdx.x == 0) cd.part[bid] = 0.0;
+    if (threadIdx.x == 0) cd.part[blk] = 0.0;
     return;
   }
   const int tid = threadIdx.x, rl = tid & 31, sgp = tid >> 5;
@@ -654,19 +642,22 @@ __global__ void __launch_bounds__(256) k_e02(Dev d, ClassDev cd, int* flag) {
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (tid == 0) cd.part[bid] = red[0];
+  if (tid == 0) cd.part[blk] = red[0];
 }
 
 // Per-class sum of partials (Neumaier-compensated, fixed order) divided by
 // ||C||^2; out[k] for k < 9, out[9] = E2, out[10] = E0 - E_core,
 // out[11] = ||C||^2; e2 receives E2.  One block.
-__global__ void __launch_bounds__(256) k_finish(Dev d, PartList pl, double* out, double* e2) {
+__device__ __forceinline__ void finish_body(const Dev& d, const ClassDev* cds) {
   __shared__ double ss[256], sc[256];
   __shared__ double cls[MRPT2_N_CLASS];
+  double* out = d.out_parts;
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
     double s = 0.0, comp = 0.0;
-    for (int64_t i = threadIdx.x; i < pl.n[k]; i += 256) {
-      const double x = pl.p[k][i];
+    const int64_t nk = cds[k].n_part;
+    const double* pk = cds[k].part;
+    for (int64_t i = threadIdx.x; i < nk; i += 256) {
+      const double x = pk[i];
       const double t = s + x;
       comp += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
       s = t;
@@ -702,7 +693,7 @@ __global__ void __launch_bounds__(256) k_finish(Dev d, PartList pl, double* out,
       out[10] = d.scal[0];
       out[11] = d.scal[1];
     }
-    *e2 = tot;
+    *d.out_e2 = tot;
   }
 }
 

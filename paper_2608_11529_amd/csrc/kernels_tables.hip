@@ -7,11 +7,13 @@ namespace mrpt2 {
 // Slab of the factor columns of every occupied-type spinor x (frozen core,
 // core, active): slab[x][pc][L] = sqrt|w| B[L][n_fc + pc][x], and the scaled
 // diagonals dg[L][p] = sqrt|w| Re B[L][p][p].
-// grid (ceil(rank/64), n_corr), block 256.
-__global__ void __launch_bounds__(256) k_pack(Dev d, const double2* __restrict__ B, int l0, int rank) {
+// Grid (ceil(rank/64), n_corr) per factor set, block 256.
+__device__ __forceinline__ void pack_body(const Dev& d, int t, const uint3 bid) {
+  const double2* __restrict__ B = d.sets.B[t];
+  const int l0 = d.sets.l0[t], rank = d.sets.rank[t];
   __shared__ double2 tile[64][17];
-  const int pc = blockIdx.y;
-  const int Lb = blockIdx.x * 64;
+  const int pc = bid.y;
+  const int Lb = bid.x * 64;
   const int row = d.n_fc + pc;
   for (int x0 = 0; x0 < d.n_occ; x0 += 16) {
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
@@ -36,9 +38,11 @@ __global__ void __launch_bounds__(256) k_pack(Dev d, const double2* __restrict__
 }
 
 // grid (ceil(n/256), rank)
-__global__ void __launch_bounds__(256) k_diag(Dev d, const double2* __restrict__ B, int l0, int rank) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  const int L = blockIdx.y;
+__device__ __forceinline__ void diag_body(const Dev& d, int t, const uint3 bid) {
+  const double2* __restrict__ B = d.sets.B[t];
+  const int l0 = d.sets.l0[t], rank = d.sets.rank[t];
+  const int p = bid.x * 256 + threadIdx.x;
+  const int L = bid.y;
   if (p >= d.n || L >= rank) return;
   d.dg[(int64_t)(l0 + L) * d.n + p] = d.scale[l0 + L] * B[((int64_t)L * d.n + p) * d.n + p].x;
 }
@@ -46,9 +50,10 @@ __global__ void __launch_bounds__(256) k_diag(Dev d, const double2* __restrict__
 // Pair energies W_pq = (pp|qq) - (pq|qp) over all spinors, streaming every
 // factor once: (pq|qp) = sum_L w_L |B_pq|^2 for Hermitian B.
 // grid (ceil(n/256), n), block 256.  Sets flag on non-finite results.
-__global__ void __launch_bounds__(256) k_wpass(Dev d, SetPtrs sp, int* flag) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  const int p = blockIdx.y;
+__device__ __forceinline__ void wpass_body(const Dev& d, int* flag, const uint3 bid) {
+  const SetPtrs& sp = d.sets;
+  const int q = bid.x * 256 + threadIdx.x;
+  const int p = bid.y;
   if (q >= d.n) return;
   double coul = 0.0, exch = 0.0;
   for (int t = 0; t < sp.n_sets; ++t) {
@@ -87,8 +92,9 @@ __global__ void __launch_bounds__(256) k_wpass(Dev d, SetPtrs sp, int* flag) {
 
 // Orbital energies in the field of the frozen and correlated core:
 // eps_p = h_pp + sum_{j in core, j != p} W_pj (frozen core included).
-__global__ void __launch_bounds__(256) k_eps(Dev d, const double2* __restrict__ h, int* flag) {
-  const int pc = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void eps_body(const Dev& d, int* flag, const uint3 bid) {
+  const double2* __restrict__ h = d.h;
+  const int pc = bid.x * 256 + threadIdx.x;
   if (pc >= d.n_corr) return;
   const int g = d.n_fc + pc;
   double e = h[(int64_t)g * d.n + g].x;
@@ -99,8 +105,8 @@ __global__ void __launch_bounds__(256) k_eps(Dev d, const double2* __restrict__ 
 }
 
 // dsum[L] = sum over frozen and correlated core j of dg[L][j].
-__global__ void __launch_bounds__(256) k_dsum(Dev d) {
-  const int L = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void dsum_body(const Dev& d, const uint3 bid) {
+  const int L = bid.x * 256 + threadIdx.x;
   if (L >= d.n_l) return;
   double s = 0.0;
   for (int j = 0; j < d.n_fc + d.n_c; ++j) s += d.dg[(int64_t)L * d.n + j];
@@ -110,9 +116,10 @@ __global__ void __launch_bounds__(256) k_dsum(Dev d) {
 // Core Fock matrix f_pq = h_pq + sum_{j in core} [(pq|jj) - (pj|jq)] for p
 // active or virtual and q core or active (frozen-core fold of Sec. 2 plus the
 // correlated core).  grid (n_o, n_a + n_v), one wavefront per entry.
-__global__ void __launch_bounds__(64) k_fock(Dev d, const double2* __restrict__ h) {
-  const int qo = blockIdx.x;
-  const int pr = blockIdx.y;
+__device__ __forceinline__ void fock_body(const Dev& d, const uint3 bid) {
+  const double2* __restrict__ h = d.h;
+  const int qo = bid.x;
+  const int pr = bid.y;
   const int lane = threadIdx.x;
   const int pcorr = d.n_c + pr;
   double2 acc = make_double2(0.0, 0.0);
@@ -216,11 +223,11 @@ __device__ __forceinline__ int acc_col(int j) {
 //   = sum_L w_L (B_ax B_by - B_ay B_bx),
 // one 64 x 64 tile (I, J), I <= J, of virtual pairs per block, K = 2 n_l.
 // grid (n_tp, n_pairs), block 256.
-__global__ void __launch_bounds__(256) k_abuild(Dev d) {
+__device__ __forceinline__ void abuild_body(const Dev& d, const uint3 bid) {
   __shared__ double2 sA[64 * KP];
   __shared__ double2 sB[64 * KP];
-  const int64_t tp = blockIdx.x;
-  int64_t pr = blockIdx.y;
+  const int64_t tp = bid.x;
+  int64_t pr = bid.y;
   int xo = 0;
   while (pr >= d.n_o - 1 - xo) {
     pr -= d.n_o - 1 - xo;
@@ -249,7 +256,7 @@ __global__ void __launch_bounds__(256) k_abuild(Dev d) {
   };
   d4 accR[2][2], accI[2][2];
   cgemm64(fa, fb, 2 * nl, sA, sB, accR, accI);
-  double2* out = d.A + ((int64_t)blockIdx.y * d.n_tp + tp) * 4096;
+  double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -346,11 +353,11 @@ __device__ __forceinline__ int acc_row_f32(int i, int r) {
 }
 
 // Mixed-precision form of k_abuild (same operands, same output layout).
-__global__ void __launch_bounds__(256) k_abuild_f32(Dev d) {
+__device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {
   __shared__ float2 sA[64 * KP32];
   __shared__ float2 sB[64 * KP32];
-  const int64_t tp = blockIdx.x;
-  int64_t pr = blockIdx.y;
+  const int64_t tp = bid.x;
+  int64_t pr = bid.y;
   int xo = 0;
   while (pr >= d.n_o - 1 - xo) {
     pr -= d.n_o - 1 - xo;
@@ -379,7 +386,7 @@ __global__ void __launch_bounds__(256) k_abuild_f32(Dev d) {
   };
   double accR[2][2][4], accI[2][2][4];
   cgemm64_f32(fa, fb, 2 * nl, sA, sB, accR, accI);
-  double2* out = d.A + ((int64_t)blockIdx.y * d.n_tp + tp) * 4096;
+  double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -393,13 +400,13 @@ __global__ void __launch_bounds__(256) k_abuild_f32(Dev d) {
 // occupied ones: G[x][p][y][q] = (px|qy), x, y core or active, p active or
 // virtual, q active.  One GEMM: rows (x, p), columns (y, q), K = n_l.
 // grid (ceil(N/64), ceil(M/64)), block 256.
-__global__ void __launch_bounds__(256) k_gbuild(Dev d) {
+__device__ __forceinline__ void gbuild_body(const Dev& d, const uint3 bid) {
   __shared__ double2 sA[64 * KP];
   __shared__ double2 sB[64 * KP];
   const int npr = d.n_a + d.n_v;
   const int64_t M = (int64_t)d.n_o * npr;
   const int64_t N = (int64_t)d.n_o * d.n_a;
-  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int64_t m0 = (int64_t)bid.y * 64, n0 = (int64_t)bid.x * 64;
   const int nl = d.n_l;
   const double* sg = d.sign;
   auto fa = [&](int r, int k) -> double2 {

@@ -1,6 +1,8 @@
 // C interface: plan management and the launch sequence of one energy
 // evaluation (tables -> reference energy -> integral builds -> per-class
-// sigma contraction with the Epstein-Nesbet epilogue -> reductions).
+// sigma contraction with the Epstein-Nesbet epilogue -> reductions).  Every
+// launch covers all instances of the plan (batched form); the sequence is
+// fixed by the plan, so it can be captured into a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -13,12 +15,17 @@
 
 #include "kernels_tables.hip"
 #include "kernels_energy.hip"
+#include "kernels_batched.hip"
 
 struct mrpt2_plan_s {
   mrpt2::Plan p;
 };
 
 using namespace mrpt2;
+
+static_assert(sizeof(Inst) <= kInstBytes, "instance descriptor exceeds its reserved bytes");
+static_assert(kInstStride == kInstBytes, "host and device descriptor strides differ");
+static_assert(sizeof(Job) == sizeof(JobH), "job layout differs between host and device");
 
 namespace {
 
@@ -62,7 +69,16 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.sigp = (double2*)(W + ip.off_sigp);
   d.scal = (double*)(W + ip.off_scal);
   d.dsum = (double*)(W + ip.off_dsum);
-  d.c = in ? (const double2*)in->c : nullptr;
+  d.h = (const double2*)in->h;
+  d.c = (const double2*)in->c;
+  int l0 = 0;
+  d.sets.n_sets = ip.d.n_sets;
+  for (int t = 0; t < ip.d.n_sets; ++t) {
+    d.sets.B[t] = (const double2*)in->B[t];
+    d.sets.rank[t] = ip.d.rank[t];
+    d.sets.l0[t] = l0;
+    l0 += ip.d.rank[t];
+  }
   return d;
 }
 
@@ -88,74 +104,29 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.D = (double2*)(W + cp.off_D);
   c.mask = (uint32_t*)(W + cp.off_mask);
   c.part = (double*)(W + ip.off_part_class[k]);
+  c.n_part = (cp.strings.empty() || cp.n_rows == 0) ? 0 : cp.n_blocks;
   const int64_t rb = cdiv(cp.n_rows, 256);
   c.nsc = rb > 0 ? (int)(sigma_blocks(ip, k) / rb) : 1;
   return c;
 }
 
-// Steps shared by the energy and the reference Hamiltonian: factor slabs,
-// pair energies, orbital energies, core Fock matrix, occupied integrals.
-// Timing slots of mrpt2_energy_timed (milliseconds, summed over instances).
-enum {
-  ST_TABLES = 0, ST_GBUILD = 1, ST_REF = 2, ST_ABUILD = 3, ST_SIGMA0 = 4,       // 4..12 sigma per class
-  ST_PREP0 = 13,                                                               // 13..21 class tables + couplings
-  ST_FINISH = 22, ST_N = 23
-};
-
 struct Timer {
-  hipEvent_t ev[2 * ST_N * 8];
-  int slot[ST_N * 8];
+  hipEvent_t ev[2 * 128];
+  int slot[128];
   int n = 0;
   bool on = false;
-  hipStream_t st;
-  int open_slot = -1;
+  hipStream_t st = nullptr;
   void begin(int s) {
-    if (!on || n >= ST_N * 8) return;
+    if (!on || s < 0 || n >= 128) return;
     slot[n] = s;
     hipEventRecord(ev[2 * n], st);
-    open_slot = n;
   }
-  void end() {
-    if (!on || open_slot < 0) return;
-    hipEventRecord(ev[2 * open_slot + 1], st);
+  void end(int s) {
+    if (!on || s < 0 || n >= 128) return;
+    hipEventRecord(ev[2 * n + 1], st);
     ++n;
-    open_slot = -1;
   }
 };
-
-mrpt2_status tables(const InstancePlan& ip, const mrpt2_inputs* in, Dev& d, hipStream_t st, int* flag,
-                    Timer* tm) {
-  SetPtrs sp{};
-  sp.n_sets = ip.d.n_sets;
-  int l0 = 0;
-  for (int t = 0; t < ip.d.n_sets; ++t) {
-    const int rank = ip.d.rank[t];
-    const double2* B = (const double2*)in->B[t];
-    if (rank > 0 && !B) return MRPT2_ERR_ARG;
-    sp.B[t] = B;
-    sp.rank[t] = rank;
-    sp.l0[t] = l0;
-    if (rank > 0) {
-      hipLaunchKernelGGL(k_pack, dim3(cdiv(rank, 64), ip.n_corr), dim3(256), 0, st, d, B, l0, rank);
-      hipLaunchKernelGGL(k_diag, dim3(cdiv(ip.n, 256), rank), dim3(256), 0, st, d, B, l0, rank);
-    }
-    l0 += rank;
-  }
-  hipLaunchKernelGGL(k_wpass, dim3(cdiv(ip.n, 256), ip.n), dim3(256), 0, st, d, sp, flag);
-  hipLaunchKernelGGL(k_eps, dim3(cdiv(ip.n_corr, 256)), dim3(256), 0, st, d, (const double2*)in->h, flag);
-  hipLaunchKernelGGL(k_dsum, dim3(cdiv(ip.n_l, 256)), dim3(256), 0, st, d);
-  if (ip.n_o > 0 && ip.n_a + ip.n_v > 0)
-    hipLaunchKernelGGL(k_fock, dim3(ip.n_o, ip.n_a + ip.n_v), dim3(64), 0, st, d, (const double2*)in->h);
-  tm->end();
-  tm->begin(ST_GBUILD);
-  if (ip.n_a > 0) {
-    const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
-    hipLaunchKernelGGL(k_gbuild, dim3(cdiv(N, 64), cdiv(M, 64)), dim3(256), 0, st, d);
-  }
-  tm->end();
-  HIPCHK(hipGetLastError());
-  return MRPT2_OK;
-}
 
 mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t wbytes) {
   if (!pers || !work) return MRPT2_ERR_ARG;
@@ -164,105 +135,104 @@ mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t w
   return MRPT2_OK;
 }
 
-mrpt2_status run_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
-                        size_t workspace_bytes, hipStream_t st, double* e2, double* parts, Timer& tm) {
-  if (!plan || !in || !e2) return MRPT2_ERR_ARG;
-  const Plan& P = plan->p;
-  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
-  if (s != MRPT2_OK) return s;
-  const char* pers = (const char*)persistent;
-  char* work = (char*)workspace;
+// Fill the instance descriptors in pinned host memory and copy them to the
+// workspace (asynchronously, on stream).
+mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, char* work, hipStream_t st,
+                          double* e2, double* parts, double* hpp_out, int only) {
+  const size_t bytes = kInstBytes * P.inst.size();
+  if (!P.pinned) HIPCHK(hipHostMalloc(&P.pinned, bytes, hipHostMallocDefault));
+  std::memset(P.pinned, 0, bytes);
+  for (size_t i = 0; i < P.inst.size(); ++i) {
+    if (only >= 0 && (int)i != only) continue;
+    const mrpt2_inputs* ini = in + (only >= 0 ? 0 : i);
+    const InstancePlan& ip = P.inst[i];
+    if (!ini->h || (only < 0 && !ini->c)) return MRPT2_ERR_ARG;
+    for (int t = 0; t < ip.d.n_sets; ++t)
+      if (ip.d.rank[t] > 0 && !ini->B[t]) return MRPT2_ERR_ARG;
+    Inst* I = (Inst*)((char*)P.pinned + kInstBytes * i);
+    I->d = make_dev(ip, pers, work, ini);
+    I->d.out_e2 = e2 ? e2 + i : nullptr;
+    I->d.out_parts = parts ? parts + 12 * i : nullptr;
+    I->d.out_hpp = (double2*)hpp_out;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cls[k] = make_class(ip, k, pers, work);
+  }
+  HIPCHK(hipMemcpyAsync(work + P.off_insts, P.pinned, bytes, hipMemcpyHostToDevice, st));
+  return MRPT2_OK;
+}
+
+// Enqueue a launch sequence.
+mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers, char* work, hipStream_t st,
+                 Timer& tm) {
+  const Inst* insts = (const Inst*)(work + P.off_insts);
+  const Job* jobs_all = (const Job*)(pers + P.off_jobs);
   int* flag = (int*)(work + P.off_flag);
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
-  for (size_t ii = 0; ii < P.inst.size(); ++ii) {
-    const InstancePlan& ip = P.inst[ii];
-    const mrpt2_inputs* ini = in + ii;
-    if (!ini->h || !ini->c) return MRPT2_ERR_ARG;
-    Dev d = make_dev(ip, pers, work, ini);
-    tm.begin(ST_TABLES);
-    s = tables(ip, ini, d, st, flag, &tm);
-    if (s != MRPT2_OK) return s;
-    const int np = (int)ip.pstrings.size();
-    tm.begin(ST_REF);
-    hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, d.hpp);
-    hipLaunchKernelGGL(k_sigp, dim3(np), dim3(64), 0, st, d, (const double2*)d.hpp);
-    hipLaunchKernelGGL(k_e0, dim3(1), dim3(256), 0, st, d, flag);
-    tm.end();
-    if (ip.n_v >= 2 && ip.n_pairs > 0) {
-      tm.begin(ST_ABUILD);
-      if (ip.d.precision == MRPT2_MIXED)
-        hipLaunchKernelGGL(k_abuild_f32, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
-      else
-        hipLaunchKernelGGL(k_abuild, dim3(ip.n_tp, ip.n_pairs), dim3(256), 0, st, d);
-      tm.end();
-    }
-    PartList pl{};
-    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-      const ClassPlan& cp = ip.cls[k];
-      ClassDev cd = make_class(ip, k, pers, work);
-      pl.p[k] = cd.part;
-      pl.n[k] = 0;
-      if (cp.strings.empty() || cp.n_rows == 0) continue;
-      const int mx = std::max(ip.n_c, ip.n_v);
-      tm.begin(ST_PREP0 + k);
-      hipLaunchKernelGGL(k_class_tables, dim3(cd.n_str, cdiv(std::max(mx, 1), 256)), dim3(256), 0, st, d, cd);
-      if (cp.v < 2 && cd.n_pat > 0)
-        hipLaunchKernelGGL(k_xbuild, dim3(cdiv(cp.n_rows, 256), cd.n_pat), dim3(256), 0, st, d, cd);
-      tm.end();
-      const int64_t nb = sigma_blocks(ip, k);
-      pl.n[k] = nb;
-      dim3 g(nb), b(256);
-      tm.begin(ST_SIGMA0 + k);
-      pl.n[k] = cp.n_blocks;
-      if (cp.kernel == KERN_E22) {
-        // dedicated vector kernel: one block per (virtual tile pair, core pair)
-        hipLaunchKernelGGL(k_e22, dim3(ip.n_tp, cp.n_holes), dim3(256), 0, st, d, cd, flag);
-        tm.end();
-        continue;
-      }
-      if (cp.kernel == KERN_E12) {
-        // one core hole, two virtual electrons: coefficients densified per
-        // string, couplings held in registers; one block per (tile pair, core)
-        hipLaunchKernelGGL(k_dense_coef, dim3(cdiv(cd.n_str, 256)), dim3(256), 0, st, d, cd);
-        const dim3 g12(ip.n_tp * 16, cp.n_holes);
-        if (cd.n_pat <= 8) hipLaunchKernelGGL((k_e12<8>), g12, dim3(256), 0, st, d, cd, flag);
-        else if (cd.n_pat <= 16) hipLaunchKernelGGL((k_e12<16>), g12, dim3(256), 0, st, d, cd, flag);
-        else if (cd.n_pat <= 24) hipLaunchKernelGGL((k_e12<24>), g12, dim3(256), 0, st, d, cd, flag);
-        else hipLaunchKernelGGL((k_e12<32>), g12, dim3(256), 0, st, d, cd, flag);
-        tm.end();
-        continue;
-      }
-      if (cp.kernel == KERN_E02) {
-        // no core hole, two virtual electrons: couplings of a 32-row block in LDS
-        if (hipFuncSetAttribute((const void*)k_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
+  for (const Launch& L : seq) {
+    const Job* jobs = jobs_all + L.job0;
+    const dim3 g((unsigned)L.nblocks), b256(256), b64(64);
+    const int nj = L.njobs, ka = L.arg;
+    tm.begin(L.stage);
+    switch (L.kid) {
+      case K_CLEAR: hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag); break;
+      case K_PACK: hipLaunchKernelGGL(k_b_pack, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DIAG: hipLaunchKernelGGL(k_b_diag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_WPASS: hipLaunchKernelGGL(k_b_wpass, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_EPS: hipLaunchKernelGGL(k_b_eps, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSUM: hipLaunchKernelGGL(k_b_dsum, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_FOCK: hipLaunchKernelGGL(k_b_fock, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_GBUILD: hipLaunchKernelGGL(k_b_gbuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_HPP: hipLaunchKernelGGL(k_b_hpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIGP: hipLaunchKernelGGL(k_b_sigp, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E0: hipLaunchKernelGGL(k_b_e0, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_ABUILD: hipLaunchKernelGGL(k_b_abuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_ABUILD32: hipLaunchKernelGGL(k_b_abuild_f32, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_CTAB: hipLaunchKernelGGL(k_b_class_tables, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_XBUILD: hipLaunchKernelGGL(k_b_xbuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DCOEF: hipLaunchKernelGGL(k_b_dense_coef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E22: hipLaunchKernelGGL(k_b_e22, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_8: hipLaunchKernelGGL((k_b_e12<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_16: hipLaunchKernelGGL((k_b_e12<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_24: hipLaunchKernelGGL((k_b_e12<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_32: hipLaunchKernelGGL((k_b_e12<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02:
+        if (hipFuncSetAttribute((const void*)k_b_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)kE02MaxLds) != hipSuccess)
           return MRPT2_ERR_HIP;
-        hipLaunchKernelGGL(k_e02, dim3(ip.n_tp * 128), dim3(256), (size_t)cd.n_pat * 512, st, d, cd, flag);
-        tm.end();
-        continue;
-      }
-      switch (k) {
-        case 0: hipLaunchKernelGGL((k_sigma<2, 2>), g, b, 0, st, d, cd, flag); break;
-        case 1: hipLaunchKernelGGL((k_sigma<1, 2>), g, b, 0, st, d, cd, flag); break;
-        case 2: hipLaunchKernelGGL((k_sigma<0, 2>), g, b, 0, st, d, cd, flag); break;
-        case 3: hipLaunchKernelGGL((k_sigma<2, 1>), g, b, 0, st, d, cd, flag); break;
-        case 4: hipLaunchKernelGGL((k_sigma<1, 1>), g, b, 0, st, d, cd, flag); break;
-        case 5: hipLaunchKernelGGL((k_sigma<0, 1>), g, b, 0, st, d, cd, flag); break;
-        case 6: hipLaunchKernelGGL((k_sigma<2, 0>), g, b, 0, st, d, cd, flag); break;
-        case 7: hipLaunchKernelGGL((k_sigma<1, 0>), g, b, 0, st, d, cd, flag); break;
-        default: hipLaunchKernelGGL((k_sigma<0, 0>), g, b, 0, st, d, cd, flag); break;
-      }
-      tm.end();
+        hipLaunchKernelGGL(k_b_e02, g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);
+        break;
+      case K_SIG22: hipLaunchKernelGGL((k_b_sigma<2, 2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG12: hipLaunchKernelGGL((k_b_sigma<1, 2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG02: hipLaunchKernelGGL((k_b_sigma<0, 2, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG21: hipLaunchKernelGGL((k_b_sigma<2, 1, 3>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG11: hipLaunchKernelGGL((k_b_sigma<1, 1, 4>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG01: hipLaunchKernelGGL((k_b_sigma<0, 1, 5>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG20: hipLaunchKernelGGL((k_b_sigma<2, 0, 6>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG10: hipLaunchKernelGGL((k_b_sigma<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_SIG00: hipLaunchKernelGGL((k_b_sigma<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_FINISH: hipLaunchKernelGGL(k_b_finish, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      default: return MRPT2_ERR_ARG;
     }
-    tm.begin(ST_FINISH);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, pl, parts ? parts + 12 * ii : nullptr, e2 + ii);
-    tm.end();
+    tm.end(L.stage);
     HIPCHK(hipGetLastError());
   }
+  return MRPT2_OK;
+}
+
+mrpt2_status read_flag(const Plan& P, const void* workspace, hipStream_t st) {
   int hflag = 0;
-  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&hflag, (const char*)workspace + P.off_flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+}
+
+mrpt2_status energy_enqueue(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
+                            size_t workspace_bytes, hipStream_t st, double* e2, double* parts, Timer& tm) {
+  if (!plan || !in || !e2) return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, e2, parts, nullptr, -1);
+  if (s != MRPT2_OK) return s;
+  return run(P, P.energy, (const char*)persistent, (char*)workspace, st, tm);
 }
 
 }  // namespace
@@ -320,8 +290,21 @@ mrpt2_status mrpt2_plan_ref_strings(mrpt2_plan_t plan, int32_t inst, uint64_t* b
 mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
                           size_t workspace_bytes, hipStream_t st, double* e2, double* parts) {
   Timer tm;
-  tm.on = false;
-  return run_energy(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+  mrpt2_status s = energy_enqueue(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+  if (s != MRPT2_OK) return s;
+  return read_flag(plan->p, workspace, st);
+}
+
+mrpt2_status mrpt2_energy_async(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                void* workspace, size_t workspace_bytes, hipStream_t st, double* e2,
+                                double* parts) {
+  Timer tm;
+  return energy_enqueue(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+}
+
+mrpt2_status mrpt2_check(mrpt2_plan_t plan, const void* workspace, hipStream_t st) {
+  if (!plan || !workspace) return MRPT2_ERR_ARG;
+  return read_flag(plan->p, workspace, st);
 }
 
 mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
@@ -331,10 +314,10 @@ mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const
   Timer tm;
   tm.on = true;
   tm.st = st;
-  const int nev = 2 * ST_N * 8;
-  for (int i = 0; i < nev; ++i)
+  for (int i = 0; i < 256; ++i)
     if (hipEventCreate(&tm.ev[i]) != hipSuccess) return MRPT2_ERR_HIP;
-  mrpt2_status s = run_energy(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+  mrpt2_status s = energy_enqueue(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
+  if (s == MRPT2_OK) s = read_flag(plan->p, workspace, st);
   for (int i = 0; i < ST_N; ++i) stage_ms[i] = 0.0f;
   if (s == MRPT2_OK || s == MRPT2_ERR_NUMERIC) {
     for (int i = 0; i < tm.n; ++i) {
@@ -342,7 +325,7 @@ mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const
       if (hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]) == hipSuccess) stage_ms[tm.slot[i]] += ms;
     }
   }
-  for (int i = 0; i < nev; ++i) hipEventDestroy(tm.ev[i]);
+  for (int i = 0; i < 256; ++i) hipEventDestroy(tm.ev[i]);
   return s;
 }
 
@@ -350,25 +333,15 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
                                          const void* persistent, void* workspace, size_t workspace_bytes,
                                          hipStream_t st, double* hpp) {
   if (!plan || !in || !hpp || inst < 0 || inst >= (int)plan->p.inst.size()) return MRPT2_ERR_ARG;
-  const Plan& P = plan->p;
+  Plan& P = plan->p;
   mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
   if (s != MRPT2_OK) return s;
-  char* work = (char*)workspace;
-  int* flag = (int*)(work + P.off_flag);
-  const InstancePlan& ip = P.inst[inst];
-  if (!in->h) return MRPT2_ERR_ARG;
-  Dev d = make_dev(ip, (const char*)persistent, work, in);
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
-  Timer tm;
-  s = tables(ip, in, d, st, flag, &tm);
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, nullptr, nullptr, hpp, inst);
   if (s != MRPT2_OK) return s;
-  const int np = (int)ip.pstrings.size();
-  hipLaunchKernelGGL(k_hpp, dim3(cdiv(np, 16), cdiv(np, 16)), dim3(16, 16), 0, st, d, (double2*)hpp);
-  HIPCHK(hipGetLastError());
-  int hflag = 0;
-  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
+  Timer tm;
+  s = run(P, P.reference[inst], (const char*)persistent, (char*)workspace, st, tm);
+  if (s != MRPT2_OK) return s;
+  return read_flag(P, workspace, st);
 }
 
 mrpt2_status mrpt2_plan_class_blocks(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t* n_blocks) {
@@ -412,7 +385,11 @@ mrpt2_status mrpt2_class_partials(mrpt2_plan_t plan, int32_t inst, int32_t cls, 
   return MRPT2_OK;
 }
 
-void mrpt2_plan_destroy(mrpt2_plan_t plan) { delete plan; }
+void mrpt2_plan_destroy(mrpt2_plan_t plan) {
+  if (!plan) return;
+  if (plan->p.pinned) (void)hipHostFree(plan->p.pinned);
+  delete plan;
+}
 
 const char* mrpt2_status_string(mrpt2_status s) {
   switch (s) {

@@ -257,6 +257,177 @@ int64_t sigma_blocks(const InstancePlan& ip, int k) {
   return rb * nsc;
 }
 
+namespace {
+
+int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Append one launch over the given per-instance jobs (skipping empty grids).
+void add_launch(Plan* P, std::vector<Launch>* seq, int kid, int stage, const std::vector<JobH>& js,
+                size_t dyn = 0, int arg = 0) {
+  Launch L;
+  L.kid = kid;
+  L.stage = stage;
+  L.job0 = (int64_t)P->jobs.size();
+  L.dyn_lds = dyn;
+  L.arg = arg;
+  int64_t blk = 0;
+  for (JobH j : js) {
+    if (j.gx <= 0 || j.gy <= 0) continue;
+    j.blk0 = blk;
+    blk += (int64_t)j.gx * j.gy;
+    P->jobs.push_back(j);
+  }
+  L.njobs = (int)((int64_t)P->jobs.size() - L.job0);
+  L.nblocks = blk;
+  if (L.njobs > 0) seq->push_back(L);
+}
+
+JobH job(int inst, int64_t gx, int64_t gy, int arg = 0) {
+  JobH j;
+  j.inst = inst;
+  j.gx = (int32_t)gx;
+  j.gy = (int32_t)gy;
+  j.arg = arg;
+  j.blk0 = 0;
+  return j;
+}
+
+// Factor tables and the occupied-block integrals for the instances in `which`.
+void table_launches(Plan* P, std::vector<Launch>* seq, const std::vector<int>& which) {
+  std::vector<JobH> js;
+  for (int i : which) {
+    const InstancePlan& ip = P->inst[i];
+    for (int t = 0; t < ip.d.n_sets; ++t)
+      if (ip.d.rank[t] > 0) js.push_back(job(i, cdiv64(ip.d.rank[t], 64), ip.n_corr, t));
+  }
+  add_launch(P, seq, K_PACK, ST_TABLES, js);
+  js.clear();
+  for (int i : which) {
+    const InstancePlan& ip = P->inst[i];
+    for (int t = 0; t < ip.d.n_sets; ++t)
+      if (ip.d.rank[t] > 0) js.push_back(job(i, cdiv64(ip.n, 256), ip.d.rank[t], t));
+  }
+  add_launch(P, seq, K_DIAG, ST_TABLES, js);
+  js.clear();
+  for (int i : which) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n));
+  add_launch(P, seq, K_WPASS, ST_TABLES, js);
+  js.clear();
+  for (int i : which) js.push_back(job(i, cdiv64(P->inst[i].n_corr, 256), 1));
+  add_launch(P, seq, K_EPS, ST_TABLES, js);
+  js.clear();
+  for (int i : which) js.push_back(job(i, cdiv64(P->inst[i].n_l, 256), 1));
+  add_launch(P, seq, K_DSUM, ST_TABLES, js);
+  js.clear();
+  for (int i : which) js.push_back(job(i, P->inst[i].n_o, P->inst[i].n_a + P->inst[i].n_v));
+  add_launch(P, seq, K_FOCK, ST_TABLES, js);
+  js.clear();
+  for (int i : which) {
+    const InstancePlan& ip = P->inst[i];
+    if (ip.n_a == 0) continue;
+    const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
+    js.push_back(job(i, cdiv64(N, 64), cdiv64(M, 64)));
+  }
+  add_launch(P, seq, K_GBUILD, ST_GBUILD, js);
+}
+
+}  // namespace
+
+void build_launches(Plan* P) {
+  P->jobs.clear();
+  P->energy.clear();
+  P->reference.clear();
+  const int ni = (int)P->inst.size();
+  std::vector<int> all(ni);
+  for (int i = 0; i < ni; ++i) all[i] = i;
+  std::vector<Launch>* seq = &P->energy;
+  add_launch(P, seq, K_CLEAR, ST_NONE, {job(0, 1, 1)});
+  table_launches(P, seq, all);
+  std::vector<JobH> js;
+  for (int i : all) {
+    const int np = (int)P->inst[i].pstrings.size();
+    js.push_back(job(i, cdiv64(np, 16), cdiv64(np, 16)));
+  }
+  add_launch(P, seq, K_HPP, ST_REF, js, 0, 0);
+  js.clear();
+  for (int i : all) js.push_back(job(i, (int64_t)P->inst[i].pstrings.size(), 1));
+  add_launch(P, seq, K_SIGP, ST_REF, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, 1, 1));
+  add_launch(P, seq, K_E0, ST_REF, js);
+  for (int prec = 0; prec < 2; ++prec) {
+    js.clear();
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      if (ip.n_v >= 2 && ip.n_pairs > 0 && (ip.d.precision == MRPT2_MIXED) == (prec == 1))
+        js.push_back(job(i, ip.n_tp, ip.n_pairs));
+    }
+    add_launch(P, seq, prec ? K_ABUILD32 : K_ABUILD, ST_ABUILD, js);
+  }
+  for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+    js.clear();
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      const ClassPlan& cp = ip.cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      js.push_back(job(i, (int64_t)cp.strings.size(), cdiv64(std::max(std::max(ip.n_c, ip.n_v), 1), 256), k));
+    }
+    add_launch(P, seq, K_CTAB, ST_PREP0 + k, js);
+    js.clear();
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0 || cp.v == 2 || cp.patterns.empty()) continue;
+      js.push_back(job(i, cdiv64(cp.n_rows, 256), (int64_t)cp.patterns.size(), k));
+    }
+    add_launch(P, seq, K_XBUILD, ST_PREP0 + k, js);
+    js.clear();
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.kernel == KERN_E12 && !cp.strings.empty() && cp.n_rows > 0)
+        js.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+    }
+    add_launch(P, seq, K_DCOEF, ST_PREP0 + k, js);
+    // sigma: dedicated kernels, then the generic kernel for the rest
+    std::vector<JobH> e22, e12[4], e02, gen;
+    size_t e02_lds = 0;
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      const ClassPlan& cp = ip.cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      if (cp.kernel == KERN_E22) {
+        e22.push_back(job(i, ip.n_tp, cp.n_holes, k));
+      } else if (cp.kernel == KERN_E12) {
+        const size_t J = cp.patterns.size();
+        const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
+        e12[v].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
+      } else if (cp.kernel == KERN_E02) {
+        e02.push_back(job(i, ip.n_tp * 128, 1, k));
+        e02_lds = std::max(e02_lds, cp.patterns.size() * 512);
+      } else {
+        gen.push_back(job(i, sigma_blocks(ip, k), 1, k));
+      }
+    }
+    add_launch(P, seq, K_E22, ST_SIGMA0 + k, e22);
+    add_launch(P, seq, K_E12_8, ST_SIGMA0 + k, e12[0]);
+    add_launch(P, seq, K_E12_16, ST_SIGMA0 + k, e12[1]);
+    add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[2]);
+    add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[3]);
+    add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02, e02_lds);
+    add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
+  }
+  js.clear();
+  for (int i : all) js.push_back(job(i, 1, 1));
+  add_launch(P, seq, K_FINISH, ST_FINISH, js);
+  // reference Hamiltonian of one instance: its tables and H_PP
+  P->reference.resize(ni);
+  for (int i = 0; i < ni; ++i) {
+    std::vector<Launch>* r = &P->reference[i];
+    add_launch(P, r, K_CLEAR, ST_NONE, {job(0, 1, 1)});
+    table_launches(P, r, {i});
+    const int np = (int)P->inst[i].pstrings.size();
+    add_launch(P, r, K_HPP, ST_REF, {job(i, cdiv64(np, 16), cdiv64(np, 16))}, 0, 1);
+  }
+}
+
 void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
   const ClassPlan& cp = ip.cls[k];
   std::memset(o, 0, sizeof(*o));
@@ -566,11 +737,18 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
   }
   out->off_flag = work;
   work = align_up(work + 256);
+  out->off_insts = work;
+  work = align_up(work + kInstBytes * n_inst);
+  build_launches(out);
+  out->off_jobs = pers;
+  pers = align_up(pers + out->jobs.size() * sizeof(JobH));
   out->persistent_bytes = pers;
   out->workspace_bytes = work;
   out->host_blob.assign(pers, 0);
   for (auto& ip : out->inst)
     std::memcpy(out->host_blob.data() + ip.persistent_base, ip.host_blob.data(), ip.persistent_bytes);
+  if (!out->jobs.empty())
+    std::memcpy(out->host_blob.data() + out->off_jobs, out->jobs.data(), out->jobs.size() * sizeof(JobH));
   return MRPT2_OK;
 }
 

@@ -80,17 +80,59 @@ struct InstancePlan {
   std::vector<char> host_blob;        // persistent region image
 };
 
+// Kernels of the launch sequence.  Every launch covers all instances: a job
+// per instance (and factor set or class where needed) gives its grid; the
+// kernel finds its job from the flat block index.
+enum KernelId : int {
+  K_CLEAR, K_PACK, K_DIAG, K_WPASS, K_EPS, K_DSUM, K_FOCK, K_GBUILD, K_HPP, K_SIGP, K_E0,
+  K_ABUILD, K_ABUILD32, K_CTAB, K_XBUILD, K_DCOEF, K_E22, K_E12_8, K_E12_16, K_E12_24, K_E12_32,
+  K_E02, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH
+};
+
+// Timing slots (mrpt2_energy_timed).
+enum StageId : int {
+  ST_NONE = -1, ST_TABLES = 0, ST_GBUILD = 1, ST_REF = 2, ST_ABUILD = 3, ST_SIGMA0 = 4,
+  ST_PREP0 = 13, ST_FINISH = 22, ST_N = 23
+};
+
+struct JobH {                         // host image of the device Job
+  int32_t inst, gx, gy, arg;
+  int64_t blk0;
+};
+
+struct Launch {
+  int kid = 0;
+  int stage = ST_NONE;
+  int64_t job0 = 0;                   // first job (index into the job table)
+  int njobs = 0;
+  int64_t nblocks = 0;
+  size_t dyn_lds = 0;
+  int arg = 0;                        // kernel-wide argument (hpp: write the caller's buffer)
+};
+
+constexpr size_t kInstBytes = 4096;   // device bytes reserved per instance descriptor
+
 struct Plan {
   std::vector<InstancePlan> inst;
   size_t persistent_bytes = 0;
   size_t workspace_bytes = 0;
   size_t off_flag = 0;                // device error flag in the workspace
+  size_t off_insts = 0;               // instance descriptors in the workspace
+  size_t off_jobs = 0;                // job table in the persistent region
+  std::vector<JobH> jobs;
+  std::vector<Launch> energy;         // launch sequence of mrpt2_energy (all instances)
+  std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
   std::vector<char> host_blob;
+  void* pinned = nullptr;             // host staging of the instance descriptors
 };
 
 // Kernel that evaluates a class.
 enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3 };
 constexpr size_t kE02MaxLds = 150 * 1024;   // LDS bytes of the (0,2) kernel's coupling block
+
+struct Plan;
+// Launch sequences and job table of a plan whose instances are built.
+void build_launches(Plan* P);
 
 // Description of partial-sum block b of class k (see mrpt2_block).
 void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* out);
