@@ -115,6 +115,9 @@ def bench_batched(args):
         c, _ = ground_state(e1, h, Bs)
         ins.append((h, Bs, c))
         singles.append(e1)
+        if len(singles) % 8 == 0:
+            print("[bench] c3: %d instances ready (%.1f s)" % (len(singles), time.time() - t),
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     print("[bench] c3: %d instances generated and solved in %.1f s" % (n_inst, time.time() - t),
           file=sys.stderr, flush=True)

@@ -111,6 +111,13 @@ typedef struct {
   const double* c;                     /* complex [N_P], plan order */
 } mrpt2_inputs;
 
+/* Gradient outputs of one instance (device pointers, caller-owned, overwritten). */
+typedef struct {
+  double* dh;                          /* complex [n][n] */
+  double* dB[MRPT2_MAX_SETS];          /* complex [rank_t][n][n] */
+  double* dc;                          /* complex [N_P], plan order */
+} mrpt2_grads;
+
 typedef struct mrpt2_plan_s* mrpt2_plan_t;
 
 /* Build the plan for n_inst instances (host only; no device work).
@@ -185,6 +192,36 @@ mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in,
 mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
                                          const void* persistent, void* workspace,
                                          size_t workspace_bytes, hipStream_t stream, double* hpp);
+
+/* Bytes of the gradient workspace of mrpt2_energy_backward (256-byte aligned
+ * device allocation, caller-owned). */
+mrpt2_status mrpt2_plan_backward_size(mrpt2_plan_t plan, size_t* grad_workspace_bytes);
+
+/* Gradient of E2 (eq. pt2en with the Epstein-Nesbet partition, eq. zeroh)
+ * with respect to every input, for every instance: the adjoint of the energy
+ * evaluation, derived from its steps (the paper gives no gradient).
+ * The forward pass is recomputed first on `workspace` (same contents as after
+ * mrpt2_energy); the first-order vector sigma_K / (E0 - H_KK) is recomputed
+ * per block and never stored.  grad_e2: device [n_inst], the upstream
+ * gradient dL/dE2 per instance; the outputs are dL/dh, dL/dB_t, dL/dc.
+ * Convention: for a complex input z the output is dL/dRe z + i dL/dIm z.  h
+ * and every B_t[L] are Hermitian parameters, so dh and dB_t[L] are projected,
+ * (G + G^H) / 2; dc is unconstrained (it is orthogonal to c and to i c, as E2
+ * depends only on the ray of c).  Layouts as in mrpt2_inputs (interleaved
+ * complex FP64, row-major); dB_t must be given for every set with rank > 0.
+ * e2: device [n_inst] receiving E2 of the recomputed forward pass, or NULL.
+ * The gradient workspace is cleared by the call; accumulation order is not
+ * fixed (FP64 atomics), so results are reproducible to rounding.  The
+ * arithmetic is FP64 in both precisions of the plan (the mixed form uses its
+ * FP32-MFMA pair integrals in the recomputed forward pass).  Synchronises the
+ * stream once to read the error flag.  Errors: MRPT2_ERR_ARG for null
+ * pointers or misaligned regions, MRPT2_ERR_WORKSPACE if a region is too
+ * small, MRPT2_ERR_NUMERIC for a non-finite input or zero denominator,
+ * MRPT2_ERR_HIP for launch or runtime failures. */
+mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                   void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                   size_t grad_workspace_bytes, const double* grad_e2,
+                                   const mrpt2_grads* grads, hipStream_t stream, double* e2);
 
 /* Work decomposition of one excitation class: mrpt2_energy writes one
  * partial sum per block, sum over the block's external determinants of

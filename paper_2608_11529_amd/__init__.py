@@ -58,6 +58,9 @@ class Plan:
         capi.check(capi.lib().mrpt2_plan_sizes(h, ctypes.byref(p), ctypes.byref(w)), "mrpt2_plan_sizes")
         self.persistent_bytes = p.value
         self.workspace_bytes = w.value
+        g = ctypes.c_size_t()
+        capi.check(capi.lib().mrpt2_plan_backward_size(h, ctypes.byref(g)), "mrpt2_plan_backward_size")
+        self.grad_bytes = g.value
 
     def info(self, inst=0):
         inf = capi.Info()
@@ -182,6 +185,39 @@ class Engine:
         del keep
         return self.e2, self.parts, dict(zip(capi.STAGES, list(ms)))
 
+    def backward(self, insts, grad_e2=None):
+        """Gradients of E2 for every instance: list of (dh, [dB_t], dc)
+        complex128 device tensors (dh, dB Hermitian-projected), and the
+        device tensor of E2 per instance.  grad_e2: device float64 [n_inst]
+        upstream gradients (ones when None).  The gradient workspace is
+        allocated on first use and kept."""
+        torch = self.torch
+        if getattr(self, "grad_workspace", None) is None:
+            self.grad_workspace = torch.empty(max(self.plan.grad_bytes, 256), dtype=torch.uint8,
+                                              device=self.device)
+        if grad_e2 is None:
+            grad_e2 = torch.ones(self.plan.n_inst, dtype=torch.float64, device=self.device)
+        grad_e2 = grad_e2.to(device=self.device, dtype=torch.float64).contiguous()
+        arr, keep = self._inputs(insts)
+        outs = []
+        garr = (capi.Grads * len(insts))()
+        for i, (h, Bs, c) in enumerate(insts):
+            dh = torch.empty_like(h)
+            dBs = [torch.empty_like(B) for B in Bs]
+            dc = torch.empty_like(c)
+            garr[i].dh = dh.data_ptr()
+            for t, dB in enumerate(dBs):
+                garr[i].dB[t] = dB.data_ptr()
+            garr[i].dc = dc.data_ptr()
+            outs.append((dh, dBs, dc))
+        code = capi.lib().mrpt2_energy_backward(self.plan.handle, arr, self.persistent.data_ptr(),
+                                                self.workspace.data_ptr(), self.plan.workspace_bytes,
+                                                self.grad_workspace.data_ptr(), self.plan.grad_bytes,
+                                                grad_e2.data_ptr(), garr, self._sptr(), self.e2.data_ptr())
+        capi.check(code, "mrpt2_energy_backward")
+        del keep
+        return outs, self.e2
+
     def class_partials(self, cls, inst=0):
         """Block partial sums of class cls from the last energy() (host numpy,
         not divided by ||C||^2)."""
@@ -204,3 +240,41 @@ class Engine:
         capi.check(code, "mrpt2_reference_hamiltonian")
         del keep
         return out
+
+
+def _autograd_function():
+    import torch
+
+    class EnergyFn(torch.autograd.Function):
+        """E2 of one instance as a differentiable function of (h, B_1..B_k, c).
+        The forward pass runs mrpt2_energy; the backward pass runs
+        mrpt2_energy_backward (which recomputes the forward pass and the
+        first-order vector block by block).  Gradients follow torch's
+        convention for complex inputs; dh and dB are Hermitian-projected."""
+
+        @staticmethod
+        def forward(ctx, engine, h, c, *Bs):
+            e2 = engine.energy([(h, list(Bs), c)], parts=False)[0].clone()
+            ctx.engine = engine
+            ctx.save_for_backward(h, c, *Bs)
+            return e2
+
+        @staticmethod
+        def backward(ctx, grad):
+            h, c, *Bs = ctx.saved_tensors
+            g = grad.reshape(1).to(torch.float64).contiguous()
+            (dh, dBs, dc), = ctx.engine.backward([(h, list(Bs), c)], g)[0]
+            return (None, dh, dc, *dBs)
+
+    return EnergyFn
+
+
+_ENERGY_FN = None
+
+
+def energy(engine, h, Bs, c):
+    """Differentiable E2 (torch autograd) of a one-instance engine."""
+    global _ENERGY_FN
+    if _ENERGY_FN is None:
+        _ENERGY_FN = _autograd_function()
+    return _ENERGY_FN.apply(engine, h, c, *Bs)

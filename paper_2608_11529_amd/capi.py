@@ -74,6 +74,14 @@ class Inputs(ctypes.Structure):
     ]
 
 
+class Grads(ctypes.Structure):
+    _fields_ = [
+        ("dh", ctypes.c_void_p),
+        ("dB", ctypes.c_void_p * MAX_SETS),
+        ("dc", ctypes.c_void_p),
+    ]
+
+
 class Block(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int32),
@@ -128,6 +136,11 @@ def lib():
         L.mrpt2_plan_class_strings.restype = st
         L.mrpt2_class_partials.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.mrpt2_class_partials.restype = st
+        L.mrpt2_plan_backward_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.mrpt2_plan_backward_size.restype = st
+        L.mrpt2_energy_backward.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp,
+                                            ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp]
+        L.mrpt2_energy_backward.restype = st
         L.mrpt2_plan_destroy.argtypes = [vp]
         L.mrpt2_plan_destroy.restype = None
         L.mrpt2_status_string.argtypes = [st]
@@ -146,4 +159,5 @@ EXPORTED = [
     "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
+    "mrpt2_plan_backward_size", "mrpt2_energy_backward",
 ]

@@ -73,7 +73,7 @@ struct Pattern;
 
 struct ClassDev {
   int h, v, n_pat;
-  int64_t n_str, n_rows, n_holes;
+  int64_t n_str, n_rows, n_holes, n_conn;
   const uint64_t* strings;
   const int32_t* conn_ptr;
   const int32_t* conn;
@@ -89,11 +89,46 @@ struct ClassDev {
   uint32_t* mask;  // [S] nonzero patterns per string
 };
 
+// Adjoint (backward) state of one instance: gradients of E2 with respect to
+// the intermediate tables, accumulated in the gradient workspace, and the
+// caller's output buffers.
+struct GradDev {
+  double* scal;        // [0] dE2/d(E0 - E_core), [1] E2 of the recomputed forward pass
+  double* Wb;          // [n][n]      adjoint of W
+  double* Wsym;        // [n][n]      Wb + Wb^T
+  double* epsb;        // [n_corr]    adjoint of eps
+  double2* fb;         // f layout    adjoint of the core Fock block
+  double2* Gb;         // G layout    adjoint of (px|qy)
+  double2* Ab;         // A layout    adjoint of <ab||xy>
+  double2* slabb;      // slab layout adjoint of the scaled factor columns
+  double* dgb;         // [n_l][n]    adjoint of the scaled diagonals
+  double* dsumb;       // [n_l]       adjoint of dsum
+  double2* hb;         // [n][n]      adjoint of h (before projection)
+  double2* cb;         // [n_p]       adjoint of C from the external space
+  double4* zero;       // region cleared before the adjoint kernels
+  int64_t n_zero;      // its size in 32-byte units
+  const double* grad_e2;   // upstream gradient dL/dE2 (device scalar)
+  double2* out_dh;     // [n][n]
+  double2* out_dc;     // [n_p]
+  double2* out_dB[4];  // per factor set [rank][n][n]
+  double* out_e2;      // E2 of the forward pass (or null)
+};
+
+struct ClassGrad {
+  double2* Xb;         // [n_pat][n_rows] adjoint of X (v < 2)
+  double* Tb;          // [parts][S]  per-part sums of dE2/dDelta over each string
+  double2* cbe;        // [parts][n_conn] per-part coefficient adjoints per coupling
+  int parts;           // row parts of the string-owned pass
+  int64_t rows_per_part;
+};
+
 // Everything a kernel needs about one instance (uploaded once per call).
 // Descriptors sit kInstStride bytes apart in device memory.
 struct Inst {
   Dev d;
   ClassDev cls[9];
+  GradDev g;
+  ClassGrad cg[9];
 };
 constexpr size_t kInstStride = 4096;
 

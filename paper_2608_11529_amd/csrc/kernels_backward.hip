@@ -1,0 +1,705 @@
+// Adjoint of the MRPT2 energy: dE2/dh, dE2/dB (every factor set) and dE2/dC.
+//
+// With t_K = sigma_K / Delta_K and N = ||C||^2,
+//   E2 = sum_K |sigma_K|^2 / (N Delta_K),
+// the gradient (convention dE/dRe z + i dE/dIm z) of each determinant's term is
+//   sigma-bar_K = 2 t_K / N,   Delta-bar_K = -|t_K|^2 / N,
+// and E2 itself carries -E2/N per unit of N.  The first-order vector is never
+// stored: each pass recomputes sigma_K and Delta_K for the determinants it
+// owns.  Per class two passes share the work:
+//   row pass    (one thread per row, every string): the adjoints of the
+//               couplings X (or the pair integrals A), of the row constants
+//               of Delta (eps, W of core/virtual spinors) and of the string
+//               tables Uc, Uv, contracted with the string occupations;
+//   string pass (one thread per string, a range of rows): the adjoint of the
+//               coefficients through each coupling, and of T (and so of E0
+//               and of the active-space energy of the string).
+// The table adjoints are then carried back through the forward steps: the
+// reference energy (H_PP), the coupling build, the pair and occupied-block
+// integrals (complex FP64 MFMA, transposed), the core Fock block, the orbital
+// energies and the pair energies W, and the last pass writes every factor's
+// gradient once, Hermitian-projected: (G + G^H) / 2.
+//
+// Accumulations that many threads share use FP64 atomics; their order is not
+// fixed, so the gradient is reproducible to rounding, not bit for bit.
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace mrpt2 {
+
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ void catomic(double2* p, double2 v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+__device__ __forceinline__ int64_t gidx(const Dev& d, int xo, int pr, int yo, int qa) {
+  return (((int64_t)xo * (d.n_a + d.n_v) + pr) * d.n_o + yo) * d.n_a + qa;
+}
+
+// Region clear.  grid (gx), block 256, grid-stride.
+__device__ __forceinline__ void bzero_body(const GradDev& g, const uint3 bid, int64_t nblk) {
+  const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
+  for (int64_t i = (int64_t)bid.x * 256 + threadIdx.x; i < g.n_zero; i += nblk * 256) g.zero[i] = z;
+}
+
+// ---- row decoding shared by the two passes ----------------------------------
+struct Row {
+  int c0, c1, a, b;
+  int64_t rab;
+  bool valid;
+};
+
+template <int H, int V>
+__device__ __forceinline__ Row decode_row(const Dev& d, const ClassDev& cd, int64_t r) {
+  Row w;
+  w.c0 = w.c1 = w.a = w.b = -1;
+  w.rab = 0;
+  w.valid = r < cd.n_rows;
+  if (!w.valid) r = cd.n_rows - 1;
+  if (V == 2) {
+    const int64_t per = d.n_tp * 4096;
+    const int64_t hole = r / per;
+    w.rab = r % per;
+    const int64_t tp = w.rab >> 12;
+    const int la = (int)((w.rab >> 6) & 63), lb = (int)(w.rab & 63);
+    w.a = d.tile_pairs[2 * tp] * 64 + la;
+    w.b = d.tile_pairs[2 * tp + 1] * 64 + lb;
+    if (!(w.a < w.b && w.b < d.n_v)) {
+      w.valid = false;
+      w.a = 0;
+      w.b = d.n_v > 1 ? 1 : 0;
+    }
+    if (H == 1) w.c0 = (int)hole;
+    if (H == 2) {
+      w.c0 = d.hole_pairs[2 * hole];
+      w.c1 = d.hole_pairs[2 * hole + 1];
+    }
+  } else {
+    int64_t hi = r;
+    if (V == 1) {
+      w.a = (int)(r % d.n_v);
+      hi = r / d.n_v;
+    }
+    if (H == 1) w.c0 = (int)hi;
+    if (H == 2) {
+      w.c0 = d.hole_pairs[2 * hi];
+      w.c1 = d.hole_pairs[2 * hi + 1];
+    }
+  }
+  return w;
+}
+
+// Row constant of Delta (the part that does not depend on the string).
+template <int H, int V>
+__device__ __forceinline__ double row_const(const Dev& d, const Row& w) {
+  const int64_t gfc = d.n_fc, gv = d.n_fc + d.n_o;
+  double qr = 0.0;
+  if (H >= 1) qr += d.eps[w.c0];
+  if (H == 2) qr += d.eps[w.c1] - d.W[(gfc + w.c0) * d.n + gfc + w.c1];
+  if (V >= 1) qr -= d.eps[d.n_o + w.a];
+  if (V == 2) qr -= d.eps[d.n_o + w.b] + d.W[(gv + w.a) * d.n + gv + w.b];
+  if (H >= 1 && V >= 1) {
+    qr += d.W[(gfc + w.c0) * d.n + gv + w.a];
+    if (V == 2) qr += d.W[(gfc + w.c0) * d.n + gv + w.b];
+    if (H == 2) {
+      qr += d.W[(gfc + w.c1) * d.n + gv + w.a];
+      if (V == 2) qr += d.W[(gfc + w.c1) * d.n + gv + w.b];
+    }
+  }
+  return qr;
+}
+
+// Offset of the coupling of pattern j in row r: into A (v = 2) or X (v < 2).
+template <int H, int V>
+__device__ __forceinline__ int64_t coupling_at(const Dev& d, const ClassDev& cd, int j, const Row& w, int64_t r) {
+  if (V == 2) {
+    const int nc = d.n_c;
+    int64_t pair;
+    if (H == 2) {
+      pair = occ_pair(w.c0, w.c1, d.n_o);
+    } else {
+      const Pattern pt = cd.pat[j];
+      pair = (H == 1) ? occ_pair(w.c0, nc + pt.a0, d.n_o) : occ_pair(nc + pt.a0, nc + pt.a1, d.n_o);
+    }
+    return pair * d.n_tp * 4096 + w.rab;
+  }
+  return (int64_t)j * cd.n_rows + r;
+}
+
+template <int H, int V>
+__device__ __forceinline__ double string_delta(const ClassDev& cd, const Dev& d, int64_t s, const Row& w) {
+  double del = cd.T[s];
+  if (H >= 1) del += cd.Uc[s * d.n_c + w.c0];
+  if (H == 2) del += cd.Uc[s * d.n_c + w.c1];
+  if (V >= 1) del -= cd.Uv[s * d.n_v + w.a];
+  if (V == 2) del -= cd.Uv[s * d.n_v + w.b];
+  return del;
+}
+
+// ---- row pass ------------------------------------------------------------------
+// One thread per row, every string of the class.  Accumulates, per row:
+//   couplings:  Xbar[j][r] += sigma-bar * conj(sign C_beta)   (the thread owns the row)
+//   q  = sum_s Delta-bar             (row constant of Delta)
+//   y_t = sum_{s containing t} Delta-bar   (tables Uc, Uv: W of the row's
+//         core holes and virtual spinors with active spinor t)
+// then adds q and y into the adjoints of eps and W.
+// grid (ceil(rows / 256)), block 256, dynamic LDS n_a * 256 doubles.
+template <int H, int V>
+__device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid) {
+  extern __shared__ double sY[];
+  const int tid = threadIdx.x;
+  const int64_t r = (int64_t)bid.x * 256 + tid;
+  const Row w = decode_row<H, V>(d, cd, r);
+  const int64_t rr = w.valid ? r : cd.n_rows - 1;
+  const int na = d.n_a;
+  for (int t = 0; t < na; ++t) sY[t * 256 + tid] = 0.0;
+  const double qr = row_const<H, V>(d, w);
+  const double N = d.scal[1];
+  const double twoN = 2.0 / N, oneN = 1.0 / N;
+  double2* Xb = (V == 2) ? g.Ab : cg.Xb;
+  const double2* X = (V == 2) ? d.A : cd.X;
+  double q = 0.0;
+  const int64_t S = cd.n_str;
+  for (int64_t s = 0; s < S; ++s) {
+    const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
+    if (e1 == e0) continue;
+    double2 sig = make_double2(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const int32_t cb = cd.conn[2 * e];
+      double2 cv = d.c[cb & 0x7fffffff];
+      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+      sig = cfma(cv, X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, rr)], sig);
+    }
+    const double del = string_delta<H, V>(cd, d, s, w) + qr;
+    const double iv = 1.0 / del;
+    const double2 t = make_double2(sig.x * iv, sig.y * iv);
+    const double2 sb = make_double2(twoN * t.x, twoN * t.y);
+    const double dl = -oneN * cabs2(t);
+    if (w.valid) {
+      for (int e = e0; e < e1; ++e) {
+        const int32_t cb = cd.conn[2 * e];
+        double2 cv = d.c[cb & 0x7fffffff];
+        if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+        double2* p = Xb + coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, rr);
+        *p = cadd(*p, cmul(sb, cconj(cv)));
+      }
+      q += dl;
+      uint64_t x = cd.strings[s];
+      while (x) {
+        const int tt = __builtin_ctzll(x);
+        x &= x - 1;
+        sY[tt * 256 + tid] += dl;
+      }
+    }
+  }
+  if (!w.valid) return;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  double* Wb = g.Wb;
+  // row constant: eps and W of holes and virtual spinors
+  if (H >= 1) atomicAdd(&g.epsb[w.c0], q);
+  if (H == 2) {
+    atomicAdd(&g.epsb[w.c1], q);
+    atomicAdd(&Wb[(gfc + w.c0) * n + gfc + w.c1], -q);
+  }
+  if (V >= 1) atomicAdd(&g.epsb[d.n_o + w.a], -q);
+  if (V == 2) {
+    atomicAdd(&g.epsb[d.n_o + w.b], -q);
+    atomicAdd(&Wb[(gv + w.a) * n + gv + w.b], -q);
+  }
+  if (H >= 1 && V >= 1) {
+    atomicAdd(&Wb[(gfc + w.c0) * n + gv + w.a], q);
+    if (V == 2) atomicAdd(&Wb[(gfc + w.c0) * n + gv + w.b], q);
+    if (H == 2) {
+      atomicAdd(&Wb[(gfc + w.c1) * n + gv + w.a], q);
+      if (V == 2) atomicAdd(&Wb[(gfc + w.c1) * n + gv + w.b], q);
+    }
+  }
+  // string tables: Uc[s][c] = sum_{t in s} W[c][t], Uv[s][a] = sum_{t in s} W[a][t]
+  for (int t = 0; t < na; ++t) {
+    const double y = sY[t * 256 + tid];
+    if (y == 0.0) continue;
+    if (H >= 1) atomicAdd(&Wb[(gfc + w.c0) * n + ga + t], y);
+    if (H == 2) atomicAdd(&Wb[(gfc + w.c1) * n + ga + t], y);
+    if (V >= 1) atomicAdd(&Wb[(gv + w.a) * n + ga + t], -y);
+    if (V == 2) atomicAdd(&Wb[(gv + w.b) * n + ga + t], -y);
+  }
+}
+
+// ---- string pass -------------------------------------------------------------
+// One thread per string, rows [part * rows_per_part, ...).  Accumulates, per
+// string and part:  cbe[e] = sum_r sign conj(X[j_e][r]) sigma-bar  (coefficient
+// adjoint through coupling e), and Tb[s] = sum_r Delta-bar.
+// grid (ceil(S / 256), parts), block 256.
+template <int H, int V>
+__device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid) {
+  const int64_t S = cd.n_str;
+  int64_t s = (int64_t)bid.x * 256 + threadIdx.x;
+  const bool live = s < S;
+  if (!live) s = S - 1;
+  const int part = bid.y;
+  const int64_t r0 = (int64_t)part * cg.rows_per_part;
+  const int64_t r1 = min(cd.n_rows, r0 + cg.rows_per_part);
+  const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
+  const double N = d.scal[1];
+  const double twoN = 2.0 / N, oneN = 1.0 / N;
+  const double2* X = (V == 2) ? d.A : cd.X;
+  double2* cbe = cg.cbe + (int64_t)part * cd.n_conn;
+  double tq = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const Row w = decode_row<H, V>(d, cd, r);
+    if (!w.valid) continue;
+    if (e1 == e0) continue;
+    double2 sig = make_double2(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const int32_t cb = cd.conn[2 * e];
+      double2 cv = d.c[cb & 0x7fffffff];
+      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+      sig = cfma(cv, X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, r)], sig);
+    }
+    const double del = string_delta<H, V>(cd, d, s, w) + row_const<H, V>(d, w);
+    const double iv = 1.0 / del;
+    const double2 t = make_double2(sig.x * iv, sig.y * iv);
+    const double2 sb = make_double2(twoN * t.x, twoN * t.y);
+    tq -= oneN * cabs2(t);
+    if (live) {
+      for (int e = e0; e < e1; ++e) {
+        const double2 xv = X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, r)];
+        double2 v = cmul(cconj(xv), sb);
+        if (cd.conn[2 * e] < 0) v = make_double2(-v.x, -v.y);
+        cbe[e] = cadd(cbe[e], v);
+      }
+    }
+  }
+  if (live) cg.Tb[(int64_t)part * S + s] = tq;
+}
+
+// ---- per-string adjoints -------------------------------------------------------
+// T[s] = (E0 - E_core) - E_act(s):  dE0 += Tbar[s];  E_act(s) = sum_{t in s} eps_t
+// + sum_{t<u in s} W_tu receives -Tbar[s].  Coupling adjoints go to C.
+// grid (ceil(S / 256)), block 256.
+__device__ __forceinline__ void bstrfin_body(const Dev& d, const ClassDev& cd, const GradDev& g,
+                                             const ClassGrad& cg, const uint3 bid) {
+  __shared__ double red[256];
+  const int64_t S = cd.n_str;
+  const int64_t s = (int64_t)bid.x * 256 + threadIdx.x;
+  double T = 0.0;
+  if (s < S) {
+    for (int p = 0; p < cg.parts; ++p) T += cg.Tb[(int64_t)p * S + s];
+    const double ea = -T;
+    const int64_t n = d.n, ga = d.n_fc + d.n_c;
+    uint64_t x = cd.strings[s];
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      atomicAdd(&g.epsb[d.n_c + t], ea);
+      uint64_t y = x;
+      while (y) {
+        const int u = __builtin_ctzll(y);
+        y &= y - 1;
+        atomicAdd(&g.Wb[(ga + t) * n + ga + u], ea);
+      }
+    }
+    for (int e = cd.conn_ptr[s]; e < cd.conn_ptr[s + 1]; ++e) {
+      double2 v = make_double2(0.0, 0.0);
+      for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.cbe[(int64_t)p * cd.n_conn + e]);
+      catomic(&g.cb[cd.conn[2 * e] & 0x7fffffff], v);
+    }
+  }
+  red[threadIdx.x] = T;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&g.scal[0], red[0]);
+}
+
+// ---- reference energy ------------------------------------------------------------
+// E0 - E_core = Re(C^H H~ C) / N: the adjoint of H~[i][j] is
+// Ebar C_i conj(C_j) / N, carried into f, G, eps and W by the Slater-Condon
+// rules of the forward build.  grid (ceil(np/16), ceil(np/16)), block 256.
+__device__ __forceinline__ void bhpp_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int j = bid.x * 16 + (threadIdx.x & 15);
+  const int i = bid.y * 16 + (threadIdx.x >> 4);
+  if (i >= d.n_p || j >= d.n_p) return;
+  const uint64_t bi = d.pstrings[i], bj = d.pstrings[j];
+  const uint64_t cre = bi & ~bj, ann = bj & ~bi;
+  const int nd = __popcll(cre);
+  if (nd > 2) return;
+  const double sc = g.scal[0] / d.scal[1];
+  const double2 ci = d.c[i], cj = d.c[j];
+  double2 hb = cmul(ci, cconj(cj));
+  hb = make_double2(sc * hb.x, sc * hb.y);
+  const int nc = d.n_c;
+  const int64_t n = d.n, ga = d.n_fc + d.n_c;
+  auto below = [](uint64_t s, int p) { return __popcll(s & ((1ull << p) - 1)) & 1; };
+  if (nd == 0) {
+    const double ea = hb.x;
+    uint64_t x = bi;
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      atomicAdd(&g.epsb[nc + t], ea);
+      uint64_t y = x;
+      while (y) {
+        const int u = __builtin_ctzll(y);
+        y &= y - 1;
+        atomicAdd(&g.Wb[(ga + t) * n + ga + u], ea);
+      }
+    }
+  } else if (nd == 1) {
+    const int p = __builtin_ctzll(cre), q = __builtin_ctzll(ann);
+    int par = below(bj, q);
+    const uint64_t mid = bj & ~(1ull << q);
+    par ^= below(mid, p);
+    const double2 xb = par ? make_double2(-hb.x, -hb.y) : hb;
+    catomic(&g.fb[(int64_t)p * d.n_o + nc + q], xb);
+    uint64_t x = mid;
+    while (x) {
+      const int w = __builtin_ctzll(x);
+      x &= x - 1;
+      catomic(&g.Gb[gidx(d, nc + q, p, nc + w, w)], xb);
+      catomic(&g.Gb[gidx(d, nc + w, p, nc + q, w)], make_double2(-xb.x, -xb.y));
+    }
+  } else {
+    const int q1 = __builtin_ctzll(ann), q2 = 63 - __builtin_clzll(ann);
+    const int p1 = __builtin_ctzll(cre), p2 = 63 - __builtin_clzll(cre);
+    uint64_t s = bj;
+    int par = below(s, q1);
+    s &= ~(1ull << q1);
+    par ^= below(s, q2);
+    s &= ~(1ull << q2);
+    par ^= below(s, p1);
+    s |= 1ull << p1;
+    par ^= below(s, p2);
+    const double2 xb = par ? make_double2(-hb.x, -hb.y) : hb;
+    catomic(&g.Gb[gidx(d, nc + q1, p2, nc + q2, p1)], xb);
+    catomic(&g.Gb[gidx(d, nc + q2, p2, nc + q1, p1)], make_double2(-xb.x, -xb.y));
+  }
+}
+
+// ---- couplings of the classes with at most one virtual electron ------------------
+// Transpose of the coupling build: Xbar[j][r] into f and G.
+// grid (ceil(rows/256), n_pat), block 256.
+__device__ __forceinline__ void bxbuild_body(const Dev& d, const ClassDev& cd, const GradDev& g,
+                                             const ClassGrad& cg, const uint3 bid) {
+  const int64_t r = bid.x * 256ll + threadIdx.x;
+  const int j = bid.y;
+  if (r >= cd.n_rows) return;
+  const double2 xb = cg.Xb[(int64_t)j * cd.n_rows + r];
+  if (xb.x == 0.0 && xb.y == 0.0) return;
+  int c0, c1, a;
+  decode_small_row(d, cd, r, &c0, &c1, &a);
+  const Pattern pt = cd.pat[j];
+  const int nc = d.n_c, na = d.n_a;
+  const double2 mxb = make_double2(-xb.x, -xb.y);
+  if (pt.kind == PAT_SINGLE) {
+    const int qo = (cd.h == 1) ? c0 : nc + pt.a0;
+    const int pr = (cd.v == 1) ? na + a : pt.r0;
+    catomic(&g.fb[(int64_t)pr * d.n_o + qo], xb);
+  } else if (pt.kind == PAT_SPECT) {
+    const int qo = (cd.h == 1) ? c0 : nc + pt.a0;
+    const int pr = (cd.v == 1) ? na + a : pt.r0;
+    const int w = pt.w;
+    catomic(&g.Gb[gidx(d, qo, pr, nc + w, w)], xb);
+    catomic(&g.Gb[gidx(d, nc + w, pr, qo, w)], mxb);
+  } else {
+    int q, s;
+    if (cd.h == 2) { q = c0; s = c1; }
+    else if (cd.h == 1) { q = c0; s = nc + pt.a0; }
+    else { q = nc + pt.a0; s = nc + pt.a1; }
+    int rr, pr;
+    if (cd.v == 1) { rr = pt.r0; pr = na + a; }
+    else { rr = pt.r0; pr = pt.r1; }
+    catomic(&g.Gb[gidx(d, q, pr, s, rr)], xb);
+    catomic(&g.Gb[gidx(d, s, pr, q, rr)], mxb);
+  }
+}
+
+// ---- pair integrals: A[xy][ab] = sum_L w_L (S_x[a] S_y[b] - S_y[a] S_x[b]) ----------
+// with S_x[a][L] = sqrt|w_L| B[L][a][x].  With Atilde_xy[a][b] = Abar_xy[a][b]
+// - Abar_xy[b][a] (zero where A is not stored) and Atilde_yx = Atilde_xy^T,
+//   Sbar_x[a][L] = sign_L sum_{y != x} sum_b Atilde_xy[a][b] conj(S_y[b][L]),
+// one complex FP64 MFMA GEMM per occupied x with K = (n_o - 1) n_v.
+// grid (ceil(n_l/64), ceil(n_v/64) * n_o), block 256.
+__device__ __forceinline__ double2 abar_at(const Dev& d, const GradDev& g, int64_t pair, int a, int b) {
+  const int I = a >> 6, J = b >> 6;
+  if (I > J) return make_double2(0.0, 0.0);
+  const int64_t tp = (int64_t)I * d.n_vt - (int64_t)I * (I - 1) / 2 + (J - I);
+  return g.Ab[(pair * d.n_tp + tp) * 4096 + (a & 63) * 64 + (b & 63)];
+}
+
+__device__ __forceinline__ void bagemm_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int nvt = (d.n_v + 63) / 64;
+  const int x = bid.y / nvt;
+  const int a0 = (bid.y % nvt) * 64;
+  const int L0 = bid.x * 64;
+  const int nv = d.n_v, nl = d.n_l, no = d.n_o;
+  auto fa = [&](int r, int k) -> double2 {
+    const int a = a0 + r;
+    if (a >= nv) return make_double2(0.0, 0.0);
+    const int yp = k / nv, b = k % nv;
+    const int y = yp < x ? yp : yp + 1;
+    if (x < y) {
+      const int64_t pr = occ_pair(x, y, no);
+      return csub(abar_at(d, g, pr, a, b), abar_at(d, g, pr, b, a));
+    }
+    const int64_t pr = occ_pair(y, x, no);
+    return csub(abar_at(d, g, pr, b, a), abar_at(d, g, pr, a, b));
+  };
+  auto fb = [&](int c, int k) -> double2 {
+    const int L = L0 + c;
+    if (L >= nl) return make_double2(0.0, 0.0);
+    const int yp = k / nv, b = k % nv;
+    const int y = yp < x ? yp : yp + 1;
+    return cconj(d.slab[((int64_t)(d.n_fc + y) * d.n_corr + no + b) * nl + L]);
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, (no - 1) * nv, sA, sB, accR, accI);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + acc_row(i, r), L = L0 + acc_col(j);
+        if (a < nv && L < nl) {
+          double2* p = g.slabb + ((int64_t)(d.n_fc + x) * d.n_corr + no + a) * nl + L;
+          const double sg = d.sign[L];
+          *p = cadd(*p, make_double2(sg * accR[i][j][r], sg * accI[i][j][r]));
+        }
+      }
+}
+
+// ---- occupied-block integrals: G[m][k] = sum_L w_L P[m][L] Q[k][L] -----------------
+// m = (x, p) over occupied x and active/virtual p, k = (y, q) over occupied y and
+// active q, P[m] = S_x[p], Q[k] = S_y[q].
+//   Pbar[m][L] = sign_L sum_k Gbar[m][k] conj(Q[k][L])   (which = 0)
+//   Qbar[k][L] = sign_L sum_m Gbar[m][k] conj(P[m][L])   (which = 1)
+// grid (ceil(n_l/64), ceil(rows/64)), block 256.
+__device__ __forceinline__ void bggemm_body(const Dev& d, const GradDev& g, int which, const uint3 bid) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int npr = d.n_a + d.n_v;
+  const int64_t M = (int64_t)d.n_o * npr, N = (int64_t)d.n_o * d.n_a;
+  const int64_t R = which ? N : M, K = which ? M : N;
+  const int64_t m0 = (int64_t)bid.y * 64;
+  const int L0 = bid.x * 64;
+  const int nl = d.n_l;
+  auto prow = [&](int64_t m) -> int64_t {    // slab row of P[m]
+    return ((int64_t)(d.n_fc + m / npr) * d.n_corr + d.n_c + m % npr);
+  };
+  auto qrow = [&](int64_t k) -> int64_t {    // slab row of Q[k]
+    return ((int64_t)(d.n_fc + k / d.n_a) * d.n_corr + d.n_c + k % d.n_a);
+  };
+  auto fa = [&](int r, int k) -> double2 {
+    const int64_t m = m0 + r;
+    if (m >= R) return make_double2(0.0, 0.0);
+    return which ? g.Gb[(int64_t)k * N + m] : g.Gb[m * N + k];
+  };
+  auto fb = [&](int c, int k) -> double2 {
+    const int L = L0 + c;
+    if (L >= nl) return make_double2(0.0, 0.0);
+    return cconj(d.slab[(which ? prow(k) : qrow(k)) * nl + L]);
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, (int)K, sA, sB, accR, accI);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + acc_row(i, r);
+        const int L = L0 + acc_col(j);
+        if (m < R && L < nl) {
+          double2* p = g.slabb + (which ? qrow(m) : prow(m)) * nl + L;
+          const double sg = d.sign[L];
+          *p = cadd(*p, make_double2(sg * accR[i][j][r], sg * accI[i][j][r]));
+        }
+      }
+}
+
+// ---- core Fock block -------------------------------------------------------------
+// f[p][q] = h_pq + sum_L w_L dsum_L B_pq - sum_{j core} sum_L w_L B_pj conj(B_qj)
+// in slab form (p active/virtual row pr, q core/active qo).  Adjoint into the
+// slab entries of frozen/core columns j and of column q.
+// grid (n_occ, n_corr), block 64 (threads over L).
+__device__ __forceinline__ void bfock_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int x = bid.x;        // slab column (global occupied index)
+  const int pc = bid.y;       // slab row (correlated index)
+  const int nl = d.n_l, no = d.n_o, nc = d.n_c, npr = d.n_a + d.n_v;
+  const bool core_col = x < d.n_fc + nc;
+  const bool coul = x >= d.n_fc && pc >= nc;
+  if (!core_col && !coul) return;
+  const double2* fb = g.fb;
+  for (int L = threadIdx.x; L < nl; L += 64) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (core_col) {
+      if (pc >= nc) {            // B_pj with p = pr: -sum_q fbar[pr][q] S_j[q]
+        const int pr = pc - nc;
+        for (int qo = 0; qo < no; ++qo)
+          acc = csub(acc, cmul(fb[(int64_t)pr * no + qo], d.slab[((int64_t)x * d.n_corr + qo) * nl + L]));
+      }
+      if (pc < no) {             // B_qj with q = pc: -sum_p conj(fbar[p][q]) S_j[p]
+        for (int pr = 0; pr < npr; ++pr)
+          acc = csub(acc, cmul(cconj(fb[(int64_t)pr * no + pc]), d.slab[((int64_t)x * d.n_corr + nc + pr) * nl + L]));
+      }
+    }
+    if (coul) {
+      const double2 f = fb[(int64_t)(pc - nc) * no + (x - d.n_fc)];
+      acc = cadd(acc, make_double2(d.dsum[L] * f.x, d.dsum[L] * f.y));
+    }
+    const double sg = d.sign[L];
+    double2* p = g.slabb + ((int64_t)x * d.n_corr + pc) * nl + L;
+    *p = cadd(*p, make_double2(sg * acc.x, sg * acc.y));
+  }
+}
+
+// dsumbar[L] = sign_L sum_{p, q} Re(conj(fbar[p][q]) S_q[p][L]).  grid (ceil(n_l/256)).
+__device__ __forceinline__ void bdsum_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int L = bid.x * 256 + threadIdx.x;
+  if (L >= d.n_l) return;
+  const int no = d.n_o, npr = d.n_a + d.n_v;
+  double acc = 0.0;
+  for (int qo = 0; qo < no; ++qo)
+    for (int pr = 0; pr < npr; ++pr) {
+      const double2 f = g.fb[(int64_t)pr * no + qo];
+      const double2 v = d.slab[((int64_t)(d.n_fc + qo) * d.n_corr + d.n_c + pr) * d.n_l + L];
+      acc += f.x * v.x + f.y * v.y;
+    }
+  g.dsumb[L] = d.sign[L] * acc;
+}
+
+// h receives fbar (active/virtual x core/active block) and epsbar (diagonal);
+// eps_p = h_pp + sum_{j core, j != p} W_pj gives Wbar[p][j] += epsbar[p].
+// grid (ceil(n_corr / 256), 1 + n_o): row 0 handles eps, rows 1.. the f column qo.
+__device__ __forceinline__ void bhfe_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int i = bid.x * 256 + threadIdx.x;
+  const int64_t n = d.n;
+  if (bid.y == 0) {
+    if (i >= d.n_corr) return;
+    const int64_t gg = d.n_fc + i;
+    const double e = g.epsb[i];
+    atomicAdd(&g.hb[gg * n + gg].x, e);
+    for (int j = 0; j < d.n_fc + d.n_c; ++j)
+      if (j != gg) g.Wb[gg * n + j] += e;
+  } else {
+    const int qo = bid.y - 1;
+    const int npr = d.n_a + d.n_v;
+    if (i >= npr) return;
+    const int64_t gp = d.n_fc + d.n_c + i, gq = d.n_fc + qo;
+    catomic(g.hb + gp * n + gq, g.fb[(int64_t)i * d.n_o + qo]);
+  }
+}
+
+// Wsym = Wbar + Wbar^T.  grid (ceil(n/256), n).
+__device__ __forceinline__ void bwsym_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int q = bid.x * 256 + threadIdx.x;
+  const int p = bid.y;
+  if (q >= d.n) return;
+  const int64_t n = d.n;
+  g.Wsym[p * n + q] = (p == q) ? 0.0 : g.Wb[p * n + q] + g.Wb[(int64_t)q * n + p];
+}
+
+// dgbar[L][p] = sign_L sum_q Wsym[q][p] dg[L][q] + [p frozen/core] dsumbar[L]
+// (W_pq Coulomb part sign_L dg_p dg_q; dsum_L = sum_{j core} dg[L][j]).
+// grid (ceil(n/256), n_l).
+__device__ __forceinline__ void bdg_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int p = bid.x * 256 + threadIdx.x;
+  const int L = bid.y;
+  if (p >= d.n) return;
+  const int64_t n = d.n;
+  const double* dg = d.dg + (int64_t)L * n;
+  double acc = 0.0;
+  for (int q = 0; q < d.n; ++q) acc = fma(g.Wsym[(int64_t)q * n + p], dg[q], acc);
+  acc *= d.sign[L];
+  if (p < d.n_fc + d.n_c) acc += g.dsumb[L];
+  g.dgb[(int64_t)L * n + p] = acc;
+}
+
+// ---- factor gradients ----------------------------------------------------------------
+// Raw gradient of factor L of set t at (p, q):
+//   R = -2 sign s^2 Wbar[p][q] B[p][q]          (p != q; exchange part of W)
+//     + [p == q] s dgbar[L][p]                  (diagonals)
+//     + [q occupied type, p correlated] s slabbar[q][p - n_fc][L]
+// written as gradE2 (R(p,q) + conj(R(q,p))) / 2.  32 x 32 tiles through LDS.
+// grid (ceil(n/32), ceil(n/32) * rank), block 256 (32 x 8).
+__device__ __forceinline__ double2 raw_dB(const Dev& d, const GradDev& g, int Lg, int p, int q, double2 b) {
+  const double s = d.scale[Lg], sg = d.sign[Lg];
+  double2 r = make_double2(0.0, 0.0);
+  const int64_t n = d.n;
+  if (p != q) {
+    const double c = -2.0 * sg * s * s * g.Wb[(int64_t)p * n + q];
+    r = make_double2(c * b.x, c * b.y);
+  } else {
+    r.x = s * g.dgb[(int64_t)Lg * n + p];
+  }
+  if (q < d.n_occ && p >= d.n_fc) {
+    const double2 v = g.slabb[((int64_t)q * d.n_corr + (p - d.n_fc)) * d.n_l + Lg];
+    r = cadd(r, make_double2(s * v.x, s * v.y));
+  }
+  return r;
+}
+
+__device__ __forceinline__ void bdB_body(const Dev& d, const GradDev& g, int t, const uint3 bid) {
+  __shared__ double2 tT[32][33];
+  const int nt = (d.n + 31) / 32;
+  const int L = bid.y / nt;
+  const int P0 = (bid.y % nt) * 32, Q0 = bid.x * 32;
+  const int Lg = d.sets.l0[t] + L;
+  const double2* B = d.sets.B[t] + (int64_t)L * d.n * d.n;
+  double2* out = g.out_dB[t] + (int64_t)L * d.n * d.n;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t n = d.n;
+  // transposed partner: R(q, p) for q in [Q0, Q0+32), p in [P0, P0+32)
+  for (int k = ty; k < 32; k += 8) {
+    const int q = Q0 + k, p = P0 + tx;
+    double2 v = make_double2(0.0, 0.0);
+    if (q < d.n && p < d.n) v = raw_dB(d, g, Lg, q, p, B[(int64_t)q * n + p]);
+    tT[k][tx] = v;
+  }
+  __syncthreads();
+  const double ge = *g.grad_e2;
+  for (int k = ty; k < 32; k += 8) {
+    const int p = P0 + k, q = Q0 + tx;
+    if (p < d.n && q < d.n) {
+      const double2 a = raw_dB(d, g, Lg, p, q, B[(int64_t)p * n + q]);
+      const double2 c = tT[tx][k];
+      out[(int64_t)p * n + q] = make_double2(0.5 * ge * (a.x + c.x), 0.5 * ge * (a.y - c.y));
+    }
+  }
+}
+
+// dh = gradE2 (hbar + hbar^H) / 2.  grid (ceil(n/256), n).
+__device__ __forceinline__ void bdh_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int q = bid.x * 256 + threadIdx.x;
+  const int p = bid.y;
+  if (q >= d.n) return;
+  const int64_t n = d.n;
+  const double2 a = g.hb[(int64_t)p * n + q], c = g.hb[(int64_t)q * n + p];
+  const double ge = *g.grad_e2;
+  g.out_dh[(int64_t)p * n + q] = make_double2(0.5 * ge * (a.x + c.x), 0.5 * ge * (a.y - c.y));
+}
+
+// dC = gradE2 [cbar + Ebar (2/N)(sigma_P - E0 C) - (2 E2 / N) C].  grid (ceil(np/256)).
+__device__ __forceinline__ void bdc_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  const int i = bid.x * 256 + threadIdx.x;
+  if (i >= d.n_p) return;
+  const double N = d.scal[1], E0 = d.scal[0];
+  const double eb = g.scal[0], e2 = g.scal[1];
+  const double2 c = d.c[i], sp = d.sigp[i];
+  const double k1 = 2.0 * eb / N, k2 = -2.0 * e2 / N;
+  double2 v = g.cb[i];
+  v.x += k1 * (sp.x - E0 * c.x) + k2 * c.x;
+  v.y += k1 * (sp.y - E0 * c.y) + k2 * c.y;
+  const double ge = *g.grad_e2;
+  g.out_dc[i] = make_double2(ge * v.x, ge * v.y);
+  if (i == 0 && g.out_e2) *g.out_e2 = e2;
+}
+
+}  // namespace mrpt2

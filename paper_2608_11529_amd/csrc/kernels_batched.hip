@@ -100,6 +100,74 @@ __global__ void __launch_bounds__(256) k_b_finish(MRPT2_ARGS) {
   finish_body(I.d, I.cls);
 }
 
+// ---- adjoint ----
+__global__ void __launch_bounds__(256) k_b_bzero(MRPT2_ARGS) {
+  MRPT2_JOB
+  bzero_body(I.g, bid, jb.gx);
+}
+template <int H, int V, int K>
+__global__ void __launch_bounds__(256) k_b_brow(MRPT2_ARGS) {
+  MRPT2_JOB
+  brow_body<H, V>(I.d, I.cls[K], I.g, I.cg[K], bid);
+}
+template <int H, int V, int K>
+__global__ void __launch_bounds__(256) k_b_bstr(MRPT2_ARGS) {
+  MRPT2_JOB
+  bstr_body<H, V>(I.d, I.cls[K], I.g, I.cg[K], bid);
+}
+__global__ void __launch_bounds__(256) k_b_bsfin(MRPT2_ARGS) {
+  MRPT2_JOB
+  bstrfin_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);
+}
+__global__ void __launch_bounds__(256) k_b_bhpp(MRPT2_ARGS) {
+  MRPT2_JOB
+  bhpp_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bxb(MRPT2_ARGS) {
+  MRPT2_JOB
+  bxbuild_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);
+}
+__global__ void __launch_bounds__(256) k_b_bag(MRPT2_ARGS) {
+  MRPT2_JOB
+  bagemm_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bgg(MRPT2_ARGS) {
+  MRPT2_JOB
+  bggemm_body(I.d, I.g, jb.arg, bid);
+}
+__global__ void __launch_bounds__(64) k_b_bfock(MRPT2_ARGS) {
+  MRPT2_JOB
+  bfock_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bdsum(MRPT2_ARGS) {
+  MRPT2_JOB
+  bdsum_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bhfe(MRPT2_ARGS) {
+  MRPT2_JOB
+  bhfe_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bwsym(MRPT2_ARGS) {
+  MRPT2_JOB
+  bwsym_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bdg(MRPT2_ARGS) {
+  MRPT2_JOB
+  bdg_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bdb(MRPT2_ARGS) {
+  MRPT2_JOB
+  bdB_body(I.d, I.g, jb.arg, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bdh(MRPT2_ARGS) {
+  MRPT2_JOB
+  bdh_body(I.d, I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_bdc(MRPT2_ARGS) {
+  MRPT2_JOB
+  bdc_body(I.d, I.g, bid);
+}
+
 #undef MRPT2_JOB
 
 }  // namespace mrpt2

@@ -15,6 +15,7 @@
 
 #include "kernels_tables.hip"
 #include "kernels_energy.hip"
+#include "kernels_backward.hip"
 #include "kernels_batched.hip"
 
 struct mrpt2_plan_s {
@@ -93,6 +94,7 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.n_str = (int64_t)cp.strings.size();
   c.n_rows = cp.n_rows;
   c.n_holes = cp.n_holes;
+  c.n_conn = cp.n_conn;
   c.strings = (const uint64_t*)(P + cp.off_strings);
   c.conn_ptr = (const int32_t*)(P + cp.off_conn_ptr);
   c.conn = (const int32_t*)(P + cp.off_conn);
@@ -107,6 +109,43 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.n_part = (cp.strings.empty() || cp.n_rows == 0) ? 0 : cp.n_blocks;
   const int64_t rb = cdiv(cp.n_rows, 256);
   c.nsc = rb > 0 ? (int)(sigma_blocks(ip, k) / rb) : 1;
+  return c;
+}
+
+GradDev make_grad(const InstancePlan& ip, char* gw, const mrpt2_grads* out, const double* grad_e2, double* e2) {
+  GradDev g{};
+  char* G = gw + ip.grad_base;
+  g.scal = (double*)(G + ip.off_gs);
+  g.Wb = (double*)(G + ip.off_Wb);
+  g.Wsym = (double*)(G + ip.off_Wsym);
+  g.epsb = (double*)(G + ip.off_epsb);
+  g.fb = (double2*)(G + ip.off_fb);
+  g.Gb = (double2*)(G + ip.off_Gb);
+  g.Ab = (double2*)(G + ip.off_Ab);
+  g.slabb = (double2*)(G + ip.off_slabb);
+  g.dgb = (double*)(G + ip.off_dgb);
+  g.dsumb = (double*)(G + ip.off_dsumb);
+  g.hb = (double2*)(G + ip.off_hb);
+  g.cb = (double2*)(G + ip.off_cb);
+  g.zero = (double4*)G;
+  g.n_zero = (int64_t)(ip.grad_bytes / 32);
+  g.grad_e2 = grad_e2;
+  g.out_dh = (double2*)out->dh;
+  g.out_dc = (double2*)out->dc;
+  for (int t = 0; t < ip.d.n_sets; ++t) g.out_dB[t] = (double2*)out->dB[t];
+  g.out_e2 = e2;
+  return g;
+}
+
+ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
+  const ClassPlan& cp = ip.cls[k];
+  char* G = gw + ip.grad_base;
+  ClassGrad c{};
+  c.Xb = (double2*)(G + cp.off_Xb);
+  c.Tb = (double*)(G + cp.off_Tb);
+  c.cbe = (double2*)(G + cp.off_cbe);
+  c.parts = cp.parts;
+  c.rows_per_part = cp.rows_per_part;
   return c;
 }
 
@@ -138,7 +177,8 @@ mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t w
 // Fill the instance descriptors in pinned host memory and copy them to the
 // workspace (asynchronously, on stream).
 mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, char* work, hipStream_t st,
-                          double* e2, double* parts, double* hpp_out, int only) {
+                          double* e2, double* parts, double* hpp_out, int only, char* gw = nullptr,
+                          const mrpt2_grads* grads = nullptr, const double* grad_e2 = nullptr) {
   const size_t bytes = kInstBytes * P.inst.size();
   if (!P.pinned) HIPCHK(hipHostMalloc(&P.pinned, bytes, hipHostMallocDefault));
   std::memset(P.pinned, 0, bytes);
@@ -155,6 +195,16 @@ mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, cha
     I->d.out_parts = parts ? parts + 12 * i : nullptr;
     I->d.out_hpp = (double2*)hpp_out;
     for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cls[k] = make_class(ip, k, pers, work);
+    if (gw) {
+      const mrpt2_grads* go = grads + i;
+      if (!go->dh || !go->dc || !grad_e2) return MRPT2_ERR_ARG;
+      for (int t = 0; t < ip.d.n_sets; ++t)
+        if (ip.d.rank[t] > 0 && !go->dB[t]) return MRPT2_ERR_ARG;
+      I->g = make_grad(ip, gw, go, grad_e2 + i, e2 ? e2 + i : nullptr);
+      I->d.out_e2 = I->g.scal + 1;
+      I->d.out_parts = nullptr;
+      for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cg[k] = make_class_grad(ip, k, gw);
+    }
   }
   HIPCHK(hipMemcpyAsync(work + P.off_insts, P.pinned, bytes, hipMemcpyHostToDevice, st));
   return MRPT2_OK;
@@ -209,6 +259,47 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_SIG10: hipLaunchKernelGGL((k_b_sigma<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG00: hipLaunchKernelGGL((k_b_sigma<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_FINISH: hipLaunchKernelGGL(k_b_finish, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BZERO: hipLaunchKernelGGL(k_b_bzero, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+#define MRPT2_BROW(ID, H, V, K)                                                                    \
+  case ID:                                                                                        \
+    if (L.dyn_lds > 65536 &&                                                                      \
+        hipFuncSetAttribute((const void*)k_b_brow<H, V, K>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)L.dyn_lds) != hipSuccess)                                        \
+      return MRPT2_ERR_HIP;                                                                       \
+    hipLaunchKernelGGL((k_b_brow<H, V, K>), g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);   \
+    break;
+      MRPT2_BROW(K_BROW22, 2, 2, 0)
+      MRPT2_BROW(K_BROW12, 1, 2, 1)
+      MRPT2_BROW(K_BROW02, 0, 2, 2)
+      MRPT2_BROW(K_BROW21, 2, 1, 3)
+      MRPT2_BROW(K_BROW11, 1, 1, 4)
+      MRPT2_BROW(K_BROW01, 0, 1, 5)
+      MRPT2_BROW(K_BROW20, 2, 0, 6)
+      MRPT2_BROW(K_BROW10, 1, 0, 7)
+      MRPT2_BROW(K_BROW00, 0, 0, 8)
+#undef MRPT2_BROW
+      case K_BSTR22: hipLaunchKernelGGL((k_b_bstr<2, 2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR12: hipLaunchKernelGGL((k_b_bstr<1, 2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR02: hipLaunchKernelGGL((k_b_bstr<0, 2, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR21: hipLaunchKernelGGL((k_b_bstr<2, 1, 3>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR11: hipLaunchKernelGGL((k_b_bstr<1, 1, 4>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR01: hipLaunchKernelGGL((k_b_bstr<0, 1, 5>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR20: hipLaunchKernelGGL((k_b_bstr<2, 0, 6>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR10: hipLaunchKernelGGL((k_b_bstr<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSTR00: hipLaunchKernelGGL((k_b_bstr<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BSFIN: hipLaunchKernelGGL(k_b_bsfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BHPP: hipLaunchKernelGGL(k_b_bhpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BXB: hipLaunchKernelGGL(k_b_bxb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BAG: hipLaunchKernelGGL(k_b_bag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BGG: hipLaunchKernelGGL(k_b_bgg, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BFOCK: hipLaunchKernelGGL(k_b_bfock, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BDSUM: hipLaunchKernelGGL(k_b_bdsum, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BHFE: hipLaunchKernelGGL(k_b_bhfe, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BWSYM: hipLaunchKernelGGL(k_b_bwsym, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BDG: hipLaunchKernelGGL(k_b_bdg, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BDB: hipLaunchKernelGGL(k_b_bdb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BDH: hipLaunchKernelGGL(k_b_bdh, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BDC: hipLaunchKernelGGL(k_b_bdc, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       default: return MRPT2_ERR_ARG;
     }
     tm.end(L.stage);
@@ -327,6 +418,31 @@ mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const
   }
   for (int i = 0; i < 256; ++i) hipEventDestroy(tm.ev[i]);
   return s;
+}
+
+mrpt2_status mrpt2_plan_backward_size(mrpt2_plan_t plan, size_t* grad_workspace_bytes) {
+  if (!plan || !grad_workspace_bytes) return MRPT2_ERR_ARG;
+  *grad_workspace_bytes = plan->p.grad_bytes;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                   void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                   size_t grad_workspace_bytes, const double* grad_e2, const mrpt2_grads* grads,
+                                   hipStream_t st, double* e2) {
+  if (!plan || !in || !grads || !grad_e2 || !grad_workspace) return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  if (grad_workspace_bytes < P.grad_bytes) return MRPT2_ERR_WORKSPACE;
+  if ((uintptr_t)grad_workspace & 255) return MRPT2_ERR_ARG;
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, e2, nullptr, nullptr, -1,
+                   (char*)grad_workspace, grads, grad_e2);
+  if (s != MRPT2_OK) return s;
+  Timer tm;
+  s = run(P, P.backward, (const char*)persistent, (char*)workspace, st, tm);
+  if (s != MRPT2_OK) return s;
+  return read_flag(P, workspace, st);
 }
 
 mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,

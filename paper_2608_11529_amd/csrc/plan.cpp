@@ -335,6 +335,7 @@ void table_launches(Plan* P, std::vector<Launch>* seq, const std::vector<int>& w
 void build_launches(Plan* P) {
   P->jobs.clear();
   P->energy.clear();
+  P->backward.clear();
   P->reference.clear();
   const int ni = (int)P->inst.size();
   std::vector<int> all(ni);
@@ -417,6 +418,102 @@ void build_launches(Plan* P) {
   js.clear();
   for (int i : all) js.push_back(job(i, 1, 1));
   add_launch(P, seq, K_FINISH, ST_FINISH, js);
+  // adjoint: clear the gradient workspace, recompute the forward pass, then
+  // the per-class passes and the chain back through the tables
+  seq = &P->backward;
+  js.clear();
+  for (int i : all) {
+    const int64_t n32 = (int64_t)(P->inst[i].grad_bytes / 32);
+    js.push_back(job(i, std::max<int64_t>(1, std::min<int64_t>(cdiv64(n32, 256), 65536)), 1));
+  }
+  add_launch(P, seq, K_BZERO, ST_NONE, js);
+  for (const Launch& L : P->energy) seq->push_back(L);
+  for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+    std::vector<JobH> jr, jsr;
+    size_t lds = 0;
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      const ClassPlan& cp = ip.cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      jr.push_back(job(i, cdiv64(cp.n_rows, 256), 1, k));
+      jsr.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
+      lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
+    }
+    add_launch(P, seq, K_BROW22 + k, ST_NONE, jr, lds);
+    add_launch(P, seq, K_BSTR22 + k, ST_NONE, jsr);
+  }
+  for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+    js.clear();
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0) continue;
+      js.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+    }
+    add_launch(P, seq, K_BSFIN, ST_NONE, js);
+  }
+  js.clear();
+  for (int i : all) {
+    const int np = (int)P->inst[i].pstrings.size();
+    js.push_back(job(i, cdiv64(np, 16), cdiv64(np, 16)));
+  }
+  add_launch(P, seq, K_BHPP, ST_NONE, js);
+  js.clear();
+  for (int k = 0; k < MRPT2_N_CLASS; ++k)
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0 || cp.v == 2 || cp.patterns.empty()) continue;
+      js.push_back(job(i, cdiv64(cp.n_rows, 256), (int64_t)cp.patterns.size(), k));
+    }
+  add_launch(P, seq, K_BXB, ST_NONE, js);
+  js.clear();
+  for (int i : all) {
+    const InstancePlan& ip = P->inst[i];
+    if (ip.n_v >= 2 && ip.n_o >= 2)
+      js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
+  }
+  add_launch(P, seq, K_BAG, ST_NONE, js);
+  for (int which = 0; which < 2; ++which) {
+    js.clear();
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      if (ip.n_a == 0) continue;
+      const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
+      js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(which ? N : M, 64), which));
+    }
+    add_launch(P, seq, K_BGG, ST_NONE, js);
+  }
+  js.clear();
+  for (int i : all) js.push_back(job(i, P->inst[i].n_occ, P->inst[i].n_corr));
+  add_launch(P, seq, K_BFOCK, ST_NONE, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n_l, 256), 1));
+  add_launch(P, seq, K_BDSUM, ST_NONE, js);
+  js.clear();
+  for (int i : all) {
+    const InstancePlan& ip = P->inst[i];
+    js.push_back(job(i, cdiv64(std::max(ip.n_corr, ip.n_a + ip.n_v), 256), 1 + ip.n_o));
+  }
+  add_launch(P, seq, K_BHFE, ST_NONE, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n));
+  add_launch(P, seq, K_BWSYM, ST_NONE, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n_l));
+  add_launch(P, seq, K_BDG, ST_NONE, js);
+  js.clear();
+  for (int i : all) {
+    const InstancePlan& ip = P->inst[i];
+    const int64_t nt = cdiv64(ip.n, 32);
+    for (int t = 0; t < ip.d.n_sets; ++t)
+      if (ip.d.rank[t] > 0) js.push_back(job(i, nt, nt * ip.d.rank[t], t));
+  }
+  add_launch(P, seq, K_BDB, ST_NONE, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n));
+  add_launch(P, seq, K_BDH, ST_NONE, js);
+  js.clear();
+  for (int i : all) js.push_back(job(i, cdiv64((int64_t)P->inst[i].pstrings.size(), 256), 1));
+  add_launch(P, seq, K_BDC, ST_NONE, js);
   // reference Hamiltonian of one instance: its tables and H_PP
   P->reference.resize(ni);
   for (int i = 0; i < ni; ++i) {
@@ -501,7 +598,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
   }
   out->inst.clear();
   out->inst.resize(n_inst);
-  size_t pers = 0, work = 0;
+  size_t pers = 0, work = 0, grad = 0;
   for (int ii = 0; ii < n_inst; ++ii) {
     const mrpt2_desc& d = dd[ii];
     InstancePlan& ip = out->inst[ii];
@@ -706,6 +803,39 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
     }
     ip.workspace_bytes = W.cur;
+    // ---- gradient workspace layout (adjoint) ----
+    Layout Gw;
+    ip.off_gs = Gw.take(16 * 8);
+    ip.off_Wb = Gw.take((size_t)ip.n * ip.n * 8);
+    ip.off_Wsym = Gw.take((size_t)ip.n * ip.n * 8);
+    ip.off_epsb = Gw.take((size_t)ip.n_corr * 8);
+    ip.off_fb = Gw.take((size_t)(ip.n_a + ip.n_v) * ip.n_o * 16);
+    ip.off_Gb = Gw.take((size_t)ip.n_o * (ip.n_a + ip.n_v) * ip.n_o * std::max(ip.n_a, 1) * 16);
+    ip.off_Ab = Gw.take(ip.n_v >= 2 ? (size_t)ip.n_pairs * ip.n_tp * kTile * kTile * 16 : 0);
+    ip.off_slabb = Gw.take((size_t)ip.n_occ * ip.n_corr * ip.n_l * 16);
+    ip.off_dgb = Gw.take((size_t)ip.n_l * ip.n * 8);
+    ip.off_dsumb = Gw.take((size_t)ip.n_l * 8);
+    ip.off_hb = Gw.take((size_t)ip.n * ip.n * 16);
+    ip.off_cb = Gw.take(NP * 16);
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      ClassPlan& cp = ip.cls[k];
+      const int64_t S = (int64_t)cp.strings.size();
+      cp.parts = 1;
+      cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
+      if (S > 0 && cp.n_rows > 0) {
+        // string-owned pass: enough (string block, row part) blocks to fill the
+        // device, partial coupling adjoints bounded to 256 MB
+        const int64_t sblk = (S + 255) / 256;
+        int64_t parts = std::min<int64_t>(cp.n_rows, std::max<int64_t>(1, (2048 + sblk - 1) / sblk));
+        parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)((256ull << 20) / (16 * std::max<int64_t>(cp.n_conn, 1)))));
+        cp.rows_per_part = (cp.n_rows + parts - 1) / parts;
+        cp.parts = (int)((cp.n_rows + cp.rows_per_part - 1) / cp.rows_per_part);
+      }
+      cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
+      cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);
+      cp.off_cbe = Gw.take((size_t)cp.parts * cp.n_conn * 16);
+    }
+    ip.grad_bytes = Gw.cur;
     // info
     mrpt2_info& inf = ip.info;
     std::memset(&inf, 0, sizeof(inf));
@@ -732,9 +862,12 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
     inf.bytes_factors = 16.0 * nl * ip.n * ip.n;
     ip.persistent_base = pers;
     ip.workspace_base = work;
+    ip.grad_base = grad;
     pers = align_up(pers + ip.persistent_bytes);
     work = align_up(work + ip.workspace_bytes);
+    grad = align_up(grad + ip.grad_bytes);
   }
+  out->grad_bytes = grad;
   out->off_flag = work;
   work = align_up(work + 256);
   out->off_insts = work;

@@ -46,6 +46,10 @@ struct ClassPlan {
   size_t off_strings = 0, off_conn_ptr = 0, off_conn = 0, off_pat = 0;
   // device offsets within the instance's workspace
   size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
+  // gradient workspace offsets (adjoint): coupling adjoints, string-pass partials
+  size_t off_Xb = 0, off_Tb = 0, off_cbe = 0;
+  int parts = 1;                       // row parts of the string-owned adjoint pass
+  int64_t rows_per_part = 0;
   bool dense_coef = false;             // coefficients as a dense [S][n_pat] table + masks
   int kernel = 0;                      // KERN_* below
   int64_t n_blocks = 0;                // partial sums written by the class's kernel
@@ -73,6 +77,10 @@ struct InstancePlan {
   size_t off_dg = 0, off_slab = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
   size_t off_hpp = 0, off_sigp = 0, off_scal = 0, off_dsum = 0, off_part = 0;
   size_t workspace_bytes = 0, workspace_base = 0;
+  // gradient workspace layout (adjoint)
+  size_t off_gs = 0, off_Wb = 0, off_Wsym = 0, off_epsb = 0, off_fb = 0, off_Gb = 0, off_Ab = 0;
+  size_t off_slabb = 0, off_dgb = 0, off_dsumb = 0, off_hb = 0, off_cb = 0;
+  size_t grad_bytes = 0, grad_base = 0;
   int64_t n_part = 0;                 // partial-sum slots
   size_t off_part_class[MRPT2_N_CLASS]{};
   int64_t n_part_class[MRPT2_N_CLASS]{};
@@ -86,7 +94,11 @@ struct InstancePlan {
 enum KernelId : int {
   K_CLEAR, K_PACK, K_DIAG, K_WPASS, K_EPS, K_DSUM, K_FOCK, K_GBUILD, K_HPP, K_SIGP, K_E0,
   K_ABUILD, K_ABUILD32, K_CTAB, K_XBUILD, K_DCOEF, K_E22, K_E12_8, K_E12_16, K_E12_24, K_E12_32,
-  K_E02, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH
+  K_E02, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
+  // adjoint
+  K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
+  K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
+  K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC
 };
 
 // Timing slots (mrpt2_energy_timed).
@@ -121,6 +133,8 @@ struct Plan {
   size_t off_jobs = 0;                // job table in the persistent region
   std::vector<JobH> jobs;
   std::vector<Launch> energy;         // launch sequence of mrpt2_energy (all instances)
+  std::vector<Launch> backward;       // launch sequence of mrpt2_energy_backward
+  size_t grad_bytes = 0;              // gradient workspace of mrpt2_energy_backward
   std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
   std::vector<char> host_blob;
   void* pinned = nullptr;             // host staging of the instance descriptors
