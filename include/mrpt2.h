@@ -223,6 +223,20 @@ mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, co
                                    size_t grad_workspace_bytes, const double* grad_e2,
                                    const mrpt2_grads* grads, hipStream_t stream, double* e2);
 
+/* mrpt2_energy_backward with its stages timed by HIP events on `stream`:
+ * stage_ms (host, 49 floats) receives milliseconds per stage: 0..22 as in
+ * mrpt2_energy_timed (the recomputed forward pass), 23 + k and 32 + k the
+ * row-owned and string-owned adjoint passes of class k, then 41 per-string
+ * adjoints, 42 reference energy, 43 coupling build, 44 pair integrals, 45
+ * occupied-block integrals, 46 Fock/orbital/pair-energy tables, 47 output
+ * gradients, 48 workspace clear.  Same errors as mrpt2_energy_backward;
+ * MRPT2_ERR_ARG if stage_ms is NULL. */
+mrpt2_status mrpt2_energy_backward_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                         void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                         size_t grad_workspace_bytes, const double* grad_e2,
+                                         const mrpt2_grads* grads, hipStream_t stream, double* e2,
+                                         float* stage_ms);
+
 /* Work decomposition of one excitation class: mrpt2_energy writes one
  * partial sum per block, sum over the block's external determinants of
  * |sigma_K|^2 / (E0 - H_KK) (not yet divided by ||C||^2).  A block covers

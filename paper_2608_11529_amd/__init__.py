@@ -185,7 +185,7 @@ class Engine:
         del keep
         return self.e2, self.parts, dict(zip(capi.STAGES, list(ms)))
 
-    def backward(self, insts, grad_e2=None):
+    def backward(self, insts, grad_e2=None, timed=False):
         """Gradients of E2 for every instance: list of (dh, [dB_t], dc)
         complex128 device tensors (dh, dB Hermitian-projected), and the
         device tensor of E2 per instance.  grad_e2: device float64 [n_inst]
@@ -210,11 +210,15 @@ class Engine:
                 garr[i].dB[t] = dB.data_ptr()
             garr[i].dc = dc.data_ptr()
             outs.append((dh, dBs, dc))
-        code = capi.lib().mrpt2_energy_backward(self.plan.handle, arr, self.persistent.data_ptr(),
-                                                self.workspace.data_ptr(), self.plan.workspace_bytes,
-                                                self.grad_workspace.data_ptr(), self.plan.grad_bytes,
-                                                grad_e2.data_ptr(), garr, self._sptr(), self.e2.data_ptr())
-        capi.check(code, "mrpt2_energy_backward")
+        args = (self.plan.handle, arr, self.persistent.data_ptr(), self.workspace.data_ptr(),
+                self.plan.workspace_bytes, self.grad_workspace.data_ptr(), self.plan.grad_bytes,
+                grad_e2.data_ptr(), garr, self._sptr(), self.e2.data_ptr())
+        if timed:
+            ms = (ctypes.c_float * capi.N_STAGE_B)()
+            capi.check(capi.lib().mrpt2_energy_backward_timed(*args, ms), "mrpt2_energy_backward_timed")
+            del keep
+            return outs, self.e2, dict(zip(capi.STAGES_B, list(ms)))
+        capi.check(capi.lib().mrpt2_energy_backward(*args), "mrpt2_energy_backward")
         del keep
         return outs, self.e2
 

@@ -18,6 +18,11 @@ N_STAGE = 23
 STAGES = (["factor_tables", "occupied_integrals", "reference_energy", "pair_integrals"]
           + ["sigma_%d%d" % c for c in CLASSES] + ["prep_%d%d" % c for c in CLASSES] + ["reduce"])
 
+N_STAGE_B = 49
+STAGES_B = (STAGES + ["bwd_row_%d%d" % c for c in CLASSES] + ["bwd_str_%d%d" % c for c in CLASSES]
+            + ["bwd_string_fin", "bwd_reference", "bwd_couplings", "bwd_pair_integrals",
+               "bwd_occupied_integrals", "bwd_tables", "bwd_outputs", "bwd_clear"])
+
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "inconsistent or unsupported sizes",
     3: "unsupported option", 4: "persistent or workspace region too small",
@@ -141,6 +146,10 @@ def lib():
         L.mrpt2_energy_backward.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp,
                                             ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp]
         L.mrpt2_energy_backward.restype = st
+        L.mrpt2_energy_backward_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp,
+                                                  ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp,
+                                                  ctypes.POINTER(ctypes.c_float)]
+        L.mrpt2_energy_backward_timed.restype = st
         L.mrpt2_plan_destroy.argtypes = [vp]
         L.mrpt2_plan_destroy.restype = None
         L.mrpt2_status_string.argtypes = [st]
@@ -159,5 +168,5 @@ EXPORTED = [
     "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
-    "mrpt2_plan_backward_size", "mrpt2_energy_backward",
+    "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed",
 ]

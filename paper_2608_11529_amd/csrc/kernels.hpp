@@ -118,6 +118,7 @@ struct ClassGrad {
   double2* Xb;         // [n_pat][n_rows] adjoint of X (v < 2)
   double* Tb;          // [parts][S]  per-part sums of dE2/dDelta over each string
   double2* cbe;        // [parts][n_conn] per-part coefficient adjoints per coupling
+  double* r1;          // [parts][S] class (2,2): per-part sums of |A|^2 / Delta per string
   int parts;           // row parts of the string-owned pass
   int64_t rows_per_part;
 };

@@ -275,6 +275,310 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
   if (live) cg.Tb[(int64_t)part * S + s] = tq;
 }
 
+// ---- class (2,2) ------------------------------------------------------------------
+// sigma_K = <ab||cc'> C_alpha, Delta = G(alpha) + Y_a(alpha) + Y_b(alpha) - W_ab as in
+// the forward kernel.  With w = 1/Delta and cw = |C_alpha|^2:
+//   Abar[cc'][ab] = (2/N) A S1,   S1 = sum_alpha cw w,          (written once)
+//   row constants receive -(1/N) |A|^2 S2,   S2 = sum_alpha cw w^2,
+//   Cbar_alpha    = (2/N) C_alpha sum_{cc', ab} |A|^2 w          (per-block partial R1),
+//   Tbar[alpha]   = -(1/N) sum_{cc', ab} cw |A|^2 w^2            (per-block partial),
+//   Uv tables: va(alpha, a) = cw sum_b |A|^2 w^2 contracted with the occupations
+//   of alpha per chunk of strings (W[a][t] for active t), likewise for b,
+//   Uc tables: per core pair, sum_a va contracted the same way.
+// Each thread owns 4 x 4 (a, b) of the 64 x 64 tile and walks the reference
+// strings in chunks of B22C staged in LDS; a block loops over the core pairs of
+// its group (kB22Group), so per-string partials are per (pair group, tile pair).
+// grid (n_tp, ceil(C(n_c,2) / kB22Group)), block 256.
+constexpr int B22C = 32;
+
+__device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                         const uint3 bid) {
+  __shared__ double sYa[B22C][64];
+  __shared__ double sYb[B22C][64];
+  __shared__ double sVa[B22C][64];
+  __shared__ double sVb[B22C][64];
+  __shared__ double sR1[B22C][16];
+  __shared__ double sG[B22C];
+  __shared__ double sCw[B22C];
+  __shared__ double sQ[B22C];
+  __shared__ uint64_t sStr[B22C];
+  __shared__ double ya0[64], yb0[64];
+  __shared__ double red[256];
+  const int tp = bid.x;
+  const int64_t nhp = cd.n_holes;
+  const int64_t hp0 = (int64_t)bid.y * kB22Group;
+  const int64_t hp1 = min(nhp, hp0 + kB22Group);
+  const int64_t part = (int64_t)bid.y * d.n_tp + tp;
+  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+  const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
+  const int nv = d.n_v, nc = d.n_c, na = d.n_a, np = d.n_p;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const double* __restrict__ W = d.W;
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  double* Tpart = cg.Tb + part * np;
+  double* Rpart = cg.r1 + part * np;
+  // contraction threads: (x = tid & 63, t = tg + 4 m)
+  const int cx = tid & 63, tg = tid >> 6;
+  double Ya[16], Yb[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) Ya[m] = Yb[m] = 0.0;
+  double wab[4][4];
+  bool ok[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
+      ok[i][j] = (a < b) && (b < nv);
+      wab[i][j] = ok[i][j] ? W[(gv + a) * n + gv + b] : 0.0;
+    }
+  for (int64_t hp = hp0; hp < hp1; ++hp) {
+    const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
+    const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+    double A2[4][4], S1[4][4], S2[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        A2[i][j] = ok[i][j] ? cabs2(Ablk[(ta + 16 * i) * 64 + tb + 16 * j]) : 0.0;
+        S1[i][j] = S2[i][j] = 0.0;
+      }
+    __syncthreads();
+    if (tid < 64) {
+      const int a = I * 64 + tid;
+      ya0[tid] = (a < nv) ? -d.eps[d.n_o + a] + W[(gfc + c0) * n + gv + a] + W[(gfc + c1) * n + gv + a] : -1.0;
+    } else if (tid < 128) {
+      const int b = J * 64 + tid - 64;
+      yb0[tid - 64] = (b < nv) ? -d.eps[d.n_o + b] + W[(gfc + c0) * n + gv + b] + W[(gfc + c1) * n + gv + b] : -1.0;
+    }
+    const double gconst = d.eps[c0] + d.eps[c1] - W[(gfc + c0) * n + gfc + c1];
+    double Zc = 0.0;   // thread t < n_a: sum over alpha with t of Q2(alpha)
+    for (int s0 = 0; s0 < np; s0 += B22C) {
+      __syncthreads();
+      for (int e = tid; e < B22C * 64; e += 256) {
+        const int al = e >> 6, l = e & 63;
+        const int s = s0 + al;
+        const int a = I * 64 + l, b = J * 64 + l;
+        double ya = ya0[l], yb = yb0[l];
+        if (s < np) {
+          if (a < nv) ya -= cd.Uv[(int64_t)s * nv + a];
+          if (b < nv) yb -= cd.Uv[(int64_t)s * nv + b];
+        }
+        sYa[al][l] = ya;
+        sYb[al][l] = yb;
+        sVa[al][l] = 0.0;
+        sVb[al][l] = 0.0;
+      }
+      for (int e = tid; e < B22C * 16; e += 256) sR1[e >> 4][e & 15] = 0.0;
+      if (tid < B22C) {
+        const int s = s0 + tid;
+        if (s < np) {
+          sG[tid] = cd.T[s] + cd.Uc[(int64_t)s * nc + c0] + cd.Uc[(int64_t)s * nc + c1] + gconst;
+          sCw[tid] = cabs2(d.c[s]);
+          sStr[tid] = d.pstrings[s];
+        } else {
+          sG[tid] = 1e30;
+          sCw[tid] = 0.0;
+          sStr[tid] = 0;
+        }
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int al = 0; al < B22C; al += 4) {
+        double gk[4], cw[4], za[4][4], yb[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          gk[k] = sG[al + k];
+          cw[k] = sCw[al + k];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) za[i][k] = gk[k] + sYa[al + k][ta + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
+        double r1[4] = {0.0, 0.0, 0.0, 0.0};
+        double va[4][4], vb[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) va[i][k] = vb[i][k] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            double dd[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dd[k] = ok[i][j] ? (za[i][k] + yb[j][k]) - wab[i][j] : 1.0;
+            const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
+            const double r = rcp_nr(p01 * p23);
+            const double r01 = r * p23, r23 = r * p01;
+            double w1[4];
+            w1[0] = r01 * dd[1];
+            w1[1] = r01 * dd[0];
+            w1[2] = r23 * dd[3];
+            w1[3] = r23 * dd[2];
+            const double a2 = A2[i][j];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const double w2 = w1[k] * w1[k];
+              S1[i][j] = fma(cw[k], w1[k], S1[i][j]);
+              S2[i][j] = fma(cw[k], w2, S2[i][j]);
+              r1[k] = fma(a2, w1[k], r1[k]);
+              const double q2 = a2 * w2;
+              va[i][k] += q2;
+              vb[j][k] += q2;
+            }
+          }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) atomicAdd(&sVa[al + k][ta + 16 * i], cw[k] * va[i][k]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) atomicAdd(&sVb[al + k][tb + 16 * j], cw[k] * vb[j][k]);
+          atomicAdd(&sR1[al + k][ta], r1[k]);
+        }
+      }
+      __syncthreads();
+      // per-string partials of this block
+      if (tid < B22C) {
+        const int s = s0 + tid;
+        double q = 0.0, r = 0.0;
+        for (int x = 0; x < 64; ++x) q += sVa[tid][x];
+        for (int x = 0; x < 16; ++x) r += sR1[tid][x];
+        sQ[tid] = q;
+        if (s < np) {
+          if (hp == hp0) {
+            Tpart[s] = -oneN * q;
+            Rpart[s] = r;
+          } else {
+            Tpart[s] -= oneN * q;
+            Rpart[s] += r;
+          }
+        }
+      }
+      __syncthreads();
+      // occupation contractions (Uv of a and b; Uc of the core pair)
+      for (int al = 0; al < B22C; ++al) {
+        const uint64_t str = sStr[al];
+        const double va = sVa[al][cx], vb = sVb[al][cx];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int t = tg + 4 * m;
+          if (t < na && ((str >> t) & 1ull)) {
+            Ya[m] += va;
+            Yb[m] += vb;
+          }
+        }
+      }
+      if (tid < na) {
+        for (int al = 0; al < B22C; ++al)
+          if ((sStr[al] >> tid) & 1ull) Zc += sQ[al];
+      }
+    }
+    // pair-integral adjoint tile (written once) and row constants
+    double2* Ab = g.Ab + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+    double rowa[4] = {0.0, 0.0, 0.0, 0.0}, colb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (ok[i][j]) {
+          const int li = (ta + 16 * i) * 64 + tb + 16 * j;
+          const double2 av = Ablk[li];
+          Ab[li] = make_double2(twoN * S1[i][j] * av.x, twoN * S1[i][j] * av.y);
+          const double gq = -oneN * A2[i][j] * S2[i][j];   // sum over alpha of Delta-bar
+          const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
+          atomicAdd(&g.Wb[(gv + a) * n + gv + b], -gq);
+          rowa[i] += gq;
+          colb[j] += gq;
+        }
+    __syncthreads();
+    if (tid < 128) sVa[tid >> 6][tid & 63] = 0.0;   // row sums in sVa[0], column sums in sVa[1]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) atomicAdd(&sVa[0][ta + 16 * i], rowa[i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) atomicAdd(&sVa[1][tb + 16 * j], colb[j]);
+    __syncthreads();
+    if (tid < 128) {
+      const int x = tid & 63;
+      const double v = sVa[tid >> 6][x];
+      const int vv = (tid < 64 ? I : J) * 64 + x;
+      if (vv < nv && v != 0.0) {
+        atomicAdd(&g.epsb[d.n_o + vv], -v);
+        atomicAdd(&g.Wb[(gfc + c0) * n + gv + vv], v);
+        atomicAdd(&g.Wb[(gfc + c1) * n + gv + vv], v);
+      }
+      red[tid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int x = 0; x < 64; ++x) tot += red[x];
+      atomicAdd(&g.epsb[c0], tot);
+      atomicAdd(&g.epsb[c1], tot);
+      atomicAdd(&g.Wb[(gfc + c0) * n + gfc + c1], -tot);
+    }
+    if (tid < na && Zc != 0.0) {
+      atomicAdd(&g.Wb[(gfc + c0) * n + ga + tid], -oneN * Zc);
+      atomicAdd(&g.Wb[(gfc + c1) * n + ga + tid], -oneN * Zc);
+    }
+  }
+  // Uv adjoints of this tile pair (summed over the block's core pairs)
+  const int av = I * 64 + cx, bv = J * 64 + cx;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int t = tg + 4 * m;
+    if (t >= na) continue;
+    if (av < nv && Ya[m] != 0.0) atomicAdd(&g.Wb[(gv + av) * n + ga + t], oneN * Ya[m]);
+    if (bv < nv && Yb[m] != 0.0) atomicAdd(&g.Wb[(gv + bv) * n + ga + t], oneN * Yb[m]);
+  }
+}
+
+// Per-string adjoints of class (2,2) from the per-block partials: Tbar (as in
+// the generic case) and Cbar_alpha = (2/N) C_alpha sum R1.  grid (ceil(np/256)).
+__device__ __forceinline__ void b22fin_body(const Dev& d, const ClassDev& cd, const GradDev& g,
+                                            const ClassGrad& cg, const uint3 bid) {
+  __shared__ double red[256];
+  const int np = d.n_p;
+  const int64_t s = (int64_t)bid.x * 256 + threadIdx.x;
+  double T = 0.0;
+  if (s < np) {
+    double R = 0.0;
+    for (int p = 0; p < cg.parts; ++p) {
+      T += cg.Tb[(int64_t)p * np + s];
+      R += cg.r1[(int64_t)p * np + s];
+    }
+    const double ea = -T;
+    const int64_t n = d.n, ga = d.n_fc + d.n_c;
+    uint64_t x = cd.strings[s];
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      atomicAdd(&g.epsb[d.n_c + t], ea);
+      uint64_t y = x;
+      while (y) {
+        const int u = __builtin_ctzll(y);
+        y &= y - 1;
+        atomicAdd(&g.Wb[(ga + t) * n + ga + u], ea);
+      }
+    }
+    const double k = 2.0 / d.scal[1] * R;
+    const double2 c = d.c[s];
+    catomic(&g.cb[s], make_double2(k * c.x, k * c.y));
+  }
+  red[threadIdx.x] = T;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(&g.scal[0], red[0]);
+}
+
 // ---- per-string adjoints -------------------------------------------------------
 // T[s] = (E0 - E_core) - E_act(s):  dE0 += Tbar[s];  E_act(s) = sum_{t in s} eps_t
 // + sum_{t<u in s} W_tu receives -Tbar[s].  Coupling adjoints go to C.

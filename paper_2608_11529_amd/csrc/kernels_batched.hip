@@ -115,6 +115,14 @@ __global__ void __launch_bounds__(256) k_b_bstr(MRPT2_ARGS) {
   MRPT2_JOB
   bstr_body<H, V>(I.d, I.cls[K], I.g, I.cg[K], bid);
 }
+__global__ void __launch_bounds__(256) k_b_b22(MRPT2_ARGS) {
+  MRPT2_JOB
+  b22_body(I.d, I.cls[0], I.g, I.cg[0], bid);
+}
+__global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
+  MRPT2_JOB
+  b22fin_body(I.d, I.cls[0], I.g, I.cg[0], bid);
+}
 __global__ void __launch_bounds__(256) k_b_bsfin(MRPT2_ARGS) {
   MRPT2_JOB
   bstrfin_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);

@@ -144,6 +144,7 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.Xb = (double2*)(G + cp.off_Xb);
   c.Tb = (double*)(G + cp.off_Tb);
   c.cbe = (double2*)(G + cp.off_cbe);
+  c.r1 = (double*)(G + cp.off_r1);
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
   return c;
@@ -288,6 +289,8 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BSTR10: hipLaunchKernelGGL((k_b_bstr<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BSTR00: hipLaunchKernelGGL((k_b_bstr<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BSFIN: hipLaunchKernelGGL(k_b_bsfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22: hipLaunchKernelGGL(k_b_b22, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BHPP: hipLaunchKernelGGL(k_b_bhpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BXB: hipLaunchKernelGGL(k_b_bxb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAG: hipLaunchKernelGGL(k_b_bag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
@@ -426,10 +429,10 @@ mrpt2_status mrpt2_plan_backward_size(mrpt2_plan_t plan, size_t* grad_workspace_
   return MRPT2_OK;
 }
 
-mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
-                                   void* workspace, size_t workspace_bytes, void* grad_workspace,
-                                   size_t grad_workspace_bytes, const double* grad_e2, const mrpt2_grads* grads,
-                                   hipStream_t st, double* e2) {
+static mrpt2_status backward_enqueue(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                     void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                     size_t grad_workspace_bytes, const double* grad_e2, const mrpt2_grads* grads,
+                                     hipStream_t st, double* e2, Timer& tm) {
   if (!plan || !in || !grads || !grad_e2 || !grad_workspace) return MRPT2_ERR_ARG;
   Plan& P = plan->p;
   mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
@@ -439,10 +442,42 @@ mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, co
   s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, e2, nullptr, nullptr, -1,
                    (char*)grad_workspace, grads, grad_e2);
   if (s != MRPT2_OK) return s;
+  return run(P, P.backward, (const char*)persistent, (char*)workspace, st, tm);
+}
+
+mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                   void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                   size_t grad_workspace_bytes, const double* grad_e2, const mrpt2_grads* grads,
+                                   hipStream_t st, double* e2) {
   Timer tm;
-  s = run(P, P.backward, (const char*)persistent, (char*)workspace, st, tm);
+  mrpt2_status s = backward_enqueue(plan, in, persistent, workspace, workspace_bytes, grad_workspace,
+                                    grad_workspace_bytes, grad_e2, grads, st, e2, tm);
   if (s != MRPT2_OK) return s;
-  return read_flag(P, workspace, st);
+  return read_flag(plan->p, workspace, st);
+}
+
+mrpt2_status mrpt2_energy_backward_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                         void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                         size_t grad_workspace_bytes, const double* grad_e2,
+                                         const mrpt2_grads* grads, hipStream_t st, double* e2, float* stage_ms) {
+  if (!stage_ms) return MRPT2_ERR_ARG;
+  Timer tm;
+  tm.on = true;
+  tm.st = st;
+  for (int i = 0; i < 256; ++i)
+    if (hipEventCreate(&tm.ev[i]) != hipSuccess) return MRPT2_ERR_HIP;
+  mrpt2_status s = backward_enqueue(plan, in, persistent, workspace, workspace_bytes, grad_workspace,
+                                    grad_workspace_bytes, grad_e2, grads, st, e2, tm);
+  if (s == MRPT2_OK) s = read_flag(plan->p, workspace, st);
+  for (int i = 0; i < ST_NB; ++i) stage_ms[i] = 0.0f;
+  if (s == MRPT2_OK || s == MRPT2_ERR_NUMERIC) {
+    for (int i = 0; i < tm.n; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]) == hipSuccess) stage_ms[tm.slot[i]] += ms;
+    }
+  }
+  for (int i = 0; i < 256; ++i) hipEventDestroy(tm.ev[i]);
+  return s;
 }
 
 mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,

@@ -426,37 +426,44 @@ void build_launches(Plan* P) {
     const int64_t n32 = (int64_t)(P->inst[i].grad_bytes / 32);
     js.push_back(job(i, std::max<int64_t>(1, std::min<int64_t>(cdiv64(n32, 256), 65536)), 1));
   }
-  add_launch(P, seq, K_BZERO, ST_NONE, js);
+  add_launch(P, seq, K_BZERO, ST_BZERO, js);
   for (const Launch& L : P->energy) seq->push_back(L);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr;
+    std::vector<JobH> jr, jsr, j22;
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
+      if (cp.kernel == KERN_E22) {
+        j22.push_back(job(i, ip.n_tp, cdiv64(cp.n_holes, kB22Group), k));
+        continue;
+      }
       jr.push_back(job(i, cdiv64(cp.n_rows, 256), 1, k));
       jsr.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
       lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
     }
-    add_launch(P, seq, K_BROW22 + k, ST_NONE, jr, lds);
-    add_launch(P, seq, K_BSTR22 + k, ST_NONE, jsr);
+    add_launch(P, seq, K_B22, ST_BROW0 + k, j22);
+    add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
+    add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
   }
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
     js.clear();
+    std::vector<JobH> j22;
     for (int i : all) {
       const ClassPlan& cp = P->inst[i].cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
-      js.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+      (cp.kernel == KERN_E22 ? j22 : js).push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
     }
-    add_launch(P, seq, K_BSFIN, ST_NONE, js);
+    add_launch(P, seq, K_B22FIN, ST_BFIN, j22);
+    add_launch(P, seq, K_BSFIN, ST_BFIN, js);
   }
   js.clear();
   for (int i : all) {
     const int np = (int)P->inst[i].pstrings.size();
     js.push_back(job(i, cdiv64(np, 16), cdiv64(np, 16)));
   }
-  add_launch(P, seq, K_BHPP, ST_NONE, js);
+  add_launch(P, seq, K_BHPP, ST_BHPP, js);
   js.clear();
   for (int k = 0; k < MRPT2_N_CLASS; ++k)
     for (int i : all) {
@@ -464,14 +471,14 @@ void build_launches(Plan* P) {
       if (cp.strings.empty() || cp.n_rows == 0 || cp.v == 2 || cp.patterns.empty()) continue;
       js.push_back(job(i, cdiv64(cp.n_rows, 256), (int64_t)cp.patterns.size(), k));
     }
-  add_launch(P, seq, K_BXB, ST_NONE, js);
+  add_launch(P, seq, K_BXB, ST_BXB, js);
   js.clear();
   for (int i : all) {
     const InstancePlan& ip = P->inst[i];
     if (ip.n_v >= 2 && ip.n_o >= 2)
       js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
   }
-  add_launch(P, seq, K_BAG, ST_NONE, js);
+  add_launch(P, seq, K_BAG, ST_BPAIR, js);
   for (int which = 0; which < 2; ++which) {
     js.clear();
     for (int i : all) {
@@ -480,26 +487,26 @@ void build_launches(Plan* P) {
       const int64_t M = (int64_t)ip.n_o * (ip.n_a + ip.n_v), N = (int64_t)ip.n_o * ip.n_a;
       js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(which ? N : M, 64), which));
     }
-    add_launch(P, seq, K_BGG, ST_NONE, js);
+    add_launch(P, seq, K_BGG, ST_BOCC, js);
   }
   js.clear();
   for (int i : all) js.push_back(job(i, P->inst[i].n_occ, P->inst[i].n_corr));
-  add_launch(P, seq, K_BFOCK, ST_NONE, js);
+  add_launch(P, seq, K_BFOCK, ST_BTAB, js);
   js.clear();
   for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n_l, 256), 1));
-  add_launch(P, seq, K_BDSUM, ST_NONE, js);
+  add_launch(P, seq, K_BDSUM, ST_BTAB, js);
   js.clear();
   for (int i : all) {
     const InstancePlan& ip = P->inst[i];
     js.push_back(job(i, cdiv64(std::max(ip.n_corr, ip.n_a + ip.n_v), 256), 1 + ip.n_o));
   }
-  add_launch(P, seq, K_BHFE, ST_NONE, js);
+  add_launch(P, seq, K_BHFE, ST_BTAB, js);
   js.clear();
   for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n));
-  add_launch(P, seq, K_BWSYM, ST_NONE, js);
+  add_launch(P, seq, K_BWSYM, ST_BTAB, js);
   js.clear();
   for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n_l));
-  add_launch(P, seq, K_BDG, ST_NONE, js);
+  add_launch(P, seq, K_BDG, ST_BTAB, js);
   js.clear();
   for (int i : all) {
     const InstancePlan& ip = P->inst[i];
@@ -507,13 +514,13 @@ void build_launches(Plan* P) {
     for (int t = 0; t < ip.d.n_sets; ++t)
       if (ip.d.rank[t] > 0) js.push_back(job(i, nt, nt * ip.d.rank[t], t));
   }
-  add_launch(P, seq, K_BDB, ST_NONE, js);
+  add_launch(P, seq, K_BDB, ST_BOUT, js);
   js.clear();
   for (int i : all) js.push_back(job(i, cdiv64(P->inst[i].n, 256), P->inst[i].n));
-  add_launch(P, seq, K_BDH, ST_NONE, js);
+  add_launch(P, seq, K_BDH, ST_BOUT, js);
   js.clear();
   for (int i : all) js.push_back(job(i, cdiv64((int64_t)P->inst[i].pstrings.size(), 256), 1));
-  add_launch(P, seq, K_BDC, ST_NONE, js);
+  add_launch(P, seq, K_BDC, ST_BOUT, js);
   // reference Hamiltonian of one instance: its tables and H_PP
   P->reference.resize(ni);
   for (int i = 0; i < ni; ++i) {
@@ -822,7 +829,10 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       const int64_t S = (int64_t)cp.strings.size();
       cp.parts = 1;
       cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
-      if (S > 0 && cp.n_rows > 0) {
+      if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E22) {
+        // (2,2) adjoint kernel: per-string partials per (core-pair group, tile pair)
+        cp.parts = (int)(((cp.n_holes + kB22Group - 1) / kB22Group) * ip.n_tp);
+      } else if (S > 0 && cp.n_rows > 0) {
         // string-owned pass: enough (string block, row part) blocks to fill the
         // device, partial coupling adjoints bounded to 256 MB
         const int64_t sblk = (S + 255) / 256;
@@ -833,7 +843,9 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
       cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);
-      cp.off_cbe = Gw.take((size_t)cp.parts * cp.n_conn * 16);
+      const bool b22 = cp.kernel == KERN_E22;
+      cp.off_cbe = Gw.take(b22 ? 0 : (size_t)cp.parts * cp.n_conn * 16);
+      cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
     }
     ip.grad_bytes = Gw.cur;
     // info

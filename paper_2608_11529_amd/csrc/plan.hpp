@@ -13,6 +13,7 @@ namespace mrpt2 {
 constexpr int kTile = 64;           // virtual tile edge of the pair-integral blocks
 constexpr int kMaxAct = 64;         // active spinors fit one 64-bit string
 constexpr int kMaxDenseJ = 32;      // patterns held in registers by the dense-coefficient kernels
+constexpr int kB22Group = 4;        // core pairs per block of the (2,2) adjoint kernel
 
 // Excitation classes, indexed as in mrpt2_info.
 constexpr int kClassH[MRPT2_N_CLASS] = {2, 1, 0, 2, 1, 0, 2, 1, 0};
@@ -47,7 +48,7 @@ struct ClassPlan {
   // device offsets within the instance's workspace
   size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
   // gradient workspace offsets (adjoint): coupling adjoints, string-pass partials
-  size_t off_Xb = 0, off_Tb = 0, off_cbe = 0;
+  size_t off_Xb = 0, off_Tb = 0, off_cbe = 0, off_r1 = 0;
   int parts = 1;                       // row parts of the string-owned adjoint pass
   int64_t rows_per_part = 0;
   bool dense_coef = false;             // coefficients as a dense [S][n_pat] table + masks
@@ -98,13 +99,17 @@ enum KernelId : int {
   // adjoint
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
-  K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC
+  K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
+  K_B22, K_B22FIN
 };
 
 // Timing slots (mrpt2_energy_timed).
 enum StageId : int {
   ST_NONE = -1, ST_TABLES = 0, ST_GBUILD = 1, ST_REF = 2, ST_ABUILD = 3, ST_SIGMA0 = 4,
-  ST_PREP0 = 13, ST_FINISH = 22, ST_N = 23
+  ST_PREP0 = 13, ST_FINISH = 22, ST_N = 23,
+  // adjoint (mrpt2_energy_backward_timed): per-class row and string passes, then the chain
+  ST_BROW0 = 23, ST_BSTR0 = 32, ST_BFIN = 41, ST_BHPP = 42, ST_BXB = 43, ST_BPAIR = 44, ST_BOCC = 45,
+  ST_BTAB = 46, ST_BOUT = 47, ST_BZERO = 48, ST_NB = 49
 };
 
 struct JobH {                         // host image of the device Job
