@@ -119,8 +119,10 @@ struct ClassGrad {
   double* Tb;          // [parts][S]  per-part sums of dE2/dDelta over each string
   double2* cbe;        // [parts][n_conn] per-part coefficient adjoints per coupling
   double* r1;          // [parts][S] class (2,2): per-part sums of |A|^2 / Delta per string
+  double2* dbp;        // [parts][S][n_pat] dense-coefficient adjoints (class (1,2)) or null
+  int row_split;       // string chunks of the row-owned pass (> 1: shared rows, atomics)
   int parts;           // row parts of the string-owned pass
-  int64_t rows_per_part;
+  int64_t rows_per_part;   // rows per part (tile pairs per part for class (1,2))
 };
 
 // Everything a kernel needs about one instance (uploaded once per call).

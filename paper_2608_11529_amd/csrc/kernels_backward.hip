@@ -143,7 +143,7 @@ __device__ __forceinline__ double string_delta(const ClassDev& cd, const Dev& d,
 //   y_t = sum_{s containing t} Delta-bar   (tables Uc, Uv: W of the row's
 //         core holes and virtual spinors with active spinor t)
 // then adds q and y into the adjoints of eps and W.
-// grid (ceil(rows / 256)), block 256, dynamic LDS n_a * 256 doubles.
+// grid (ceil(rows / 256), string chunks), block 256, dynamic LDS n_a * 256 doubles.
 template <int H, int V>
 __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
@@ -161,7 +161,13 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
   const double2* X = (V == 2) ? d.A : cd.X;
   double q = 0.0;
   const int64_t S = cd.n_str;
-  for (int64_t s = 0; s < S; ++s) {
+  // strings [s_lo, s_hi) of this block; with several string chunks the
+  // coupling adjoints of a row are shared and added atomically
+  const int nsc = cg.row_split;
+  const int64_t chunk = (S + nsc - 1) / nsc;
+  const int64_t s_lo = (int64_t)bid.y * chunk, s_hi = min(S, s_lo + chunk);
+  const bool shared_rows = nsc > 1;
+  for (int64_t s = s_lo; s < s_hi; ++s) {
     const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
     if (e1 == e0) continue;
     double2 sig = make_double2(0.0, 0.0);
@@ -182,7 +188,8 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
         double2 cv = d.c[cb & 0x7fffffff];
         if (cb < 0) cv = make_double2(-cv.x, -cv.y);
         double2* p = Xb + coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, rr);
-        *p = cadd(*p, cmul(sb, cconj(cv)));
+        if (shared_rows) catomic(p, cmul(sb, cconj(cv)));
+        else *p = cadd(*p, cmul(sb, cconj(cv)));
       }
       q += dl;
       uint64_t x = cd.strings[s];
@@ -579,6 +586,306 @@ __device__ __forceinline__ void b22fin_body(const Dev& d, const ClassDev& cd, co
   if (threadIdx.x == 0) atomicAdd(&g.scal[0], red[0]);
 }
 
+// ---- class (1,2) ---------------------------------------------------------------------
+// sigma_K = sum_j D[s][j] X_j with X_j = <ab||c t_j> (dense coefficients), and
+//   Delta = T + eps_c + Uc_c - eps_a - Uv_a - eps_b - Uv_b - W_ab + W_ca + W_cb.
+// Row pass (the forward kernel's layout, one thread per (a, b) of a 16 x 16
+// sub-tile, couplings and their adjoints in registers): Abar for the core-active
+// pairs, the row constants, and the Uv tables (per-string sums over b and over a
+// reduced across lanes, contracted with the string occupations per chunk).
+// grid (16 n_tp, n_c), block 256.
+constexpr int B12C = 32;
+
+__device__ __forceinline__ double xsum16(double v) {   // sum over the 16 lanes sharing tid >> 4
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+__device__ __forceinline__ double xsum4(double v) {    // sum over lanes l, l^16, l^32, l^48
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+template <int MJ>
+__device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid) {
+  __shared__ double sUa[B12C][16];
+  __shared__ double sUb[B12C][16];
+  __shared__ double sG[B12C];
+  __shared__ double2 sD[B12C][MJ];
+  __shared__ uint32_t sM[B12C];
+  __shared__ uint64_t sStr[B12C];
+  __shared__ double sVa[B12C][16];
+  __shared__ double sVb[B12C][16];
+  __shared__ double sRow[16], sCol[16];
+  const int tp = bid.x >> 4, sub = bid.x & 15;
+  const int sa = sub >> 2, sb = sub & 3;
+  const int c = bid.y;
+  const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+  if (I == Jt && sa > sb) return;            // sub-tile below the diagonal: no rows
+  const int tid = threadIdx.x, ia = tid >> 4, ib = tid & 15;
+  const int la = sa * 16 + ia, lb = sb * 16 + ib;
+  const int nv = d.n_v, nc = d.n_c, na = d.n_a;
+  int a = I * 64 + la, b = Jt * 64 + lb;
+  const bool valid = (a < b) && (b < nv);
+  if (!valid) {
+    a = 0;
+    b = nv > 1 ? 1 : 0;
+  }
+  const int J = cd.n_pat;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const double* __restrict__ W = d.W;
+  const double rowc = -d.eps[d.n_o + a] - d.eps[d.n_o + b] - W[(gv + a) * n + gv + b] + W[(gfc + c) * n + gv + a] +
+                      W[(gfc + c) * n + gv + b];
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  double2 X[MJ], Xb[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j) {
+    X[j] = make_double2(0.0, 0.0);
+    Xb[j] = make_double2(0.0, 0.0);
+    if (j < J) {
+      const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
+      X[j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
+    }
+  }
+  const double epsc = d.eps[c];
+  const int cx = tid & 15, tg = tid >> 4;
+  double Ya[4] = {0.0, 0.0, 0.0, 0.0}, Yb[4] = {0.0, 0.0, 0.0, 0.0};
+  double q = 0.0;
+  const int64_t S = cd.n_str;
+  for (int64_t s0 = 0; s0 < S; s0 += B12C) {
+    __syncthreads();
+    for (int e = tid; e < B12C * 16; e += 256) {
+      const int sl = e >> 4, l = e & 15;
+      const int64_t s = s0 + sl;
+      const int aa = I * 64 + sa * 16 + l, bb = Jt * 64 + sb * 16 + l;
+      sUa[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
+      sUb[sl][l] = (s < S && bb < nv) ? cd.Uv[s * nv + bb] : 0.0;
+      sVa[sl][l] = 0.0;
+      sVb[sl][l] = 0.0;
+    }
+    for (int e = tid; e < B12C * MJ; e += 256) {
+      const int sl = e / MJ, j = e % MJ;
+      const int64_t s = s0 + sl;
+      sD[sl][j] = (s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
+    }
+    if (tid < B12C) {
+      const int64_t s = s0 + tid;
+      sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : 1e30;
+      sM[tid] = (s < S) ? cd.mask[s] : 0u;
+      sStr[tid] = (s < S) ? cd.strings[s] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int sl = 0; sl < B12C; sl += 4) {
+      const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
+      double2 sg[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < MJ; ++j)
+        if (um & (1u << j)) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
+        }
+      double dd[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dd[k] = valid ? (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib] : 1.0;
+      const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
+      const double r = rcp_nr(p01 * p23);
+      const double r01 = r * p23, r23 = r * p01;
+      double w[4];
+      w[0] = r01 * dd[1];
+      w[1] = r01 * dd[0];
+      w[2] = r23 * dd[3];
+      w[3] = r23 * dd[2];
+      double2 sbv[4];
+      double dl[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 t = make_double2(sg[k].x * w[k], sg[k].y * w[k]);
+        sbv[k] = valid ? make_double2(twoN * t.x, twoN * t.y) : make_double2(0.0, 0.0);
+        dl[k] = valid ? -oneN * cabs2(t) : 0.0;
+        q += dl[k];
+      }
+#pragma unroll
+      for (int j = 0; j < MJ; ++j)
+        if (um & (1u << j)) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Xb[j] = cadd(Xb[j], cmul(sbv[k], cconj(sD[sl + k][j])));
+        }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double va = xsum16(dl[k]);
+        if (ib == 0) sVa[sl + k][ia] = va;
+        const double vb = xsum4(dl[k]);
+        if ((tid & 63) < 16) atomicAdd(&sVb[sl + k][ib], vb);
+      }
+    }
+    __syncthreads();
+    for (int sl = 0; sl < B12C; ++sl) {
+      const uint64_t str = sStr[sl];
+      const double va = sVa[sl][cx], vb = sVb[sl][cx];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int t = tg + 16 * m;
+        if (t < na && ((str >> t) & 1ull)) {
+          Ya[m] += va;
+          Yb[m] += vb;
+        }
+      }
+    }
+  }
+  // pair-integral adjoints of this row (each written once)
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+      if (j < J) {
+        const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
+        g.Ab[(pr * d.n_tp + tp) * 4096 + la * 64 + lb] = Xb[j];
+      }
+    atomicAdd(&g.Wb[(gv + a) * n + gv + b], -q);
+  }
+  // row constants: eps and W of c, a, b
+  __syncthreads();
+  if (tid < 16) {
+    sRow[tid] = 0.0;
+    sCol[tid] = 0.0;
+  }
+  __syncthreads();
+  const double qr = xsum16(q);
+  if (ib == 0) sRow[ia] = qr;
+  const double qc = xsum4(q);
+  if ((tid & 63) < 16) atomicAdd(&sCol[ib], qc);
+  __syncthreads();
+  if (tid < 32) {
+    const bool isa = tid < 16;
+    const int x = tid & 15;
+    const double v = isa ? sRow[x] : sCol[x];
+    const int vv = isa ? I * 64 + sa * 16 + x : Jt * 64 + sb * 16 + x;
+    if (vv < nv && v != 0.0) {
+      atomicAdd(&g.epsb[d.n_o + vv], -v);
+      atomicAdd(&g.Wb[(gfc + c) * n + gv + vv], v);
+    }
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int y = 0; y < 16; ++y) tot += sRow[y];
+      atomicAdd(&g.epsb[c], tot);
+    }
+  }
+  // Uv tables of the sub-tile's a and b
+  const int av = I * 64 + sa * 16 + cx, bv = Jt * 64 + sb * 16 + cx;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int t = tg + 16 * m;
+    if (t >= na) continue;
+    if (av < nv && Ya[m] != 0.0) atomicAdd(&g.Wb[(gv + av) * n + ga + t], -Ya[m]);
+    if (bv < nv && Yb[m] != 0.0) atomicAdd(&g.Wb[(gv + bv) * n + ga + t], -Yb[m]);
+  }
+}
+
+// String pass of class (1,2): one thread per string (its dense coefficients
+// and their adjoints in registers), the couplings of one a-row (64 b of a
+// tile) staged in LDS at a time.  Per part (core c, group of tile pairs):
+//   Dbar[s][j] = sum_rows conj(X_j) sigma-bar,   Tbar[s] = sum_rows Delta-bar,
+// and the Uc table of c: W[c][t] += sum_s [t in s] Tbar_part[s].
+// grid (ceil(S/256), n_c * groups), block 256.
+template <int MJ>
+__device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid) {
+  __shared__ double2 sX[64][MJ];
+  __shared__ double sQ[64];
+  __shared__ double sZ[64];
+  const int tid = threadIdx.x;
+  const int64_t S = cd.n_str;
+  int64_t s = (int64_t)bid.x * 256 + tid;
+  const bool live = s < S;
+  if (!live) s = S - 1;
+  const int part = bid.y;
+  const int ngr = (int)((d.n_tp + cg.rows_per_part - 1) / cg.rows_per_part);
+  const int c = part / ngr;
+  const int64_t tp0 = (int64_t)(part % ngr) * cg.rows_per_part;
+  const int64_t tp1 = min(d.n_tp, tp0 + cg.rows_per_part);
+  const int J = cd.n_pat;
+  const int nv = d.n_v, nc = d.n_c, na = d.n_a;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  double2 D[MJ], Db[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j) {
+    D[j] = (j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
+    Db[j] = make_double2(0.0, 0.0);
+  }
+  uint32_t um = live ? cd.mask[s] : 0u;
+  for (int o = 1; o < 64; o <<= 1) um |= __shfl_xor(um, o, 64);
+  const double Gs = cd.T[s] + cd.Uc[s * nc + c] + d.eps[c];
+  const double* Uvs = cd.Uv + s * nv;
+  double tq = 0.0;
+  if (tid < 64) sZ[tid] = 0.0;
+  __syncthreads();
+  for (int64_t tp = tp0; tp < tp1; ++tp) {
+    const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+    for (int la = 0; la < 64; ++la) {
+      const int a = I * 64 + la;
+      if (a >= nv || Jt * 64 + 63 <= a) break;
+      __syncthreads();
+      for (int e = tid; e < 64 * MJ; e += 256) {
+        const int j = e >> 6, lb = e & 63;
+        const int b = Jt * 64 + lb;
+        double2 v = make_double2(0.0, 0.0);
+        if (j < J && b > a && b < nv) {
+          const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
+          v = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
+        }
+        sX[lb][j] = v;
+      }
+      if (tid < 64) {
+        const int b = Jt * 64 + tid;
+        sQ[tid] = (b > a && b < nv) ? -d.eps[d.n_o + a] - d.eps[d.n_o + b] - d.W[(gv + a) * n + gv + b] +
+                                          d.W[(gfc + c) * n + gv + a] + d.W[(gfc + c) * n + gv + b]
+                                    : 0.0;
+      }
+      __syncthreads();
+      const double ga_s = Gs - Uvs[a];
+      const int lb0 = max(0, a + 1 - Jt * 64);
+      const int lb1 = min(64, nv - Jt * 64);
+      for (int lb = lb0; lb < lb1; ++lb) {
+        const int b = Jt * 64 + lb;
+        double2 sg = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+          if (um & (1u << j)) sg = cfma(D[j], sX[lb][j], sg);
+        const double del = ga_s + sQ[lb] - Uvs[b];
+        const double w = 1.0 / del;
+        const double2 t = make_double2(sg.x * w, sg.y * w);
+        const double2 sbv = make_double2(twoN * t.x, twoN * t.y);
+        tq -= oneN * cabs2(t);
+#pragma unroll
+        for (int j = 0; j < MJ; ++j)
+          if (um & (1u << j)) Db[j] = cadd(Db[j], cmul(sbv, cconj(sX[lb][j])));
+      }
+    }
+  }
+  if (live) {
+    double2* out = cg.dbp + ((int64_t)part * S + s) * J;
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+      if (j < J) out[j] = Db[j];
+    cg.Tb[(int64_t)part * S + s] = tq;
+    uint64_t x = cd.strings[s];
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      atomicAdd(&sZ[t], tq);
+    }
+  }
+  __syncthreads();
+  if (tid < na && sZ[tid] != 0.0) atomicAdd(&g.Wb[(gfc + c) * n + ga + tid], sZ[tid]);
+}
+
 // ---- per-string adjoints -------------------------------------------------------
 // T[s] = (E0 - E_core) - E_act(s):  dE0 += Tbar[s];  E_act(s) = sum_{t in s} eps_t
 // + sum_{t<u in s} W_tu receives -Tbar[s].  Coupling adjoints go to C.
@@ -607,8 +914,15 @@ __device__ __forceinline__ void bstrfin_body(const Dev& d, const ClassDev& cd, c
     }
     for (int e = cd.conn_ptr[s]; e < cd.conn_ptr[s + 1]; ++e) {
       double2 v = make_double2(0.0, 0.0);
-      for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.cbe[(int64_t)p * cd.n_conn + e]);
-      catomic(&g.cb[cd.conn[2 * e] & 0x7fffffff], v);
+      const int32_t cb = cd.conn[2 * e];
+      if (cg.dbp) {          // dense coefficients: Cbar_beta += sign Dbar[s][j]
+        const int j = cd.conn[2 * e + 1];
+        for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.dbp[((int64_t)p * S + s) * cd.n_pat + j]);
+        if (cb < 0) v = make_double2(-v.x, -v.y);
+      } else {
+        for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.cbe[(int64_t)p * cd.n_conn + e]);
+      }
+      catomic(&g.cb[cb & 0x7fffffff], v);
     }
   }
   red[threadIdx.x] = T;

@@ -123,6 +123,16 @@ __global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
   MRPT2_JOB
   b22fin_body(I.d, I.cls[0], I.g, I.cg[0], bid);
 }
+template <int MJ>
+__global__ void __launch_bounds__(256) k_b_b12r(MRPT2_ARGS) {
+  MRPT2_JOB
+  b12r_body<MJ>(I.d, I.cls[1], I.g, I.cg[1], bid);
+}
+template <int MJ>
+__global__ void __launch_bounds__(256) k_b_b12s(MRPT2_ARGS) {
+  MRPT2_JOB
+  b12s_body<MJ>(I.d, I.cls[1], I.g, I.cg[1], bid);
+}
 __global__ void __launch_bounds__(256) k_b_bsfin(MRPT2_ARGS) {
   MRPT2_JOB
   bstrfin_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);

@@ -145,6 +145,8 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.Tb = (double*)(G + cp.off_Tb);
   c.cbe = (double2*)(G + cp.off_cbe);
   c.r1 = (double*)(G + cp.off_r1);
+  c.dbp = cp.kernel == KERN_E12 ? (double2*)(G + cp.off_dbp) : nullptr;
+  c.row_split = cp.row_split;
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
   return c;
@@ -291,6 +293,14 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BSFIN: hipLaunchKernelGGL(k_b_bsfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22: hipLaunchKernelGGL(k_b_b22, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12R_8: hipLaunchKernelGGL((k_b_b12r<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12R_16: hipLaunchKernelGGL((k_b_b12r<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12R_24: hipLaunchKernelGGL((k_b_b12r<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12R_32: hipLaunchKernelGGL((k_b_b12r<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12S_8: hipLaunchKernelGGL((k_b_b12s<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12S_16: hipLaunchKernelGGL((k_b_b12s<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12S_24: hipLaunchKernelGGL((k_b_b12s<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12S_32: hipLaunchKernelGGL((k_b_b12s<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BHPP: hipLaunchKernelGGL(k_b_bhpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BXB: hipLaunchKernelGGL(k_b_bxb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAG: hipLaunchKernelGGL(k_b_bag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;

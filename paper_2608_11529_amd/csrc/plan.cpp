@@ -429,7 +429,7 @@ void build_launches(Plan* P) {
   add_launch(P, seq, K_BZERO, ST_BZERO, js);
   for (const Launch& L : P->energy) seq->push_back(L);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22;
+    std::vector<JobH> jr, jsr, j22, j12r[4], j12s[4];
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
@@ -439,11 +439,22 @@ void build_launches(Plan* P) {
         j22.push_back(job(i, ip.n_tp, cdiv64(cp.n_holes, kB22Group), k));
         continue;
       }
-      jr.push_back(job(i, cdiv64(cp.n_rows, 256), 1, k));
+      if (cp.kernel == KERN_E12) {
+        const size_t J = cp.patterns.size();
+        const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
+        j12r[v].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
+        j12s[v].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
+        continue;
+      }
+      jr.push_back(job(i, cdiv64(cp.n_rows, 256), cp.row_split, k));
       jsr.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
       lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
     }
     add_launch(P, seq, K_B22, ST_BROW0 + k, j22);
+    for (int v = 0; v < 4; ++v) {
+      add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v]);
+      add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
+    }
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
   }
@@ -829,9 +840,18 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       const int64_t S = (int64_t)cp.strings.size();
       cp.parts = 1;
       cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
+      cp.row_split = 1;
       if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E22) {
         // (2,2) adjoint kernel: per-string partials per (core-pair group, tile pair)
         cp.parts = (int)(((cp.n_holes + kB22Group - 1) / kB22Group) * ip.n_tp);
+      } else if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E12) {
+        // (1,2) string pass: parts = core x group of tile pairs
+        const int64_t sblk = (S + 255) / 256;
+        int64_t ngr = std::min<int64_t>(ip.n_tp, std::max<int64_t>(1, (2048 + sblk * cp.n_holes - 1) / (sblk * cp.n_holes)));
+        const int64_t tpg = (ip.n_tp + ngr - 1) / ngr;
+        ngr = (ip.n_tp + tpg - 1) / tpg;
+        cp.rows_per_part = tpg;
+        cp.parts = (int)(cp.n_holes * ngr);
       } else if (S > 0 && cp.n_rows > 0) {
         // string-owned pass: enough (string block, row part) blocks to fill the
         // device, partial coupling adjoints bounded to 256 MB
@@ -840,12 +860,16 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
         parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)((256ull << 20) / (16 * std::max<int64_t>(cp.n_conn, 1)))));
         cp.rows_per_part = (cp.n_rows + parts - 1) / parts;
         cp.parts = (int)((cp.n_rows + cp.rows_per_part - 1) / cp.rows_per_part);
+        // row pass: few rows -> split the strings over blocks as well
+        const int64_t rb = (cp.n_rows + 255) / 256;
+        if (rb < 512) cp.row_split = (int)std::min<int64_t>(S, (2048 + rb - 1) / rb);
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
       cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);
-      const bool b22 = cp.kernel == KERN_E22;
-      cp.off_cbe = Gw.take(b22 ? 0 : (size_t)cp.parts * cp.n_conn * 16);
+      const bool b22 = cp.kernel == KERN_E22, b12 = cp.kernel == KERN_E12;
+      cp.off_cbe = Gw.take((b22 || b12) ? 0 : (size_t)cp.parts * cp.n_conn * 16);
       cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
+      cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
     }
     ip.grad_bytes = Gw.cur;
     // info
