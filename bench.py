@@ -148,6 +148,47 @@ def bench_batched(args):
     print("[bench] c3 batched %.1f ms, sequential %.1f ms, max |dE2| batched vs sequential %.3g"
           % (ms_batched, ms_seq, dmax), file=sys.stderr, flush=True)
     dom = max(stage, key=lambda k: stage[k])
+    bwd = None
+    if args.backward_steps > 0:
+        # adjoint: the gradients of all 64 instances with their inputs exceed
+        # one GPU's memory, so the batched and the sequential adjoint are
+        # compared on the first 16 instances
+        del singles, eng
+        torch.cuda.empty_cache()
+        nb = 16
+        sub = ins[:nb]
+        bplan = M.Plan([M.desc_of_problem(pb, precision=prec) for pb in pbs[:nb]])
+        beng = M.Engine(bplan, dev)
+        n_ext_b = sum(bplan.info(i).n_ext for i in range(nb))
+        beng.backward(sub)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.backward_steps):
+            outs_b, _ = beng.backward(sub)
+        torch.cuda.synchronize()
+        ms_bb = (time.perf_counter() - t0) * 1000.0 / args.backward_steps
+        ref = [(x[0].clone(), x[2].clone()) for x in outs_b]
+        del outs_b, beng
+        torch.cuda.empty_cache()
+        seng = [M.Engine(M.Plan(M.desc_of_problem(pb, precision=prec)), dev) for pb in pbs[:nb]]
+        for i, e1 in enumerate(seng):
+            e1.backward([sub[i]])
+            e1.grad_workspace = None
+        torch.cuda.synchronize()
+        dgrad = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.backward_steps):
+            for i, e1 in enumerate(seng):
+                (dh, _, dc), = e1.backward([sub[i]])[0]
+                e1.grad_workspace = None
+                dgrad = max(dgrad, float((dh - ref[i][0]).abs().max().item()), float((dc - ref[i][1]).abs().max().item()))
+        torch.cuda.synchronize()
+        ms_bs = (time.perf_counter() - t0) * 1000.0 / args.backward_steps
+        print("[bench] c3 backward (16 instances): batched %.1f ms, sequential %.1f ms" % (ms_bb, ms_bs),
+              file=sys.stderr, flush=True)
+        bwd = {"instances": nb, "n_ext": n_ext_b, "batched_ms": ms_bb, "sequential_ms": ms_bs,
+               "grad_evals_per_s": nb * 1000.0 / ms_bb, "max_abs_dgrad_batched_vs_sequential": dgrad,
+               "note": "sequential timing includes the per-call gradient workspace allocation"}
     return {
         "metric": "external dets/sec + E2 evals/sec (mixed vs FP64, |dE2| Eh), 1 MI355X",
         "value": n_ext / (ms_batched * 1e-3), "unit": "dets/s",
@@ -162,6 +203,7 @@ def bench_batched(args):
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
         "roofline": {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
                      "frac": None, "traffic": None, "ms_per_launch": stage[dom]},
+        "backward": bwd,
     }
 
 
@@ -173,6 +215,8 @@ def main():
     ap.add_argument("--config", default="c4")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--backward-steps", type=int, default=1,
+                    help="timed adjoint calls after the forward measurement (0: none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (N=%d requested); the multi-GPU "
@@ -283,6 +327,36 @@ def main():
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
         "roofline": roof,
     }
+    if args.backward_steps > 0:
+        # adjoint of the headline form: one call recomputes the forward pass and
+        # returns dE2/dh, dE2/dB (every set) and dE2/dC
+        for p in list(engs):
+            if p != args.precision:
+                del engs[p]
+        eng = engs[args.precision]
+        del res
+        torch.cuda.empty_cache()
+        bsum, t0 = {}, time.perf_counter()
+        for _ in range(args.backward_steps):
+            outs, _, bms = eng.backward(insts, timed=True)
+            for k, v in bms.items():
+                bsum[k] = bsum.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        bwd_ms = (time.perf_counter() - t0) * 1000.0 / args.backward_steps
+        (dh, dBs, dc), = outs
+        bst = {k: v / args.backward_steps for k, v in bsum.items()}
+        out["backward"] = {
+            "precision": args.precision, "steps": args.backward_steps, "ms_per_step": bwd_ms,
+            "grad_evals_per_s": 1000.0 / bwd_ms, "dets_per_s": info.n_ext / (bwd_ms * 1e-3),
+            "ratio_to_forward": bwd_ms / ms_per_step,
+            "max_abs_grad": {"dh": float(dh.abs().max().item()), "dc": float(dc.abs().max().item()),
+                             "dB": [float(x.abs().max().item()) for x in dBs]},
+            "stages_ms": {k: round(v, 2) for k, v in bst.items() if v > 0.05},
+        }
+        print("[bench] backward (%s): %.1f ms/step (%.2f x forward)" % (args.precision, bwd_ms, bwd_ms / ms_per_step),
+              file=sys.stderr, flush=True)
+        del outs, dh, dBs, dc
+        eng.grad_workspace = None
     if not args.no_cpu_baseline:
         del Bs, h, engs, eng
         torch.cuda.empty_cache()

@@ -889,18 +889,19 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
 // ---- per-string adjoints -------------------------------------------------------
 // T[s] = (E0 - E_core) - E_act(s):  dE0 += Tbar[s];  E_act(s) = sum_{t in s} eps_t
 // + sum_{t<u in s} W_tu receives -Tbar[s].  Coupling adjoints go to C.
-// grid (ceil(S / 256)), block 256.
+// Thread i handles string i (if i < S) and coupling i (if i < n_conn).
+// grid (ceil(max(S, n_conn) / 256)), block 256.
 __device__ __forceinline__ void bstrfin_body(const Dev& d, const ClassDev& cd, const GradDev& g,
                                              const ClassGrad& cg, const uint3 bid) {
   __shared__ double red[256];
   const int64_t S = cd.n_str;
-  const int64_t s = (int64_t)bid.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
   double T = 0.0;
-  if (s < S) {
-    for (int p = 0; p < cg.parts; ++p) T += cg.Tb[(int64_t)p * S + s];
+  if (i < S) {
+    for (int p = 0; p < cg.parts; ++p) T += cg.Tb[(int64_t)p * S + i];
     const double ea = -T;
     const int64_t n = d.n, ga = d.n_fc + d.n_c;
-    uint64_t x = cd.strings[s];
+    uint64_t x = cd.strings[i];
     while (x) {
       const int t = __builtin_ctzll(x);
       x &= x - 1;
@@ -912,18 +913,25 @@ __device__ __forceinline__ void bstrfin_body(const Dev& d, const ClassDev& cd, c
         atomicAdd(&g.Wb[(ga + t) * n + ga + u], ea);
       }
     }
-    for (int e = cd.conn_ptr[s]; e < cd.conn_ptr[s + 1]; ++e) {
-      double2 v = make_double2(0.0, 0.0);
-      const int32_t cb = cd.conn[2 * e];
-      if (cg.dbp) {          // dense coefficients: Cbar_beta += sign Dbar[s][j]
-        const int j = cd.conn[2 * e + 1];
-        for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.dbp[((int64_t)p * S + s) * cd.n_pat + j]);
-        if (cb < 0) v = make_double2(-v.x, -v.y);
-      } else {
-        for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.cbe[(int64_t)p * cd.n_conn + e]);
+  }
+  if (i < cd.n_conn) {
+    const int32_t cb = cd.conn[2 * i];
+    double2 v = make_double2(0.0, 0.0);
+    if (cg.dbp) {          // dense coefficients: Cbar_beta += sign Dbar[s][j]
+      // string of coupling i: the last s with conn_ptr[s] <= i
+      int64_t lo = 0, hi = S - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (cd.conn_ptr[mid] <= i) lo = mid;
+        else hi = mid - 1;
       }
-      catomic(&g.cb[cb & 0x7fffffff], v);
+      const int j = cd.conn[2 * i + 1];
+      for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.dbp[((int64_t)p * S + lo) * cd.n_pat + j]);
+      if (cb < 0) v = make_double2(-v.x, -v.y);
+    } else {
+      for (int p = 0; p < cg.parts; ++p) v = cadd(v, cg.cbe[(int64_t)p * cd.n_conn + i]);
     }
+    catomic(&g.cb[cb & 0x7fffffff], v);
   }
   red[threadIdx.x] = T;
   __syncthreads();

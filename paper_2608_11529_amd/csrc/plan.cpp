@@ -464,7 +464,8 @@ void build_launches(Plan* P) {
     for (int i : all) {
       const ClassPlan& cp = P->inst[i].cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
-      (cp.kernel == KERN_E22 ? j22 : js).push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+      if (cp.kernel == KERN_E22) j22.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+      else js.push_back(job(i, cdiv64(std::max<int64_t>((int64_t)cp.strings.size(), cp.n_conn), 256), 1, k));
     }
     add_launch(P, seq, K_B22FIN, ST_BFIN, j22);
     add_launch(P, seq, K_BSFIN, ST_BFIN, js);

@@ -153,3 +153,19 @@ def test_finite_differences_c1():
         num = (4 * v[1] - v[0]) / 3
         print(f"[gpu] c1 direction {k}: analytic {ana:.12e} fd {num:.12e}", flush=True)
         assert abs(num - ana) <= 1e-6 * max(abs(ana), 1e-3), (k, num, ana)
+
+
+@pytest.mark.parametrize("name", ["s_tiles", "c0"])
+def test_mixed_precision_gradient_close_to_fp64(name):
+    """The mixed form recomputes its FP32-MFMA pair integrals in the adjoint's
+    forward pass; its gradient stays within 1e-6 (relative to the largest
+    entry) of the FP64 one."""
+    pb, plan, eng, h, Bs, c, _, _ = gpu_inputs(name, precision=0)
+    (dh, dB, dc), = eng.backward([(h, Bs, c)])[0]
+    dh, dB, dc = dh.cpu().numpy(), [x.cpu().numpy() for x in dB], dc.cpu().numpy()
+    _, _, eng32, _, _, _, _, _ = gpu_inputs(name, precision=1)
+    (mh, mB, mc), = eng32.backward([(h, Bs, c)])[0]
+    assert close(mh.cpu().numpy(), dh, 1e-6)[0]
+    assert close(mc.cpu().numpy(), dc, 1e-6)[0]
+    for x, y in zip(mB, dB):
+        assert close(x.cpu().numpy(), y, 1e-6)[0]
