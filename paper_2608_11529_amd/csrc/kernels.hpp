@@ -78,6 +78,7 @@ struct ClassDev {
   const int32_t* conn_ptr;
   const int32_t* conn;
   const Pattern* pat;
+  const int32_t* ekey;   // per coupling: integral key | sign << 31
   double* T;     // [S]
   double* Uc;    // [S][n_c]
   double* Uv;    // [S][n_v]
@@ -120,6 +121,7 @@ struct ClassGrad {
   double2* cbe;        // [parts][n_conn] per-part coefficient adjoints per coupling
   double* r1;          // [parts][S] class (2,2): per-part sums of |A|^2 / Delta per string
   double2* dbp;        // [parts][S][n_pat] dense-coefficient adjoints (class (1,2)) or null
+  double2* ecoef;      // [n_conn] sign * C_beta per coupling
   int row_split;       // string chunks of the row-owned pass (> 1: shared rows, atomics)
   int parts;           // row parts of the string-owned pass
   int64_t rows_per_part;   // rows per part (tile pairs per part for class (1,2))

@@ -109,21 +109,21 @@ __device__ __forceinline__ double row_const(const Dev& d, const Row& w) {
   return qr;
 }
 
-// Offset of the coupling of pattern j in row r: into A (v = 2) or X (v < 2).
+// Offset of a coupling in row r from its key (see the plan's coupling keys):
+// into A (v = 2: occupied pair of the row and the pattern, then the row's
+// place in the tile pair) or X (v < 2: pattern j, row r).
 template <int H, int V>
-__device__ __forceinline__ int64_t coupling_at(const Dev& d, const ClassDev& cd, int j, const Row& w, int64_t r) {
+__device__ __forceinline__ int64_t coupling_off(const Dev& d, const ClassDev& cd, int32_t key, const Row& w,
+                                                int64_t r) {
+  key &= 0x7fffffff;
   if (V == 2) {
-    const int nc = d.n_c;
     int64_t pair;
-    if (H == 2) {
-      pair = occ_pair(w.c0, w.c1, d.n_o);
-    } else {
-      const Pattern pt = cd.pat[j];
-      pair = (H == 1) ? occ_pair(w.c0, nc + pt.a0, d.n_o) : occ_pair(nc + pt.a0, nc + pt.a1, d.n_o);
-    }
+    if (H == 2) pair = occ_pair(w.c0, w.c1, d.n_o);
+    else if (H == 1) pair = occ_pair(w.c0, d.n_c + key, d.n_o);
+    else pair = key;
     return pair * d.n_tp * 4096 + w.rab;
   }
-  return (int64_t)j * cd.n_rows + r;
+  return (int64_t)key * cd.n_rows + r;
 }
 
 template <int H, int V>
@@ -136,13 +136,26 @@ __device__ __forceinline__ double string_delta(const ClassDev& cd, const Dev& d,
   return del;
 }
 
+// sign * C_beta per coupling of a class.  grid (ceil(n_conn / 256)).
+__device__ __forceinline__ void becoef_body(const Dev& d, const ClassDev& cd, const ClassGrad& cg,
+                                            const uint3 bid) {
+  const int64_t e = (int64_t)bid.x * 256 + threadIdx.x;
+  if (e >= cd.n_conn) return;
+  const int32_t cb = cd.conn[2 * e];
+  double2 cv = d.c[cb & 0x7fffffff];
+  if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+  cg.ecoef[e] = cv;
+}
+
 // ---- row pass ------------------------------------------------------------------
-// One thread per row, every string of the class.  Accumulates, per row:
-//   couplings:  Xbar[j][r] += sigma-bar * conj(sign C_beta)   (the thread owns the row)
+// One thread per row; the block walks the strings of its chunk (all strings
+// unless the class has few rows).  Accumulates, per row:
+//   couplings:  Xbar[j][r] += sigma-bar * conj(sign C_beta)
 //   q  = sum_s Delta-bar             (row constant of Delta)
 //   y_t = sum_{s containing t} Delta-bar   (tables Uc, Uv: W of the row's
 //         core holes and virtual spinors with active spinor t)
-// then adds q and y into the adjoints of eps and W.
+// then adds q and y into the adjoints of eps and W.  The coupling lists are
+// the same for every thread of the block, so their loads are uniform.
 // grid (ceil(rows / 256), string chunks), block 256, dynamic LDS n_a * 256 doubles.
 template <int H, int V>
 __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
@@ -159,6 +172,8 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
   const double twoN = 2.0 / N, oneN = 1.0 / N;
   double2* Xb = (V == 2) ? g.Ab : cg.Xb;
   const double2* X = (V == 2) ? d.A : cd.X;
+  const double2* __restrict__ ec = cg.ecoef;
+  const int32_t* __restrict__ ek = cd.ekey;
   double q = 0.0;
   const int64_t S = cd.n_str;
   // strings [s_lo, s_hi) of this block; with several string chunks the
@@ -171,25 +186,26 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
     if (e1 == e0) continue;
     double2 sig = make_double2(0.0, 0.0);
-    for (int e = e0; e < e1; ++e) {
-      const int32_t cb = cd.conn[2 * e];
-      double2 cv = d.c[cb & 0x7fffffff];
-      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
-      sig = cfma(cv, X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, rr)], sig);
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      double2 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = X[coupling_off<H, V>(d, cd, ek[e + u], w, rr)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sig = cfma(ec[e + u], xv[u], sig);
     }
+    for (; e < e1; ++e) sig = cfma(ec[e], X[coupling_off<H, V>(d, cd, ek[e], w, rr)], sig);
     const double del = string_delta<H, V>(cd, d, s, w) + qr;
     const double iv = 1.0 / del;
     const double2 t = make_double2(sig.x * iv, sig.y * iv);
     const double2 sb = make_double2(twoN * t.x, twoN * t.y);
     const double dl = -oneN * cabs2(t);
     if (w.valid) {
-      for (int e = e0; e < e1; ++e) {
-        const int32_t cb = cd.conn[2 * e];
-        double2 cv = d.c[cb & 0x7fffffff];
-        if (cb < 0) cv = make_double2(-cv.x, -cv.y);
-        double2* p = Xb + coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, rr);
-        if (shared_rows) catomic(p, cmul(sb, cconj(cv)));
-        else *p = cadd(*p, cmul(sb, cconj(cv)));
+      for (e = e0; e < e1; ++e) {
+        double2* p = Xb + coupling_off<H, V>(d, cd, ek[e], w, rr);
+        const double2 v = cmul(sb, cconj(ec[e]));
+        if (shared_rows) catomic(p, v);
+        else *p = cadd(*p, v);
       }
       q += dl;
       uint64_t x = cd.strings[s];
@@ -234,10 +250,13 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
 }
 
 // ---- string pass -------------------------------------------------------------
-// One thread per string, rows [part * rows_per_part, ...).  Accumulates, per
-// string and part:  cbe[e] = sum_r sign conj(X[j_e][r]) sigma-bar  (coefficient
-// adjoint through coupling e), and Tb[s] = sum_r Delta-bar.
-// grid (ceil(S / 256), parts), block 256.
+// One thread per string, rows [part * rows_per_part, ...) taken RCH at a time
+// so that each coupling's integrals for those rows are independent loads.
+// Accumulates, per string and part:  cbe[e] = sum_r sign conj(X[j_e][r])
+// sigma-bar (coefficient adjoint through coupling e), and Tb[s] = sum_r
+// Delta-bar.  grid (ceil(S / 256), parts), block 256.
+constexpr int RCH = 8;
+
 template <int H, int V>
 __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
@@ -252,30 +271,54 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
   const double N = d.scal[1];
   const double twoN = 2.0 / N, oneN = 1.0 / N;
   const double2* X = (V == 2) ? d.A : cd.X;
+  const double2* __restrict__ ec = cg.ecoef;
+  const int32_t* __restrict__ ek = cd.ekey;
   double2* cbe = cg.cbe + (int64_t)part * cd.n_conn;
   double tq = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const Row w = decode_row<H, V>(d, cd, r);
-    if (!w.valid) continue;
-    if (e1 == e0) continue;
-    double2 sig = make_double2(0.0, 0.0);
-    for (int e = e0; e < e1; ++e) {
-      const int32_t cb = cd.conn[2 * e];
-      double2 cv = d.c[cb & 0x7fffffff];
-      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
-      sig = cfma(cv, X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, r)], sig);
+  for (int64_t rc = r0; rc < r1; rc += RCH) {
+    Row w[RCH];
+    int64_t rk[RCH];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < RCH; ++k) {
+      rk[k] = rc + k < r1 ? rc + k : r1 - 1;
+      w[k] = decode_row<H, V>(d, cd, rk[k]);
+      w[k].valid = w[k].valid && (rc + k < r1);
+      any = any || w[k].valid;
     }
-    const double del = string_delta<H, V>(cd, d, s, w) + row_const<H, V>(d, w);
-    const double iv = 1.0 / del;
-    const double2 t = make_double2(sig.x * iv, sig.y * iv);
-    const double2 sb = make_double2(twoN * t.x, twoN * t.y);
-    tq -= oneN * cabs2(t);
+    if (!any || e1 == e0) continue;
+    double2 sig[RCH];
+#pragma unroll
+    for (int k = 0; k < RCH; ++k) sig[k] = make_double2(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const double2 cv = ec[e];
+      const int32_t key = ek[e];
+      double2 xv[RCH];
+#pragma unroll
+      for (int k = 0; k < RCH; ++k) xv[k] = X[coupling_off<H, V>(d, cd, key, w[k], rk[k])];
+#pragma unroll
+      for (int k = 0; k < RCH; ++k) sig[k] = cfma(cv, xv[k], sig[k]);
+    }
+    double2 sb[RCH];
+#pragma unroll
+    for (int k = 0; k < RCH; ++k) {
+      const double del = string_delta<H, V>(cd, d, s, w[k]) + row_const<H, V>(d, w[k]);
+      const double iv = w[k].valid ? 1.0 / del : 0.0;
+      const double2 t = make_double2(sig[k].x * iv, sig[k].y * iv);
+      sb[k] = make_double2(twoN * t.x, twoN * t.y);
+      tq -= oneN * cabs2(t);
+    }
     if (live) {
       for (int e = e0; e < e1; ++e) {
-        const double2 xv = X[coupling_at<H, V>(d, cd, cd.conn[2 * e + 1], w, r)];
-        double2 v = cmul(cconj(xv), sb);
-        if (cd.conn[2 * e] < 0) v = make_double2(-v.x, -v.y);
-        cbe[e] = cadd(cbe[e], v);
+        const int32_t key = ek[e];
+        double2 xv[RCH];
+#pragma unroll
+        for (int k = 0; k < RCH; ++k) xv[k] = X[coupling_off<H, V>(d, cd, key, w[k], rk[k])];
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < RCH; ++k) acc = cadd(acc, cmul(cconj(xv[k]), sb[k]));
+        if (key < 0) acc = make_double2(-acc.x, -acc.y);
+        cbe[e] = cadd(cbe[e], acc);
       }
     }
   }
@@ -298,6 +341,7 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
 // grid (n_tp, ceil(C(n_c,2) / kB22Group)), block 256.
 constexpr int B22C = 32;
 
+template <int NM>   // contraction slots per thread: active spinors t = tg + 4 m, m < NM (n_a <= 4 NM)
 __device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                          const uint3 bid) {
   __shared__ double sYa[B22C][64];
@@ -326,9 +370,9 @@ __device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const
   double* Rpart = cg.r1 + part * np;
   // contraction threads: (x = tid & 63, t = tg + 4 m)
   const int cx = tid & 63, tg = tid >> 6;
-  double Ya[16], Yb[16];
+  double Ya[NM], Yb[NM];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) Ya[m] = Yb[m] = 0.0;
+  for (int m = 0; m < NM; ++m) Ya[m] = Yb[m] = 0.0;
   double wab[4][4];
   bool ok[4][4];
 #pragma unroll
@@ -469,15 +513,13 @@ __device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const
       __syncthreads();
       // occupation contractions (Uv of a and b; Uc of the core pair)
       for (int al = 0; al < B22C; ++al) {
-        const uint64_t str = sStr[al];
+        const uint64_t str = sStr[al] >> tg;
         const double va = sVa[al][cx], vb = sVb[al][cx];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          const int t = tg + 4 * m;
-          if (t < na && ((str >> t) & 1ull)) {
-            Ya[m] += va;
-            Yb[m] += vb;
-          }
+        for (int m = 0; m < NM; ++m) {
+          const bool on = (str >> (4 * m)) & 1ull;   // active spinor tg + 4 m (bits >= n_a are zero)
+          Ya[m] += on ? va : 0.0;
+          Yb[m] += on ? vb : 0.0;
         }
       }
       if (tid < na) {
@@ -537,7 +579,7 @@ __device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const
   // Uv adjoints of this tile pair (summed over the block's core pairs)
   const int av = I * 64 + cx, bv = J * 64 + cx;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
+  for (int m = 0; m < NM; ++m) {
     const int t = tg + 4 * m;
     if (t >= na) continue;
     if (av < nv && Ya[m] != 0.0) atomicAdd(&g.Wb[(gv + av) * n + ga + t], oneN * Ya[m]);

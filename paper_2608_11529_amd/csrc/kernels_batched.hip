@@ -115,9 +115,14 @@ __global__ void __launch_bounds__(256) k_b_bstr(MRPT2_ARGS) {
   MRPT2_JOB
   bstr_body<H, V>(I.d, I.cls[K], I.g, I.cg[K], bid);
 }
+__global__ void __launch_bounds__(256) k_b_becoef(MRPT2_ARGS) {
+  MRPT2_JOB
+  becoef_body(I.d, I.cls[jb.arg], I.cg[jb.arg], bid);
+}
+template <int NM>
 __global__ void __launch_bounds__(256) k_b_b22(MRPT2_ARGS) {
   MRPT2_JOB
-  b22_body(I.d, I.cls[0], I.g, I.cg[0], bid);
+  b22_body<NM>(I.d, I.cls[0], I.g, I.cg[0], bid);
 }
 __global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
   MRPT2_JOB

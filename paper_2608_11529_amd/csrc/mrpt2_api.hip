@@ -99,6 +99,7 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.conn_ptr = (const int32_t*)(P + cp.off_conn_ptr);
   c.conn = (const int32_t*)(P + cp.off_conn);
   c.pat = (const Pattern*)(P + cp.off_pat);
+  c.ekey = (const int32_t*)(P + cp.off_ekey);
   c.T = (double*)(W + cp.off_T);
   c.Uc = (double*)(W + cp.off_Uc);
   c.Uv = (double*)(W + cp.off_Uv);
@@ -147,6 +148,7 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.r1 = (double*)(G + cp.off_r1);
   c.dbp = cp.kernel == KERN_E12 ? (double2*)(G + cp.off_dbp) : nullptr;
   c.row_split = cp.row_split;
+  c.ecoef = (double2*)(G + cp.off_ecoef);
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
   return c;
@@ -291,7 +293,9 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BSTR10: hipLaunchKernelGGL((k_b_bstr<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BSTR00: hipLaunchKernelGGL((k_b_bstr<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BSFIN: hipLaunchKernelGGL(k_b_bsfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B22: hipLaunchKernelGGL(k_b_b22, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BECOEF: hipLaunchKernelGGL(k_b_becoef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22: hipLaunchKernelGGL((k_b_b22<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22W: hipLaunchKernelGGL((k_b_b22<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_8: hipLaunchKernelGGL((k_b_b12r<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_16: hipLaunchKernelGGL((k_b_b12r<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

@@ -428,15 +428,23 @@ void build_launches(Plan* P) {
   }
   add_launch(P, seq, K_BZERO, ST_BZERO, js);
   for (const Launch& L : P->energy) seq->push_back(L);
+  js.clear();
+  for (int k = 0; k < MRPT2_N_CLASS; ++k)
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.strings.empty() || cp.n_rows == 0 || cp.n_conn == 0) continue;
+      js.push_back(job(i, cdiv64(cp.n_conn, 256), 1, k));
+    }
+  add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22, j12r[4], j12s[4];
+    std::vector<JobH> jr, jsr, j22, j22w, j12r[4], j12s[4];
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
       if (cp.kernel == KERN_E22) {
-        j22.push_back(job(i, ip.n_tp, cdiv64(cp.n_holes, kB22Group), k));
+        (ip.n_a <= 32 ? j22 : j22w).push_back(job(i, ip.n_tp, cdiv64(cp.n_holes, kB22Group), k));
         continue;
       }
       if (cp.kernel == KERN_E12) {
@@ -451,6 +459,7 @@ void build_launches(Plan* P) {
       lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
     }
     add_launch(P, seq, K_B22, ST_BROW0 + k, j22);
+    add_launch(P, seq, K_B22W, ST_BROW0 + k, j22w);
     for (int v = 0; v < 4; ++v) {
       add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v]);
       add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
@@ -762,6 +771,25 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.off_conn_ptr = P.take(cp.conn_ptr.size() * 4);
       cp.off_conn = P.take(cp.conn.size() * 4);
       cp.off_pat = P.take(cp.patterns.size() * sizeof(Pattern));
+      // coupling keys: the pattern index (v < 2), or the part of the pair
+      // integral's occupied pair that the pattern fixes (v = 2: none with two
+      // core holes, the active spinor with one, the active pair with none)
+      cp.ekey.resize(cp.n_conn);
+      for (int64_t e = 0; e < cp.n_conn; ++e) {
+        const int j = cp.conn[2 * e + 1];
+        const Pattern& pt = cp.patterns[j];
+        int32_t key = j;
+        if (cp.v == 2) {
+          if (cp.h == 2) key = 0;
+          else if (cp.h == 1) key = pt.a0;
+          else {
+            const int x = ip.n_c + pt.a0, y = ip.n_c + pt.a1;
+            key = (int32_t)((int64_t)x * ip.n_o - (int64_t)x * (x + 1) / 2 + (y - x - 1));
+          }
+        }
+        cp.ekey[e] = key | (cp.conn[2 * e] < 0 ? (int32_t)0x80000000 : 0);
+      }
+      cp.off_ekey = P.take(cp.ekey.size() * 4);
     }
     ip.persistent_bytes = P.cur;
     ip.host_blob.assign(ip.persistent_bytes, 0);
@@ -779,6 +807,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       put(cp.off_conn_ptr, cp.conn_ptr.data(), cp.conn_ptr.size() * 4);
       put(cp.off_conn, cp.conn.data(), cp.conn.size() * 4);
       put(cp.off_pat, cp.patterns.data(), cp.patterns.size() * sizeof(Pattern));
+      put(cp.off_ekey, cp.ekey.data(), cp.ekey.size() * 4);
     }
     // ---- workspace layout ----
     Layout W;
@@ -871,6 +900,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.off_cbe = Gw.take((b22 || b12) ? 0 : (size_t)cp.parts * cp.n_conn * 16);
       cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
+      cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
     }
     ip.grad_bytes = Gw.cur;
     // info
