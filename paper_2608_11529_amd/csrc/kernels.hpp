@@ -122,6 +122,8 @@ struct ClassGrad {
   double* r1;          // [parts][S] class (2,2): per-part sums of |A|^2 / Delta per string
   double2* dbp;        // [parts][S][n_pat] dense-coefficient adjoints (class (1,2)) or null
   double2* ecoef;      // [n_conn] sign * C_beta per coupling
+  double* wpart;       // class (2,2): per-block partials of the Uv adjoint [blocks][n_v][n_a]
+  int64_t wblocks;     // number of those blocks (string blocks x parts)
   int row_split;       // string chunks of the row-owned pass (> 1: shared rows, atomics)
   int parts;           // row parts of the string-owned pass
   int64_t rows_per_part;   // rows per part (tile pairs per part for class (1,2))

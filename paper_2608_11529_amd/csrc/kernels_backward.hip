@@ -196,7 +196,7 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     }
     for (; e < e1; ++e) sig = cfma(ec[e], X[coupling_off<H, V>(d, cd, ek[e], w, rr)], sig);
     const double del = string_delta<H, V>(cd, d, s, w) + qr;
-    const double iv = 1.0 / del;
+    const double iv = rcp_nr(del);
     const double2 t = make_double2(sig.x * iv, sig.y * iv);
     const double2 sb = make_double2(twoN * t.x, twoN * t.y);
     const double dl = -oneN * cabs2(t);
@@ -303,7 +303,7 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
 #pragma unroll
     for (int k = 0; k < RCH; ++k) {
       const double del = string_delta<H, V>(cd, d, s, w[k]) + row_const<H, V>(d, w[k]);
-      const double iv = w[k].valid ? 1.0 / del : 0.0;
+      const double iv = w[k].valid ? rcp_nr(del) : 0.0;
       const double2 t = make_double2(sig[k].x * iv, sig[k].y * iv);
       sb[k] = make_double2(twoN * t.x, twoN * t.y);
       tq -= oneN * cabs2(t);
@@ -327,53 +327,37 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
 
 // ---- class (2,2) ------------------------------------------------------------------
 // sigma_K = <ab||cc'> C_alpha, Delta = G(alpha) + Y_a(alpha) + Y_b(alpha) - W_ab as in
-// the forward kernel.  With w = 1/Delta and cw = |C_alpha|^2:
-//   Abar[cc'][ab] = (2/N) A S1,   S1 = sum_alpha cw w,          (written once)
-//   row constants receive -(1/N) |A|^2 S2,   S2 = sum_alpha cw w^2,
-//   Cbar_alpha    = (2/N) C_alpha sum_{cc', ab} |A|^2 w          (per-block partial R1),
-//   Tbar[alpha]   = -(1/N) sum_{cc', ab} cw |A|^2 w^2            (per-block partial),
-//   Uv tables: va(alpha, a) = cw sum_b |A|^2 w^2 contracted with the occupations
-//   of alpha per chunk of strings (W[a][t] for active t), likewise for b,
-//   Uc tables: per core pair, sum_a va contracted the same way.
-// Each thread owns 4 x 4 (a, b) of the 64 x 64 tile and walks the reference
-// strings in chunks of B22C staged in LDS; a block loops over the core pairs of
-// its group (kB22Group), so per-string partials are per (pair group, tile pair).
-// grid (n_tp, ceil(C(n_c,2) / kB22Group)), block 256.
-constexpr int B22C = 32;
-
-template <int NM>   // contraction slots per thread: active spinors t = tg + 4 m, m < NM (n_a <= 4 NM)
-__device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
-                                         const uint3 bid) {
-  __shared__ double sYa[B22C][64];
-  __shared__ double sYb[B22C][64];
-  __shared__ double sVa[B22C][64];
-  __shared__ double sVb[B22C][64];
-  __shared__ double sR1[B22C][16];
-  __shared__ double sG[B22C];
-  __shared__ double sCw[B22C];
-  __shared__ double sQ[B22C];
-  __shared__ uint64_t sStr[B22C];
+// the forward kernel, w = 1/Delta, cw = |C_alpha|^2.  Two kernels share the work.
+//
+// Row-owned (the forward kernel's layout; each thread 4 x 4 (a, b) of a tile,
+// strings staged in LDS): S1 = sum_alpha cw w and S2 = sum_alpha cw w^2, four
+// fractions merged per reciprocal, give
+//   Abar[cc'][ab] = (2/N) A S1  (written once)  and the row constants'
+//   adjoint -(1/N) |A|^2 S2  (eps and W of c, c', a, b; W_ab).
+// grid (n_tp, C(n_c,2)), block 256.
+__device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, const GradDev& g, const uint3 bid) {
+  __shared__ double sYa[AC22][64];
+  __shared__ double sYb[AC22][64];
+  __shared__ double sG[AC22];
+  __shared__ double sCw[AC22];
   __shared__ double ya0[64], yb0[64];
   __shared__ double red[256];
-  const int tp = bid.x;
-  const int64_t nhp = cd.n_holes;
-  const int64_t hp0 = (int64_t)bid.y * kB22Group;
-  const int64_t hp1 = min(nhp, hp0 + kB22Group);
-  const int64_t part = (int64_t)bid.y * d.n_tp + tp;
+  const int tp = bid.x, hp = bid.y;
+  const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
   const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
   const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
-  const int nv = d.n_v, nc = d.n_c, na = d.n_a, np = d.n_p;
-  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const int nv = d.n_v, nc = d.n_c;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o;
   const double* __restrict__ W = d.W;
-  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
-  double* Tpart = cg.Tb + part * np;
-  double* Rpart = cg.r1 + part * np;
-  // contraction threads: (x = tid & 63, t = tg + 4 m)
-  const int cx = tid & 63, tg = tid >> 6;
-  double Ya[NM], Yb[NM];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) Ya[m] = Yb[m] = 0.0;
-  double wab[4][4];
+  if (tid < 64) {
+    const int a = I * 64 + tid;
+    ya0[tid] = (a < nv) ? -d.eps[d.n_o + a] + W[(gfc + c0) * n + gv + a] + W[(gfc + c1) * n + gv + a] : -1.0;
+  } else if (tid < 128) {
+    const int b = J * 64 + tid - 64;
+    yb0[tid - 64] = (b < nv) ? -d.eps[d.n_o + b] + W[(gfc + c0) * n + gv + b] + W[(gfc + c1) * n + gv + b] : -1.0;
+  }
+  const double gconst = d.eps[c0] + d.eps[c1] - W[(gfc + c0) * n + gfc + c1];
+  double wab[4][4], S1[4][4], S2[4][4];
   bool ok[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -382,209 +366,295 @@ __device__ __forceinline__ void b22_body(const Dev& d, const ClassDev& cd, const
       const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
       ok[i][j] = (a < b) && (b < nv);
       wab[i][j] = ok[i][j] ? W[(gv + a) * n + gv + b] : 0.0;
+      S1[i][j] = S2[i][j] = 0.0;
     }
-  for (int64_t hp = hp0; hp < hp1; ++hp) {
-    const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
-    const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
-    double A2[4][4], S1[4][4], S2[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        A2[i][j] = ok[i][j] ? cabs2(Ablk[(ta + 16 * i) * 64 + tb + 16 * j]) : 0.0;
-        S1[i][j] = S2[i][j] = 0.0;
-      }
+  const int np = d.n_p;
+  for (int s0 = 0; s0 < np; s0 += AC22) {
     __syncthreads();
-    if (tid < 64) {
-      const int a = I * 64 + tid;
-      ya0[tid] = (a < nv) ? -d.eps[d.n_o + a] + W[(gfc + c0) * n + gv + a] + W[(gfc + c1) * n + gv + a] : -1.0;
-    } else if (tid < 128) {
-      const int b = J * 64 + tid - 64;
-      yb0[tid - 64] = (b < nv) ? -d.eps[d.n_o + b] + W[(gfc + c0) * n + gv + b] + W[(gfc + c1) * n + gv + b] : -1.0;
+    for (int e = tid; e < AC22 * 64; e += 256) {
+      const int al = e >> 6, l = e & 63;
+      const int s = s0 + al;
+      const int a = I * 64 + l, b = J * 64 + l;
+      double ya = ya0[l], yb = yb0[l];
+      if (s < np) {
+        if (a < nv) ya -= cd.Uv[(int64_t)s * nv + a];
+        if (b < nv) yb -= cd.Uv[(int64_t)s * nv + b];
+      }
+      sYa[al][l] = ya;
+      sYb[al][l] = yb;
     }
-    const double gconst = d.eps[c0] + d.eps[c1] - W[(gfc + c0) * n + gfc + c1];
-    double Zc = 0.0;   // thread t < n_a: sum over alpha with t of Q2(alpha)
-    for (int s0 = 0; s0 < np; s0 += B22C) {
-      __syncthreads();
-      for (int e = tid; e < B22C * 64; e += 256) {
-        const int al = e >> 6, l = e & 63;
-        const int s = s0 + al;
-        const int a = I * 64 + l, b = J * 64 + l;
-        double ya = ya0[l], yb = yb0[l];
-        if (s < np) {
-          if (a < nv) ya -= cd.Uv[(int64_t)s * nv + a];
-          if (b < nv) yb -= cd.Uv[(int64_t)s * nv + b];
-        }
-        sYa[al][l] = ya;
-        sYb[al][l] = yb;
-        sVa[al][l] = 0.0;
-        sVb[al][l] = 0.0;
+    if (tid < AC22) {
+      const int s = s0 + tid;
+      if (s < np) {
+        sG[tid] = cd.T[s] + cd.Uc[(int64_t)s * nc + c0] + cd.Uc[(int64_t)s * nc + c1] + gconst;
+        sCw[tid] = cabs2(d.c[s]);
+      } else {
+        sG[tid] = 1e30;
+        sCw[tid] = 0.0;
       }
-      for (int e = tid; e < B22C * 16; e += 256) sR1[e >> 4][e & 15] = 0.0;
-      if (tid < B22C) {
-        const int s = s0 + tid;
-        if (s < np) {
-          sG[tid] = cd.T[s] + cd.Uc[(int64_t)s * nc + c0] + cd.Uc[(int64_t)s * nc + c1] + gconst;
-          sCw[tid] = cabs2(d.c[s]);
-          sStr[tid] = d.pstrings[s];
-        } else {
-          sG[tid] = 1e30;
-          sCw[tid] = 0.0;
-          sStr[tid] = 0;
-        }
-      }
-      __syncthreads();
+    }
+    __syncthreads();
 #pragma unroll 1
-      for (int al = 0; al < B22C; al += 4) {
-        double gk[4], cw[4], za[4][4], yb[4][4];
+    for (int al = 0; al < AC22; al += 4) {
+      double gk[4], cw[4], za[4][4], yb[4][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          gk[k] = sG[al + k];
-          cw[k] = sCw[al + k];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) za[i][k] = gk[k] + sYa[al + k][ta + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
-        double r1[4] = {0.0, 0.0, 0.0, 0.0};
-        double va[4][4], vb[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) va[i][k] = vb[i][k] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            double dd[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dd[k] = ok[i][j] ? (za[i][k] + yb[j][k]) - wab[i][j] : 1.0;
-            const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
-            const double r = rcp_nr(p01 * p23);
-            const double r01 = r * p23, r23 = r * p01;
-            double w1[4];
-            w1[0] = r01 * dd[1];
-            w1[1] = r01 * dd[0];
-            w1[2] = r23 * dd[3];
-            w1[3] = r23 * dd[2];
-            const double a2 = A2[i][j];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const double w2 = w1[k] * w1[k];
-              S1[i][j] = fma(cw[k], w1[k], S1[i][j]);
-              S2[i][j] = fma(cw[k], w2, S2[i][j]);
-              r1[k] = fma(a2, w1[k], r1[k]);
-              const double q2 = a2 * w2;
-              va[i][k] += q2;
-              vb[j][k] += q2;
-            }
-          }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) atomicAdd(&sVa[al + k][ta + 16 * i], cw[k] * va[i][k]);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) atomicAdd(&sVb[al + k][tb + 16 * j], cw[k] * vb[j][k]);
-          atomicAdd(&sR1[al + k][ta], r1[k]);
-        }
+      for (int k = 0; k < 4; ++k) {
+        gk[k] = sG[al + k];
+        cw[k] = sCw[al + k];
       }
-      __syncthreads();
-      // per-string partials of this block
-      if (tid < B22C) {
-        const int s = s0 + tid;
-        double q = 0.0, r = 0.0;
-        for (int x = 0; x < 64; ++x) q += sVa[tid][x];
-        for (int x = 0; x < 16; ++x) r += sR1[tid][x];
-        sQ[tid] = q;
-        if (s < np) {
-          if (hp == hp0) {
-            Tpart[s] = -oneN * q;
-            Rpart[s] = r;
-          } else {
-            Tpart[s] -= oneN * q;
-            Rpart[s] += r;
-          }
-        }
-      }
-      __syncthreads();
-      // occupation contractions (Uv of a and b; Uc of the core pair)
-      for (int al = 0; al < B22C; ++al) {
-        const uint64_t str = sStr[al] >> tg;
-        const double va = sVa[al][cx], vb = sVb[al][cx];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) {
-          const bool on = (str >> (4 * m)) & 1ull;   // active spinor tg + 4 m (bits >= n_a are zero)
-          Ya[m] += on ? va : 0.0;
-          Yb[m] += on ? vb : 0.0;
-        }
-      }
-      if (tid < na) {
-        for (int al = 0; al < B22C; ++al)
-          if ((sStr[al] >> tid) & 1ull) Zc += sQ[al];
-      }
-    }
-    // pair-integral adjoint tile (written once) and row constants
-    double2* Ab = g.Ab + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
-    double rowa[4] = {0.0, 0.0, 0.0, 0.0}, colb[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 4; ++k) za[i][k] = gk[k] + sYa[al + k][ta + 16 * i];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (ok[i][j]) {
-          const int li = (ta + 16 * i) * 64 + tb + 16 * j;
-          const double2 av = Ablk[li];
-          Ab[li] = make_double2(twoN * S1[i][j] * av.x, twoN * S1[i][j] * av.y);
-          const double gq = -oneN * A2[i][j] * S2[i][j];   // sum over alpha of Delta-bar
-          const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
-          atomicAdd(&g.Wb[(gv + a) * n + gv + b], -gq);
-          rowa[i] += gq;
-          colb[j] += gq;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double d0 = (za[i][0] + yb[j][0]) - wab[i][j];
+          const double d1 = (za[i][1] + yb[j][1]) - wab[i][j];
+          const double d2 = (za[i][2] + yb[j][2]) - wab[i][j];
+          const double d3 = (za[i][3] + yb[j][3]) - wab[i][j];
+          const double p01 = d0 * d1, p23 = d2 * d3;
+          const double r = rcp_nr(p01 * p23);
+          const double q0 = d1 * p23, q1 = d0 * p23, q2 = d3 * p01, q3 = d2 * p01;
+          const double n1 = fma(cw[0], q0, fma(cw[1], q1, fma(cw[2], q2, cw[3] * q3)));
+          const double n2 = fma(cw[0] * q0, q0, fma(cw[1] * q1, q1, fma(cw[2] * q2, q2, cw[3] * q3 * q3)));
+          S1[i][j] = fma(n1, r, S1[i][j]);
+          S2[i][j] = fma(n2, r * r, S2[i][j]);
         }
-    __syncthreads();
-    if (tid < 128) sVa[tid >> 6][tid & 63] = 0.0;   // row sums in sVa[0], column sums in sVa[1]
-    __syncthreads();
+    }
+  }
+  // pair-integral adjoint tile and row constants
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+  double2* Ab = g.Ab + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+  double rowa[4] = {0.0, 0.0, 0.0, 0.0}, colb[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) atomicAdd(&sVa[0][ta + 16 * i], rowa[i]);
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) atomicAdd(&sVa[1][tb + 16 * j], colb[j]);
-    __syncthreads();
-    if (tid < 128) {
-      const int x = tid & 63;
-      const double v = sVa[tid >> 6][x];
-      const int vv = (tid < 64 ? I : J) * 64 + x;
-      if (vv < nv && v != 0.0) {
-        atomicAdd(&g.epsb[d.n_o + vv], -v);
-        atomicAdd(&g.Wb[(gfc + c0) * n + gv + vv], v);
-        atomicAdd(&g.Wb[(gfc + c1) * n + gv + vv], v);
+    for (int j = 0; j < 4; ++j)
+      if (ok[i][j]) {
+        const int li = (ta + 16 * i) * 64 + tb + 16 * j;
+        const double2 av = Ablk[li];
+        Ab[li] = make_double2(twoN * S1[i][j] * av.x, twoN * S1[i][j] * av.y);
+        const double gq = -oneN * cabs2(av) * S2[i][j];   // sum over alpha of Delta-bar
+        const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
+        atomicAdd(&g.Wb[(gv + a) * n + gv + b], -gq);
+        rowa[i] += gq;
+        colb[j] += gq;
       }
-      red[tid] = v;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double tot = 0.0;
-      for (int x = 0; x < 64; ++x) tot += red[x];
-      atomicAdd(&g.epsb[c0], tot);
-      atomicAdd(&g.epsb[c1], tot);
-      atomicAdd(&g.Wb[(gfc + c0) * n + gfc + c1], -tot);
-    }
-    if (tid < na && Zc != 0.0) {
-      atomicAdd(&g.Wb[(gfc + c0) * n + ga + tid], -oneN * Zc);
-      atomicAdd(&g.Wb[(gfc + c1) * n + ga + tid], -oneN * Zc);
-    }
-  }
-  // Uv adjoints of this tile pair (summed over the block's core pairs)
-  const int av = I * 64 + cx, bv = J * 64 + cx;
+  __syncthreads();
+  double* sRC = &sYa[0][0];   // row sums [0..63], column sums [64..127]
+  if (tid < 128) sRC[tid] = 0.0;
+  __syncthreads();
 #pragma unroll
-  for (int m = 0; m < NM; ++m) {
-    const int t = tg + 4 * m;
-    if (t >= na) continue;
-    if (av < nv && Ya[m] != 0.0) atomicAdd(&g.Wb[(gv + av) * n + ga + t], oneN * Ya[m]);
-    if (bv < nv && Yb[m] != 0.0) atomicAdd(&g.Wb[(gv + bv) * n + ga + t], oneN * Yb[m]);
+  for (int i = 0; i < 4; ++i) atomicAdd(&sRC[ta + 16 * i], rowa[i]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) atomicAdd(&sRC[64 + tb + 16 * j], colb[j]);
+  __syncthreads();
+  if (tid < 128) {
+    const int x = tid & 63;
+    const double v = sRC[tid];
+    const int vv = (tid < 64 ? I : J) * 64 + x;
+    if (vv < nv && v != 0.0) {
+      atomicAdd(&g.epsb[d.n_o + vv], -v);
+      atomicAdd(&g.Wb[(gfc + c0) * n + gv + vv], v);
+      atomicAdd(&g.Wb[(gfc + c1) * n + gv + vv], v);
+    }
+    red[tid] = v;
   }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int x = 0; x < 64; ++x) tot += red[x];
+    atomicAdd(&g.epsb[c0], tot);
+    atomicAdd(&g.epsb[c1], tot);
+    atomicAdd(&g.Wb[(gfc + c0) * n + gfc + c1], -tot);
+  }
+}
+
+// String-owned (one thread per reference string alpha; the block walks all
+// tile pairs for a group of core pairs, in 32 x 32 sub-tiles whose |A|^2 and
+// W_ab are staged in LDS and read by every thread):
+//   R1(alpha) = sum |A|^2 w        -> Cbar_alpha = (2/N) C_alpha R1,
+//   Tbar(alpha) = -(1/N) cw sum |A|^2 w^2,
+//   Uv tables: per virtual a (b), x(alpha, a) = cw sum_{c c', b (a)} |A|^2 w^2
+//   is kept in a private LDS slot per thread, then contracted with the string
+//   occupations, W[a][t] += (1/N) sum_alpha [t in alpha] x(alpha, a), into a
+//   per-block partial of W (reduced by the next kernel);
+//   Uc: per core pair likewise with -1/N, straight into W.
+// grid (ceil(n_p / 128), ceil(C(n_c,2) / group)), block 128 (B22T), dynamic
+// LDS 2 * 32 * B22T doubles.
+constexpr int B22T = 128;
+
+// Contract one 32-row slab of per-thread values with the string occupations:
+// wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < 32, t < n_a.
+__device__ __forceinline__ void b22_contract(const double* buf, const uint64_t* sStr, double* wpart, int v0, int nv,
+                                             int na) {
+  const int tid = threadIdx.x, cx = tid & 31, tq = tid >> 5;
+  double acc[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+  for (int l = 0; l < B22T; ++l) {
+    const double v = buf[cx * B22T + l];
+    const uint64_t x = sStr[l] >> tq;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) acc[m] += ((x >> (4 * m)) & 1ull) ? v : 0.0;
+  }
+  const int vv = v0 + cx;
+  if (vv < nv) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int t = tq + 4 * m;
+      if (t < na) wpart[(int64_t)vv * na + t] += acc[m];
+    }
+  }
+}
+
+__device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid, int64_t nsblk) {
+  __shared__ double sBuf[32 * B22T];   // per-thread column: a side, then b side of a sub-tile
+  __shared__ double sA2[32][32];
+  __shared__ double sWab[32][32];
+  __shared__ double sUc[64];
+  __shared__ uint64_t sStr[B22T];
+  const int tid = threadIdx.x;
+  const int np = d.n_p, nv = d.n_v, nc = d.n_c, na = d.n_a;
+  int s = bid.x * B22T + tid;
+  const bool live = s < np;
+  if (!live) s = np - 1;
+  const int64_t nhp = cd.n_holes;
+  const int64_t hp0 = (int64_t)bid.y * cg.rows_per_part, hp1 = min(nhp, hp0 + cg.rows_per_part);
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const double* __restrict__ W = d.W;
+  const double N = d.scal[1], oneN = 1.0 / N;
+  const double cw = live ? cabs2(d.c[s]) : 0.0;
+  const uint64_t str = live ? d.pstrings[s] : 0ull;
+  sStr[tid] = str;
+  const double Ts = cd.T[s];
+  const double* Uvs = cd.Uv + (int64_t)s * nv;
+  const double* Ucs = cd.Uc + (int64_t)s * nc;
+  double* wpart = cg.wpart + ((int64_t)bid.y * nsblk + bid.x) * nv * na;
+  double R1 = 0.0, T2 = 0.0;
+  constexpr int NB = 32;
+  for (int64_t tp = 0; tp < d.n_tp; ++tp) {
+    const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+    for (int ha = 0; ha < 64; ha += 32) {
+      const int a0 = I * 64 + ha;
+      if (a0 >= nv || J * 64 + 63 <= a0) continue;
+      for (int hb = 0; hb < 64; hb += NB) {
+        const int b0 = J * 64 + hb;
+        if (b0 >= nv || b0 + NB - 1 <= a0) continue;
+#pragma unroll
+        for (int la = 0; la < 32; ++la) sBuf[la * B22T + tid] = 0.0;
+        double vb[NB];
+#pragma unroll
+        for (int lb = 0; lb < NB; ++lb) vb[lb] = 0.0;
+        for (int64_t hp = hp0; hp < hp1; ++hp) {
+          const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
+          const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
+          __syncthreads();
+          for (int e = tid; e < 32 * 32; e += B22T) {
+            const int la = e >> 5, lb = e & 31;
+            const int a = a0 + la, b = b0 + lb;
+            const bool ok = (a < b) && (b < nv);
+            sA2[la][lb] = ok ? cabs2(Ablk[(ha + la) * 64 + hb + lb]) : 0.0;
+            sWab[la][lb] = ok ? W[(gv + a) * n + gv + b] : 0.0;
+          }
+          if (tid < 64) sUc[tid] = 0.0;
+          __syncthreads();
+          const double Gc = Ts + Ucs[c0] + Ucs[c1] + d.eps[c0] + d.eps[c1] - W[(gfc + c0) * n + gfc + c1];
+          double yb[NB];
+#pragma unroll
+          for (int lb = 0; lb < NB; ++lb) {
+            const int b = b0 + lb;
+            yb[lb] = (b < nv) ? -d.eps[d.n_o + b] - Uvs[b] + W[(gfc + c0) * n + gv + b] + W[(gfc + c1) * n + gv + b]
+                              : 0.0;
+          }
+          double q2c = 0.0;
+          for (int la = 0; la < 32; ++la) {
+            const int a = a0 + la;
+            if (a >= nv || b0 + NB - 1 <= a) break;
+            const double base =
+                Gc - d.eps[d.n_o + a] - Uvs[a] + W[(gfc + c0) * n + gv + a] + W[(gfc + c1) * n + gv + a];
+            double va = 0.0;
+#pragma unroll
+            for (int lb = 0; lb < NB; lb += 4) {
+              double dd[4], a2[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                a2[k] = sA2[la][lb + k];
+                dd[k] = a2[k] != 0.0 ? (base + yb[lb + k]) - sWab[la][lb + k] : 1.0;
+              }
+              const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
+              const double r = rcp_nr(p01 * p23);
+              const double r01 = r * p23, r23 = r * p01;
+              double w[4];
+              w[0] = r01 * dd[1];
+              w[1] = r01 * dd[0];
+              w[2] = r23 * dd[3];
+              w[3] = r23 * dd[2];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                R1 = fma(a2[k], w[k], R1);
+                const double t2 = a2[k] * w[k] * w[k];
+                va += t2;
+                vb[lb + k] += t2;
+              }
+            }
+            q2c += va;
+            sBuf[la * B22T + tid] += cw * va;
+          }
+          T2 += q2c;
+          // Uc of this core pair: W[c][t] -= (1/N) sum_alpha [t in alpha] cw q2c
+          if (live && q2c != 0.0) {
+            uint64_t x = str;
+            while (x) {
+              const int t = __builtin_ctzll(x);
+              x &= x - 1;
+              atomicAdd(&sUc[t], cw * q2c);
+            }
+          }
+          __syncthreads();
+          if (tid < na && sUc[tid] != 0.0) {
+            atomicAdd(&g.Wb[(gfc + c0) * n + ga + tid], -oneN * sUc[tid]);
+            atomicAdd(&g.Wb[(gfc + c1) * n + ga + tid], -oneN * sUc[tid]);
+          }
+        }
+        // the sub-tile's a side, then its b side, contracted with the occupations
+        __syncthreads();
+        b22_contract(sBuf, sStr, wpart, a0, nv, na);
+        __syncthreads();
+#pragma unroll
+        for (int lb = 0; lb < NB; ++lb) sBuf[lb * B22T + tid] = cw * vb[lb];
+        __syncthreads();
+        b22_contract(sBuf, sStr, wpart, b0, nv, na);
+        __syncthreads();
+      }
+    }
+  }
+  if (live) {
+    cg.Tb[(int64_t)bid.y * np + s] = -oneN * cw * T2;
+    cg.r1[(int64_t)bid.y * np + s] = R1;
+  }
+}
+
+// Uv tables of class (2,2): W[a][t] += (1/N) sum over the string-owned kernel's
+// blocks of their partials.  grid (ceil(n_v n_a / 256)).
+__device__ __forceinline__ void b22w_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid, int64_t nblk) {
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int64_t per = (int64_t)d.n_v * d.n_a;
+  if (i >= per) return;
+  double v = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) v += cg.wpart[b * per + i];
+  const int a = (int)(i / d.n_a), t = (int)(i % d.n_a);
+  const int64_t gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  if (v != 0.0) g.Wb[(gv + a) * d.n + ga + t] += v / d.scal[1];
 }
 
 // Per-string adjoints of class (2,2) from the per-block partials: Tbar (as in
@@ -894,20 +964,37 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
       const double ga_s = Gs - Uvs[a];
       const int lb0 = max(0, a + 1 - Jt * 64);
       const int lb1 = min(64, nv - Jt * 64);
-      for (int lb = lb0; lb < lb1; ++lb) {
-        const int b = Jt * 64 + lb;
-        double2 sg = make_double2(0.0, 0.0);
+      // four consecutive b share one reciprocal (products of the denominators)
+      for (int lb = lb0; lb < lb1; lb += 4) {
+        double2 sg[4];
+        double dd[4];
 #pragma unroll
-        for (int j = 0; j < MJ; ++j)
-          if (um & (1u << j)) sg = cfma(D[j], sX[lb][j], sg);
-        const double del = ga_s + sQ[lb] - Uvs[b];
-        const double w = 1.0 / del;
-        const double2 t = make_double2(sg.x * w, sg.y * w);
-        const double2 sbv = make_double2(twoN * t.x, twoN * t.y);
-        tq -= oneN * cabs2(t);
+        for (int k = 0; k < 4; ++k) {
+          const int l = min(lb + k, lb1 - 1);
+          sg[k] = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int j = 0; j < MJ; ++j)
-          if (um & (1u << j)) Db[j] = cadd(Db[j], cmul(sbv, cconj(sX[lb][j])));
+          for (int j = 0; j < MJ; ++j)
+            if (um & (1u << j)) sg[k] = cfma(D[j], sX[l][j], sg[k]);
+          dd[k] = ga_s + sQ[l] - Uvs[Jt * 64 + l];
+        }
+        const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
+        const double r = rcp_nr(p01 * p23);
+        const double r01 = r * p23, r23 = r * p01;
+        double w[4];
+        w[0] = r01 * dd[1];
+        w[1] = r01 * dd[0];
+        w[2] = r23 * dd[3];
+        w[3] = r23 * dd[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (lb + k >= lb1) break;
+          const double2 t = make_double2(sg[k].x * w[k], sg[k].y * w[k]);
+          const double2 sbv = make_double2(twoN * t.x, twoN * t.y);
+          tq -= oneN * cabs2(t);
+#pragma unroll
+          for (int j = 0; j < MJ; ++j)
+            if (um & (1u << j)) Db[j] = cadd(Db[j], cmul(sbv, cconj(sX[lb + k][j])));
+        }
       }
     }
   }

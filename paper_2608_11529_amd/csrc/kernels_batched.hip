@@ -119,10 +119,17 @@ __global__ void __launch_bounds__(256) k_b_becoef(MRPT2_ARGS) {
   MRPT2_JOB
   becoef_body(I.d, I.cls[jb.arg], I.cg[jb.arg], bid);
 }
-template <int NM>
-__global__ void __launch_bounds__(256) k_b_b22(MRPT2_ARGS) {
+__global__ void __launch_bounds__(256) k_b_b22a(MRPT2_ARGS) {
   MRPT2_JOB
-  b22_body<NM>(I.d, I.cls[0], I.g, I.cg[0], bid);
+  b22a_body(I.d, I.cls[0], I.g, bid);
+}
+__global__ void __launch_bounds__(B22T) k_b_b22b(MRPT2_ARGS) {
+  MRPT2_JOB
+  b22b_body(I.d, I.cls[0], I.g, I.cg[0], bid, jb.gx);
+}
+__global__ void __launch_bounds__(256) k_b_b22w(MRPT2_ARGS) {
+  MRPT2_JOB
+  b22w_body(I.d, I.cls[0], I.g, I.cg[0], bid, I.cg[0].wblocks);
 }
 __global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
   MRPT2_JOB

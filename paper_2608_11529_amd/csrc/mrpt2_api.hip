@@ -149,6 +149,8 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.dbp = cp.kernel == KERN_E12 ? (double2*)(G + cp.off_dbp) : nullptr;
   c.row_split = cp.row_split;
   c.ecoef = (double2*)(G + cp.off_ecoef);
+  c.wpart = (double*)(G + cp.off_wpart);
+  c.wblocks = cp.kernel == KERN_E22 ? (int64_t)cp.parts * ((int64_t)(cp.strings.size() + B22T - 1) / B22T) : 0;
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
   return c;
@@ -294,12 +296,15 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BSTR00: hipLaunchKernelGGL((k_b_bstr<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BSFIN: hipLaunchKernelGGL(k_b_bsfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BECOEF: hipLaunchKernelGGL(k_b_becoef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B22: hipLaunchKernelGGL((k_b_b22<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B22W: hipLaunchKernelGGL((k_b_b22<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22A: hipLaunchKernelGGL(k_b_b22a, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22WR: hipLaunchKernelGGL(k_b_b22w, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22B: hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_8: hipLaunchKernelGGL((k_b_b12r<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_16: hipLaunchKernelGGL((k_b_b12r<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_24: hipLaunchKernelGGL((k_b_b12r<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12R_20: hipLaunchKernelGGL((k_b_b12r<20>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B12S_20: hipLaunchKernelGGL((k_b_b12s<20>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_32: hipLaunchKernelGGL((k_b_b12r<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12S_8: hipLaunchKernelGGL((k_b_b12s<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12S_16: hipLaunchKernelGGL((k_b_b12s<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

@@ -437,33 +437,38 @@ void build_launches(Plan* P) {
     }
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22, j22w, j12r[4], j12s[4];
+    std::vector<JobH> jr, jsr, j22a, j22b, j22w, j12r[4], j12s[5];
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
       if (cp.kernel == KERN_E22) {
-        (ip.n_a <= 32 ? j22 : j22w).push_back(job(i, ip.n_tp, cdiv64(cp.n_holes, kB22Group), k));
+        j22a.push_back(job(i, ip.n_tp, cp.n_holes, k));
+        j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 128), cp.parts, k));
+        j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
         continue;
       }
       if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         j12r[v].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
-        j12s[v].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
+        const int vs = (J > 16 && J <= 20) ? 4 : v;
+        j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
       jr.push_back(job(i, cdiv64(cp.n_rows, 256), cp.row_split, k));
       jsr.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
       lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
     }
-    add_launch(P, seq, K_B22, ST_BROW0 + k, j22);
-    add_launch(P, seq, K_B22W, ST_BROW0 + k, j22w);
+    add_launch(P, seq, K_B22A, ST_BROW0 + k, j22a);
+    add_launch(P, seq, K_B22B, ST_BSTR0 + k, j22b);
+    add_launch(P, seq, K_B22WR, ST_BSTR0 + k, j22w);
     for (int v = 0; v < 4; ++v) {
       add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v]);
       add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
     }
+    add_launch(P, seq, K_B12S_20, ST_BSTR0 + k, j12s[4]);
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
   }
@@ -872,8 +877,12 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
       cp.row_split = 1;
       if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E22) {
-        // (2,2) adjoint kernel: per-string partials per (core-pair group, tile pair)
-        cp.parts = (int)(((cp.n_holes + kB22Group - 1) / kB22Group) * ip.n_tp);
+        // (2,2) string-owned adjoint kernel (128 strings per block): parts = groups of core pairs
+        const int64_t sblk = (S + 127) / 128;
+        int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (2048 + sblk - 1) / sblk));
+        const int64_t grp = (cp.n_holes + parts - 1) / parts;
+        cp.rows_per_part = grp;
+        cp.parts = (int)((cp.n_holes + grp - 1) / grp);
       } else if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E12) {
         // (1,2) string pass: parts = core x group of tile pairs
         const int64_t sblk = (S + 255) / 256;
@@ -901,6 +910,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
       cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
+      cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + 127) / 128) * ip.n_v * ip.n_a * 8 : 0);
     }
     ip.grad_bytes = Gw.cur;
     // info
