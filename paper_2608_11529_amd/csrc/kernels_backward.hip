@@ -721,7 +721,7 @@ __device__ __forceinline__ double xsum4(double v) {    // sum over lanes l, l^16
   return v;
 }
 
-template <int MJ>
+template <int MJ, int GS>
 __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
   __shared__ double sUa[B12C][16];
@@ -792,32 +792,40 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
     }
     __syncthreads();
 #pragma unroll 1
-    for (int sl = 0; sl < B12C; sl += 4) {
-      const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
-      double2 sg[4];
+    for (int sl = 0; sl < B12C; sl += GS) {
+      uint32_t um = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+      for (int k = 0; k < GS; ++k) um |= sM[sl + k];
+      double2 sg[GS];
+#pragma unroll
+      for (int k = 0; k < GS; ++k) sg[k] = make_double2(0.0, 0.0);
 #pragma unroll
       for (int j = 0; j < MJ; ++j)
         if (um & (1u << j)) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
+          for (int k = 0; k < GS; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
         }
-      double dd[4];
+      double dd[GS];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) dd[k] = valid ? (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib] : 1.0;
-      const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
-      const double r = rcp_nr(p01 * p23);
-      const double r01 = r * p23, r23 = r * p01;
-      double w[4];
-      w[0] = r01 * dd[1];
-      w[1] = r01 * dd[0];
-      w[2] = r23 * dd[3];
-      w[3] = r23 * dd[2];
-      double2 sbv[4];
-      double dl[4];
+      for (int k = 0; k < GS; ++k) dd[k] = valid ? (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib] : 1.0;
+      double w[GS];
+      if (GS == 4) {
+        const double p01 = dd[0] * dd[1], p23 = dd[2 % GS] * dd[3 % GS];
+        const double r = rcp_nr(p01 * p23);
+        const double r01 = r * p23, r23 = r * p01;
+        w[0] = r01 * dd[1];
+        w[1] = r01 * dd[0];
+        w[2 % GS] = r23 * dd[3 % GS];
+        w[3 % GS] = r23 * dd[2 % GS];
+      } else {
+        const double r = rcp_nr(dd[0] * dd[1 % GS]);
+        w[0] = r * dd[1 % GS];
+        w[1 % GS] = r * dd[0];
+      }
+      double2 sbv[GS];
+      double dl[GS];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < GS; ++k) {
         const double2 t = make_double2(sg[k].x * w[k], sg[k].y * w[k]);
         sbv[k] = valid ? make_double2(twoN * t.x, twoN * t.y) : make_double2(0.0, 0.0);
         dl[k] = valid ? -oneN * cabs2(t) : 0.0;
@@ -827,10 +835,10 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       for (int j = 0; j < MJ; ++j)
         if (um & (1u << j)) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) Xb[j] = cadd(Xb[j], cmul(sbv[k], cconj(sD[sl + k][j])));
+          for (int k = 0; k < GS; ++k) Xb[j] = cadd(Xb[j], cmul(sbv[k], cconj(sD[sl + k][j])));
         }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < GS; ++k) {
         const double va = xsum16(dl[k]);
         if (ib == 0) sVa[sl + k][ia] = va;
         const double vb = xsum4(dl[k]);

@@ -136,9 +136,9 @@ __global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
   b22fin_body(I.d, I.cls[0], I.g, I.cg[0], bid);
 }
 template <int MJ>
-__global__ void __launch_bounds__(256) k_b_b12r(MRPT2_ARGS) {
+__global__ void __launch_bounds__(256, (MJ == 20 ? 2 : 1)) k_b_b12r(MRPT2_ARGS) {
   MRPT2_JOB
-  b12r_body<MJ>(I.d, I.cls[1], I.g, I.cg[1], bid);
+  b12r_body<MJ, (MJ > 16 ? 2 : 4)>(I.d, I.cls[1], I.g, I.cg[1], bid);
 }
 template <int MJ>
 __global__ void __launch_bounds__(256) k_b_b12s(MRPT2_ARGS) {

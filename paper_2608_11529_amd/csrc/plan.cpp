@@ -437,7 +437,7 @@ void build_launches(Plan* P) {
     }
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22a, j22b, j22w, j12r[4], j12s[5];
+    std::vector<JobH> jr, jsr, j22a, j22b, j22w, j12r[5], j12s[5];
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
@@ -452,8 +452,8 @@ void build_launches(Plan* P) {
       if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
-        j12r[v].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
         const int vs = (J > 16 && J <= 20) ? 4 : v;
+        j12r[vs].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
         j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
@@ -468,6 +468,7 @@ void build_launches(Plan* P) {
       add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v]);
       add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
     }
+    add_launch(P, seq, K_B12R_20, ST_BROW0 + k, j12r[4]);
     add_launch(P, seq, K_B12S_20, ST_BSTR0 + k, j12s[4]);
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
