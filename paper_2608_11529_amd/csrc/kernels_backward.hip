@@ -334,7 +334,7 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
 // fractions merged per reciprocal, give
 //   Abar[cc'][ab] = (2/N) A S1  (written once)  and the row constants'
 //   adjoint -(1/N) |A|^2 S2  (eps and W of c, c', a, b; W_ab).
-// grid (n_tp, C(n_c,2)), block 256.
+// grid (C(n_c,2), n_tp), block 256.
 __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, const GradDev& g, const uint3 bid) {
   __shared__ double sYa[AC22][64];
   __shared__ double sYb[AC22][64];
@@ -342,7 +342,7 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
   __shared__ double sCw[AC22];
   __shared__ double ya0[64], yb0[64];
   __shared__ double red[256];
-  const int tp = bid.x, hp = bid.y;
+  const int hp = bid.x, tp = bid.y;   // core pairs fastest: blocks of one tile pair share its tables in L2
   const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
   const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
   const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
@@ -705,7 +705,7 @@ __device__ __forceinline__ void b22fin_body(const Dev& d, const ClassDev& cd, co
 // sub-tile, couplings and their adjoints in registers): Abar for the core-active
 // pairs, the row constants, and the Uv tables (per-string sums over b and over a
 // reduced across lanes, contracted with the string occupations per chunk).
-// grid (16 n_tp, n_c), block 256.
+// grid (n_c, 16 n_tp), block 256.
 constexpr int B12C = 32;
 
 __device__ __forceinline__ double xsum16(double v) {   // sum over the 16 lanes sharing tid >> 4
@@ -733,9 +733,10 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
   __shared__ double sVa[B12C][16];
   __shared__ double sVb[B12C][16];
   __shared__ double sRow[16], sCol[16];
-  const int tp = bid.x >> 4, sub = bid.x & 15;
+  const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
+  const int tp = tps >> 4, sub = tps & 15;
   const int sa = sub >> 2, sb = sub & 3;
-  const int c = bid.y;
+  const int c = bid.x;
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
   if (I == Jt && sa > sb) return;            // sub-tile below the diagonal: no rows
   const int tid = threadIdx.x, ia = tid >> 4, ib = tid & 15;

@@ -325,7 +325,7 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
 // 64 x 64 tile and walks alpha four at a time, merging the four fractions
 // c1/d1 + ... + c4/d4 into one numerator and denominator so that a single
 // reciprocal serves four determinants.
-// grid (n_tp, C(n_c, 2)), block 256.
+// grid (C(n_c, 2), n_tp), block 256.
 constexpr int AC22 = 32;
 
 __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
@@ -335,7 +335,7 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
   __shared__ double sCw[AC22];
   __shared__ double ya0[64], yb0[64];
   __shared__ double red[256];
-  const int tp = bid.x, hp = bid.y;
+  const int hp = bid.x, tp = bid.y;   // core pairs fastest: blocks of one tile pair share its tables in L2
   const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
   const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
   const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
@@ -476,7 +476,7 @@ __device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd
 // the couplings <ab||ct> of its row in registers; strings are walked in
 // chunks staged in LDS, patterns present in a string selected by a
 // wave-uniform mask, and four fractions |sigma|^2 / Delta merged per
-// reciprocal.  grid (16 n_tp, n_c), block 256.
+// reciprocal.  grid (n_c, 16 n_tp), block 256.
 constexpr int SC12 = 32;
 
 template <int MJ>
@@ -487,12 +487,13 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
   __shared__ double2 sD[SC12][MJ];
   __shared__ uint32_t sM[SC12];
   __shared__ double red[256];
-  const int tp = bid.x >> 4, sub = bid.x & 15;
+  const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
+  const int tp = tps >> 4, sub = tps & 15;
   const int sa = sub >> 2, sb = sub & 3;
-  const int c = bid.y;
+  const int c = bid.x;
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
   if (I == Jt && sa > sb) {                    // block entirely below the diagonal
-    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + bid.x] = 0.0;
+    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + tps] = 0.0;
     return;
   }
   const int tid = threadIdx.x;
@@ -576,7 +577,7 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + bid.x] = red[0];
+  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + tps] = red[0];
 }
 
 

@@ -395,11 +395,11 @@ void build_launches(Plan* P) {
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
       if (cp.kernel == KERN_E22) {
-        e22.push_back(job(i, ip.n_tp, cp.n_holes, k));
+        e22.push_back(job(i, cp.n_holes, ip.n_tp, k));
       } else if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
-        e12[v].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
+        e12[v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
       } else if (cp.kernel == KERN_E02) {
         e02.push_back(job(i, ip.n_tp * 128, 1, k));
         e02_lds = std::max(e02_lds, cp.patterns.size() * 512);
@@ -444,7 +444,7 @@ void build_launches(Plan* P) {
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
       if (cp.kernel == KERN_E22) {
-        j22a.push_back(job(i, ip.n_tp, cp.n_holes, k));
+        j22a.push_back(job(i, cp.n_holes, ip.n_tp, k));
         j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 128), cp.parts, k));
         j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
         continue;
@@ -453,7 +453,7 @@ void build_launches(Plan* P) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         const int vs = (J > 16 && J <= 20) ? 4 : v;
-        j12r[vs].push_back(job(i, ip.n_tp * 16, cp.n_holes, k));
+        j12r[vs].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
         j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
