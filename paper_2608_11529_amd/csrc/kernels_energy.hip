@@ -322,9 +322,9 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
 //   G = T(alpha) + eps_c + Uc_c(alpha) + eps_c' + Uc_c'(alpha) - W_cc',
 //   Y_a = -eps_a - Uv_a(alpha) + W_ca + W_c'a.
 // Pure FP64 vector work: each thread owns a 4 x 4 block of (a, b) of a
-// 64 x 64 tile and walks alpha four at a time, merging the four fractions
-// c1/d1 + ... + c4/d4 into one numerator and denominator so that a single
-// reciprocal serves four determinants.
+// 64 x 64 tile and walks alpha eight at a time, merging the eight fractions
+// c1/d1 + ... + c8/d8 into one numerator and denominator (pairwise products)
+// so that a single reciprocal serves eight determinants.
 // grid (C(n_c, 2), n_tp), block 256.
 constexpr int AC22 = 32;
 
@@ -390,35 +390,39 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
     }
     __syncthreads();
 #pragma unroll 1
-    for (int al = 0; al < AC22; al += 4) {
-      double g[4], cw[4], za[4][4], yb[4][4];
+    for (int al = 0; al < AC22; al += 8) {
+      double g[8], cw[8], za[4][8], yb[4][8];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 8; ++k) {
         g[k] = sG[al + k];
         cw[k] = sCw[al + k];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) za[i][k] = g[k] + sYa[al + k][ta + 16 * i];
+        for (int k = 0; k < 8; ++k) za[i][k] = g[k] + sYa[al + k][ta + 16 * i];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
+        for (int k = 0; k < 8; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const double d0 = (za[i][0] + yb[j][0]) - wab[i][j];
-          const double d1 = (za[i][1] + yb[j][1]) - wab[i][j];
-          const double d2 = (za[i][2] + yb[j][2]) - wab[i][j];
-          const double d3 = (za[i][3] + yb[j][3]) - wab[i][j];
-          const double n01 = fma(cw[0], d1, cw[1] * d0);
-          const double q01 = d0 * d1;
-          const double n23 = fma(cw[2], d3, cw[3] * d2);
-          const double q23 = d2 * d3;
-          const double num = fma(n01, q23, n23 * q01);
-          const double den = q01 * q23;
+          // sum_k cw_k / d_k over eight strings as one fraction: pairwise
+          // numerators and denominators, one reciprocal
+          double n2[4], q2[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double da = (za[i][2 * k] + yb[j][2 * k]) - wab[i][j];
+            const double db = (za[i][2 * k + 1] + yb[j][2 * k + 1]) - wab[i][j];
+            n2[k] = fma(cw[2 * k], db, cw[2 * k + 1] * da);
+            q2[k] = da * db;
+          }
+          const double n4a = fma(n2[0], q2[1], n2[1] * q2[0]), q4a = q2[0] * q2[1];
+          const double n4b = fma(n2[2], q2[3], n2[3] * q2[2]), q4b = q2[2] * q2[3];
+          const double num = fma(n4a, q4b, n4b * q4a);
+          const double den = q4a * q4b;
           acc[i][j] = fma(num, rcp_nr(den), acc[i][j]);
         }
     }
