@@ -51,6 +51,11 @@ struct Dev {
   const int32_t* tile_pairs; // [n_tp][2]
   double* dg;                // [n_l][n]   scale * Re B[L][p][p]
   double2* slab;             // [n_occ][n_corr][n_l]   scale * B[L][n_fc+pc][x]
+  float2* slab32;            // mixed form only, else null: [n_o][n_v][n_l2], FP32
+                             // slab of the virtual rows of the occupied x >= n_fc,
+                             // times i where the factor weight is negative; the
+                             // rows are padded with zero to the even n_l2
+  int n_l2;                  // n_l rounded up to even
   double* W;                 // [n][n]
   double* eps;               // [n_corr]
   double2* f;                // [n_a+n_v][n_o]

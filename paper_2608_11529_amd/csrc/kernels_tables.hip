@@ -6,7 +6,10 @@ namespace mrpt2 {
 
 // Slab of the factor columns of every occupied-type spinor x (frozen core,
 // core, active): slab[x][pc][L] = sqrt|w| B[L][n_fc + pc][x], and the scaled
-// diagonals dg[L][p] = sqrt|w| Re B[L][p][p].
+// diagonals dg[L][p] = sqrt|w| Re B[L][p][p].  The mixed form also writes the
+// FP32 copy slab32 of the virtual rows (pc >= n_o) of the non-frozen x, with
+// the column multiplied by i where w < 0: a product of two such entries then
+// carries the weight's sign, with the rounding of the unrotated product.
 // Grid (ceil(rank/64), n_corr) per factor set, block 256.
 __device__ __forceinline__ void pack_body(const Dev& d, int t, const uint3 bid) {
   const double2* __restrict__ B = d.sets.B[t];
@@ -31,6 +34,12 @@ __device__ __forceinline__ void pack_body(const Dev& d, int t, const uint3 bid) 
         const double s = d.scale[l0 + L];
         const double2 v = tile[li][xi];
         d.slab[((int64_t)x * d.n_corr + pc) * d.n_l + l0 + L] = make_double2(s * v.x, s * v.y);
+        if (d.slab32 && x >= d.n_fc && pc >= d.n_o) {
+          const int64_t o = ((int64_t)(x - d.n_fc) * d.n_v + (pc - d.n_o)) * d.n_l2 + l0 + L;
+          const float re = (float)(s * v.x), im = (float)(s * v.y);
+          d.slab32[o] = d.sign[l0 + L] < 0.0 ? make_float2(-im, re) : make_float2(re, im);
+          if (l0 + L + 1 == d.n_l && d.n_l2 > d.n_l) d.slab32[o + 1] = make_float2(0.f, 0.f);
+        }
       }
     }
     __syncthreads();
@@ -275,8 +284,9 @@ constexpr int KP32 = KC32 + 1;
 // result D[i][j] sits in lane j + 16 (i/4), register i%4.  Products and the
 // sums over one stage (KC32 complex k) are FP32; every stage's partial sums
 // are added into FP64 accumulators, so the FP32 rounding of a sum grows
-// with the stage length only.  Operands are rounded to FP32 once when they
-// are staged.
+// with the stage length only.  The loaders return two complex FP32 operands
+// (k, k+1) for even k: the next stage's loads are issued before the MFMAs of
+// the current stage and complete behind them.
 template <class FA, class FB>
 __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, float2* sB,
                                             double (&accR)[2][2][4], double (&accI)[2][2][4]) {
@@ -293,16 +303,31 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
       }
   const int kq = lane >> 4;
   const int kcl = kq >> 1, comp = kq & 1;
+  constexpr int HP = KC32 / 2;                // operand pairs per staged row
+  constexpr int PER = 64 * HP / 256;          // pairs per thread and operand
+  float4 ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / HP, k = k0 + 2 * (e % HP);
+      ra[u] = k < K ? fa(r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
+      rb[u] = k < K ? fb(r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < K; k0 += KC32) {
-    for (int e = tid; e < 64 * KC32; e += 256) {
-      const int r = e / KC32, kk = e % KC32;
-      const bool in = (k0 + kk) < K;
-      const double2 a = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
-      const double2 b = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
-      sA[r * KP32 + kk] = make_float2((float)a.x, (float)a.y);
-      sB[r * KP32 + kk] = make_float2((float)b.x, (float)b.y);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int o = (e / HP) * KP32 + 2 * (e % HP);
+      sA[o] = make_float2(ra[u].x, ra[u].y);
+      sA[o + 1] = make_float2(ra[u].z, ra[u].w);
+      sB[o] = make_float2(rb[u].x, rb[u].y);
+      sB[o + 1] = make_float2(rb[u].z, rb[u].w);
     }
     __syncthreads();
+    if (k0 + KC32 < K) fetch(k0 + KC32);
     f4 pR[2][2], pI[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -352,7 +377,8 @@ __device__ __forceinline__ int acc_row_f32(int i, int r) {
   return (wv >> 1) * 32 + i * 16 + 4 * (lane >> 4) + r;
 }
 
-// Mixed-precision form of k_abuild (same operands, same output layout).
+// Mixed-precision form of k_abuild: the same integrals and output layout,
+// from the FP32 slab.
 __device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {
   __shared__ float2 sA[64 * KP32];
   __shared__ float2 sB[64 * KP32];
@@ -365,27 +391,30 @@ __device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {
   }
   const int yo = xo + 1 + (int)pr;
   const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
-  const int nl = d.n_l;
-  const double2* Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
-  const double2* Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
-  const double* sg = d.sign;
+  // K runs over [x-columns, y-columns] of the FP32 slab (rows of n_l2 pairs,
+  // zero-padded): A[a][k] = (S_x[a] | S_y[a]), B[b][k] = (S_y[b] | -S_x[b]);
+  // the factor signs are carried by the slab itself.
+  const int nl2 = d.n_l2;
+  const float4* Sx = (const float4*)(d.slab32 + (int64_t)xo * d.n_v * nl2);
+  const float4* Sy = (const float4*)(d.slab32 + (int64_t)yo * d.n_v * nl2);
   const int nv = d.n_v;
-  auto fa = [&](int r, int k) -> double2 {
+  const int h2 = nl2 >> 1;
+  auto fa = [&](int r, int k) -> float4 {
     const int a = I * 64 + r;
-    if (a >= nv) return make_double2(0.0, 0.0);
-    const int L = k < nl ? k : k - nl;
-    const double2 v = (k < nl ? Sx : Sy)[(int64_t)a * nl + L];
-    return make_double2(sg[L] * v.x, sg[L] * v.y);
+    if (a >= nv) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kp = k >> 1;
+    return kp < h2 ? Sx[(int64_t)a * h2 + kp] : Sy[(int64_t)a * h2 + kp - h2];
   };
-  auto fb = [&](int r, int k) -> double2 {
+  auto fb = [&](int r, int k) -> float4 {
     const int b = J * 64 + r;
-    if (b >= nv) return make_double2(0.0, 0.0);
-    if (k < nl) return Sy[(int64_t)b * nl + k];
-    const double2 v = Sx[(int64_t)b * nl + (k - nl)];
-    return make_double2(-v.x, -v.y);
+    if (b >= nv) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kp = k >> 1;
+    if (kp < h2) return Sy[(int64_t)b * h2 + kp];
+    const float4 v = Sx[(int64_t)b * h2 + kp - h2];
+    return make_float4(-v.x, -v.y, -v.z, -v.w);
   };
   double accR[2][2][4], accI[2][2][4];
-  cgemm64_f32(fa, fb, 2 * nl, sA, sB, accR, accI);
+  cgemm64_f32(fa, fb, 2 * nl2, sA, sB, accR, accI);
   double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
 #pragma unroll
   for (int i = 0; i < 2; ++i)

@@ -61,6 +61,8 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.tile_pairs = (const int32_t*)(P + ip.off_tile_pairs);
   d.dg = (double*)(W + ip.off_dg);
   d.slab = (double2*)(W + ip.off_slab);
+  d.n_l2 = ip.n_l + (ip.n_l & 1);
+  d.slab32 = (ip.d.precision == MRPT2_MIXED && ip.n_v >= 2) ? (float2*)(W + ip.off_slab32) : nullptr;
   d.W = (double*)(W + ip.off_W);
   d.eps = (double*)(W + ip.off_eps);
   d.f = (double2*)(W + ip.off_f);

@@ -820,6 +820,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
     const size_t NP = ip.pstrings.size();
     ip.off_dg = W.take((size_t)ip.n_l * ip.n * 8);
     ip.off_slab = W.take((size_t)ip.n_occ * ip.n_corr * ip.n_l * 16);
+    ip.off_slab32 = W.take((ip.d.precision == MRPT2_MIXED && ip.n_v >= 2)
+                               ? (size_t)ip.n_o * ip.n_v * (ip.n_l + (ip.n_l & 1)) * 8 : 0);
     ip.off_W = W.take((size_t)ip.n * ip.n * 8);
     ip.off_eps = W.take((size_t)ip.n * 8);
     ip.off_f = W.take((size_t)(ip.n_a + ip.n_v) * ip.n_o * 16);

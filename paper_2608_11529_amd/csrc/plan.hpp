@@ -76,7 +76,7 @@ struct InstancePlan {
   size_t off_pstrings = 0, off_hole_pairs = 0, off_tile_pairs = 0, off_sign = 0, off_scale = 0;
   size_t persistent_bytes = 0, persistent_base = 0;
   // workspace layout
-  size_t off_dg = 0, off_slab = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
+  size_t off_dg = 0, off_slab = 0, off_slab32 = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
   size_t off_hpp = 0, off_sigp = 0, off_scal = 0, off_dsum = 0, off_part = 0;
   size_t workspace_bytes = 0, workspace_base = 0;
   // gradient workspace layout (adjoint)
