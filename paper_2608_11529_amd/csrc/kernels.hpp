@@ -93,6 +93,13 @@ struct ClassDev {
   int nsc;       // string chunks
   double2* D;    // [S][n_pat] dense coefficients (classes with few patterns)
   uint32_t* mask;  // [S] nonzero patterns per string
+  // class (0,2): string tiles and their dense coefficient blocks
+  int64_t n_tiles;
+  const int32_t* tile_s0;   // [n_tiles + 1]
+  const int32_t* tile_k0;   // [n_tiles + 1]
+  const int32_t* tile_sup;  // [tile_k0[n_tiles]] occupied-pair index or -1
+  const int32_t* ccol;      // [n_conn]
+  double2* Md;              // tile t: [64][K_t] at 64 * tile_k0[t]
 };
 
 // Adjoint (backward) state of one instance: gradients of E2 with respect to

@@ -89,6 +89,10 @@ __global__ void __launch_bounds__(256) k_b_e02(MRPT2_ARGS) {
   MRPT2_JOB
   e02_body(I.d, I.cls[2], flag, bid);
 }
+__global__ void __launch_bounds__(64) k_b_e02coef(MRPT2_ARGS) {
+  MRPT2_JOB
+  e02coef_body(I.d, I.cls[jb.arg], bid);
+}
 template <int H, int V, int K>
 __global__ void __launch_bounds__(SIG_THREADS) k_b_sigma(MRPT2_ARGS) {
   MRPT2_JOB

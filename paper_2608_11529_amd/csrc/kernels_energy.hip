@@ -589,59 +589,108 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
 // L = core + alpha'' + {t, w} by a_t a_w -> a+_b a+_a:
 //   sigma_K = sum_{t<w} <ab||tw> sign C_L,
 //   Delta   = T - eps_a - Uv_a - eps_b - Uv_b - W_ab.
-// 32 rows (fixed a, 32 consecutive b) per block with the couplings of every
-// pattern staged in LDS; eight interleaved string streams per block walk the
-// excitation lists.  grid (128 n_tp), block 256, dynamic LDS n_pat * 512 B.
+// The strings come in tiles of at most 64 of one occupation category (plan
+// order); a tile's coefficients sign C_L form a dense block Md[s][col] over
+// the tile's support columns (its strings' active pairs), so that sigma over
+// a tile and 64 virtual pairs is one complex GEMM with K = support size.
+
+// Dense coefficient blocks, one thread per tile row.  grid (n_tiles), block 64.
+__device__ __forceinline__ void e02coef_body(const Dev& d, const ClassDev& cd, const uint3 bid) {
+  const int64_t t = bid.x;
+  const int r = threadIdx.x;
+  const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
+  const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
+  double2* row = cd.Md + (int64_t)64 * k0 + (int64_t)r * K;
+  for (int k = 0; k < K; ++k) row[k] = make_double2(0.0, 0.0);
+  const int s = s0 + r;
+  if (s >= s1) return;
+  for (int e = cd.conn_ptr[s]; e < cd.conn_ptr[s + 1]; ++e) {
+    const int32_t cb = cd.conn[2 * e];
+    double2 cv = d.c[cb & 0x7fffffff];
+    if (cb < 0) cv = make_double2(-cv.x, -cv.y);
+    const int k = cd.ccol[e];
+    row[k] = make_double2(row[k].x + cv.x, row[k].y + cv.y);
+  }
+}
+
+// sigma for (tile, virtual a, 64 virtual b of a tile pair) on FP64 MFMA, then
+// |sigma|^2 / Delta summed over the valid (string, a < b) entries, four
+// fractions per reciprocal.  grid (n_tiles, 64 n_tp): tiles fastest, so that
+// the blocks sharing one row of pair integrals run together.  block 256.
 __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
-  extern __shared__ double2 sX[];
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
   __shared__ double red[256];
-  const int64_t blk = bid.x;
-  const int64_t tp = blk >> 7;
-  const int la = (int)((blk >> 1) & 63), half = (int)(blk & 1);
+  const int64_t t = bid.x;
+  const int64_t tp = bid.y >> 6;
+  const int la = (int)(bid.y & 63);
+  const int64_t blk = (int64_t)bid.y * cd.n_tiles + t;
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
-  const int nv = d.n_v, nc = d.n_c;
-  const int a0 = I * 64 + la;
-  const int bmax = Jt * 64 + half * 32 + 31;
-  if (a0 >= nv || a0 >= bmax) {               // no valid (a, b) in this block
+  const int nv = d.n_v;
+  const int a = I * 64 + la;
+  if (a + 1 >= nv || a >= Jt * 64 + 63) {      // no valid (a, b) in this block
     if (threadIdx.x == 0) cd.part[blk] = 0.0;
     return;
   }
-  const int tid = threadIdx.x, rl = tid & 31, sgp = tid >> 5;
-  const int J = cd.n_pat;
-  for (int e = tid; e < J * 32; e += 256) {
-    const int j = e >> 5, r = e & 31;
-    const Pattern pt = cd.pat[j];
-    const int64_t pr = occ_pair(nc + pt.a0, nc + pt.a1, d.n_o);
-    sX[e] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + half * 32 + r];
-  }
-  __syncthreads();
-  int a = a0, b = Jt * 64 + half * 32 + rl;
-  const bool valid = (a < b) && (b < nv);
-  if (!valid) {
-    a = 0;
-    b = nv > 1 ? 1 : 0;
-  }
+  const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
+  const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
+  const double2* M = cd.Md + (int64_t)64 * k0;
+  const int32_t* sup = cd.tile_sup + k0;
+  const double2* Ar = d.A + tp * 4096 + la * 64;
+  auto fa = [&](int r, int k) -> double2 { return M[r * K + k]; };
+  auto fb = [&](int r, int k) -> double2 {
+    const int pr = sup[k];
+    return pr < 0 ? make_double2(0.0, 0.0) : Ar[(int64_t)pr * d.n_tp * 4096 + r];
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64<true>(fa, fb, K, sA, sB, accR, accI);
   const int64_t gv = d.n_fc + d.n_o;
-  const double rowc = -d.eps[d.n_o + a] - d.eps[d.n_o + b] - d.W[(gv + a) * d.n + gv + b];
-  const int64_t S = cd.n_str;
+  const double ea = d.eps[d.n_o + a];
+  double rowc[2];
+  bool bok[2];
+  int bb[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int b = Jt * 64 + acc_col(j);
+    bok[j] = (a < b) && (b < nv);
+    bb[j] = bok[j] ? b : a;
+    rowc[j] = bok[j] ? -ea - d.eps[d.n_o + b] - d.W[(gv + a) * d.n + gv + b] : 0.0;
+  }
   double acc = 0.0;
-  for (int64_t s = sgp; s < S; s += 8) {
-    const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
-    double2 sig = make_double2(0.0, 0.0);
-    for (int e = e0; e < e1; ++e) {
-      const int32_t cb = cd.conn[2 * e];
-      const int j = cd.conn[2 * e + 1];
-      double2 cv = d.c[cb & 0x7fffffff];
-      if (cb < 0) cv = make_double2(-cv.x, -cv.y);
-      sig = cfma(cv, sX[j * 32 + rl], sig);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    double Ts[4], ua[4];
+    bool sok[4];
+    int64_t so[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = s0 + acc_row(i, r);
+      sok[r] = s < s1;
+      const int sv = sok[r] ? s : s0;
+      so[r] = (int64_t)sv * nv;
+      Ts[r] = cd.T[sv];
+      ua[r] = cd.Uv[so[r] + a];
     }
-    if (e1 > e0) {
-      const double del = cd.T[s] + rowc - cd.Uv[s * nv + a] - cd.Uv[s * nv + b];
-      acc = fma(cabs2(sig), rcp_nr(del), acc);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double w[4], dd[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = sok[r] && bok[j];
+        const double del = (Ts[r] + rowc[j]) - ua[r] - cd.Uv[so[r] + bb[j]];
+        w[r] = ok ? accR[i][j][r] * accR[i][j][r] + accI[i][j][r] * accI[i][j][r] : 0.0;
+        dd[r] = ok ? del : 1.0;
+      }
+      const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
+      const double q01 = dd[0] * dd[1];
+      const double n23 = fma(w[2], dd[3], w[3] * dd[2]);
+      const double q23 = dd[2] * dd[3];
+      acc = fma(fma(n01, q23, n23 * q01), rcp_nr(q01 * q23), acc);
     }
   }
-  if (valid && !isfinite(acc)) *flag = 2;
-  red[tid] = valid ? acc : 0.0;
+  if (!isfinite(acc)) *flag = 2;
+  const int tid = threadIdx.x;
+  red[tid] = acc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) red[tid] += red[tid + o];

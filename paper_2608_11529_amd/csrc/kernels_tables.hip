@@ -168,7 +168,8 @@ constexpr int KP = KC + 1;
 // B[l/16][l%16]; the result D[i][j] sits in lane j + 16 (i%4), register i/4.
 // A complex product uses two real MFMAs per pair of complex k:
 //   Re += [ar, -ai] . [br; bi],   Im += [ai, ar] . [br; bi].
-template <class FA, class FB>
+// BCOL: b(c, k) is read with c fastest across threads (operands stored k-major).
+template <bool BCOL = false, class FA, class FB>
 __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double2* sB,
                                         d4 (&accR)[2][2], d4 (&accI)[2][2]) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -187,8 +188,13 @@ __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double
       const int r = e / KC, kk = e % KC;
       const bool in = (k0 + kk) < K;
       sA[r * KP + kk] = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
-      sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
+      if (!BCOL) sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
     }
+    if (BCOL)
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int c = e & 63, kk = e >> 6;
+        sB[c * KP + kk] = (k0 + kk) < K ? fb(c, k0 + kk) : make_double2(0.0, 0.0);
+      }
     __syncthreads();
 #pragma unroll 2
     for (int ks = 0; ks < KC; ks += 2) {
@@ -285,8 +291,8 @@ constexpr int KP32 = KC32 + 1;
 // sums over one stage (KC32 complex k) are FP32; every stage's partial sums
 // are added into FP64 accumulators, so the FP32 rounding of a sum grows
 // with the stage length only.  The loaders return two complex FP32 operands
-// (k, k+1) for even k: the next stage's loads are issued before the MFMAs of
-// the current stage and complete behind them.
+// (k, k+1) for even k: each stage's loads are issued two stages ahead and
+// complete behind the MFMAs of the stages in between.
 template <class FA, class FB>
 __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, float2* sB,
                                             double (&accR)[2][2][4], double (&accI)[2][2][4]) {
@@ -305,8 +311,9 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
   const int kcl = kq >> 1, comp = kq & 1;
   constexpr int HP = KC32 / 2;                // operand pairs per staged row
   constexpr int PER = 64 * HP / 256;          // pairs per thread and operand
-  float4 ra[PER], rb[PER];
-  auto fetch = [&](int k0) {
+  // two register sets: the loads of a stage are issued two stages ahead
+  float4 ra0[PER], rb0[PER], ra1[PER], rb1[PER];
+  auto fetch = [&](float4 (&ra)[PER], float4 (&rb)[PER], int k0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
@@ -315,8 +322,7 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
       rb[u] = k < K ? fb(r, k) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += KC32) {
+  auto stage = [&](float4 (&ra)[PER], float4 (&rb)[PER], int k0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
@@ -327,7 +333,7 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
       sB[o + 1] = make_float2(rb[u].z, rb[u].w);
     }
     __syncthreads();
-    if (k0 + KC32 < K) fetch(k0 + KC32);
+    if (k0 + 2 * KC32 < K) fetch(ra, rb, k0 + 2 * KC32);
     f4 pR[2][2], pI[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -369,6 +375,12 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
           accI[i][j][r] += (double)pI[i][j][r];
         }
     __syncthreads();
+  };
+  fetch(ra0, rb0, 0);
+  if (KC32 < K) fetch(ra1, rb1, KC32);
+  for (int k0 = 0; k0 < K; k0 += 2 * KC32) {
+    stage(ra0, rb0, k0);
+    if (k0 + KC32 < K) stage(ra1, rb1, k0 + KC32);
   }
 }
 

@@ -108,6 +108,12 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.X = (double2*)(W + cp.off_X);
   c.D = (double2*)(W + cp.off_D);
   c.mask = (uint32_t*)(W + cp.off_mask);
+  c.n_tiles = cp.n_tiles;
+  c.tile_s0 = (const int32_t*)(P + cp.off_tile_s0);
+  c.tile_k0 = (const int32_t*)(P + cp.off_tile_k0);
+  c.tile_sup = (const int32_t*)(P + cp.off_tile_sup);
+  c.ccol = (const int32_t*)(P + cp.off_ccol);
+  c.Md = (double2*)(W + cp.off_Md);
   c.part = (double*)(W + ip.off_part_class[k]);
   c.n_part = (cp.strings.empty() || cp.n_rows == 0) ? 0 : cp.n_blocks;
   const int64_t rb = cdiv(cp.n_rows, 256);
@@ -252,12 +258,8 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E12_16: hipLaunchKernelGGL((k_b_e12<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_24: hipLaunchKernelGGL((k_b_e12<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_32: hipLaunchKernelGGL((k_b_e12<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E02:
-        if (hipFuncSetAttribute((const void*)k_b_e02, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kE02MaxLds) != hipSuccess)
-          return MRPT2_ERR_HIP;
-        hipLaunchKernelGGL(k_b_e02, g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);
-        break;
+      case K_E02: hipLaunchKernelGGL(k_b_e02, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02COEF: hipLaunchKernelGGL(k_b_e02coef, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG22: hipLaunchKernelGGL((k_b_sigma<2, 2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG12: hipLaunchKernelGGL((k_b_sigma<1, 2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG02: hipLaunchKernelGGL((k_b_sigma<0, 2, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

@@ -330,6 +330,78 @@ void table_launches(Plan* P, std::vector<Launch>* seq, const std::vector<int>& w
   add_launch(P, seq, K_GBUILD, ST_GBUILD, js);
 }
 
+// Class (0,2): order the strings of each occupation category by the set of
+// active pairs they couple through, then cut them into tiles of at most
+// kStrTile consecutive strings of one category.  A tile's support is the
+// union of its strings' pairs; its coefficients form a dense [tile][support]
+// block whose product with the pair integrals is one small complex GEMM.
+// Returns false (generic kernel) if some string has no coupling.
+bool tile_by_support(InstancePlan& ip, ClassPlan& cp, const std::vector<int>& ss, const std::vector<int>& off) {
+  const size_t S = cp.strings.size();
+  auto category = [&](uint64_t al) {
+    std::vector<int> m(ss.size());
+    for (size_t q = 0; q < ss.size(); ++q)
+      m[q] = popc((al >> off[q]) & (ss[q] >= 64 ? ~0ull : (1ull << ss[q]) - 1));
+    return m;
+  };
+  std::vector<std::pair<std::vector<int>, std::vector<int>>> key(S);
+  for (size_t s = 0; s < S; ++s) {
+    key[s].first = category(cp.strings[s]);
+    for (int e = cp.conn_ptr[s]; e < cp.conn_ptr[s + 1]; ++e) {
+      const Pattern& p = cp.patterns[cp.conn[2 * e + 1]];
+      key[s].second.push_back(p.a0 * 64 + p.a1);
+    }
+    if (key[s].second.empty()) return false;
+    std::sort(key[s].second.begin(), key[s].second.end());
+  }
+  std::vector<size_t> ord(S);
+  for (size_t s = 0; s < S; ++s) ord[s] = s;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+  std::vector<uint64_t> sorted(S);
+  std::vector<std::vector<int>> cat(S);
+  for (size_t s = 0; s < S; ++s) {
+    sorted[s] = cp.strings[ord[s]];
+    cat[s] = key[ord[s]].first;
+  }
+  cp.strings.swap(sorted);
+  cp.patterns.clear();
+  cp.conn.clear();
+  cp.conn_ptr.clear();
+  build_class(ip, cp);
+  cp.tile_s0.assign(1, 0);
+  cp.tile_k0.assign(1, 0);
+  cp.tile_sup.clear();
+  cp.ccol.assign(cp.n_conn, -1);
+  std::vector<int32_t> col(cp.patterns.size(), -1);
+  size_t s = 0;
+  while (s < S) {
+    size_t e = s;
+    while (e < S && e - s < (size_t)kStrTile && cat[e] == cat[s]) ++e;
+    std::vector<int> used;
+    for (size_t t = s; t < e; ++t)
+      for (int c = cp.conn_ptr[t]; c < cp.conn_ptr[t + 1]; ++c) {
+        const int j = cp.conn[2 * c + 1];
+        if (col[j] < 0) {
+          col[j] = (int32_t)used.size();
+          used.push_back(j);
+        }
+        cp.ccol[c] = col[j];
+      }
+    for (int j : used) {
+      const Pattern& p = cp.patterns[j];
+      const int x = ip.n_c + p.a0, y = ip.n_c + p.a1;
+      cp.tile_sup.push_back((int32_t)((int64_t)x * ip.n_o - (int64_t)x * (x + 1) / 2 + (y - x - 1)));
+      col[j] = -1;
+    }
+    if (used.size() & 1) cp.tile_sup.push_back(-1);
+    cp.tile_s0.push_back((int32_t)e);
+    cp.tile_k0.push_back((int32_t)cp.tile_sup.size());
+    s = e;
+  }
+  cp.n_tiles = (int64_t)cp.tile_s0.size() - 1;
+  return true;
+}
+
 }  // namespace
 
 void build_launches(Plan* P) {
@@ -387,9 +459,14 @@ void build_launches(Plan* P) {
         js.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
     }
     add_launch(P, seq, K_DCOEF, ST_PREP0 + k, js);
+    js.clear();
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.kernel == KERN_E02 && !cp.strings.empty() && cp.n_rows > 0) js.push_back(job(i, cp.n_tiles, 1, k));
+    }
+    add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
     std::vector<JobH> e22, e12[4], e02, gen;
-    size_t e02_lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -401,8 +478,7 @@ void build_launches(Plan* P) {
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         e12[v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
       } else if (cp.kernel == KERN_E02) {
-        e02.push_back(job(i, ip.n_tp * 128, 1, k));
-        e02_lds = std::max(e02_lds, cp.patterns.size() * 512);
+        e02.push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
       } else {
         gen.push_back(job(i, sigma_blocks(ip, k), 1, k));
       }
@@ -412,7 +488,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12_16, ST_SIGMA0 + k, e12[1]);
     add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[2]);
     add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[3]);
-    add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02, e02_lds);
+    add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02);
     add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
   }
   js.clear();
@@ -594,12 +670,15 @@ void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
     return;
   }
   if (cp.kernel == KERN_E02) {
-    const int64_t tp = b >> 7;
-    const int la = (int)((b >> 1) & 63), half = (int)(b & 1);
+    const int64_t t = b % cp.n_tiles, rc = b / cp.n_tiles;
+    const int64_t tp = rc >> 6;
+    const int la = (int)(rc & 63);
     set_holes(0);
     const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
     o->a_lo = clampv(I * 64 + la); o->a_hi = clampv(I * 64 + la + 1);
-    o->b_lo = clampv(J * 64 + half * 32); o->b_hi = clampv(J * 64 + half * 32 + 32);
+    o->b_lo = clampv(J * 64); o->b_hi = clampv(J * 64 + 64);
+    o->s_lo = cp.tile_s0[t];
+    o->s_hi = cp.tile_s0[t + 1];
     return;
   }
   // generic kernel: rows x string chunk
@@ -737,6 +816,13 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       if (!cp.strings.empty()) build_class(ip, cp);
       if (k == 1 && !cp.strings.empty() && cp.patterns.size() <= (size_t)kMaxDenseJ)
         sort_by_pattern_mask(ip, cp);
+      if (k == 2 && !cp.strings.empty() && !tile_by_support(ip, cp, ss, off)) {
+        cp.n_tiles = 0;
+        cp.tile_s0.clear();
+        cp.tile_k0.clear();
+        cp.tile_sup.clear();
+        cp.ccol.clear();
+      }
     }
     // the (2,2) class walks the reference strings themselves
     if (!ip.cls[0].strings.empty() && ip.cls[0].strings != ip.pstrings) {
@@ -796,6 +882,10 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
         cp.ekey[e] = key | (cp.conn[2 * e] < 0 ? (int32_t)0x80000000 : 0);
       }
       cp.off_ekey = P.take(cp.ekey.size() * 4);
+      cp.off_tile_s0 = P.take(cp.tile_s0.size() * 4);
+      cp.off_tile_k0 = P.take(cp.tile_k0.size() * 4);
+      cp.off_tile_sup = P.take(cp.tile_sup.size() * 4);
+      cp.off_ccol = P.take(cp.ccol.size() * 4);
     }
     ip.persistent_bytes = P.cur;
     ip.host_blob.assign(ip.persistent_bytes, 0);
@@ -814,6 +904,10 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       put(cp.off_conn, cp.conn.data(), cp.conn.size() * 4);
       put(cp.off_pat, cp.patterns.data(), cp.patterns.size() * sizeof(Pattern));
       put(cp.off_ekey, cp.ekey.data(), cp.ekey.size() * 4);
+      put(cp.off_tile_s0, cp.tile_s0.data(), cp.tile_s0.size() * 4);
+      put(cp.off_tile_k0, cp.tile_k0.data(), cp.tile_k0.size() * 4);
+      put(cp.off_tile_sup, cp.tile_sup.data(), cp.tile_sup.size() * 4);
+      put(cp.off_ccol, cp.ccol.data(), cp.ccol.size() * 4);
     }
     // ---- workspace layout ----
     Layout W;
@@ -844,16 +938,17 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
       // kernel choice and partial-sum blocks: the dedicated kernels' grids
       // ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per tile pair x
-      // core; (0,2): 128 half-rows per tile pair) or the generic kernel's
+      // core; (0,2): string tile x 64 rows of a tile pair) or the generic kernel's
       cp.kernel = KERN_GENERIC;
       if (S && cp.n_rows > 0) {
         if (k == 0) cp.kernel = KERN_E22;
         else if (k == 1 && cp.dense_coef) cp.kernel = KERN_E12;
-        else if (k == 2 && !cp.patterns.empty() && cp.patterns.size() * 512 <= kE02MaxLds) cp.kernel = KERN_E02;
+        else if (k == 2 && cp.n_tiles > 0) cp.kernel = KERN_E02;
       }
+      cp.off_Md = W.take(cp.kernel == KERN_E02 ? (size_t)kStrTile * cp.tile_k0.back() * 16 : 0);
       cp.n_blocks = (cp.kernel == KERN_E22)   ? ip.n_tp * cp.n_holes
                     : (cp.kernel == KERN_E12) ? ip.n_tp * 16 * cp.n_holes
-                    : (cp.kernel == KERN_E02) ? ip.n_tp * 128
+                    : (cp.kernel == KERN_E02) ? ip.n_tp * 64 * cp.n_tiles
                                               : sigma_blocks(ip, k);
       ip.n_part_class[k] = cp.n_blocks;
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);

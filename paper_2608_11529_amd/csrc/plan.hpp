@@ -53,6 +53,15 @@ struct ClassPlan {
   int64_t rows_per_part = 0;           // rows per part (tile pairs per part for the (1,2) kernels)
   int row_split = 1;                   // string chunks of the generic row-owned adjoint pass
   bool dense_coef = false;             // coefficients as a dense [S][n_pat] table + masks
+  // class (0,2) contraction kernel: tiles of at most 64 consecutive strings of
+  // one occupation category; a tile's support is the union of the active
+  // pairs its strings couple through
+  std::vector<int32_t> tile_s0;        // [n_tiles + 1] first string of each tile
+  std::vector<int32_t> tile_k0;        // [n_tiles + 1] first support column (counts padded to even)
+  std::vector<int32_t> tile_sup;       // per support column: occupied-pair index of the active pair, or -1
+  std::vector<int32_t> ccol;           // per coupling: its column in the support of the string's tile
+  int64_t n_tiles = 0;
+  size_t off_tile_s0 = 0, off_tile_k0 = 0, off_tile_sup = 0, off_ccol = 0, off_Md = 0;
   int kernel = 0;                      // KERN_* below
   int64_t n_blocks = 0;                // partial sums written by the class's kernel
 };
@@ -96,7 +105,7 @@ struct InstancePlan {
 enum KernelId : int {
   K_CLEAR, K_PACK, K_DIAG, K_WPASS, K_EPS, K_DSUM, K_FOCK, K_GBUILD, K_HPP, K_SIGP, K_E0,
   K_ABUILD, K_ABUILD32, K_CTAB, K_XBUILD, K_DCOEF, K_E22, K_E12_8, K_E12_16, K_E12_24, K_E12_32,
-  K_E02, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
+  K_E02, K_E02COEF, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
   // adjoint
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
@@ -149,7 +158,7 @@ struct Plan {
 
 // Kernel that evaluates a class.
 enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3 };
-constexpr size_t kE02MaxLds = 150 * 1024;   // LDS bytes of the (0,2) kernel's coupling block
+constexpr int kStrTile = 64;                // strings per tile of the (0,2) contraction kernel
 
 struct Plan;
 // Launch sequences and job table of a plan whose instances are built.
