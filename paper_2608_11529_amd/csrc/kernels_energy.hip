@@ -326,7 +326,7 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
 // c1/d1 + ... + c8/d8 into one numerator and denominator (pairwise products)
 // so that a single reciprocal serves eight determinants.
 // grid (C(n_c, 2), n_tp), block 256.
-constexpr int AC22 = 32;
+constexpr int AC22 = 64;
 
 __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sYa[AC22][64];
@@ -481,7 +481,7 @@ __device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd
 // chunks staged in LDS, patterns present in a string selected by a
 // wave-uniform mask, and four fractions |sigma|^2 / Delta merged per
 // reciprocal.  grid (n_c, 16 n_tp), block 256.
-constexpr int SC12 = 32;
+constexpr int SC12 = 64;
 
 template <int MJ>
 __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
