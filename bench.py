@@ -90,6 +90,11 @@ def cpu_baseline(pb, seconds=15.0):
     }
 
 
+def tuning_note(autotune):
+    n = len(autotune.load_table())
+    return "autotuned table (%d size buckets)" % n if n else "built-in rules"
+
+
 def bench_batched(args):
     """c3: 64 independent instances of uneven size (core 4-20, active 6-12 at
     half filling in 2-3 subspaces with one hop, virtual 50-400, DC rank
@@ -98,6 +103,7 @@ def bench_batched(args):
     import torch
     import synth.problems as SP
     import paper_2608_11529_amd as M
+    from paper_2608_11529_amd import autotune
     from paper_2608_11529_amd.reference import ground_state
 
     n_inst = 64
@@ -110,8 +116,8 @@ def bench_batched(args):
     for pb in pbs:
         h = SP.one_body(pb, dev)
         Bs = SP.factors(pb, dev)
-        p1 = M.Plan(M.desc_of_problem(pb, precision=prec))
-        e1 = M.Engine(p1, dev)
+        d1 = M.desc_of_problem(pb, precision=prec)
+        e1 = M.Engine(M.Plan(d1, tuning=autotune.tuning_for(d1)), dev)
         c, _ = ground_state(e1, h, Bs)
         ins.append((h, Bs, c))
         singles.append(e1)
@@ -121,7 +127,8 @@ def bench_batched(args):
     torch.cuda.synchronize()
     print("[bench] c3: %d instances generated and solved in %.1f s" % (n_inst, time.time() - t),
           file=sys.stderr, flush=True)
-    plan = M.Plan([M.desc_of_problem(pb, precision=prec) for pb in pbs])
+    bdescs = [M.desc_of_problem(pb, precision=prec) for pb in pbs]
+    plan = M.Plan(bdescs, tuning=autotune.tuning_for(bdescs))
     eng = M.Engine(plan, dev)
     n_ext = sum(plan.info(i).n_ext for i in range(n_inst))
     for _ in range(args.warmup):
@@ -157,7 +164,7 @@ def bench_batched(args):
         torch.cuda.empty_cache()
         nb = 16
         sub = ins[:nb]
-        bplan = M.Plan([M.desc_of_problem(pb, precision=prec) for pb in pbs[:nb]])
+        bplan = M.Plan(bdescs[:nb], tuning=autotune.tuning_for(bdescs[:nb]))
         beng = M.Engine(bplan, dev)
         n_ext_b = sum(bplan.info(i).n_ext for i in range(nb))
         beng.backward(sub)
@@ -170,7 +177,7 @@ def bench_batched(args):
         ref = [(x[0].clone(), x[2].clone()) for x in outs_b]
         del outs_b, beng
         torch.cuda.empty_cache()
-        seng = [M.Engine(M.Plan(M.desc_of_problem(pb, precision=prec)), dev) for pb in pbs[:nb]]
+        seng = [M.Engine(M.Plan(d, tuning=autotune.tuning_for(d)), dev) for d in bdescs[:nb]]
         for i, e1 in enumerate(seng):
             e1.backward([sub[i]])
             e1.grad_workspace = None
@@ -196,7 +203,7 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-mfma+f64" if prec else "f64", "data": "synthetic",
         "config": {"workload": "c3: 64 uneven instances (seeds 0-63), sum N_Q=%d, one batched call" % n_ext,
-                   "precision": args.precision, "n_ext": n_ext},
+                   "precision": args.precision, "n_ext": n_ext, "launch_shapes": tuning_note(autotune)},
         "e2_evals_per_s": n_inst * 1000.0 / ms_batched,
         "compare": {"mode": "64 one-instance calls in sequence", "ms_per_step": ms_seq,
                     "value": n_ext / (ms_seq * 1e-3), "max_abs_dE2": dmax},
@@ -238,6 +245,7 @@ def main():
     import torch
     import synth.problems as SP
     import paper_2608_11529_amd as M
+    from paper_2608_11529_amd import autotune
     from paper_2608_11529_amd.reference import ground_state
 
     if args.config == "c3":
@@ -251,7 +259,8 @@ def main():
     torch.cuda.synchronize()
     print("[bench] inputs %s generated on GPU in %.1f s" % (args.config, time.time() - t), file=sys.stderr, flush=True)
     prec = {"mixed": 1, "fp64": 0}
-    plans = {p: M.Plan(M.desc_of_problem(pb, precision=prec[p])) for p in ("fp64", "mixed")}
+    descs = {p: M.desc_of_problem(pb, precision=prec[p]) for p in ("fp64", "mixed")}
+    plans = {p: M.Plan(descs[p], tuning=autotune.tuning_for(descs[p])) for p in descs}
     info = plans["fp64"].info()
     engs = {p: M.Engine(plans[p], dev) for p in plans}
     c, e0 = ground_state(engs["fp64"], h, Bs)
@@ -329,7 +338,8 @@ def main():
                                % (args.config, pb.n_fc, pb.n_c, pb.n_a, "x".join(map(str, pb.sub_sizes)),
                                   pb.n_elec, pb.base, min(pb.max_hops, 99), n_v, n_l, pb.sets,
                                   info.n_ref, info.n_ext),
-                   "precision": args.precision, "n_ext": info.n_ext, "n_ref": info.n_ref},
+                   "precision": args.precision, "n_ext": info.n_ext, "n_ref": info.n_ref,
+                   "launch_shapes": tuning_note(autotune)},
         "e2_evals_per_s": 1000.0 / ms_per_step,
         "e2": head["e2"],
         "compare": {"precision": other, "value": info.n_ext / (res[other]["ms"] * 1e-3),

@@ -129,6 +129,31 @@ typedef struct mrpt2_plan_s* mrpt2_plan_t;
  * precision.  On error *out is NULL. */
 mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out);
 
+/* Launch shapes of one instance's work decomposition, per excitation class
+ * (class order as in mrpt2_info); 0 keeps the built-in rule.  Each value is a
+ * target block count:
+ *   sigma_blocks    the generic sigma kernel (classes without a dedicated
+ *                   kernel): rows in blocks of 256, the strings split into
+ *                   ceil(target / row blocks) chunks (default 8192);
+ *   bwd_blocks      the string-owned adjoint pass: (string block, row part)
+ *                   blocks (default 2048); more parts cost gradient workspace;
+ *   bwd_row_blocks  the generic row-owned adjoint pass when it has fewer than
+ *                   512 row blocks: strings split into
+ *                   ceil(target / row blocks) chunks (default 2048).
+ * The values change launch grids and partial-sum layouts, never the result
+ * beyond summation order.  Tables of them are written by the package's
+ * autotuner (timed sweeps per class and size bucket). */
+typedef struct {
+  int32_t sigma_blocks[MRPT2_N_CLASS];
+  int32_t bwd_blocks[MRPT2_N_CLASS];
+  int32_t bwd_row_blocks[MRPT2_N_CLASS];
+} mrpt2_tuning;
+
+/* mrpt2_plan with launch shapes: tuning is a host array of n_inst entries
+ * (or NULL for the built-in rules).  Negative values are MRPT2_ERR_ARG. */
+mrpt2_status mrpt2_plan_tuned(const mrpt2_desc* desc, int32_t n_inst, const mrpt2_tuning* tuning,
+                              mrpt2_plan_t* out);
+
 /* Bytes of the persistent region (plan tables) and of the workspace needed by
  * mrpt2_energy.  Both must be 256-byte aligned device allocations. */
 mrpt2_status mrpt2_plan_sizes(mrpt2_plan_t plan, size_t* persistent_bytes, size_t* workspace_bytes);

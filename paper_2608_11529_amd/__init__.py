@@ -43,16 +43,25 @@ def desc_of_problem(pb, precision=0, q_mode=None):
 
 
 class Plan:
-    """Host plan of one or more instances (no device work)."""
+    """Host plan of one or more instances (no device work).  tuning: None
+    (built-in launch shapes) or one capi.Tuning per instance (see autotune)."""
 
-    def __init__(self, descs):
+    def __init__(self, descs, tuning=None):
         if isinstance(descs, capi.Desc):
             descs = [descs]
         self.n_inst = len(descs)
         arr = (capi.Desc * self.n_inst)(*descs)
         self._descs = arr
         h = ctypes.c_void_p()
-        capi.check(capi.lib().mrpt2_plan(arr, self.n_inst, ctypes.byref(h)), "mrpt2_plan")
+        if tuning is None:
+            capi.check(capi.lib().mrpt2_plan(arr, self.n_inst, ctypes.byref(h)), "mrpt2_plan")
+        else:
+            if isinstance(tuning, capi.Tuning):
+                tuning = [tuning]
+            if len(tuning) != self.n_inst:
+                raise ValueError("one Tuning per instance expected")
+            tarr = (capi.Tuning * self.n_inst)(*tuning)
+            capi.check(capi.lib().mrpt2_plan_tuned(arr, self.n_inst, tarr, ctypes.byref(h)), "mrpt2_plan_tuned")
         self.handle = h
         p, w = ctypes.c_size_t(), ctypes.c_size_t()
         capi.check(capi.lib().mrpt2_plan_sizes(h, ctypes.byref(p), ctypes.byref(w)), "mrpt2_plan_sizes")

@@ -87,6 +87,15 @@ class Grads(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    """Launch-shape targets of one instance per excitation class (0 = built-in rule)."""
+    _fields_ = [
+        ("sigma_blocks", ctypes.c_int32 * N_CLASS),
+        ("bwd_blocks", ctypes.c_int32 * N_CLASS),
+        ("bwd_row_blocks", ctypes.c_int32 * N_CLASS),
+    ]
+
+
 class Block(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int32),
@@ -112,6 +121,9 @@ def lib():
         vp, st = ctypes.c_void_p, ctypes.c_int
         L.mrpt2_plan.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, ctypes.POINTER(vp)]
         L.mrpt2_plan.restype = st
+        L.mrpt2_plan_tuned.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, ctypes.POINTER(Tuning),
+                                       ctypes.POINTER(vp)]
+        L.mrpt2_plan_tuned.restype = st
         L.mrpt2_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.mrpt2_plan_sizes.restype = st
         L.mrpt2_plan_upload.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -168,5 +180,5 @@ EXPORTED = [
     "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
-    "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed",
+    "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",
 ]

@@ -357,6 +357,11 @@ mrpt2_status energy_enqueue(mrpt2_plan_t plan, const mrpt2_inputs* in, const voi
 extern "C" {
 
 mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out) {
+  return mrpt2_plan_tuned(desc, n_inst, nullptr, out);
+}
+
+mrpt2_status mrpt2_plan_tuned(const mrpt2_desc* desc, int32_t n_inst, const mrpt2_tuning* tuning,
+                              mrpt2_plan_t* out) {
   if (!out) return MRPT2_ERR_ARG;
   *out = nullptr;
   mrpt2_plan_s* p = new (std::nothrow) mrpt2_plan_s();
@@ -364,7 +369,7 @@ mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* ou
   std::string err;
   mrpt2_status st;
   try {
-    st = build_plan(desc, n_inst, &p->p, &err);
+    st = build_plan(desc, n_inst, tuning, &p->p, &err);
   } catch (...) {
     st = MRPT2_ERR_SHAPE;
   }

@@ -253,7 +253,8 @@ int64_t sigma_blocks(const InstancePlan& ip, int k) {
   const ClassPlan& cp = ip.cls[k];
   if (cp.strings.empty() || cp.n_rows == 0) return 0;
   const int64_t rb = (cp.n_rows + 255) / 256;
-  int64_t nsc = std::max<int64_t>(1, std::min<int64_t>((int64_t)cp.strings.size(), (8192 + rb - 1) / rb));
+  const int64_t target = cp.sigma_target > 0 ? cp.sigma_target : 8192;
+  int64_t nsc = std::max<int64_t>(1, std::min<int64_t>((int64_t)cp.strings.size(), (target + rb - 1) / rb));
   return rb * nsc;
 }
 
@@ -704,7 +705,8 @@ void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
   o->row_hi = r1;
 }
 
-mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string* err) {
+mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tuning, Plan* out,
+                        std::string* err) {
   if (!dd || n_inst < 1 || !out) {
     *err = "null argument or n_inst < 1";
     return MRPT2_ERR_ARG;
@@ -792,6 +794,16 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       ClassPlan& cp = ip.cls[k];
       cp.h = kClassH[k];
       cp.v = kClassV[k];
+      if (tuning) {
+        const mrpt2_tuning& tu = tuning[ii];
+        if (tu.sigma_blocks[k] < 0 || tu.bwd_blocks[k] < 0 || tu.bwd_row_blocks[k] < 0) {
+          *err = "negative launch-shape target";
+          return MRPT2_ERR_ARG;
+        }
+        cp.sigma_target = tu.sigma_blocks[k];
+        cp.bwd_target = tu.bwd_blocks[k];
+        cp.bwd_row_target = tu.bwd_row_blocks[k];
+      }
       const int ne = ip.n_e + cp.h - cp.v;
       if (ne < 0 || ne > ip.n_a || cp.h > ip.n_c || cp.v > ip.n_v) continue;
       if (cp.h == 0 && cp.v == 0 && d.q_mode == 1) continue;
@@ -974,17 +986,18 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
       cp.parts = 1;
       cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
       cp.row_split = 1;
+      const int64_t bt = cp.bwd_target > 0 ? cp.bwd_target : 2048;
       if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E22) {
         // (2,2) string-owned adjoint kernel (128 strings per block): parts = groups of core pairs
         const int64_t sblk = (S + 127) / 128;
-        int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (2048 + sblk - 1) / sblk));
+        int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (bt + sblk - 1) / sblk));
         const int64_t grp = (cp.n_holes + parts - 1) / parts;
         cp.rows_per_part = grp;
         cp.parts = (int)((cp.n_holes + grp - 1) / grp);
       } else if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E12) {
         // (1,2) string pass: parts = core x group of tile pairs
         const int64_t sblk = (S + 255) / 256;
-        int64_t ngr = std::min<int64_t>(ip.n_tp, std::max<int64_t>(1, (2048 + sblk * cp.n_holes - 1) / (sblk * cp.n_holes)));
+        int64_t ngr = std::min<int64_t>(ip.n_tp, std::max<int64_t>(1, (bt + sblk * cp.n_holes - 1) / (sblk * cp.n_holes)));
         const int64_t tpg = (ip.n_tp + ngr - 1) / ngr;
         ngr = (ip.n_tp + tpg - 1) / tpg;
         cp.rows_per_part = tpg;
@@ -993,13 +1006,14 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, Plan* out, std::string
         // string-owned pass: enough (string block, row part) blocks to fill the
         // device, partial coupling adjoints bounded to 256 MB
         const int64_t sblk = (S + 255) / 256;
-        int64_t parts = std::min<int64_t>(cp.n_rows, std::max<int64_t>(1, (2048 + sblk - 1) / sblk));
+        int64_t parts = std::min<int64_t>(cp.n_rows, std::max<int64_t>(1, (bt + sblk - 1) / sblk));
         parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)((256ull << 20) / (16 * std::max<int64_t>(cp.n_conn, 1)))));
         cp.rows_per_part = (cp.n_rows + parts - 1) / parts;
         cp.parts = (int)((cp.n_rows + cp.rows_per_part - 1) / cp.rows_per_part);
         // row pass: few rows -> split the strings over blocks as well
         const int64_t rb = (cp.n_rows + 255) / 256;
-        if (rb < 512) cp.row_split = (int)std::min<int64_t>(S, (2048 + rb - 1) / rb);
+        const int64_t rt = cp.bwd_row_target > 0 ? cp.bwd_row_target : 2048;
+        if (rb < 512) cp.row_split = (int)std::min<int64_t>(S, (rt + rb - 1) / rb);
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
       cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);

@@ -63,6 +63,8 @@ struct ClassPlan {
   int64_t n_tiles = 0;
   size_t off_tile_s0 = 0, off_tile_k0 = 0, off_tile_sup = 0, off_ccol = 0, off_Md = 0;
   int kernel = 0;                      // KERN_* below
+  // launch-shape targets (mrpt2_tuning; 0 = built-in rule)
+  int64_t sigma_target = 0, bwd_target = 0, bwd_row_target = 0;
   int64_t n_blocks = 0;                // partial sums written by the class's kernel
 };
 
@@ -168,7 +170,7 @@ void build_launches(Plan* P);
 void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* out);
 
 // Builds the plan; returns MRPT2_OK or an error with a message in *err.
-mrpt2_status build_plan(const mrpt2_desc* d, int n_inst, Plan* out, std::string* err);
+mrpt2_status build_plan(const mrpt2_desc* d, int n_inst, const mrpt2_tuning* tuning, Plan* out, std::string* err);
 
 // Number of rows per string chunk and the blocks used by the sparse-sigma
 // kernel of class k (shared by plan and launcher so the partial-sum slots
