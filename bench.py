@@ -90,6 +90,40 @@ def cpu_baseline(pb, seconds=15.0):
     }
 
 
+def roofline(dom, ms, cases, precision):
+    """Roofline of stage dom (milliseconds ms per launch) over the instances
+    cases = [(problem, plan info)]: algorithmic work summed over instances."""
+    import paper_2608_11529_amd as M
+    mixed = precision == "mixed"
+    if dom == "pair_integrals":
+        flop = sum(8.0 * ((pb.n_c + pb.n_a) * (pb.n_c + pb.n_a - 1) // 2) * pb.n_v * (pb.n_v - 1) * pb.n_l
+                   for pb, _ in cases)
+        peak = FP32_MFMA_PEAK if mixed else FP64_MFMA_PEAK
+        ach = flop / (ms * 1e-3)
+        return {"kernel": "k_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
+                          % ("_f32" if mixed else "", "FP32" if mixed else "FP64"),
+                "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None}
+    if dom == "sigma_22":
+        # six FP64 vector instructions per determinant (two adds, the share
+        # of the merged reciprocal, merge and accumulate)
+        ops = 6.0 * sum(info.n_ext_class[0] for _, info in cases)
+        ach = ops / (ms * 1e-3)
+        peak = FP64_VALU_PEAK / 2.0
+        return {"kernel": "k_e22 (class (2,2) denominators and sums, FP64 vector)", "bound": "alu",
+                "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Top/s", "frac": ach / peak, "traffic": None}
+    if dom.startswith("sigma_"):
+        k = M.CLASSES.index(tuple(int(x) for x in dom.split("_")[1]))
+        h, v = M.CLASSES[k]
+        flop = sum(8.0 * info.n_conn_class[k] * math.comb(pb.n_c, h) * math.comb(pb.n_v, v) for pb, info in cases)
+        ach = flop / (ms * 1e-3)
+        return {"kernel": "sigma contraction of class %s (complex FP64, nonzero couplings)" % dom[-2:],
+                "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK, "traffic": None}
+    return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None}
+
+
 def tuning_note(autotune):
     n = len(autotune.load_table())
     return "autotuned table (%d size buckets)" % n if n else "built-in rules"
@@ -208,8 +242,8 @@ def bench_batched(args):
         "compare": {"mode": "64 one-instance calls in sequence", "ms_per_step": ms_seq,
                     "value": n_ext / (ms_seq * 1e-3), "max_abs_dE2": dmax},
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
-        "roofline": {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
-                     "frac": None, "traffic": None, "ms_per_launch": stage[dom]},
+        "roofline": dict(roofline(dom, stage[dom], [(pb, plan.info(i)) for i, pb in enumerate(pbs)], args.precision),
+                         ms_per_launch=stage[dom]),
         "backward": bwd,
     }
 
@@ -294,34 +328,7 @@ def main():
 
     # roofline of the dominant kernel of the headline path
     dom = max(stage, key=lambda k: stage[k])
-    n_v, n_l = pb.n_v, pb.n_l
-    n_o = pb.n_c + pb.n_a
-    if dom == "pair_integrals":
-        flop = 8.0 * (n_o * (n_o - 1) // 2) * n_v * (n_v - 1) * n_l
-        ach = flop / (stage[dom] * 1e-3)
-        peak = FP32_MFMA_PEAK if args.precision == "mixed" else FP64_MFMA_PEAK
-        roof = {"kernel": "k_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
-                          % ("_f32" if args.precision == "mixed" else "", "FP32" if args.precision == "mixed" else "FP64"),
-                "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None}
-    elif dom == "sigma_22":
-        ops = 6.0 * info.n_ext_class[0]
-        ach = ops / (stage[dom] * 1e-3)
-        peak = FP64_VALU_PEAK / 2.0
-        roof = {"kernel": "k_e22 (class (2,2) denominators and sums, FP64 vector)", "bound": "alu",
-                "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Top/s",
-                "frac": ach / peak, "traffic": None}
-    else:
-        k = M.CLASSES.index(tuple(int(x) for x in dom.split("_")[1])) if dom.startswith("sigma_") else None
-        if k is not None:
-            flop = 8.0 * info.n_conn_class[k] * math.comb(pb.n_c, M.CLASSES[k][0]) * math.comb(n_v, M.CLASSES[k][1])
-            ach = flop / (stage[dom] * 1e-3)
-            roof = {"kernel": "sigma contraction of class %s (complex FP64, nonzero couplings)" % dom[-2:],
-                    "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                    "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK, "traffic": None}
-        else:
-            roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
-                    "frac": None, "traffic": None}
+    roof = roofline(dom, stage[dom], [(pb, info)], args.precision)
     roof["ms_per_launch"] = stage[dom]
     other = "fp64" if args.precision == "mixed" else "mixed"
     out = {

@@ -135,6 +135,8 @@ struct ClassGrad {
   double2* dbp;        // [parts][S][n_pat] dense-coefficient adjoints (class (1,2)) or null
   double2* ecoef;      // [n_conn] sign * C_beta per coupling
   double* wpart;       // class (2,2): per-block partials of the Uv adjoint [blocks][n_v][n_a]
+  double* UvT;         // generic one-virtual classes: string tables transposed for the
+  double* UcT;         // string-owned pass, Uv^T [n_v][S] (v = 1), Uc^T [n_c][S] (h >= 1)
   int64_t wblocks;     // number of those blocks (string blocks x parts)
   int row_split;       // string chunks of the row-owned pass (> 1: shared rows, atomics)
   int parts;           // row parts of the string-owned pass

@@ -136,6 +136,20 @@ __device__ __forceinline__ double string_delta(const ClassDev& cd, const Dev& d,
   return del;
 }
 
+// The same from the transposed tables (string-owned passes: lanes = strings,
+// so the loads of a wave are contiguous).
+template <int H, int V>
+__device__ __forceinline__ double string_delta_t(const ClassDev& cd, const ClassGrad& cg, int64_t s,
+                                                 const Row& w) {
+  const int64_t S = cd.n_str;
+  double del = cd.T[s];
+  if (H >= 1) del += cg.UcT[(int64_t)w.c0 * S + s];
+  if (H == 2) del += cg.UcT[(int64_t)w.c1 * S + s];
+  if (V >= 1) del -= cg.UvT[(int64_t)w.a * S + s];
+  if (V == 2) del -= cg.UvT[(int64_t)w.b * S + s];
+  return del;
+}
+
 // sign * C_beta per coupling of a class.  grid (ceil(n_conn / 256)).
 __device__ __forceinline__ void becoef_body(const Dev& d, const ClassDev& cd, const ClassGrad& cg,
                                             const uint3 bid) {
@@ -302,7 +316,10 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
     double2 sb[RCH];
 #pragma unroll
     for (int k = 0; k < RCH; ++k) {
-      const double del = string_delta<H, V>(cd, d, s, w[k]) + row_const<H, V>(d, w[k]);
+      // one-virtual classes read the transposed tables (contiguous across the
+      // wave); two-virtual rows of a chunk share cache lines of Uv[s]
+      const double sd = V <= 1 ? string_delta_t<H, V>(cd, cg, s, w[k]) : string_delta<H, V>(cd, d, s, w[k]);
+      const double del = sd + row_const<H, V>(d, w[k]);
       const double iv = w[k].valid ? rcp_nr(del) : 0.0;
       const double2 t = make_double2(sig[k].x * iv, sig[k].y * iv);
       sb[k] = make_double2(twoN * t.x, twoN * t.y);
@@ -512,6 +529,36 @@ __device__ __forceinline__ void b22_contract(const double* buf, const uint64_t* 
       const int t = tq + 4 * m;
       if (t < na) wpart[(int64_t)vv * na + t] += acc[m];
     }
+  }
+}
+
+// String tables transposed for the generic string-owned pass of the
+// one-virtual classes, whose lanes are strings: out[x][s] = in[s][x] with
+// in = Uv (which = 0, x < n_v) or Uc (which = 1, x < n_c).  32 x 32 tiles
+// through LDS.
+// grid (ceil(S / 32), ceil(m / 32)), block 256.
+__device__ __forceinline__ void btrans_body(const Dev& d, const ClassDev& cd, const ClassGrad& cg, int which,
+                                            const uint3 bid) {
+  __shared__ double tile[32][33];
+  const int64_t S = cd.n_str;
+  const int m = which ? d.n_c : d.n_v;
+  const double* in = which ? cd.Uc : cd.Uv;
+  double* out = which ? cg.UcT : cg.UvT;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t s0 = (int64_t)bid.x * 32;
+  const int x0 = bid.y * 32;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t s = s0 + ty + 8 * k;
+    const int x = x0 + tx;
+    tile[ty + 8 * k][tx] = (s < S && x < m) ? in[s * m + x] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int x = x0 + ty + 8 * k;
+    const int64_t s = s0 + tx;
+    if (s < S && x < m) out[(int64_t)x * S + s] = tile[tx][ty + 8 * k];
   }
 }
 

@@ -127,6 +127,10 @@ __global__ void __launch_bounds__(256) k_b_b22a(MRPT2_ARGS) {
   MRPT2_JOB
   b22a_body(I.d, I.cls[0], I.g, bid);
 }
+__global__ void __launch_bounds__(256) k_b_btrans(MRPT2_ARGS) {
+  MRPT2_JOB
+  btrans_body(I.d, I.cls[jb.arg >> 1], I.cg[jb.arg >> 1], jb.arg & 1, bid);
+}
 __global__ void __launch_bounds__(B22T) k_b_b22b(MRPT2_ARGS) {
   MRPT2_JOB
   b22b_body(I.d, I.cls[0], I.g, I.cg[0], bid, jb.gx);

@@ -158,6 +158,8 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.row_split = cp.row_split;
   c.ecoef = (double2*)(G + cp.off_ecoef);
   c.wpart = (double*)(G + cp.off_wpart);
+  c.UvT = (double*)(G + cp.off_UvT);
+  c.UcT = (double*)(G + cp.off_UcT);
   c.wblocks = cp.kernel == KERN_E22 ? (int64_t)cp.parts * ((int64_t)(cp.strings.size() + B22T - 1) / B22T) : 0;
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
@@ -303,6 +305,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_B22A: hipLaunchKernelGGL(k_b_b22a, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22WR: hipLaunchKernelGGL(k_b_b22w, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22B: hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BTRANS: hipLaunchKernelGGL(k_b_btrans, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_8: hipLaunchKernelGGL((k_b_b12r<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12R_16: hipLaunchKernelGGL((k_b_b12r<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

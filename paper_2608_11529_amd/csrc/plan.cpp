@@ -514,15 +514,23 @@ void build_launches(Plan* P) {
     }
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22a, j22b, j22w, j12r[5], j12s[5];
+    std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[5], j12s[5];
     size_t lds = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
+      // string tables transposed for the generic string-owned pass of the
+      // one-virtual classes (arg 2 k: Uv, 2 k + 1: Uc)
+      if (cp.kernel == KERN_GENERIC && cp.v <= 1) {
+        const int64_t sb = cdiv64((int64_t)cp.strings.size(), 32);
+        if (cp.v >= 1) jt.push_back(job(i, sb, cdiv64(ip.n_v, 32), 2 * k));
+        if (cp.h >= 1) jt.push_back(job(i, sb, cdiv64(ip.n_c, 32), 2 * k + 1));
+      }
       if (cp.kernel == KERN_E22) {
         j22a.push_back(job(i, cp.n_holes, ip.n_tp, k));
         j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 128), cp.parts, k));
+
         j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
         continue;
       }
@@ -538,6 +546,7 @@ void build_launches(Plan* P) {
       jsr.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
       lds = std::max(lds, (size_t)ip.n_a * 256 * 8);
     }
+    add_launch(P, seq, K_BTRANS, ST_BSTR0 + k, jt);
     add_launch(P, seq, K_B22A, ST_BROW0 + k, j22a);
     add_launch(P, seq, K_B22B, ST_BSTR0 + k, j22b);
     add_launch(P, seq, K_B22WR, ST_BSTR0 + k, j22w);
@@ -1023,6 +1032,11 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
       cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
       cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + 127) / 128) * ip.n_v * ip.n_a * 8 : 0);
+      // string tables transposed for the generic string-owned pass of the
+      // one-virtual classes (lanes = strings)
+      const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel == KERN_GENERIC && cp.v <= 1;
+      cp.off_UvT = Gw.take((pass && cp.v >= 1) ? (size_t)S * ip.n_v * 8 : 0);
+      cp.off_UcT = Gw.take((pass && cp.h >= 1) ? (size_t)S * ip.n_c * 8 : 0);
     }
     ip.grad_bytes = Gw.cur;
     // info

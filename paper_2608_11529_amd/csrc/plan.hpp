@@ -49,6 +49,7 @@ struct ClassPlan {
   size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
   // gradient workspace offsets (adjoint): coupling adjoints, string-pass partials
   size_t off_Xb = 0, off_Tb = 0, off_cbe = 0, off_r1 = 0, off_dbp = 0, off_ecoef = 0, off_wpart = 0;
+  size_t off_UvT = 0, off_UcT = 0;
   int parts = 1;                       // row parts of the string-owned adjoint pass
   int64_t rows_per_part = 0;           // rows per part (tile pairs per part for the (1,2) kernels)
   int row_split = 1;                   // string chunks of the generic row-owned adjoint pass
@@ -112,7 +113,7 @@ enum KernelId : int {
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
   K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
-  K_BECOEF, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
+  K_BECOEF, K_BTRANS, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
   K_B12R_20, K_B12S_20
 };
 
