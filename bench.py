@@ -26,6 +26,10 @@ FP64_MFMA_PEAK = 78.6e12       # FLOP/s, dense FP64 matrix
 FP64_VALU_PEAK = 78.6e12       # FLOP/s, FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 FP32_MFMA_PEAK = 157.3e12      # FLOP/s, dense FP32 matrix
 HBM_PEAK = 8.0e12              # B/s
+# HBM bytes per launch of k_b_e22 at c4 from rocprofv3 FETCH_SIZE (calibrated
+# against a device copy, profiles/k_e22_c4_hbm_counters.md) plus its written
+# partial sums; valid for the kernel as measured there
+E22_C4_HBM_BYTES = 2.0 * 18.58e6 * 1024 + 378 * 171 * 8
 
 
 def cpu_baseline(pb, seconds=15.0):
@@ -329,7 +333,10 @@ def main():
     # roofline of the dominant kernel of the headline path
     dom = max(stage, key=lambda k: stage[k])
     roof = roofline(dom, stage[dom], [(pb, info)], args.precision)
+    n_v, n_l = pb.n_v, pb.n_l
     roof["ms_per_launch"] = stage[dom]
+    if dom == "sigma_22" and args.config == "c4":
+        roof["traffic"] = E22_C4_HBM_BYTES
     other = "fp64" if args.precision == "mixed" else "mixed"
     out = {
         "metric": "external dets/sec + E2 evals/sec (mixed vs FP64, |dE2| Eh), 1 MI355X",
