@@ -1239,42 +1239,94 @@ __device__ __forceinline__ void bxbuild_body(const Dev& d, const ClassDev& cd, c
 //   Sbar_x[a][L] = sign_L sum_{y != x} sum_b Atilde_xy[a][b] conj(S_y[b][L]),
 // one complex FP64 MFMA GEMM per occupied x with K = (n_o - 1) n_v.
 // grid (ceil(n_l/64), ceil(n_v/64) * n_o), block 256.
-__device__ __forceinline__ double2 abar_at(const Dev& d, const GradDev& g, int64_t pair, int a, int b) {
-  const int I = a >> 6, J = b >> 6;
-  if (I > J) return make_double2(0.0, 0.0);
-  const int64_t tp = (int64_t)I * d.n_vt - (int64_t)I * (I - 1) / 2 + (J - I);
-  return g.Ab[(pair * d.n_tp + tp) * 4096 + (a & 63) * 64 + (b & 63)];
-}
-
 __device__ __forceinline__ void bagemm_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  // K runs over (y != x, b) in stages of one y and 16 consecutive b, so that
+  // the Abar operand is read as contiguous runs of the tile-major adjoint:
+  // D[a][b] = Abar[a][b] - Abar[b][a] of the pair (x, y) (sign flipped for
+  // y < x), the first term row-wise from tile (I, J'), the second from tile
+  // (J', I) with a fastest and transposed through LDS.
   __shared__ double2 sA[64 * KP];
   __shared__ double2 sB[64 * KP];
   const int nvt = (d.n_v + 63) / 64;
   const int x = bid.y / nvt;
-  const int a0 = (bid.y % nvt) * 64;
+  const int I = bid.y % nvt, a0 = I * 64;
   const int L0 = bid.x * 64;
   const int nv = d.n_v, nl = d.n_l, no = d.n_o;
-  auto fa = [&](int r, int k) -> double2 {
-    const int a = a0 + r;
-    if (a >= nv) return make_double2(0.0, 0.0);
-    const int yp = k / nv, b = k % nv;
-    const int y = yp < x ? yp : yp + 1;
-    if (x < y) {
-      const int64_t pr = occ_pair(x, y, no);
-      return csub(abar_at(d, g, pr, a, b), abar_at(d, g, pr, b, a));
-    }
-    const int64_t pr = occ_pair(y, x, no);
-    return csub(abar_at(d, g, pr, b, a), abar_at(d, g, pr, a, b));
-  };
-  auto fb = [&](int c, int k) -> double2 {
-    const int L = L0 + c;
-    if (L >= nl) return make_double2(0.0, 0.0);
-    const int yp = k / nv, b = k % nv;
-    const int y = yp < x ? yp : yp + 1;
-    return cconj(d.slab[((int64_t)(d.n_fc + y) * d.n_corr + no + b) * nl + L]);
-  };
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  const int kq = lane >> 4, kcl = kq >> 1, comp = kq & 1;
   d4 accR[2][2], accI[2][2];
-  cgemm64(fa, fb, (no - 1) * nv, sA, sB, accR, accI);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto tpi = [&](int i0, int j0) -> int64_t {   // tile pair (i0 <= j0)
+    return (int64_t)i0 * nvt - (int64_t)i0 * (i0 - 1) / 2 + (j0 - i0);
+  };
+  for (int y = 0; y < no; ++y) {
+    if (y == x) continue;
+    const int64_t pr = x < y ? occ_pair(x, y, no) : occ_pair(y, x, no);
+    const double sgn = x < y ? 1.0 : -1.0;
+    const double2* Sy = d.slab + ((int64_t)(d.n_fc + y) * d.n_corr + no) * nl;
+    for (int b0 = 0; b0 < nv; b0 += KC) {
+      const int Jb = b0 >> 6, lb0 = b0 & 63;    // the 16 b lie in one tile (64 = 4 x 16)
+      // D term 1: Abar[a][b] from tile (I, Jb), rows a, 16 consecutive b
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int r = e / KC, kk = e % KC;
+        const int a = a0 + r, bb = b0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (I <= Jb && a < nv && bb < nv) v = g.Ab[(pr * d.n_tp + tpi(I, Jb)) * 4096 + r * 64 + lb0 + kk];
+        sA[r * KP + kk] = make_double2(sgn * v.x, sgn * v.y);
+      }
+      // B operand: conj(S_y[b][L]), L fastest
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int c = e & 63, kk = e >> 6;
+        const int L = L0 + c, bb = b0 + kk;
+        sB[c * KP + kk] = (L < nl && bb < nv) ? cconj(Sy[(int64_t)bb * nl + L]) : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      // D term 2: - Abar[b][a] from tile (Jb, I), 16 rows b, a fastest
+      if (Jb <= I) {
+        for (int e = tid; e < 64 * KC; e += 256) {
+          const int r = e & 63, kk = e >> 6;
+          const int a = a0 + r, bb = b0 + kk;
+          if (a < nv && bb < nv) {
+            const double2 v = g.Ab[(pr * d.n_tp + tpi(Jb, I)) * 4096 + (lb0 + kk) * 64 + r];
+            const double2 u = sA[r * KP + kk];
+            sA[r * KP + kk] = make_double2(u.x - sgn * v.x, u.y - sgn * v.y);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll 2
+      for (int ks = 0; ks < KC; ks += 2) {
+        const int kc = ks + kcl;
+        double ar[2], ai[2], bq[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const double2 v = sA[(wr + i * 16 + (lane & 15)) * KP + kc];
+          ar[i] = comp ? -v.y : v.x;
+          ai[i] = comp ? v.x : v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double2 v = sB[(wc + j * 16 + (lane & 15)) * KP + kc];
+          bq[j] = comp ? v.y : v.x;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bq[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bq[j], accI[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
