@@ -85,9 +85,10 @@ __global__ void __launch_bounds__(256) k_b_e12(MRPT2_ARGS) {
   MRPT2_JOB
   e12_body<MJ>(I.d, I.cls[1], flag, bid);
 }
+template <bool F32>
 __global__ void __launch_bounds__(256) k_b_e02(MRPT2_ARGS) {
   MRPT2_JOB
-  e02_body(I.d, I.cls[2], flag, bid);
+  e02_body<F32>(I.d, I.cls[2], flag, bid);
 }
 __global__ void __launch_bounds__(64) k_b_e02coef(MRPT2_ARGS) {
   MRPT2_JOB

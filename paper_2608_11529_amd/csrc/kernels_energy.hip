@@ -617,9 +617,13 @@ __device__ __forceinline__ void e02coef_body(const Dev& d, const ClassDev& cd, c
 // |sigma|^2 / Delta summed over the valid (string, a < b) entries, four
 // fractions per reciprocal.  grid (n_tiles, 64 n_tp): tiles fastest, so that
 // the blocks sharing one row of pair integrals run together.  block 256.
+// F32 (mixed form): the contraction on FP32 MFMA with FP64 accumulation per
+// 32-term stage; denominators and sums stay FP64.
+template <bool F32>
 __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
-  __shared__ double2 sA[64 * KP];
-  __shared__ double2 sB[64 * KP];
+  constexpr int SH = F32 ? 64 * KP32 : 2 * 64 * KP;   // float2 slots of each staging buffer
+  __shared__ __align__(16) float2 sA[SH];
+  __shared__ __align__(16) float2 sB[SH];
   __shared__ double red[256];
   const int64_t t = bid.x;
   const int64_t tp = bid.y >> 6;
@@ -642,8 +646,23 @@ __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* 
     const int pr = sup[k];
     return pr < 0 ? make_double2(0.0, 0.0) : Ar[(int64_t)pr * d.n_tp * 4096 + r];
   };
-  d4 accR[2][2], accI[2][2];
-  cgemm64<true>(fa, fb, K, sA, sB, accR, accI);
+  double accR[2][2][4], accI[2][2][4];
+  if constexpr (F32) {
+    cgemm64_f32c(fa, fb, K, sA, sB, accR, accI);
+  } else {
+    d4 aR[2][2], aI[2][2];
+    cgemm64<true>(fa, fb, K, (double2*)sA, (double2*)sB, aR, aI);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accR[i][j][r] = aR[i][j][r];
+          accI[i][j][r] = aI[i][j][r];
+        }
+  }
+  auto arow = [](int i, int r) { return F32 ? acc_row_f32(i, r) : acc_row(i, r); };
   const int64_t gv = d.n_fc + d.n_o;
   const double ea = d.eps[d.n_o + a];
   double rowc[2];
@@ -664,7 +683,7 @@ __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* 
     int64_t so[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int s = s0 + acc_row(i, r);
+      const int s = s0 + arow(i, r);
       sok[r] = s < s1;
       const int sv = sok[r] ? s : s0;
       so[r] = (int64_t)sv * nv;

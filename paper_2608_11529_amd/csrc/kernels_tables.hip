@@ -389,6 +389,82 @@ __device__ __forceinline__ int acc_row_f32(int i, int r) {
   return (wv >> 1) * 32 + i * 16 + 4 * (lane >> 4) + r;
 }
 
+// The same FP32-MFMA product for FP64 operands given element by element:
+// each is rounded to FP32 when staged (b with c fastest across threads), the
+// sums over one stage of KC32 complex k are FP32 and are added into FP64
+// accumulators.  Result layout of cgemm64_f32 (acc_row_f32, acc_col).
+template <class FA, class FB>
+__device__ __forceinline__ void cgemm64_f32c(FA fa, FB fb, int K, float2* sA, float2* sB,
+                                             double (&accR)[2][2][4], double (&accI)[2][2][4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accR[i][j][r] = 0.0;
+        accI[i][j][r] = 0.0;
+      }
+  const int kq = lane >> 4;
+  const int kcl = kq >> 1, comp = kq & 1;
+  for (int k0 = 0; k0 < K; k0 += KC32) {
+    for (int e = tid; e < 64 * KC32; e += 256) {
+      const int r = e / KC32, kk = e % KC32;
+      const double2 v = (k0 + kk) < K ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
+      sA[r * KP32 + kk] = make_float2((float)v.x, (float)v.y);
+    }
+    for (int e = tid; e < 64 * KC32; e += 256) {
+      const int c = e & 63, kk = e >> 6;
+      const double2 v = (k0 + kk) < K ? fb(c, k0 + kk) : make_double2(0.0, 0.0);
+      sB[c * KP32 + kk] = make_float2((float)v.x, (float)v.y);
+    }
+    __syncthreads();
+    f4 pR[2][2], pI[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        pR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        pI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll 4
+    for (int ks = 0; ks < KC32; ks += 2) {
+      const int kc = ks + kcl;
+      float ar[2], ai[2], bb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float2 v = sA[(wr + i * 16 + (lane & 15)) * KP32 + kc];
+        ar[i] = comp ? -v.y : v.x;
+        ai[i] = comp ? v.x : v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float2 v = sB[(wc + j * 16 + (lane & 15)) * KP32 + kc];
+        bb[j] = comp ? v.y : v.x;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          pR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bb[j], pR[i][j], 0, 0, 0);
+          pI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bb[j], pI[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accR[i][j][r] += (double)pR[i][j][r];
+          accI[i][j][r] += (double)pI[i][j][r];
+        }
+    __syncthreads();
+  }
+}
+
 // Mixed-precision form of k_abuild: the same integrals and output layout,
 // from the FP32 slab.
 __device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {

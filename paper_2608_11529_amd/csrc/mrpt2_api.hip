@@ -260,7 +260,8 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E12_16: hipLaunchKernelGGL((k_b_e12<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_24: hipLaunchKernelGGL((k_b_e12<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_32: hipLaunchKernelGGL((k_b_e12<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E02: hipLaunchKernelGGL(k_b_e02, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02: hipLaunchKernelGGL(k_b_e02<false>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02F: hipLaunchKernelGGL(k_b_e02<true>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02COEF: hipLaunchKernelGGL(k_b_e02coef, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG22: hipLaunchKernelGGL((k_b_sigma<2, 2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG12: hipLaunchKernelGGL((k_b_sigma<1, 2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

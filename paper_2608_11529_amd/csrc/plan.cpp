@@ -467,7 +467,7 @@ void build_launches(Plan* P) {
     }
     add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
-    std::vector<JobH> e22, e12[4], e02, gen;
+    std::vector<JobH> e22, e12[4], e02, e02f, gen;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -479,7 +479,7 @@ void build_launches(Plan* P) {
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         e12[v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
       } else if (cp.kernel == KERN_E02) {
-        e02.push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
+        (ip.d.precision == MRPT2_MIXED ? e02f : e02).push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
       } else {
         gen.push_back(job(i, sigma_blocks(ip, k), 1, k));
       }
@@ -490,6 +490,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[2]);
     add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[3]);
     add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02);
+    add_launch(P, seq, K_E02F, ST_SIGMA0 + k, e02f);
     add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
   }
   js.clear();

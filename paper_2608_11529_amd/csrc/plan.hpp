@@ -108,7 +108,7 @@ struct InstancePlan {
 enum KernelId : int {
   K_CLEAR, K_PACK, K_DIAG, K_WPASS, K_EPS, K_DSUM, K_FOCK, K_GBUILD, K_HPP, K_SIGP, K_E0,
   K_ABUILD, K_ABUILD32, K_CTAB, K_XBUILD, K_DCOEF, K_E22, K_E12_8, K_E12_16, K_E12_24, K_E12_32,
-  K_E02, K_E02COEF, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
+  K_E02, K_E02F, K_E02COEF, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
   // adjoint
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
