@@ -19,7 +19,8 @@ rules of oracle.literal:
 with G the sign of the operator string on L, found with oracle.space.apply_ops
 using the lowest virtual spinors as representatives.  Denominators are
 E0 - H_KK with H_KK = sum_{p in K} h_pp + sum_{p<q in K} W_pq (eq. zeroh),
-W_pq = (pp|qq) - (pq|qp).
+W_pq = (pp|qq) - (pq|qp); with the level shift b of Sec. 2.6 each inverse
+denominator is the real part of 1/(Delta + i b/Delta) (oracle.literal).
 
 Optional restrictions (used to check sampled parts of a large sum): a set of
 core-hole tuples, and index ranges for the first and second virtual spinor.
@@ -101,8 +102,9 @@ class ClassOracle:
         return float(self.hd[occ].sum() + 0.5 * self.W[np.ix_(occ, occ)].sum())
 
     # -- main ------------------------------------------------------------------
-    def e2(self, C, q_mode=0, E0=None, core_sets=None, va=None, vb=None, classes=None, strings=None):
-        """Per-class E2 parts (dict) and E0.  core_sets: allowed core-hole
+    def e2(self, C, q_mode=0, E0=None, core_sets=None, va=None, vb=None, classes=None, strings=None, b=0.0):
+        """Per-class E2 parts (dict) and E0.  b: level-shift constant (Sec.
+        2.6; 0 gives eq. pt2en exactly).  core_sets: allowed core-hole
         tuples (sorted, correlated core indices); va / vb: (lo, hi) ranges of
         virtual positions (0-based within the virtual block) for the lowest
         and the second virtual spinor of K; strings: allowed active strings
@@ -112,6 +114,7 @@ class ClassOracle:
         if E0 is None:
             _, E0 = self.reference(C)
         self.E0 = E0
+        self.b = float(b)
         self.norm = float(np.vdot(C, C).real)
         self.C = C
         self.core_sets = None if core_sets is None else set(tuple(s) for s in core_sets)
@@ -146,20 +149,26 @@ class ClassOracle:
     def _rep(self, v):
         return [int(x) for x in self.V[:v]]
 
+    def _weight(self, d):
+        """1/d, or Re 1/(d + i b/d) under the level shift (arrays or scalars)."""
+        if self.b == 0.0:
+            return 1.0 / d
+        return np.real(1.0 / (d + 1j * (self.b / d)))
+
     def _sum_vv(self, sig, D0, terms):
         """Add sum over a<b of |sig|^2 / (N (E0 - H_KK)) for K = D0 + {a, b}."""
         e0 = self.energy_of(D0)
         occ = np.array(bits(D0), dtype=np.int64)
         va = self.hd[self.V] + self.W[np.ix_(self.V, occ)].sum(axis=1)
         Hkk = e0 + va[:, None] + va[None, :] + self.W[np.ix_(self.V, self.V)]
-        t = np.abs(sig) ** 2 / (self.norm * (self.E0 - Hkk))
+        t = np.abs(sig) ** 2 * self._weight(self.E0 - Hkk) / self.norm
         terms.append(math.fsum(t[self.pair_mask].tolist()))
 
     def _sum_v(self, sig, D0, terms):
         e0 = self.energy_of(D0)
         occ = np.array(bits(D0), dtype=np.int64)
         va = self.hd[self.V] + self.W[np.ix_(self.V, occ)].sum(axis=1)
-        t = np.abs(sig) ** 2 / (self.norm * (self.E0 - (e0 + va)))
+        t = np.abs(sig) ** 2 * self._weight(self.E0 - (e0 + va)) / self.norm
         terms.append(math.fsum(t[self.mask_a].tolist()))
 
     def _sign(self, L, ops, K):
@@ -341,7 +350,7 @@ class ClassOracle:
                                 continue
                             sig += matrix_element(K, self.core | beta, self.h, self.g_occ) * self.C[j]
                 d = self.E0 - self.energy_of(K)
-                terms.append(abs(sig) ** 2 / (self.norm * d))
+                terms.append(abs(sig) ** 2 * float(self._weight(d)) / self.norm)
         return math.fsum(terms)
 
     def _c20(self, q_mode):

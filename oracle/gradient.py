@@ -12,7 +12,9 @@ torch's autograd differentiates every step:
   * H_PP, E0 = Re(C^H H_PP C) / C^H C (eq. pt2 with Psi0 = C / ||C||);
   * sigma_K = sum_L <K|H|L> C_L for K in Q (Sec. 2.3);
   * H_KK = sum_{p in K} Re h_pp + sum_{p<q in K} Re[(pp|qq) - (pq|qp)] (eq. zeroh);
-  * E2 = sum_K |sigma_K|^2 / (||C||^2 (E0 - H_KK)) (eq. pt2en).
+  * E2 = sum_K |sigma_K|^2 / (||C||^2 (E0 - H_KK)) (eq. pt2en), or with the
+    level shift b of Sec. 2.6 the inverse denominator replaced by the real
+    part of 1/(E0 - H_KK + i b/(E0 - H_KK)).
 The determinant lists and signs are plain integer bookkeeping computed once
 per space.  Only small spaces are meant (the full (pq|rs) array is built).
 
@@ -117,7 +119,7 @@ def fold_frozen_core(h, g, n_fc):
     return h[n_fc:, n_fc:], g[n_fc:, n_fc:, n_fc:, n_fc:]
 
 
-def energy(space, cl, h_full, Bs, ws, n_fc, c):
+def energy(space, cl, h_full, Bs, ws, n_fc, c, b=0.0):
     """E2 and E0 (E0 within the correlated space, frozen-core constant
     dropped) as torch scalars differentiable in h_full, every B and c.
     cl: CouplingLists of space."""
@@ -157,7 +159,11 @@ def energy(space, cl, h_full, Bs, ws, n_fc, c):
     E0 = torch.real(torch.vdot(c, Hc)) / norm
     sig_q = sigma(cl.single_q, cl.double_q, len(cl.Q))
     den = E0 - diag(cl.occ_q)
-    E2 = (torch.abs(sig_q) ** 2 / den).sum() / norm
+    if b == 0.0:
+        wgt = 1.0 / den
+    else:
+        wgt = torch.real(1.0 / torch.complex(den, b / den))
+    E2 = (torch.abs(sig_q) ** 2 * wgt).sum() / norm
     return E2, E0
 
 
@@ -166,15 +172,15 @@ def hermitian_part(G):
     return 0.5 * (G + G.conj().transpose(-1, -2))
 
 
-def energy_and_gradient(space, h_full, Bs, ws, n_fc, c, q_mode=0, cl=None):
+def energy_and_gradient(space, h_full, Bs, ws, n_fc, c, q_mode=0, cl=None, b=0.0):
     """E2 and its gradients (dh, [dB_t], dc) as numpy arrays; dh and dB are
-    Hermitian-projected."""
+    Hermitian-projected.  b: level-shift constant (Sec. 2.6)."""
     if cl is None:
         cl = CouplingLists(space, q_mode)
     h = torch.tensor(np.asarray(h_full), dtype=torch.complex128, requires_grad=True)
     B = [torch.tensor(np.asarray(x), dtype=torch.complex128, requires_grad=True) for x in Bs]
     cc = torch.tensor(np.asarray(c), dtype=torch.complex128, requires_grad=True)
-    E2, E0 = energy(space, cl, h, B, ws, n_fc, cc)
+    E2, E0 = energy(space, cl, h, B, ws, n_fc, cc, b)
     grads = torch.autograd.grad(E2, [h] + B + [cc])
     dh = hermitian_part(grads[0]).numpy()
     dB = [hermitian_part(x).numpy() for x in grads[1:-1]]

@@ -8,7 +8,11 @@ Every quantity is taken straight from its definition:
     of the normalised reference Psi0 = C / ||C||);
   * sigma_K = sum_{L in P} <K|H|L> C_L  (eq. sumsigma, for K in Q);
   * H_KK = sum_{p in K} h_pp + sum_{p<q in K} [(pp|qq) - (pq|qp)]  (eq. zeroh);
-  * E2 = sum_{K in Q} |sigma_K|^2 / (||C||^2 (E0 - H_KK))  (eq. pt2en).
+  * E2 = sum_{K in Q} |sigma_K|^2 / (||C||^2 (E0 - H_KK))  (eq. pt2en);
+  * with the imaginary level shift of Sec. 2.6 (b != 0) the inverse
+    denominator 1/(E0 - H_KK) becomes the real part of 1/(E0 - H_KK + i eps)
+    with eps = b/(E0 - H_KK) (the paper does not say to take the real part:
+    E2 is kept real, as for the unshifted sum).
 Sums are compensated (math.fsum).
 
 Integrals are passed as a callable g(p, q, r, s) = (pq|rs) and a matrix h.
@@ -100,6 +104,14 @@ def lowest_state(H):
     return float(w[0]), c
 
 
+def en_weight(d, b=0.0):
+    """Inverse Epstein-Nesbet denominator 1/d, or with the imaginary level
+    shift of Sec. 2.6 the real part of 1/(d + i b/d), as complex arithmetic."""
+    if b == 0.0:
+        return 1.0 / d
+    return (1.0 / complex(d, b / d)).real
+
+
 def external_class(space, K):
     """(core holes, virtual electrons) of determinant K."""
     h = space.n_c - bin(K & space.core_mask).count("1")
@@ -107,8 +119,9 @@ def external_class(space, K):
     return h, v
 
 
-def e2_literal(space, h, g, C, q_mode=0, H_PP=None):
-    """Returns (E2, E0, {class: E2 part}, N_Q) by explicit enumeration."""
+def e2_literal(space, h, g, C, q_mode=0, H_PP=None, b=0.0):
+    """Returns (E2, E0, {class: E2 part}, N_Q) by explicit enumeration; b is
+    the level-shift constant (0: eq. pt2en exactly)."""
     P = space.p_dets()
     if H_PP is None:
         H_PP = reference_hamiltonian(space, h, g)
@@ -142,6 +155,6 @@ def e2_literal(space, h, g, C, q_mode=0, H_PP=None):
     terms = {}
     for K, s in sigma.items():
         d = E0 - diagonal(K, hd, W)
-        terms.setdefault(external_class(space, K), []).append(abs(s) ** 2 / (norm * d))
+        terms.setdefault(external_class(space, K), []).append(abs(s) ** 2 * en_weight(d, b) / norm)
     parts = {k: math.fsum(v) for k, v in terms.items()}
     return math.fsum(parts.values()), E0, parts, len(sigma)

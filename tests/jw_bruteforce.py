@@ -61,9 +61,18 @@ def kron_index(det, n):
     return i
 
 
-def e2_bruteforce(h, g, p_dets, q_dets):
+def shifted_resolvent_sum(v, dq, b):
+    """Re v^H R^-1 v with R = diag(dq) + i b diag(dq)^-1: the second-order sum
+    with the imaginary level shift of Sec. 2.6, by a linear solve over Q."""
+    R = np.diag(dq + 1j * b / dq)
+    return float(np.real(np.vdot(v, np.linalg.solve(R, v))))
+
+
+def e2_bruteforce(h, g, p_dets, q_dets, b=0.0, vectors=False):
     """Lowest state of H restricted to P, its energy E0, and
-    E2 = sum_{K in Q} |(H Psi0)_K|^2 / (E0 - H_KK); returns (E2, E0, C, H)."""
+    E2 = sum_{K in Q} |(H Psi0)_K|^2 / (E0 - H_KK) (b = 0) or its level-shifted
+    form (shifted_resolvent_sum); returns (E2, E0, C, H), and with vectors=True
+    also ((H Psi0)_Q, E0 - H_QQ)."""
     n = h.shape[0]
     H = hamiltonian(h, g)
     pi = [kron_index(d, n) for d in p_dets]
@@ -78,5 +87,11 @@ def e2_bruteforce(h, g, p_dets, q_dets):
     s = H @ psi
     diag = H.diagonal()
     e0 = w[0]
-    terms = np.abs(s[qi]) ** 2 / (e0 - diag[qi].real)
-    return float(np.sum(terms)), float(e0), c, H
+    v, dq = s[qi], e0 - diag[qi].real
+    if b == 0.0:
+        e2 = float(np.sum(np.abs(v) ** 2 / dq))
+    else:
+        e2 = shifted_resolvent_sum(v, dq, b)
+    if vectors:
+        return e2, float(e0), c, H, (v, dq)
+    return e2, float(e0), c, H

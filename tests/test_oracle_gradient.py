@@ -24,11 +24,11 @@ def inputs(name):
     return pb, h, Bs, SP.weights(pb), np.asarray(c)
 
 
-def class_oracle_e2(pb, h, Bs, ws, c):
+def class_oracle_e2(pb, h, Bs, ws, c, b=0.0):
     """E2 from the per-class oracle (oracle.classes), which shares no code
     with oracle.gradient's energy expression."""
     co = run.class_oracle(pb, h, Bs, ws)
-    parts, _ = co.e2(c)
+    parts, _ = co.e2(c, b=b)
     return math.fsum(parts.values())
 
 
@@ -112,3 +112,30 @@ def test_identities(case):
         for g, B in zip(dB, Bs):
             val += np.real(np.vdot(g, 1j * (E @ B - B @ E)))
         assert abs(val) <= 1e-11 * scale, (name, p, val)
+
+
+@pytest.mark.parametrize("name", ["s_das"])
+def test_level_shift_gradient_matches_class_oracle_fd(name):
+    """Sec. 2.6 level shift (b = 2): value and directional derivatives of
+    oracle.gradient against central differences of the per-class oracle."""
+    b = 2.0
+    pb, h, Bs, ws, c = inputs(name)
+    E2, _, dh, dB, dc, _ = gradient.energy_and_gradient(run.space_of(pb), h, Bs, ws, pb.n_fc, c, b=b)
+    assert abs(E2 - class_oracle_e2(pb, h, Bs, ws, c, b=b)) <= 1e-12
+    assert abs(E2 - class_oracle_e2(pb, h, Bs, ws, c)) > 1e-8 * abs(E2)
+    rng = np.random.default_rng(11)
+    D = herm_dir(rng, h.shape[0])
+    num = fd(lambda x: class_oracle_e2(pb, x, Bs, ws, c, b=b), h, D)
+    ana = float(np.real(np.vdot(dh, D)))
+    assert abs(num - ana) <= 1e-7 * max(1.0, abs(ana)), ("h", num, ana)
+    L = int(rng.integers(Bs[0].shape[0]))
+    DB = np.zeros_like(Bs[0])
+    DB[L] = herm_dir(rng, h.shape[0])
+    num = fd(lambda x: class_oracle_e2(pb, h, [x] + list(Bs[1:]), ws, c, b=b), Bs[0], DB)
+    ana = float(np.real(np.vdot(dB[0], DB)))
+    assert abs(num - ana) <= 1e-7 * max(1.0, abs(ana)), ("B", num, ana)
+    Dc = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+    Dc /= np.linalg.norm(Dc)
+    num = fd(lambda x: class_oracle_e2(pb, h, Bs, ws, x, b=b), c, Dc)
+    ana = float(np.real(np.vdot(dc, Dc)))
+    assert abs(num - ana) <= 1e-7 * max(1.0, abs(ana)), ("c", num, ana)

@@ -31,8 +31,8 @@ def ground(space, h, Bs, ws):
     return g, gc, H, c
 
 
-def class_e2(space, h, Bs, ws, C, q_mode=0):
-    parts, E0 = ClassOracle(space, h, Bs, ws).e2(C, q_mode)
+def class_e2(space, h, Bs, ws, C, q_mode=0, b=0.0):
+    parts, E0 = ClassOracle(space, h, Bs, ws).e2(C, q_mode, b=b)
     return math.fsum(parts.values()), parts, E0
 
 
@@ -75,6 +75,63 @@ def test_jordan_wigner_bruteforce(case):
     assert abs(e2_lit - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
     e2_cls, _, _ = class_e2(sp, hfc, Bc, ws, c_bf)
     assert abs(e2_cls - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
+
+
+# ------------------------------------------------------------ level shift
+# Sec. 2.6: 1/Delta -> Re 1/(Delta + i eps) with eps = b/Delta.  The oracle
+# writes the shifted inverse as complex arithmetic; the pins below reach it
+# by a linear solve over Q (Jordan-Wigner), by the real closed form
+# Delta^3/(Delta^4 + b^2) (single determinant), and by its limits.
+
+def jw_problem(case):
+    name, seed, n_fc, n_c, subs, ne, nv, sets, hops, base = case
+    spec = SP.small(name, seed, n_fc, n_c, subs, ne, nv, sets, max_hops=hops, base=base)
+    h, Bs, ws = tensors(spec)
+    n = h.shape[0]
+    idx = np.arange(n)
+    g_full = integrals.eri_block(Bs, ws, idx, idx, idx, idx)
+    sp = run.space_of(spec)
+    fc_mask = (1 << n_fc) - 1
+    p_dets = [fc_mask | (d << n_fc) for d in sp.p_dets()]
+    P = set(p_dets)
+    N = bin(p_dets[0]).count("1")
+    Q = [K for K in range(1 << n)
+         if bin(K).count("1") == N and K not in P and (K & fc_mask) == fc_mask
+         and min(bin(K ^ L).count("1") for L in p_dets) <= 4]
+    return spec, h, Bs, ws, g_full, sp, p_dets, Q
+
+
+@pytest.mark.parametrize("b", [0.05, 2.0])
+@pytest.mark.parametrize("case", JW_CASES[:2], ids=[c[0] for c in JW_CASES[:2]])
+def test_level_shift_jordan_wigner_bruteforce(case, b):
+    spec, h, Bs, ws, g_full, sp, p_dets, Q = jw_problem(case)
+    e2_bf, e0_bf, c_bf, _ = e2_bruteforce(h, g_full, p_dets, Q, b=b)
+    e2_0, _, _, _ = e2_bruteforce(h, g_full, p_dets, Q)
+    assert abs(e2_bf - e2_0) > 1e-9 * abs(e2_0)          # the shift is visible
+    hfc, Bc = run.correlated_inputs(h, Bs, ws, spec.n_fc)
+    g, gc, H, c = ground(sp, hfc, Bc, ws)
+    e2_lit, _, _, _ = literal.e2_literal(sp, hfc, gc, c_bf, 0, b=b)
+    assert abs(e2_lit - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
+    e2_cls, _, _ = class_e2(sp, hfc, Bc, ws, c_bf, b=b)
+    assert abs(e2_cls - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
+
+
+def test_level_shift_limits():
+    """b -> 0 recovers eq. pt2en; for large b the shifted weight tends to
+    Delta^3 / b^2, so b^2 E2 -> sum_K |sigma_K|^2 Delta_K^3; the shift
+    shrinks every term, so |E2| decreases with b."""
+    spec, h, Bs, ws, g_full, sp, p_dets, Q = jw_problem(JW_CASES[0])
+    _, _, c_bf, _, (v, dq) = e2_bruteforce(h, g_full, p_dets, Q, vectors=True)
+    hfc, Bc = run.correlated_inputs(h, Bs, ws, spec.n_fc)
+    e0, _, _ = class_e2(sp, hfc, Bc, ws, c_bf)
+    tiny, _, _ = class_e2(sp, hfc, Bc, ws, c_bf, b=1e-9)
+    assert abs(tiny - e0) <= 1e-14 * abs(e0)
+    big = 1e8                       # next term: relative max Delta^4 / b^2 ~ 1e-9 here
+    eb, _, _ = class_e2(sp, hfc, Bc, ws, c_bf, b=big)
+    lim = float(np.sum(np.abs(v) ** 2 * dq ** 3))
+    assert abs(eb * big ** 2 - lim) <= 1e-8 * abs(lim)
+    vals = [abs(class_e2(sp, hfc, Bc, ws, c_bf, b=x)[0]) for x in (0.0, 0.1, 1.0, 10.0)]
+    assert all(a > b_ for a, b_ in zip(vals, vals[1:]))
 
 
 def test_hermiticity_of_matrix_elements():
@@ -191,6 +248,41 @@ def test_single_determinant_closed_form():
     assert abs(E0o - E0) < 1e-10
     assert abs(got - e2) < 1e-12 * abs(e2)
     assert set(k for k, v in parts.items() if v != 0.0) <= {(1, 1), (2, 2)}
+
+
+def test_level_shift_single_determinant_closed_form():
+    """n_a = 0 with the level shift: every Epstein-Nesbet term takes the real
+    weight Delta^3 / (Delta^4 + b^2)."""
+    spec, h, Bs, ws = single_det_problem(31, 4, 7, 12)
+    b = 3.0
+    n_c, n = 4, h.shape[0]
+    idx = np.arange(n)
+    g = integrals.eri_block(Bs, ws, idx, idx, idx, idx)
+    occ, vir = list(range(n_c)), list(range(n_c, n))
+    W = np.array([[(g[p, p, q, q] - g[p, q, q, p]).real if p != q else 0.0
+                   for q in range(n)] for p in range(n)])
+    hd = np.diag(h).real
+    E0 = hd[occ].sum() + sum(W[i, j] for i, j in combinations(occ, 2))
+    f = h + sum(g[:, :, j, j] - g[:, j, j, :] for j in occ)
+
+    def wt(dl):
+        return dl ** 3 / (dl ** 4 + b * b)
+
+    e2 = 0.0
+    for i in occ:
+        for a in vir:
+            rest = [j for j in occ if j != i]
+            Hkk = hd[rest].sum() + hd[a] + sum(W[p, q] for p, q in combinations(rest + [a], 2))
+            e2 += abs(f[a, i]) ** 2 * wt(E0 - Hkk)
+    for i, j in combinations(occ, 2):
+        for a, bb in combinations(vir, 2):
+            rest = [k for k in occ if k not in (i, j)]
+            Hkk = hd[rest].sum() + hd[a] + hd[bb] + sum(W[p, q] for p, q in combinations(rest + [a, bb], 2))
+            e2 += abs(g[a, i, bb, j] - g[a, j, bb, i]) ** 2 * wt(E0 - Hkk)
+    got, _, _ = class_e2(run.space_of(spec), h, Bs, ws, np.array([1.0 + 0j]), b=b)
+    unshifted, _, _ = class_e2(run.space_of(spec), h, Bs, ws, np.array([1.0 + 0j]))
+    assert abs(got - unshifted) > 1e-6 * abs(unshifted)
+    assert abs(got - e2) < 1e-12 * abs(e2)
 
 
 def test_one_body_only():
