@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--backward-steps", type=int, default=1,
                     help="timed adjoint calls after the forward measurement (0: none)")
+    ap.add_argument("--level-shift", type=float, default=0.0, metavar="B",
+                    help="also time one forward call with the imaginary level shift b = B (Sec. 2.6; "
+                         "every class then runs on the generic kernels)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -363,6 +366,28 @@ def main():
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
         "roofline": roof,
     }
+    if args.level_shift != 0.0:
+        # the shifted denominators of Sec. 2.6 on the same inputs: one untimed
+        # and one timed call (the shifted form is not the headline path)
+        dls = M.desc_of_problem(pb, precision=prec[args.precision], level_shift_b=args.level_shift)
+        els = M.Engine(M.Plan(dls, tuning=autotune.tuning_for(dls)), dev)
+        els.energy(insts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e2s, _, lms = els.energy_timed(insts)
+        torch.cuda.synchronize()
+        ls_ms = (time.perf_counter() - t0) * 1000.0
+        out["level_shift"] = {
+            "b": args.level_shift, "precision": args.precision, "ms_per_step": ls_ms,
+            "dets_per_s": info.n_ext / (ls_ms * 1e-3), "e2": float(e2s[0].item()),
+            "e2_unshifted": head["e2"], "ratio_to_unshifted": ls_ms / ms_per_step,
+            "stages_ms": {k: round(v, 2) for k, v in lms.items() if v > 0.05},
+        }
+        print("[bench] level shift b=%g (%s): %.1f ms, E2=%.12f" % (args.level_shift, args.precision, ls_ms,
+                                                                    out["level_shift"]["e2"]),
+              file=sys.stderr, flush=True)
+        del els
+        torch.cuda.empty_cache()
     if args.backward_steps > 0:
         # adjoint of the headline form: one call recomputes the forward pass and
         # returns dE2/dh, dE2/dB (every set) and dE2/dC

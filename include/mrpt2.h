@@ -82,8 +82,14 @@ typedef struct {
   int32_t rank[MRPT2_MAX_SETS];     /* Cholesky vectors per set */
   double weight[MRPT2_MAX_SETS];    /* real signed weight per set */
   int32_t precision;                /* mrpt2_precision */
-  double level_shift_b;             /* imaginary level shift b (Sec. 2.6);
-                                       must be 0 (eq. pt2 exactly) */
+  double level_shift_b;             /* imaginary level shift b (Sec. 2.6), in
+                                       Eh^2: every inverse denominator 1/Delta
+                                       becomes Re 1/(Delta + i b/Delta) =
+                                       Delta^3/(Delta^4 + b^2), in E2 and in
+                                       its gradient; only b^2 enters.  0 gives
+                                       eq. pt2 exactly.  A nonzero b runs every
+                                       excitation class on the generic sigma
+                                       and adjoint kernels (slower). */
 } mrpt2_desc;
 
 /* Sizes and exact algorithmic work of one instance. */
@@ -123,10 +129,10 @@ typedef struct mrpt2_plan_s* mrpt2_plan_t;
 /* Build the plan for n_inst instances (host only; no device work).
  * Enumerates the DAS categories, reference and external strings by
  * excitation class (Sec. 2.4), excitation lists and the work decomposition.
- * Errors: MRPT2_ERR_ARG for null pointers or n_inst < 1, MRPT2_ERR_SHAPE for
- * inconsistent sizes (electrons vs subspaces, more than 64 active spinors,
- * N_P >= 2^24), MRPT2_ERR_UNSUPPORTED for level_shift_b != 0 or an unknown
- * precision.  On error *out is NULL. */
+ * Errors: MRPT2_ERR_ARG for null pointers, n_inst < 1 or a level_shift_b
+ * that is not finite, MRPT2_ERR_SHAPE for inconsistent sizes (electrons vs
+ * subspaces, more than 64 active spinors, N_P >= 2^24), MRPT2_ERR_UNSUPPORTED
+ * for an unknown precision.  On error *out is NULL. */
 mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out);
 
 /* Launch shapes of one instance's work decomposition, per excitation class

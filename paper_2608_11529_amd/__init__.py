@@ -36,10 +36,11 @@ def make_desc(n_frozen_core, n_core, n_virt, sub_sizes, sub_base, max_hops, n_ac
     return d
 
 
-def desc_of_problem(pb, precision=0, q_mode=None):
+def desc_of_problem(pb, precision=0, q_mode=None, level_shift_b=0.0):
     """Descriptor of a synth.problems.Problem."""
     return make_desc(pb.n_fc, pb.n_c, pb.n_v, pb.sub_sizes, pb.base, min(pb.max_hops, 1 << 20),
-                     pb.n_elec, pb.sets, pb.q_mode if q_mode is None else q_mode, precision)
+                     pb.n_elec, pb.sets, pb.q_mode if q_mode is None else q_mode, precision,
+                     level_shift_b)
 
 
 class Plan:

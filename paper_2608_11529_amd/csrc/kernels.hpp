@@ -32,6 +32,30 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(r, e, r);
 }
 
+// Epstein-Nesbet weight g of one external determinant as a function of
+// Delta = E0 - H_KK, and its derivative g'.  Without a level shift g = 1/Delta.
+// With the imaginary level shift of Sec. 2.6 the denominator becomes
+// Delta + i b/Delta and its inverse is taken by the real part:
+//   g  = Delta^3 / (Delta^4 + b^2),
+//   g' = Delta^2 (3 b^2 - Delta^4) / (Delta^4 + b^2)^2.
+// b2 = b^2 is uniform over a launch, so the branch does not diverge.
+__device__ __forceinline__ double en_weight(double del, double b2) {
+  if (b2 == 0.0) return rcp_nr(del);
+  const double d2 = del * del;
+  return del * d2 * rcp_nr(fma(d2, d2, b2));
+}
+__device__ __forceinline__ void en_weight_d(double del, double b2, double& g, double& gp) {
+  if (b2 == 0.0) {
+    const double iv = rcp_nr(del);
+    g = iv;
+    gp = -iv * iv;
+    return;
+  }
+  const double d2 = del * del, d4 = d2 * d2, iq = rcp_nr(d4 + b2);
+  g = del * d2 * iq;
+  gp = d2 * fma(3.0, b2, -d4) * iq * iq;
+}
+
 // ---- per-instance device view -------------------------------------------------
 struct SetPtrs {
   const double2* B[4];
@@ -64,6 +88,7 @@ struct Dev {
   double2* hpp;              // [n_p][n_p]
   double2* sigp;             // [n_p]
   double* scal;              // [0] = E0 - E_core, [1] = ||C||^2
+  double ls_b2;              // square of the imaginary level-shift constant b (0: none)
   double* dsum;              // [n_l]
   // inputs and outputs of the current call
   const double2* h;          // [n][n]

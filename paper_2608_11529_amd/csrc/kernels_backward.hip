@@ -189,6 +189,7 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
   const double2* __restrict__ ec = cg.ecoef;
   const int32_t* __restrict__ ek = cd.ekey;
   double q = 0.0;
+  const double b2 = d.ls_b2;
   const int64_t S = cd.n_str;
   // strings [s_lo, s_hi) of this block; with several string chunks the
   // coupling adjoints of a row are shared and added atomically
@@ -210,10 +211,10 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     }
     for (; e < e1; ++e) sig = cfma(ec[e], X[coupling_off<H, V>(d, cd, ek[e], w, rr)], sig);
     const double del = string_delta<H, V>(cd, d, s, w) + qr;
-    const double iv = rcp_nr(del);
-    const double2 t = make_double2(sig.x * iv, sig.y * iv);
-    const double2 sb = make_double2(twoN * t.x, twoN * t.y);
-    const double dl = -oneN * cabs2(t);
+    double gw, gp;
+    en_weight_d(del, b2, gw, gp);
+    const double2 sb = make_double2(twoN * gw * sig.x, twoN * gw * sig.y);
+    const double dl = oneN * gp * cabs2(sig);
     if (w.valid) {
       for (e = e0; e < e1; ++e) {
         double2* p = Xb + coupling_off<H, V>(d, cd, ek[e], w, rr);
@@ -289,6 +290,7 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
   const int32_t* __restrict__ ek = cd.ekey;
   double2* cbe = cg.cbe + (int64_t)part * cd.n_conn;
   double tq = 0.0;
+  const double b2 = d.ls_b2;
   for (int64_t rc = r0; rc < r1; rc += RCH) {
     Row w[RCH];
     int64_t rk[RCH];
@@ -320,10 +322,11 @@ __device__ __forceinline__ void bstr_body(const Dev& d, const ClassDev& cd, cons
       // wave); two-virtual rows of a chunk share cache lines of Uv[s]
       const double sd = V <= 1 ? string_delta_t<H, V>(cd, cg, s, w[k]) : string_delta<H, V>(cd, d, s, w[k]);
       const double del = sd + row_const<H, V>(d, w[k]);
-      const double iv = w[k].valid ? rcp_nr(del) : 0.0;
-      const double2 t = make_double2(sig[k].x * iv, sig[k].y * iv);
-      sb[k] = make_double2(twoN * t.x, twoN * t.y);
-      tq -= oneN * cabs2(t);
+      double gw, gp;
+      en_weight_d(del, b2, gw, gp);
+      if (!w[k].valid) gw = gp = 0.0;
+      sb[k] = make_double2(twoN * gw * sig[k].x, twoN * gw * sig[k].y);
+      tq += oneN * gp * cabs2(sig[k]);
     }
     if (live) {
       for (int e = e0; e < e1; ++e) {

@@ -214,7 +214,9 @@ constexpr int SIG_THREADS = 256;
 //   Delta = (E0 - E_core) - (H_KK - E_core)
 //         = T[s] + sum_{c in holes} (eps_c + Uc[s][c]) - sum_{a in virt} (eps_a + Uv[s][a])
 //           - W_cc' - W_ab + sum_{c, a} W_ca
-//   partial += |sigma|^2 / Delta   (divided by ||C||^2 at the end)
+//   partial += |sigma|^2 g(Delta)   (divided by ||C||^2 at the end)
+// with g = 1/Delta, or its level-shifted form (en_weight).  This kernel
+// serves every class when a level shift is set.
 // One thread per row, a chunk of strings per block.  grid (rb * nsc).
 template <int H, int V>
 __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
@@ -268,6 +270,7 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
   }
   double acc = 0.0;
   bool bad = false;
+  const double b2 = d.ls_b2;
   for (int64_t s = s_lo; s < s_hi; ++s) {
     const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
     double2 sig = make_double2(0.0, 0.0);
@@ -295,7 +298,7 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
     if (V >= 1) del -= cd.Uv[s * d.n_v + a];
     if (V == 2) del -= cd.Uv[s * d.n_v + b];
     if (e1 > e0) {
-      const double t = cabs2(sig) * rcp_nr(del);
+      const double t = cabs2(sig) * en_weight(del, b2);
       if (valid) {
         if (!(del != 0.0) || !isfinite(t)) bad = true;
         acc += t;

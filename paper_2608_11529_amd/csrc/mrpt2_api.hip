@@ -71,6 +71,7 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.hpp = (double2*)(W + ip.off_hpp);
   d.sigp = (double2*)(W + ip.off_sigp);
   d.scal = (double*)(W + ip.off_scal);
+  d.ls_b2 = ip.d.level_shift_b * ip.d.level_shift_b;
   d.dsum = (double*)(W + ip.off_dsum);
   d.h = (const double2*)in->h;
   d.c = (const double2*)in->c;

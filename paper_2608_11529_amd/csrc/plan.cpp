@@ -738,9 +738,9 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       *err = "unknown precision";
       return MRPT2_ERR_UNSUPPORTED;
     }
-    if (d.level_shift_b != 0.0) {
-      *err = "level shift not supported";
-      return MRPT2_ERR_UNSUPPORTED;
+    if (!std::isfinite(d.level_shift_b)) {
+      *err = "level shift b must be finite";
+      return MRPT2_ERR_ARG;
     }
     ip.n_fc = d.n_frozen_core;
     ip.n_c = d.n_core;
@@ -955,14 +955,17 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_Uc = W.take(cp.h > 0 ? S * ip.n_c * 8 : 0);
       cp.off_Uv = W.take(cp.v > 0 ? S * ip.n_v * 8 : 0);
       cp.off_X = W.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
-      cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
+      // a level shift changes every denominator epilogue; only the generic
+      // kernels carry the shifted weight, so they take every class then
+      const bool shifted = ip.d.level_shift_b != 0.0;
+      cp.dense_coef = !shifted && (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
       cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
       // kernel choice and partial-sum blocks: the dedicated kernels' grids
       // ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per tile pair x
       // core; (0,2): string tile x 64 rows of a tile pair) or the generic kernel's
       cp.kernel = KERN_GENERIC;
-      if (S && cp.n_rows > 0) {
+      if (S && cp.n_rows > 0 && !shifted) {
         if (k == 0) cp.kernel = KERN_E22;
         else if (k == 1 && cp.dense_coef) cp.kernel = KERN_E12;
         else if (k == 2 && cp.n_tiles > 0) cp.kernel = KERN_E02;

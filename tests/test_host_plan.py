@@ -85,7 +85,7 @@ def test_table3_counts_through_the_plan():
 
 @pytest.mark.parametrize("field,value,code", [
     ("n_sub", 17, 1), ("n_sets", 0, 1), ("q_mode", 2, 1), ("precision", 7, 3),
-    ("level_shift_b", 0.05, 3), ("n_act_elec", 9, 2),
+    ("level_shift_b", float("nan"), 1), ("level_shift_b", float("inf"), 1), ("n_act_elec", 9, 2),
 ])
 def test_plan_rejects_bad_descriptors(field, value, code):
     M = lib_module()
@@ -94,6 +94,18 @@ def test_plan_rejects_bad_descriptors(field, value, code):
     with pytest.raises(M.Mrpt2Error) as ei:
         M.Plan(d)
     assert ei.value.code == code
+
+
+def test_level_shift_plans_every_class_on_the_generic_kernels():
+    """A nonzero level shift is accepted and changes neither the external
+    space nor its counts (the shift acts on the denominators only)."""
+    M = lib_module()
+    d = M.desc_of_problem(problem("s_cas"))
+    ref = M.Plan(d).info()
+    d.level_shift_b = 0.05
+    got = M.Plan(d).info()
+    assert got.n_ext == ref.n_ext
+    assert list(got.n_ext_class) == list(ref.n_ext_class)
 
 
 def test_null_arguments_return_status():
