@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--level-shift", type=float, default=0.0, metavar="B",
                     help="also time one forward call with the imaginary level shift b = B (Sec. 2.6; "
                          "every class then runs on the generic kernels)")
+    ap.add_argument("--roots", type=int, default=0, metavar="K",
+                    help="also time the state-specific E2 of the K lowest reference states in one call "
+                         "against K single-state calls")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -388,6 +391,29 @@ def main():
               file=sys.stderr, flush=True)
         del els
         torch.cuda.empty_cache()
+    if args.roots > 0:
+        # state-specific E2_m of the K lowest states: one call (shared integral
+        # build) against K single-state calls, same engine and inputs
+        from paper_2608_11529_amd.reference import states
+        eng = engs[args.precision]
+        C, e0s = states(engs["fp64"], h, Bs, args.roots)
+        eng.energy_roots([(h, Bs, C)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e2r, _ = eng.energy_roots([(h, Bs, C)])
+        torch.cuda.synchronize()
+        ms_roots = (time.perf_counter() - t0) * 1000.0
+        t0 = time.perf_counter()
+        singles = [float(eng.energy([(h, Bs, C[r].contiguous())], parts=False)[0].item()) for r in range(args.roots)]
+        torch.cuda.synchronize()
+        ms_single = (time.perf_counter() - t0) * 1000.0
+        e2r = e2r[:, 0].cpu().tolist()
+        out["roots"] = {"k": args.roots, "precision": args.precision, "ms": ms_roots, "sequential_ms": ms_single,
+                        "dets_per_s": args.roots * info.n_ext / (ms_roots * 1e-3), "e2": e2r,
+                        "e0_minus_ecore": [float(x) for x in e0s], "equal_to_single_calls": e2r == singles}
+        print("[bench] %d roots (%s): %.1f ms in one call, %.1f ms as single calls" % (args.roots, args.precision,
+                                                                                   ms_roots, ms_single),
+              file=sys.stderr, flush=True)
     if args.backward_steps > 0:
         # adjoint of the headline form: one call recomputes the forward pass and
         # returns dE2/dh, dE2/dB (every set) and dE2/dC

@@ -188,6 +188,24 @@ mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in,
                           const void* persistent, void* workspace, size_t workspace_bytes,
                           hipStream_t stream, double* e2, double* parts);
 
+/* State-specific E2 of several reference states per instance (the state
+ * index m of eq. pt2: E2_m with E0_m = <Psi_m|H|Psi_m> and the first-order
+ * vector of Psi_m, each state with its own denominators).  in[i].c points to
+ * n_roots coefficient vectors of instance i, complex [n_roots][N_P] in plan
+ * order (each normalised or not; the norm is divided out as in
+ * mrpt2_energy).  The steps that do not depend on the reference vector (the
+ * factor tables, the occupied-block and virtual-pair integrals, H_PP and the
+ * couplings) run once per call; the reference energy, the per-string
+ * denominator tables, the sigma contractions and the sums run once per state.
+ * e2: device double[n_roots][n_inst]; parts: optional device
+ * double[n_roots][n_inst][12] laid out as in mrpt2_energy.  Root m gives the
+ * same numbers as mrpt2_energy called with c = root m.  Synchronises the
+ * stream once at the end.  Errors as mrpt2_energy; MRPT2_ERR_ARG for
+ * n_roots < 1 or a NULL c. */
+mrpt2_status mrpt2_energy_roots(mrpt2_plan_t plan, const mrpt2_inputs* in, int32_t n_roots,
+                                const void* persistent, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream, double* e2, double* parts);
+
 /* mrpt2_energy without its final synchronisation: every step (a small
  * host-to-device copy of the instance descriptors from library-owned pinned
  * memory, then one batched launch per stage covering all instances) is

@@ -167,6 +167,27 @@ class Engine:
         del keep
         return (self.e2, self.parts) if parts else self.e2
 
+    def energy_roots(self, insts):
+        """State-specific E2 of several reference states at once: insts is a
+        list of (h, [B_t], C) per instance with C complex128 of shape
+        [n_roots, N_P] (the same n_roots for every instance).  The integral
+        build runs once; returns E2 [n_roots, n_inst] and the per-class
+        parts [n_roots, n_inst, 12] (device tensors)."""
+        torch = self.torch
+        shapes = {tuple(c.shape) for _, _, c in insts}
+        if any(len(sh) != 2 for sh in shapes) or len({sh[0] for sh in shapes}) != 1:
+            raise ValueError("every C must be [n_roots, N_P] with one n_roots")
+        n_roots = next(iter(shapes))[0]
+        arr, keep = self._inputs(insts)
+        e2 = torch.zeros((n_roots, self.plan.n_inst), dtype=torch.float64, device=self.device)
+        parts = torch.zeros((n_roots, self.plan.n_inst, 12), dtype=torch.float64, device=self.device)
+        code = capi.lib().mrpt2_energy_roots(self.plan.handle, arr, n_roots, self.persistent.data_ptr(),
+                                             self.workspace.data_ptr(), self.plan.workspace_bytes, self._sptr(),
+                                             e2.data_ptr(), parts.data_ptr())
+        capi.check(code, "mrpt2_energy_roots")
+        del keep
+        return e2, parts
+
     def energy_async(self, insts, stream=None):
         """Enqueue an evaluation without synchronising (capturable in a HIP
         graph).  The input tensors must stay alive until it has run; call

@@ -138,6 +138,9 @@ def lib():
         L.mrpt2_energy_async.restype = st
         L.mrpt2_check.argtypes = [vp, vp, vp]
         L.mrpt2_check.restype = st
+        L.mrpt2_energy_roots.argtypes = [vp, ctypes.POINTER(Inputs), ctypes.c_int32, vp, vp, ctypes.c_size_t,
+                                         vp, vp, vp]
+        L.mrpt2_energy_roots.restype = st
         L.mrpt2_energy_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp,
                                          ctypes.POINTER(ctypes.c_float)]
         L.mrpt2_energy_timed.restype = st
@@ -177,7 +180,7 @@ def check(code, where):
 
 EXPORTED = [
     "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
-    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
+    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_roots", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",

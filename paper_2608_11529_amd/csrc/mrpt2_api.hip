@@ -192,14 +192,35 @@ mrpt2_status check_regions(const Plan& p, const void* pers, void* work, size_t w
   return MRPT2_OK;
 }
 
+// Pinned staging for `sets` descriptor sets.  Growing it waits for the
+// stream, so that no queued copy still reads the old buffer.
+mrpt2_status ensure_pinned(Plan& P, size_t sets, hipStream_t st) {
+  const size_t need = kInstBytes * P.inst.size() * sets;
+  if (P.pinned && P.pinned_bytes >= need) return MRPT2_OK;
+  if (P.pinned) {
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipHostFree(P.pinned));
+    P.pinned = nullptr;
+    P.pinned_bytes = 0;
+  }
+  HIPCHK(hipHostMalloc(&P.pinned, need, hipHostMallocDefault));
+  P.pinned_bytes = need;
+  return MRPT2_OK;
+}
+
 // Fill the instance descriptors in pinned host memory and copy them to the
-// workspace (asynchronously, on stream).
+// workspace (asynchronously, on stream).  They are staged in descriptor set
+// `slot`: a multi-state call fills one set per state before the stream has
+// copied the earlier ones.
 mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, char* work, hipStream_t st,
                           double* e2, double* parts, double* hpp_out, int only, char* gw = nullptr,
-                          const mrpt2_grads* grads = nullptr, const double* grad_e2 = nullptr) {
+                          const mrpt2_grads* grads = nullptr, const double* grad_e2 = nullptr,
+                          int slot = 0) {
   const size_t bytes = kInstBytes * P.inst.size();
-  if (!P.pinned) HIPCHK(hipHostMalloc(&P.pinned, bytes, hipHostMallocDefault));
-  std::memset(P.pinned, 0, bytes);
+  mrpt2_status ps = ensure_pinned(P, (size_t)slot + 1, st);
+  if (ps != MRPT2_OK) return ps;
+  char* stage = (char*)P.pinned + bytes * slot;
+  std::memset(stage, 0, bytes);
   for (size_t i = 0; i < P.inst.size(); ++i) {
     if (only >= 0 && (int)i != only) continue;
     const mrpt2_inputs* ini = in + (only >= 0 ? 0 : i);
@@ -207,7 +228,7 @@ mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, cha
     if (!ini->h || (only < 0 && !ini->c)) return MRPT2_ERR_ARG;
     for (int t = 0; t < ip.d.n_sets; ++t)
       if (ip.d.rank[t] > 0 && !ini->B[t]) return MRPT2_ERR_ARG;
-    Inst* I = (Inst*)((char*)P.pinned + kInstBytes * i);
+    Inst* I = (Inst*)(stage + kInstBytes * i);
     I->d = make_dev(ip, pers, work, ini);
     I->d.out_e2 = e2 ? e2 + i : nullptr;
     I->d.out_parts = parts ? parts + 12 * i : nullptr;
@@ -224,17 +245,36 @@ mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, cha
       for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cg[k] = make_class_grad(ip, k, gw);
     }
   }
-  HIPCHK(hipMemcpyAsync(work + P.off_insts, P.pinned, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(work + P.off_insts, stage, bytes, hipMemcpyHostToDevice, st));
   return MRPT2_OK;
 }
 
+// Launches whose results depend on the reference vector (sigma_P, E0, the
+// per-string tables that hold E0, the coefficient blocks, the sigma
+// contractions and the sums).  Everything else in the energy sequence
+// depends only on h and the factors.
+bool depends_on_c(int kid) {
+  switch (kid) {
+    case K_SIGP: case K_E0: case K_CTAB: case K_DCOEF: case K_E02COEF: case K_E22:
+    case K_E12_8: case K_E12_16: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
+    case K_SIG22: case K_SIG12: case K_SIG02: case K_SIG21: case K_SIG11: case K_SIG01:
+    case K_SIG20: case K_SIG10: case K_SIG00: case K_FINISH:
+      return true;
+    default:
+      return false;
+  }
+}
+
+enum RunPart { RUN_ALL = 0, RUN_SHARED = 1, RUN_PER_STATE = 2 };
+
 // Enqueue a launch sequence.
 mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers, char* work, hipStream_t st,
-                 Timer& tm) {
+                 Timer& tm, RunPart part = RUN_ALL) {
   const Inst* insts = (const Inst*)(work + P.off_insts);
   const Job* jobs_all = (const Job*)(pers + P.off_jobs);
   int* flag = (int*)(work + P.off_flag);
   for (const Launch& L : seq) {
+    if (part != RUN_ALL && depends_on_c(L.kid) != (part == RUN_PER_STATE)) continue;
     const Job* jobs = jobs_all + L.job0;
     const dim3 g((unsigned)L.nblocks), b256(256), b64(64);
     const int nj = L.njobs, ka = L.arg;
@@ -420,6 +460,35 @@ mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void*
   mrpt2_status s = energy_enqueue(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
   if (s != MRPT2_OK) return s;
   return read_flag(plan->p, workspace, st);
+}
+
+mrpt2_status mrpt2_energy_roots(mrpt2_plan_t plan, const mrpt2_inputs* in, int32_t n_roots,
+                                const void* persistent, void* workspace, size_t workspace_bytes,
+                                hipStream_t st, double* e2, double* parts) {
+  if (!plan || !in || !e2 || n_roots < 1) return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  const size_t n = P.inst.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!in[i].c) return MRPT2_ERR_ARG;
+  s = ensure_pinned(P, (size_t)n_roots, st);
+  if (s != MRPT2_OK) return s;
+  std::vector<mrpt2_inputs> rin(in, in + n);
+  Timer tm;
+  for (int r = 0; r < n_roots; ++r) {
+    for (size_t i = 0; i < n; ++i) rin[i].c = in[i].c + 2 * (size_t)r * P.inst[i].pstrings.size();
+    s = upload_insts(P, rin.data(), (const char*)persistent, (char*)workspace, st, e2 + (size_t)r * n,
+                     parts ? parts + (size_t)12 * r * n : nullptr, nullptr, -1, nullptr, nullptr, nullptr, r);
+    if (s != MRPT2_OK) return s;
+    if (r == 0) {
+      s = run(P, P.energy, (const char*)persistent, (char*)workspace, st, tm, RUN_SHARED);
+      if (s != MRPT2_OK) return s;
+    }
+    s = run(P, P.energy, (const char*)persistent, (char*)workspace, st, tm, RUN_PER_STATE);
+    if (s != MRPT2_OK) return s;
+  }
+  return read_flag(P, workspace, st);
 }
 
 mrpt2_status mrpt2_energy_async(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,

@@ -157,6 +157,7 @@ struct Plan {
   std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
   std::vector<char> host_blob;
   void* pinned = nullptr;             // host staging of the instance descriptors
+  size_t pinned_bytes = 0;            // its size (one descriptor set per state of a multi-state call)
 };
 
 // Kernel that evaluates a class.

@@ -68,8 +68,8 @@ def shifted_resolvent_sum(v, dq, b):
     return float(np.real(np.vdot(v, np.linalg.solve(R, v))))
 
 
-def e2_bruteforce(h, g, p_dets, q_dets, b=0.0, vectors=False):
-    """Lowest state of H restricted to P, its energy E0, and
+def e2_bruteforce(h, g, p_dets, q_dets, b=0.0, vectors=False, root=0):
+    """State `root` (0: lowest) of H restricted to P, its energy E0, and
     E2 = sum_{K in Q} |(H Psi0)_K|^2 / (E0 - H_KK) (b = 0) or its level-shifted
     form (shifted_resolvent_sum); returns (E2, E0, C, H), and with vectors=True
     also ((H Psi0)_Q, E0 - H_QQ)."""
@@ -79,14 +79,14 @@ def e2_bruteforce(h, g, p_dets, q_dets, b=0.0, vectors=False):
     qi = [kron_index(d, n) for d in q_dets]
     Hpp = H[pi][:, pi].toarray()
     w, v = np.linalg.eigh(Hpp)
-    c = v[:, 0]
+    c = v[:, root]
     k = int(np.argmax(np.abs(c)))
     c = c * (abs(c[k]) / c[k])
     psi = np.zeros(2 ** n, dtype=np.complex128)
     psi[pi] = c
     s = H @ psi
     diag = H.diagonal()
-    e0 = w[0]
+    e0 = w[root]
     v, dq = s[qi], e0 - diag[qi].real
     if b == 0.0:
         e2 = float(np.sum(np.abs(v) ** 2 / dq))

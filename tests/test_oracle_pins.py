@@ -116,6 +116,23 @@ def test_level_shift_jordan_wigner_bruteforce(case, b):
     assert abs(e2_cls - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
 
 
+@pytest.mark.parametrize("root", [1, 2])
+def test_excited_reference_state_jordan_wigner(root):
+    """State-specific E2_m (the index m of eq. pt2): with the m-th eigenvector
+    of H_PP as reference, E0_m and the first-order vector are those of that
+    state; the oracle (which takes E0 from C) reproduces the brute force."""
+    spec, h, Bs, ws, g_full, sp, p_dets, Q = jw_problem(JW_CASES[1])
+    e2_bf, e0_bf, c_bf, _ = e2_bruteforce(h, g_full, p_dets, Q, root=root)
+    e2_g, e0_g, _, _ = e2_bruteforce(h, g_full, p_dets, Q)
+    assert e0_bf > e0_g + 1e-6
+    hfc, Bc = run.correlated_inputs(h, Bs, ws, spec.n_fc)
+    g, gc, H, c = ground(sp, hfc, Bc, ws)
+    e2_lit, e0_lit, _, _ = literal.e2_literal(sp, hfc, gc, c_bf, 0)
+    assert abs(e2_lit - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
+    e2_cls, _, E0c = class_e2(sp, hfc, Bc, ws, c_bf)
+    assert abs(e2_cls - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
+
+
 def test_level_shift_limits():
     """b -> 0 recovers eq. pt2en; for large b the shifted weight tends to
     Delta^3 / b^2, so b^2 E2 -> sum_K |sigma_K|^2 Delta_K^3; the shift
