@@ -268,6 +268,9 @@ def main():
     ap.add_argument("--roots", type=int, default=0, metavar="K",
                     help="also time the state-specific E2 of the K lowest reference states in one call "
                          "against K single-state calls")
+    ap.add_argument("--davidson", type=int, default=0, metavar="K",
+                    help="also time the device Davidson solver for the 1 and K lowest reference states against "
+                         "the host eigensolver path")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -391,6 +394,27 @@ def main():
               file=sys.stderr, flush=True)
         del els
         torch.cuda.empty_cache()
+    if args.davidson > 0:
+        # reference states: device block Davidson (H_PP assembled and applied
+        # on the GPU) against H_PP copied to the host and ARPACK/LAPACK
+        from paper_2608_11529_amd.reference import ground_state as host_ground_state
+        e64 = engs["fp64"]
+        dv = {}
+        for kk in sorted({1, args.davidson}):
+            e64.reference_states(h, Bs, kk)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Cd, ed, its = e64.reference_states(h, Bs, kk)
+            torch.cuda.synchronize()
+            dv[kk] = {"ms": (time.perf_counter() - t0) * 1000.0, "iterations": its, "e_minus_ecore": ed.tolist()}
+        t0 = time.perf_counter()
+        c_h, e_h = host_ground_state(e64, h, Bs)
+        torch.cuda.synchronize()
+        host_ms = (time.perf_counter() - t0) * 1000.0
+        e2d = float(engs[args.precision].energy([(h, Bs, Cd[0].contiguous())], parts=False)[0].item())
+        out["davidson"] = {"n_ref": info.n_ref, "states": dv, "host_path_ms": host_ms, "host_e0_minus_ecore": e_h,
+                           "e2_with_davidson_state": e2d, "e2_with_host_state": head["e2"]}
+        print("[bench] davidson: " + json.dumps(out["davidson"]), file=sys.stderr, flush=True)
     if args.roots > 0:
         # state-specific E2_m of the K lowest states: one call (shared integral
         # build) against K single-state calls, same engine and inputs

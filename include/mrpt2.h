@@ -242,6 +242,44 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
                                          const void* persistent, void* workspace,
                                          size_t workspace_bytes, hipStream_t stream, double* hpp);
 
+/* Bytes of the device region mrpt2_reference_states needs for n_states
+ * states of instance inst (holds H_PP, 16 N_P^2 bytes, and the search space). */
+mrpt2_status mrpt2_reference_states_size(mrpt2_plan_t plan, int32_t inst, int32_t n_states, size_t* bytes);
+
+/* The n_states lowest eigenpairs of the reference-space Hamiltonian minus the
+ * core energy, H_PP - E_core (eq. zeroh inside P: the CI problem in the
+ * primary space that yields Psi0 and the states E2_m refers to), on the
+ * device.  H_PP is assembled from the Slater-Condon rules as in
+ * mrpt2_reference_hamiltonian (into dv), then a block Davidson solver runs:
+ * the search space starts from the unit vectors of the n_states lowest
+ * diagonal elements; each iteration applies H_PP to the new directions (a
+ * dense Hermitian product, one wavefront per row), solves the projected
+ * matrix on the host (mrpt2_hermitian_eigh), forms Ritz vectors and
+ * residuals, and adds the residuals divided by (theta - diag H_PP),
+ * orthonormalised twice against the search space; the space restarts from
+ * the lowest Ritz vectors when full.
+ * dv: device region of mrpt2_reference_states_size bytes, 256-byte aligned.
+ * tol: bound on every residual norm ||H x - theta x|| (x of unit norm, Eh).
+ * c_out: device complex [n_states][N_P] (written; plan order, unit norm, the
+ * largest component real and positive); e_out: host double[n_states]
+ * (written, ascending); iterations: host int (optional, written).
+ * Errors: MRPT2_ERR_ARG for bad arguments or n_states > N_P,
+ * MRPT2_ERR_WORKSPACE if dv_bytes is too small, MRPT2_ERR_NUMERIC if
+ * max_iter iterations leave a residual above tol (the Ritz pairs reached are
+ * written) or a value is not finite. */
+mrpt2_status mrpt2_reference_states(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in, int32_t n_states,
+                                    double tol, int32_t max_iter, const void* persistent, void* workspace,
+                                    size_t workspace_bytes, void* dv, size_t dv_bytes, hipStream_t stream,
+                                    double* c_out, double* e_out, int32_t* iterations);
+
+/* Eigenpairs of a complex Hermitian n x n matrix (host memory, row-major,
+ * interleaved complex; only its Hermitian part is used) by cyclic Jacobi
+ * rotations: w (host double[n]) ascending, v (host complex [n][n]) with
+ * eigenvector j in column j.  Used for the projected matrix of the Davidson
+ * solver; meant for n up to a few hundred.  Errors: MRPT2_ERR_ARG,
+ * MRPT2_ERR_NUMERIC for non-finite input. */
+mrpt2_status mrpt2_hermitian_eigh(int32_t n, const double* a, double* w, double* v);
+
 /* Bytes of the gradient workspace of mrpt2_energy_backward (256-byte aligned
  * device allocation, caller-owned). */
 mrpt2_status mrpt2_plan_backward_size(mrpt2_plan_t plan, size_t* grad_workspace_bytes);

@@ -264,6 +264,29 @@ class Engine:
                    "mrpt2_class_partials")
         return out[:n]
 
+    def reference_states(self, h, Bs, k=1, tol=1e-10, max_iter=500, inst=0):
+        """The k lowest eigenpairs of H_PP - E_core by the library's block
+        Davidson solver on the device: C [k, N_P] complex128 device tensor in
+        plan order (unit norm, largest component real positive), energies
+        (host numpy, ascending) and the iteration count."""
+        torch = self.torch
+        n_p = self.plan.info(inst).n_ref
+        nbytes = ctypes.c_size_t()
+        capi.check(capi.lib().mrpt2_reference_states_size(self.plan.handle, inst, k, ctypes.byref(nbytes)),
+                   "mrpt2_reference_states_size")
+        dv = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        C = torch.empty((k, n_p), dtype=torch.complex128, device=self.device)
+        e = np.zeros(k)
+        its = ctypes.c_int32()
+        arr, keep = self._inputs([(h, Bs, None)])
+        code = capi.lib().mrpt2_reference_states(self.plan.handle, inst, arr, k, tol, max_iter,
+                                                 self.persistent.data_ptr(), self.workspace.data_ptr(),
+                                                 self.plan.workspace_bytes, dv.data_ptr(), nbytes.value,
+                                                 self._sptr(), C.data_ptr(), e.ctypes.data, ctypes.byref(its))
+        capi.check(code, "mrpt2_reference_states")
+        del keep, dv
+        return C, e, its.value
+
     def reference_hamiltonian(self, h, Bs, inst=0):
         torch = self.torch
         n_p = self.plan.info(inst).n_ref
@@ -275,6 +298,18 @@ class Engine:
         capi.check(code, "mrpt2_reference_hamiltonian")
         del keep
         return out
+
+
+def hermitian_eigh(a):
+    """Eigenpairs (ascending) of a small complex Hermitian host matrix with the
+    library's Jacobi solver (the one its Davidson solver uses)."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    n = a.shape[0]
+    w = np.zeros(n)
+    v = np.zeros((n, n), dtype=np.complex128)
+    capi.check(capi.lib().mrpt2_hermitian_eigh(n, a.ctypes.data, w.ctypes.data, v.ctypes.data),
+               "mrpt2_hermitian_eigh")
+    return w, v
 
 
 def _autograd_function():

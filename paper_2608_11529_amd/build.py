@@ -18,7 +18,7 @@ FLAGS = [
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, "mrpt2_api.hip"), os.path.join(CSRC, "plan.cpp")]
+    srcs = [os.path.join(CSRC, "mrpt2_api.hip"), os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "eigh.cpp")]
     tmp = LIB + ".tmp"
     cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
     if verbose:

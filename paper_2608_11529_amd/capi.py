@@ -141,6 +141,14 @@ def lib():
         L.mrpt2_energy_roots.argtypes = [vp, ctypes.POINTER(Inputs), ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                          vp, vp, vp]
         L.mrpt2_energy_roots.restype = st
+        L.mrpt2_reference_states_size.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.mrpt2_reference_states_size.restype = st
+        L.mrpt2_reference_states.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Inputs), ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp, vp,
+                                             ctypes.POINTER(ctypes.c_int32)]
+        L.mrpt2_reference_states.restype = st
+        L.mrpt2_hermitian_eigh.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.mrpt2_hermitian_eigh.restype = st
         L.mrpt2_energy_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp,
                                          ctypes.POINTER(ctypes.c_float)]
         L.mrpt2_energy_timed.restype = st
@@ -180,7 +188,8 @@ def check(code, where):
 
 EXPORTED = [
     "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
-    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_roots", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
+    "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_roots", "mrpt2_reference_states_size",
+    "mrpt2_reference_states", "mrpt2_hermitian_eigh", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",

@@ -5,9 +5,14 @@
 // fixed by the plan, so it can be captured into a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "mrpt2.h"
@@ -17,6 +22,7 @@
 #include "kernels_energy.hip"
 #include "kernels_backward.hip"
 #include "kernels_batched.hip"
+#include "kernels_davidson.hip"
 
 struct mrpt2_plan_s {
   mrpt2::Plan p;
@@ -386,6 +392,211 @@ mrpt2_status read_flag(const Plan& P, const void* workspace, hipStream_t st) {
   return hflag ? MRPT2_ERR_NUMERIC : MRPT2_OK;
 }
 
+// ---- block Davidson for the reference states --------------------------------
+// Device buffers (one region, caller-owned): H_PP [n][n], the basis V and its
+// image W = H V [mmax][n] each, restart copies of both, the Ritz vectors X and
+// residuals R [k][n], and small matrices.
+struct DvLayout {
+  int mmax = 0;
+  size_t H = 0, V = 0, W = 0, Vt = 0, Wt = 0, X = 0, R = 0, G = 0, M = 0, th = 0, sc = 0, dg = 0, total = 0;
+};
+
+DvLayout dv_layout(int64_t n, int k) {
+  DvLayout L;
+  L.mmax = (int)std::min<int64_t>(n, std::max(6 * k, 30));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t vec = (size_t)n * 16, mm = (size_t)L.mmax;
+  L.H = take((size_t)n * vec);
+  L.V = take(mm * vec);
+  L.W = take(mm * vec);
+  L.Vt = take(mm * vec);
+  L.Wt = take(mm * vec);
+  L.X = take((size_t)k * vec);
+  L.R = take((size_t)k * vec);
+  L.G = take(mm * mm * 16);
+  L.M = take(mm * mm * 16);
+  L.th = take(mm * 8);
+  L.sc = take(mm * 16);
+  L.dg = take((size_t)n * 8);
+  L.total = off;
+  return L;
+}
+
+// Synchronous small copies on the solver's stream (the host buffers are
+// ordinary memory and are reused right after).
+mrpt2_status dv_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, kind, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return MRPT2_OK;
+}
+
+#define DVCHK(x)                          \
+  do {                                    \
+    const mrpt2_status s_ = (x);          \
+    if (s_ != MRPT2_OK) return s_;        \
+  } while (0)
+
+// The k lowest eigenpairs of the n x n Hermitian matrix at L.H (already in
+// place).  Returns MRPT2_ERR_NUMERIC when max_iter iterations leave a
+// residual norm above tol (the current Ritz pairs are still written).
+mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double tol, int max_iter,
+                      hipStream_t st, double* c_out, double* e_out, int32_t* iters) {
+  using cd = std::complex<double>;
+  const int n = (int)n64, mmax = L.mmax;
+  double2* H = (double2*)(base + L.H);
+  double2* V = (double2*)(base + L.V);
+  double2* W = (double2*)(base + L.W);
+  double2* Vt = (double2*)(base + L.Vt);
+  double2* Wt = (double2*)(base + L.Wt);
+  double2* X = (double2*)(base + L.X);
+  double2* R = (double2*)(base + L.R);
+  double2* G = (double2*)(base + L.G);
+  double2* M = (double2*)(base + L.M);
+  double* th = (double*)(base + L.th);
+  double2* sc = (double2*)(base + L.sc);
+  double* dg = (double*)(base + L.dg);
+  const dim3 b256(256);
+  const unsigned nb = (unsigned)cdiv(n, 256);
+  // initial basis: unit vectors at the k lowest diagonal elements
+  hipLaunchKernelGGL(k_dv_diag, dim3(nb), b256, 0, st, H, dg, n);
+  std::vector<double> d(n);
+  DVCHK(dv_copy(d.data(), dg, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  {
+    std::vector<cd> v0((size_t)k * n, cd(0.0, 0.0));
+    for (int j = 0; j < k; ++j) v0[(size_t)j * n + idx[j]] = 1.0;
+    DVCHK(dv_copy(V, v0.data(), v0.size() * 16, hipMemcpyHostToDevice, st));
+  }
+  int m = k, nnew = k;
+  std::vector<cd> S((size_t)mmax * mmax, cd(0.0, 0.0)), g((size_t)mmax * mmax), Y((size_t)mmax * mmax),
+      mh((size_t)mmax * mmax);
+  std::vector<double> w(mmax), rn(k);
+  bool conv = false;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    for (int c = m - nnew; c < m; c += DV_COLS)
+      hipLaunchKernelGGL(k_dv_hx, dim3((unsigned)cdiv(n, 4)), b256, 0, st, H, V, W, n, c, std::min(DV_COLS, m - c));
+    hipLaunchKernelGGL(k_dv_dots, dim3((unsigned)(m * nnew)), b256, 0, st, V, 0, W, m - nnew, nnew, n, G);
+    HIPCHK(hipGetLastError());
+    DVCHK(dv_copy(g.data(), G, (size_t)m * nnew * 16, hipMemcpyDeviceToHost, st));
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < nnew; ++b) {
+        const int col = m - nnew + b;
+        S[(size_t)a * mmax + col] = g[(size_t)a * nnew + b];
+        if (a < m - nnew) S[(size_t)col * mmax + a] = std::conj(g[(size_t)a * nnew + b]);
+      }
+    for (int a = m - nnew; a < m; ++a)          // Hermitian part of the new block
+      for (int b = a; b < m; ++b) {
+        const cd h = 0.5 * (S[(size_t)a * mmax + b] + std::conj(S[(size_t)b * mmax + a]));
+        S[(size_t)a * mmax + b] = h;
+        S[(size_t)b * mmax + a] = std::conj(h);
+      }
+    // Rayleigh-Ritz on the projected matrix
+    std::vector<cd> sm((size_t)m * m);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) sm[(size_t)a * m + b] = S[(size_t)a * mmax + b];
+    DVCHK(mrpt2_hermitian_eigh(m, (const double*)sm.data(), w.data(), (double*)Y.data()));
+    // Ritz vectors X = V Y_k, residuals R = W Y_k - X diag(theta)
+    for (int a = 0; a < m; ++a)
+      for (int j = 0; j < k; ++j) mh[(size_t)a * k + j] = Y[(size_t)a * m + j];
+    DVCHK(dv_copy(M, mh.data(), (size_t)m * k * 16, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_dv_comb, dim3(nb, k), b256, 0, st, V, 0, m, M, k, X, 0, 1.0, 0.0, n);
+    hipLaunchKernelGGL(k_dv_comb, dim3(nb, k), b256, 0, st, W, 0, m, M, k, R, 0, 1.0, 0.0, n);
+    for (int a = 0; a < k; ++a)
+      for (int j = 0; j < k; ++j) mh[(size_t)a * k + j] = a == j ? cd(-w[j], 0.0) : cd(0.0, 0.0);
+    DVCHK(dv_copy(M, mh.data(), (size_t)k * k * 16, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_dv_comb, dim3(nb, k), b256, 0, st, X, 0, k, M, k, R, 0, 1.0, 1.0, n);
+    hipLaunchKernelGGL(k_dv_dots, dim3((unsigned)(k * k)), b256, 0, st, R, 0, R, 0, k, n, G);
+    HIPCHK(hipGetLastError());
+    DVCHK(dv_copy(g.data(), G, (size_t)k * k * 16, hipMemcpyDeviceToHost, st));
+    std::vector<int> open;
+    for (int j = 0; j < k; ++j) {
+      rn[j] = std::sqrt(std::max(0.0, g[(size_t)j * k + j].real()));
+      if (!std::isfinite(rn[j]) || !std::isfinite(w[j])) return MRPT2_ERR_NUMERIC;
+      if (rn[j] > tol) open.push_back(j);
+    }
+    if (open.empty()) {
+      conv = true;
+      break;
+    }
+    if (it == max_iter) break;
+    const int nu = (int)open.size();
+    if (m + nu > mmax) {
+      // restart on the q lowest Ritz vectors (X and R stay valid)
+      const int q = std::min(std::min(m, std::max(2 * k, mmax / 2)), mmax - nu);
+      for (int a = 0; a < m; ++a)
+        for (int j = 0; j < q; ++j) mh[(size_t)a * q + j] = Y[(size_t)a * m + j];
+      DVCHK(dv_copy(M, mh.data(), (size_t)m * q * 16, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_dv_comb, dim3(nb, q), b256, 0, st, V, 0, m, M, q, Vt, 0, 1.0, 0.0, n);
+      hipLaunchKernelGGL(k_dv_comb, dim3(nb, q), b256, 0, st, W, 0, m, M, q, Wt, 0, 1.0, 0.0, n);
+      HIPCHK(hipMemcpyAsync(V, Vt, (size_t)q * n * 16, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(W, Wt, (size_t)q * n * 16, hipMemcpyDeviceToDevice, st));
+      std::fill(S.begin(), S.end(), cd(0.0, 0.0));
+      for (int j = 0; j < q; ++j) S[(size_t)j * mmax + j] = w[j];
+      m = q;
+    }
+    // preconditioned residuals, orthonormalised (two Gram-Schmidt passes)
+    // against the basis and the directions accepted before them
+    std::vector<double> ths(nu);
+    for (int u = 0; u < nu; ++u) ths[u] = w[open[u]];
+    DVCHK(dv_copy(th, ths.data(), (size_t)nu * 8, hipMemcpyHostToDevice, st));
+    int acc = 0;
+    for (int u = 0; u < nu; ++u) {
+      const int row = m + acc;
+      hipLaunchKernelGGL(k_dv_prec, dim3(nb, 1), b256, 0, st, H, R + (size_t)open[u] * n, th + u, V, row, n);
+      hipLaunchKernelGGL(k_dv_dots, dim3(1), b256, 0, st, V, row, V, row, 1, n, G);
+      HIPCHK(hipGetLastError());
+      cd pre;
+      DVCHK(dv_copy(&pre, G, 16, hipMemcpyDeviceToHost, st));
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_dv_dots, dim3((unsigned)row), b256, 0, st, V, 0, V, row, 1, n, G);
+        hipLaunchKernelGGL(k_dv_comb, dim3(nb, 1), b256, 0, st, V, 0, row, G, 1, V, row, -1.0, 1.0, n);
+      }
+      hipLaunchKernelGGL(k_dv_dots, dim3(1), b256, 0, st, V, row, V, row, 1, n, G);
+      HIPCHK(hipGetLastError());
+      cd post;
+      DVCHK(dv_copy(&post, G, 16, hipMemcpyDeviceToHost, st));
+      const double p0 = std::sqrt(std::max(0.0, pre.real())), p1 = std::sqrt(std::max(0.0, post.real()));
+      if (!(p1 > 1e-8 * p0) || !(p1 > 1e-300)) continue;      // no new direction
+      const cd inv(1.0 / p1, 0.0);
+      DVCHK(dv_copy(sc, &inv, 16, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_dv_scale, dim3(nb, 1), b256, 0, st, V, row, sc, n);
+      ++acc;
+    }
+    nnew = acc;
+    m += acc;
+    if (nnew == 0) break;
+  }
+  // Ritz vectors: unit norm, largest component real and positive
+  std::vector<cd> x((size_t)k * n);
+  DVCHK(dv_copy(x.data(), X, x.size() * 16, hipMemcpyDeviceToHost, st));
+  for (int j = 0; j < k; ++j) {
+    cd* v = x.data() + (size_t)j * n;
+    double nrm = 0.0, best = -1.0;
+    int at = 0;
+    for (int i = 0; i < n; ++i) {
+      nrm += std::norm(v[i]);
+      if (std::abs(v[i]) > best) {
+        best = std::abs(v[i]);
+        at = i;
+      }
+    }
+    const cd f = std::conj(v[at]) / (std::abs(v[at]) * std::sqrt(nrm));
+    for (int i = 0; i < n; ++i) v[i] *= f;
+    e_out[j] = w[j];
+  }
+  DVCHK(dv_copy(c_out, x.data(), x.size() * 16, hipMemcpyHostToDevice, st));
+  if (iters) *iters = std::min(it, max_iter);
+  return conv ? MRPT2_OK : MRPT2_ERR_NUMERIC;
+}
+
 mrpt2_status energy_enqueue(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
                             size_t workspace_bytes, hipStream_t st, double* e2, double* parts, Timer& tm) {
   if (!plan || !in || !e2) return MRPT2_ERR_ARG;
@@ -595,6 +806,41 @@ mrpt2_status mrpt2_reference_hamiltonian(mrpt2_plan_t plan, int32_t inst, const 
   s = run(P, P.reference[inst], (const char*)persistent, (char*)workspace, st, tm);
   if (s != MRPT2_OK) return s;
   return read_flag(P, workspace, st);
+}
+
+mrpt2_status mrpt2_reference_states_size(mrpt2_plan_t plan, int32_t inst, int32_t n_states, size_t* bytes) {
+  if (!plan || !bytes || inst < 0 || inst >= (int)plan->p.inst.size() || n_states < 1) return MRPT2_ERR_ARG;
+  const int64_t n = (int64_t)plan->p.inst[inst].pstrings.size();
+  if (n_states > n) return MRPT2_ERR_ARG;
+  *bytes = dv_layout(n, n_states).total;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_reference_states(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in, int32_t n_states,
+                                    double tol, int32_t max_iter, const void* persistent, void* workspace,
+                                    size_t workspace_bytes, void* dv, size_t dv_bytes, hipStream_t st,
+                                    double* c_out, double* e_out, int32_t* iterations) {
+  if (!plan || !in || !dv || !c_out || !e_out || inst < 0 || inst >= (int)plan->p.inst.size() || n_states < 1 ||
+      max_iter < 1 || !(tol > 0.0))
+    return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  const int64_t n = (int64_t)P.inst[inst].pstrings.size();
+  if (n_states > n || n > INT32_MAX / 4) return MRPT2_ERR_ARG;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  const DvLayout L = dv_layout(n, n_states);
+  if (dv_bytes < L.total) return MRPT2_ERR_WORKSPACE;
+  if ((uintptr_t)dv & 255) return MRPT2_ERR_ARG;
+  char* base = (char*)dv;
+  // H_PP - E_core from the Slater-Condon rules (as mrpt2_reference_hamiltonian)
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, nullptr, nullptr, (double*)(base + L.H), inst);
+  if (s != MRPT2_OK) return s;
+  Timer tm;
+  s = run(P, P.reference[inst], (const char*)persistent, (char*)workspace, st, tm);
+  if (s != MRPT2_OK) return s;
+  s = read_flag(P, workspace, st);
+  if (s != MRPT2_OK) return s;
+  return davidson(base, L, n, n_states, tol, max_iter, st, c_out, e_out, iterations);
 }
 
 mrpt2_status mrpt2_plan_class_blocks(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t* n_blocks) {
