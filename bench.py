@@ -397,7 +397,7 @@ def main():
     if args.davidson > 0:
         # reference states: device block Davidson (H_PP assembled and applied
         # on the GPU) against H_PP copied to the host and ARPACK/LAPACK
-        from paper_2608_11529_amd.reference import ground_state as host_ground_state
+        from paper_2608_11529_amd.reference import host_ground_state
         e64 = engs["fp64"]
         dv = {}
         for kk in sorted({1, args.davidson}):
