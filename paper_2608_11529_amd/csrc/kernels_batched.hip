@@ -76,19 +76,20 @@ __global__ void __launch_bounds__(256) k_b_dense_coef(MRPT2_ARGS) {
   MRPT2_JOB
   dense_coef_body(I.d, I.cls[jb.arg], bid);
 }
+template <bool LS>
 __global__ void __launch_bounds__(256) k_b_e22(MRPT2_ARGS) {
   MRPT2_JOB
-  e22_body(I.d, I.cls[0], flag, bid);
+  e22_body<LS>(I.d, I.cls[0], flag, bid);
 }
-template <int MJ>
+template <int MJ, bool LS>
 __global__ void __launch_bounds__(256) k_b_e12(MRPT2_ARGS) {
   MRPT2_JOB
-  e12_body<MJ>(I.d, I.cls[1], flag, bid);
+  e12_body<MJ, LS>(I.d, I.cls[1], flag, bid);
 }
-template <bool F32>
+template <bool F32, bool LS>
 __global__ void __launch_bounds__(256) k_b_e02(MRPT2_ARGS) {
   MRPT2_JOB
-  e02_body<F32>(I.d, I.cls[2], flag, bid);
+  e02_body<F32, LS>(I.d, I.cls[2], flag, bid);
 }
 __global__ void __launch_bounds__(64) k_b_e02coef(MRPT2_ARGS) {
   MRPT2_JOB

@@ -331,6 +331,10 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
 // grid (C(n_c, 2), n_tp), block 256.
 constexpr int AC22 = 64;
 
+// LS: the imaginary level shift of Sec. 2.6, each fraction cw/Delta becoming
+// cw Delta^3 / (Delta^4 + b^2) before the merge (padding strings then take a
+// moderate denominator so that the merged products stay finite).
+template <bool LS>
 __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sYa[AC22][64];
   __shared__ double sYb[AC22][64];
@@ -367,6 +371,8 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
   const int np = d.n_p;
   const double* __restrict__ Uv = cd.Uv;
   const double* __restrict__ Uc = cd.Uc;
+  const double lsb2 = d.ls_b2;
+  (void)lsb2;
   for (int a0 = 0; a0 < np; a0 += AC22) {
     __syncthreads();
     for (int e = tid; e < AC22 * 64; e += 256) {
@@ -387,7 +393,7 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
         sG[tid] = cd.T[s] + Uc[(int64_t)s * nc + c0] + Uc[(int64_t)s * nc + c1] + gconst;
         sCw[tid] = cabs2(d.c[s]);
       } else {
-        sG[tid] = 1e30;   // padding: vanishing weight, harmless denominator
+        sG[tid] = LS ? 1e6 : 1e30;   // padding: vanishing weight, harmless denominator
         sCw[tid] = 0.0;
       }
     }
@@ -419,8 +425,15 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
           for (int k = 0; k < 4; ++k) {
             const double da = (za[i][2 * k] + yb[j][2 * k]) - wab[i][j];
             const double db = (za[i][2 * k + 1] + yb[j][2 * k + 1]) - wab[i][j];
-            n2[k] = fma(cw[2 * k], db, cw[2 * k + 1] * da);
-            q2[k] = da * db;
+            if constexpr (LS) {
+              const double a2 = da * da, b2 = db * db;
+              const double qa = fma(a2, a2, lsb2), qb = fma(b2, b2, lsb2);
+              n2[k] = fma(cw[2 * k] * da * a2, qb, cw[2 * k + 1] * db * b2 * qa);
+              q2[k] = qa * qb;
+            } else {
+              n2[k] = fma(cw[2 * k], db, cw[2 * k + 1] * da);
+              q2[k] = da * db;
+            }
           }
           const double n4a = fma(n2[0], q2[1], n2[1] * q2[0]), q4a = q2[0] * q2[1];
           const double n4b = fma(n2[2], q2[3], n2[3] * q2[2]), q4b = q2[2] * q2[3];
@@ -486,7 +499,7 @@ __device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd
 // reciprocal.  grid (n_c, 16 n_tp), block 256.
 constexpr int SC12 = 64;
 
-template <int MJ>
+template <int MJ, bool LS>
 __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sUa[SC12][16];
   __shared__ double sUb[SC12][16];
@@ -528,6 +541,8 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
   }
   const double epsc = d.eps[c];
   const int64_t S = cd.n_str;
+  const double lsb2 = d.ls_b2;
+  (void)lsb2;
   double acc = 0.0;
   for (int64_t s0 = 0; s0 < S; s0 += SC12) {
     __syncthreads();
@@ -545,7 +560,7 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
     }
     if (tid < SC12) {
       const int64_t s = s0 + tid;
-      sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : 1e30;
+      sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : (LS ? 1e6 : 1e30);
       sM[tid] = (s < S) ? cd.mask[s] : 0u;
     }
     __syncthreads();
@@ -569,6 +584,11 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
       for (int k = 0; k < 4; ++k) {
         w[k] = cabs2(sg[k]);
         dd[k] = (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib];
+        if constexpr (LS) {
+          const double d2 = dd[k] * dd[k];
+          w[k] *= dd[k] * d2;
+          dd[k] = fma(d2, d2, lsb2);
+        }
       }
       const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
       const double q01 = dd[0] * dd[1];
@@ -622,7 +642,7 @@ __device__ __forceinline__ void e02coef_body(const Dev& d, const ClassDev& cd, c
 // the blocks sharing one row of pair integrals run together.  block 256.
 // F32 (mixed form): the contraction on FP32 MFMA with FP64 accumulation per
 // 32-term stage; denominators and sums stay FP64.
-template <bool F32>
+template <bool F32, bool LS>
 __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   constexpr int SH = F32 ? 64 * KP32 : 2 * 64 * KP;   // float2 slots of each staging buffer
   __shared__ __align__(16) float2 sA[SH];
@@ -702,6 +722,11 @@ __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* 
         const double del = (Ts[r] + rowc[j]) - ua[r] - cd.Uv[so[r] + bb[j]];
         w[r] = ok ? accR[i][j][r] * accR[i][j][r] + accI[i][j][r] * accI[i][j][r] : 0.0;
         dd[r] = ok ? del : 1.0;
+        if constexpr (LS) {
+          const double d2 = dd[r] * dd[r];
+          w[r] *= dd[r] * d2;
+          dd[r] = fma(d2, d2, d.ls_b2);
+        }
       }
       const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
       const double q01 = dd[0] * dd[1];

@@ -161,13 +161,13 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.Tb = (double*)(G + cp.off_Tb);
   c.cbe = (double2*)(G + cp.off_cbe);
   c.r1 = (double*)(G + cp.off_r1);
-  c.dbp = cp.kernel == KERN_E12 ? (double2*)(G + cp.off_dbp) : nullptr;
+  c.dbp = cp.kernel_bwd == KERN_E12 ? (double2*)(G + cp.off_dbp) : nullptr;
   c.row_split = cp.row_split;
   c.ecoef = (double2*)(G + cp.off_ecoef);
   c.wpart = (double*)(G + cp.off_wpart);
   c.UvT = (double*)(G + cp.off_UvT);
   c.UcT = (double*)(G + cp.off_UcT);
-  c.wblocks = cp.kernel == KERN_E22 ? (int64_t)cp.parts * ((int64_t)(cp.strings.size() + B22T - 1) / B22T) : 0;
+  c.wblocks = cp.kernel_bwd == KERN_E22 ? (int64_t)cp.parts * ((int64_t)(cp.strings.size() + B22T - 1) / B22T) : 0;
   c.parts = cp.parts;
   c.rows_per_part = cp.rows_per_part;
   return c;
@@ -263,6 +263,7 @@ bool depends_on_c(int kid) {
   switch (kid) {
     case K_SIGP: case K_E0: case K_CTAB: case K_DCOEF: case K_E02COEF: case K_E22:
     case K_E12_8: case K_E12_16: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
+    case K_E22S: case K_E12S_8: case K_E12S_16: case K_E12S_24: case K_E12S_32: case K_E02S: case K_E02FS:
     case K_SIG22: case K_SIG12: case K_SIG02: case K_SIG21: case K_SIG11: case K_SIG01:
     case K_SIG20: case K_SIG10: case K_SIG00: case K_FINISH:
       return true;
@@ -302,13 +303,20 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_CTAB: hipLaunchKernelGGL(k_b_class_tables, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_XBUILD: hipLaunchKernelGGL(k_b_xbuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_DCOEF: hipLaunchKernelGGL(k_b_dense_coef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E22: hipLaunchKernelGGL(k_b_e22, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E12_8: hipLaunchKernelGGL((k_b_e12<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E12_16: hipLaunchKernelGGL((k_b_e12<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E12_24: hipLaunchKernelGGL((k_b_e12<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E12_32: hipLaunchKernelGGL((k_b_e12<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E02: hipLaunchKernelGGL(k_b_e02<false>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_E02F: hipLaunchKernelGGL(k_b_e02<true>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E22: hipLaunchKernelGGL(k_b_e22<false>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_8: hipLaunchKernelGGL((k_b_e12<8, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_16: hipLaunchKernelGGL((k_b_e12<16, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_24: hipLaunchKernelGGL((k_b_e12<24, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_32: hipLaunchKernelGGL((k_b_e12<32, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02: hipLaunchKernelGGL((k_b_e02<false, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02F: hipLaunchKernelGGL((k_b_e02<true, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E22S: hipLaunchKernelGGL(k_b_e22<true>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12S_8: hipLaunchKernelGGL((k_b_e12<8, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12S_16: hipLaunchKernelGGL((k_b_e12<16, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12S_24: hipLaunchKernelGGL((k_b_e12<24, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12S_32: hipLaunchKernelGGL((k_b_e12<32, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02S: hipLaunchKernelGGL((k_b_e02<false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E02FS: hipLaunchKernelGGL((k_b_e02<true, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02COEF: hipLaunchKernelGGL(k_b_e02coef, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG22: hipLaunchKernelGGL((k_b_sigma<2, 2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG12: hipLaunchKernelGGL((k_b_sigma<1, 2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

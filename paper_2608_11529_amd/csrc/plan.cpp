@@ -467,30 +467,39 @@ void build_launches(Plan* P) {
     }
     add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
-    std::vector<JobH> e22, e12[4], e02, e02f, gen;
+    // (index 1 of each pair: the level-shifted variant)
+    std::vector<JobH> e22[2], e12[2][4], e02[2], e02f[2], gen;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
+      const int ls = ip.d.level_shift_b != 0.0 ? 1 : 0;
       if (cp.kernel == KERN_E22) {
-        e22.push_back(job(i, cp.n_holes, ip.n_tp, k));
+        e22[ls].push_back(job(i, cp.n_holes, ip.n_tp, k));
       } else if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
-        e12[v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
+        e12[ls][v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
       } else if (cp.kernel == KERN_E02) {
-        (ip.d.precision == MRPT2_MIXED ? e02f : e02).push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
+        (ip.d.precision == MRPT2_MIXED ? e02f[ls] : e02[ls]).push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
       } else {
         gen.push_back(job(i, sigma_blocks(ip, k), 1, k));
       }
     }
-    add_launch(P, seq, K_E22, ST_SIGMA0 + k, e22);
-    add_launch(P, seq, K_E12_8, ST_SIGMA0 + k, e12[0]);
-    add_launch(P, seq, K_E12_16, ST_SIGMA0 + k, e12[1]);
-    add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[2]);
-    add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[3]);
-    add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02);
-    add_launch(P, seq, K_E02F, ST_SIGMA0 + k, e02f);
+    add_launch(P, seq, K_E22, ST_SIGMA0 + k, e22[0]);
+    add_launch(P, seq, K_E12_8, ST_SIGMA0 + k, e12[0][0]);
+    add_launch(P, seq, K_E12_16, ST_SIGMA0 + k, e12[0][1]);
+    add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[0][2]);
+    add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[0][3]);
+    add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02[0]);
+    add_launch(P, seq, K_E02F, ST_SIGMA0 + k, e02f[0]);
+    add_launch(P, seq, K_E22S, ST_SIGMA0 + k, e22[1]);
+    add_launch(P, seq, K_E12S_8, ST_SIGMA0 + k, e12[1][0]);
+    add_launch(P, seq, K_E12S_16, ST_SIGMA0 + k, e12[1][1]);
+    add_launch(P, seq, K_E12S_24, ST_SIGMA0 + k, e12[1][2]);
+    add_launch(P, seq, K_E12S_32, ST_SIGMA0 + k, e12[1][3]);
+    add_launch(P, seq, K_E02S, ST_SIGMA0 + k, e02[1]);
+    add_launch(P, seq, K_E02FS, ST_SIGMA0 + k, e02f[1]);
     add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
   }
   js.clear();
@@ -523,19 +532,19 @@ void build_launches(Plan* P) {
       if (cp.strings.empty() || cp.n_rows == 0) continue;
       // string tables transposed for the generic string-owned pass of the
       // one-virtual classes (arg 2 k: Uv, 2 k + 1: Uc)
-      if (cp.kernel == KERN_GENERIC && cp.v <= 1) {
+      if (cp.kernel_bwd == KERN_GENERIC && cp.v <= 1) {
         const int64_t sb = cdiv64((int64_t)cp.strings.size(), 32);
         if (cp.v >= 1) jt.push_back(job(i, sb, cdiv64(ip.n_v, 32), 2 * k));
         if (cp.h >= 1) jt.push_back(job(i, sb, cdiv64(ip.n_c, 32), 2 * k + 1));
       }
-      if (cp.kernel == KERN_E22) {
+      if (cp.kernel_bwd == KERN_E22) {
         j22a.push_back(job(i, cp.n_holes, ip.n_tp, k));
         j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 128), cp.parts, k));
 
         j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
         continue;
       }
-      if (cp.kernel == KERN_E12) {
+      if (cp.kernel_bwd == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         const int vs = (J > 16 && J <= 20) ? 4 : v;
@@ -566,7 +575,7 @@ void build_launches(Plan* P) {
     for (int i : all) {
       const ClassPlan& cp = P->inst[i].cls[k];
       if (cp.strings.empty() || cp.n_rows == 0) continue;
-      if (cp.kernel == KERN_E22) j22.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
+      if (cp.kernel_bwd == KERN_E22) j22.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
       else js.push_back(job(i, cdiv64(std::max<int64_t>((int64_t)cp.strings.size(), cp.n_conn), 256), 1, k));
     }
     add_launch(P, seq, K_B22FIN, ST_BFIN, j22);
@@ -955,21 +964,23 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_Uc = W.take(cp.h > 0 ? S * ip.n_c * 8 : 0);
       cp.off_Uv = W.take(cp.v > 0 ? S * ip.n_v * 8 : 0);
       cp.off_X = W.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
-      // a level shift changes every denominator epilogue; only the generic
-      // kernels carry the shifted weight, so they take every class then
+      // a level shift changes every denominator: the dedicated forward
+      // kernels have shifted variants, the adjoint then runs on the generic
+      // passes (the only ones that carry the shifted weight's derivative)
       const bool shifted = ip.d.level_shift_b != 0.0;
-      cp.dense_coef = !shifted && (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
+      cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
       cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
       // kernel choice and partial-sum blocks: the dedicated kernels' grids
       // ((2,2): tile pair x core pair; (1,2): 16 sub-tiles per tile pair x
       // core; (0,2): string tile x 64 rows of a tile pair) or the generic kernel's
       cp.kernel = KERN_GENERIC;
-      if (S && cp.n_rows > 0 && !shifted) {
+      if (S && cp.n_rows > 0) {
         if (k == 0) cp.kernel = KERN_E22;
         else if (k == 1 && cp.dense_coef) cp.kernel = KERN_E12;
         else if (k == 2 && cp.n_tiles > 0) cp.kernel = KERN_E02;
       }
+      cp.kernel_bwd = shifted ? KERN_GENERIC : cp.kernel;
       cp.off_Md = W.take(cp.kernel == KERN_E02 ? (size_t)kStrTile * cp.tile_k0.back() * 16 : 0);
       cp.n_blocks = (cp.kernel == KERN_E22)   ? ip.n_tp * cp.n_holes
                     : (cp.kernel == KERN_E12) ? ip.n_tp * 16 * cp.n_holes
@@ -1000,14 +1011,14 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.rows_per_part = std::max<int64_t>(cp.n_rows, 1);
       cp.row_split = 1;
       const int64_t bt = cp.bwd_target > 0 ? cp.bwd_target : 2048;
-      if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E22) {
+      if (S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_E22) {
         // (2,2) string-owned adjoint kernel (128 strings per block): parts = groups of core pairs
         const int64_t sblk = (S + 127) / 128;
         int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (bt + sblk - 1) / sblk));
         const int64_t grp = (cp.n_holes + parts - 1) / parts;
         cp.rows_per_part = grp;
         cp.parts = (int)((cp.n_holes + grp - 1) / grp);
-      } else if (S > 0 && cp.n_rows > 0 && cp.kernel == KERN_E12) {
+      } else if (S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_E12) {
         // (1,2) string pass: parts = core x group of tile pairs
         const int64_t sblk = (S + 255) / 256;
         int64_t ngr = std::min<int64_t>(ip.n_tp, std::max<int64_t>(1, (bt + sblk * cp.n_holes - 1) / (sblk * cp.n_holes)));
@@ -1030,7 +1041,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
       cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);
-      const bool b22 = cp.kernel == KERN_E22, b12 = cp.kernel == KERN_E12;
+      const bool b22 = cp.kernel_bwd == KERN_E22, b12 = cp.kernel_bwd == KERN_E12;
       cp.off_cbe = Gw.take((b22 || b12) ? 0 : (size_t)cp.parts * cp.n_conn * 16);
       cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
@@ -1038,7 +1049,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + 127) / 128) * ip.n_v * ip.n_a * 8 : 0);
       // string tables transposed for the generic string-owned pass of the
       // one-virtual classes (lanes = strings)
-      const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel == KERN_GENERIC && cp.v <= 1;
+      const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_GENERIC && cp.v <= 1;
       cp.off_UvT = Gw.take((pass && cp.v >= 1) ? (size_t)S * ip.n_v * 8 : 0);
       cp.off_UcT = Gw.take((pass && cp.h >= 1) ? (size_t)S * ip.n_c * 8 : 0);
     }

@@ -63,7 +63,8 @@ struct ClassPlan {
   std::vector<int32_t> ccol;           // per coupling: its column in the support of the string's tile
   int64_t n_tiles = 0;
   size_t off_tile_s0 = 0, off_tile_k0 = 0, off_tile_sup = 0, off_ccol = 0, off_Md = 0;
-  int kernel = 0;                      // KERN_* below
+  int kernel = 0;                      // KERN_* below (sigma contraction)
+  int kernel_bwd = 0;                  // KERN_* of the adjoint passes (generic under a level shift)
   // launch-shape targets (mrpt2_tuning; 0 = built-in rule)
   int64_t sigma_target = 0, bwd_target = 0, bwd_row_target = 0;
   int64_t n_blocks = 0;                // partial sums written by the class's kernel
@@ -108,7 +109,7 @@ struct InstancePlan {
 enum KernelId : int {
   K_CLEAR, K_PACK, K_DIAG, K_WPASS, K_EPS, K_DSUM, K_FOCK, K_GBUILD, K_HPP, K_SIGP, K_E0,
   K_ABUILD, K_ABUILD32, K_CTAB, K_XBUILD, K_DCOEF, K_E22, K_E12_8, K_E12_16, K_E12_24, K_E12_32,
-  K_E02, K_E02F, K_E02COEF, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
+  K_E02, K_E02F, K_E02COEF, K_E22S, K_E12S_8, K_E12S_16, K_E12S_24, K_E12S_32, K_E02S, K_E02FS, K_SIG22, K_SIG12, K_SIG02, K_SIG21, K_SIG11, K_SIG01, K_SIG20, K_SIG10, K_SIG00, K_FINISH,
   // adjoint
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
