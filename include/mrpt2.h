@@ -87,9 +87,9 @@ typedef struct {
                                        becomes Re 1/(Delta + i b/Delta) =
                                        Delta^3/(Delta^4 + b^2), in E2 and in
                                        its gradient; only b^2 enters.  0 gives
-                                       eq. pt2 exactly.  A nonzero b runs every
-                                       excitation class on the generic sigma
-                                       and adjoint kernels (slower). */
+                                       eq. pt2 exactly.  A nonzero b runs the
+                                       adjoint of every excitation class on the
+                                       generic passes (slower). */
 } mrpt2_desc;
 
 /* Sizes and exact algorithmic work of one instance. */
