@@ -215,8 +215,7 @@ constexpr int SIG_THREADS = 256;
 //         = T[s] + sum_{c in holes} (eps_c + Uc[s][c]) - sum_{a in virt} (eps_a + Uv[s][a])
 //           - W_cc' - W_ab + sum_{c, a} W_ca
 //   partial += |sigma|^2 g(Delta)   (divided by ||C||^2 at the end)
-// with g = 1/Delta, or its level-shifted form (en_weight).  This kernel
-// serves every class when a level shift is set.
+// with g = 1/Delta, or its level-shifted form (en_weight).
 // One thread per row, a chunk of strings per block.  grid (rb * nsc).
 template <int H, int V>
 __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {

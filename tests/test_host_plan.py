@@ -96,7 +96,7 @@ def test_plan_rejects_bad_descriptors(field, value, code):
     assert ei.value.code == code
 
 
-def test_level_shift_plans_every_class_on_the_generic_kernels():
+def test_level_shift_keeps_the_external_space():
     """A nonzero level shift is accepted and changes neither the external
     space nor its counts (the shift acts on the denominators only)."""
     M = lib_module()
