@@ -76,8 +76,9 @@ __global__ void __launch_bounds__(256) k_b_dense_coef(MRPT2_ARGS) {
   MRPT2_JOB
   dense_coef_body(I.d, I.cls[jb.arg], bid);
 }
+// three waves per SIMD: 168 VGPRs (a few spills) beat two waves at 176
 template <bool LS>
-__global__ void __launch_bounds__(256) k_b_e22(MRPT2_ARGS) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_b_e22(MRPT2_ARGS) {
   MRPT2_JOB
   e22_body<LS>(I.d, I.cls[0], flag, bid);
 }

@@ -324,21 +324,24 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
 //   G = T(alpha) + eps_c + Uc_c(alpha) + eps_c' + Uc_c'(alpha) - W_cc',
 //   Y_a = -eps_a - Uv_a(alpha) + W_ca + W_c'a.
 // Pure FP64 vector work: each thread owns a 4 x 4 block of (a, b) of a
-// 64 x 64 tile and walks alpha eight at a time, merging the eight fractions
-// c1/d1 + ... + c8/d8 into one numerator and denominator (pairwise products)
-// so that a single reciprocal serves eight determinants.
+// 64 x 64 tile and walks alpha four at a time, merging the four fractions
+// c1/d1 + ... + c4/d4 into one numerator and denominator (pairwise products)
+// so that a single reciprocal serves four determinants.  Merging four rather
+// than eight keeps the kernel within 168 VGPRs and, with 32-string LDS
+// chunks, at three waves per SIMD, which outweighs the extra reciprocals.
 // grid (C(n_c, 2), n_tp), block 256.
-constexpr int AC22 = 64;
+constexpr int AC22 = 64;            // strings per LDS chunk of the (2,2) adjoint kernels
+constexpr int E22C = 32;            // strings per LDS chunk of e22 (36 KB: three blocks per CU)
 
 // LS: the imaginary level shift of Sec. 2.6, each fraction cw/Delta becoming
 // cw Delta^3 / (Delta^4 + b^2) before the merge (padding strings then take a
 // moderate denominator so that the merged products stay finite).
 template <bool LS>
 __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
-  __shared__ double sYa[AC22][64];
-  __shared__ double sYb[AC22][64];
-  __shared__ double sG[AC22];
-  __shared__ double sCw[AC22];
+  __shared__ double sYa[E22C][64];
+  __shared__ double sYb[E22C][64];
+  __shared__ double sG[E22C];
+  __shared__ double sCw[E22C];
   __shared__ double ya0[64], yb0[64];
   __shared__ double red[256];
   const int hp = bid.x, tp = bid.y;   // core pairs fastest: blocks of one tile pair share its tables in L2
@@ -372,9 +375,9 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
   const double* __restrict__ Uc = cd.Uc;
   const double lsb2 = d.ls_b2;
   (void)lsb2;
-  for (int a0 = 0; a0 < np; a0 += AC22) {
+  for (int a0 = 0; a0 < np; a0 += E22C) {
     __syncthreads();
-    for (int e = tid; e < AC22 * 64; e += 256) {
+    for (int e = tid; e < E22C * 64; e += 256) {
       const int al = e >> 6, l = e & 63;
       const int s = a0 + al;
       const int a = I * 64 + l, b = J * 64 + l;
@@ -386,7 +389,7 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
       sYa[al][l] = ya;
       sYb[al][l] = yb;
     }
-    if (tid < AC22) {
+    if (tid < E22C) {
       const int s = a0 + tid;
       if (s < np) {
         sG[tid] = cd.T[s] + Uc[(int64_t)s * nc + c0] + Uc[(int64_t)s * nc + c1] + gconst;
@@ -398,30 +401,30 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
     }
     __syncthreads();
 #pragma unroll 1
-    for (int al = 0; al < AC22; al += 8) {
-      double g[8], cw[8], za[4][8], yb[4][8];
+    for (int al = 0; al < E22C; al += 4) {
+      double g[4], cw[4], za[4][4], yb[4][4];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < 4; ++k) {
         g[k] = sG[al + k];
         cw[k] = sCw[al + k];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) za[i][k] = g[k] + sYa[al + k][ta + 16 * i];
+        for (int k = 0; k < 4; ++k) za[i][k] = g[k] + sYa[al + k][ta + 16 * i];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
+        for (int k = 0; k < 4; ++k) yb[j][k] = sYb[al + k][tb + 16 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          // sum_k cw_k / d_k over eight strings as one fraction: pairwise
+          // sum_k cw_k / d_k over four strings as one fraction: pairwise
           // numerators and denominators, one reciprocal
-          double n2[4], q2[4];
+          double n2[2], q2[2];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < 2; ++k) {
             const double da = (za[i][2 * k] + yb[j][2 * k]) - wab[i][j];
             const double db = (za[i][2 * k + 1] + yb[j][2 * k + 1]) - wab[i][j];
             if constexpr (LS) {
@@ -434,11 +437,8 @@ __device__ __forceinline__ void e22_body(const Dev& d, const ClassDev& cd, int* 
               q2[k] = da * db;
             }
           }
-          const double n4a = fma(n2[0], q2[1], n2[1] * q2[0]), q4a = q2[0] * q2[1];
-          const double n4b = fma(n2[2], q2[3], n2[3] * q2[2]), q4b = q2[2] * q2[3];
-          const double num = fma(n4a, q4b, n4b * q4a);
-          const double den = q4a * q4b;
-          acc[i][j] = fma(num, rcp_nr(den), acc[i][j]);
+          const double num = fma(n2[0], q2[1], n2[1] * q2[0]);
+          acc[i][j] = fma(num, rcp_nr(q2[0] * q2[1]), acc[i][j]);
         }
     }
   }
