@@ -29,7 +29,7 @@ HBM_PEAK = 8.0e12              # B/s
 # HBM bytes per launch of k_b_e22 at c4 from rocprofv3 FETCH_SIZE (calibrated
 # against a device copy, profiles/k_e22_c4_hbm_counters.md) plus its written
 # partial sums; valid for the kernel as measured there
-E22_C4_HBM_BYTES = 2.0 * 18.58e6 * 1024 + 378 * 171 * 8
+E22_C4_HBM_BYTES = 2.0 * 18.32e6 * 1024 + 378 * 171 * 8
 
 
 def cpu_baseline(pb, seconds=15.0):
