@@ -452,6 +452,9 @@ mrpt2_status dv_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kin
 // The k lowest eigenpairs of the n x n Hermitian matrix at L.H (already in
 // place).  Returns MRPT2_ERR_NUMERIC when max_iter iterations leave a
 // residual norm above tol (the current Ritz pairs are still written).
+// With n > mmax = max(6k, 30), a restart keeps q >= 2k Ritz vectors (the
+// restart happens at m > mmax - k >= 5k), so the basis never holds fewer
+// than k vectors.
 mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double tol, int max_iter,
                       hipStream_t st, double* c_out, double* e_out, int32_t* iters) {
   using cd = std::complex<double>;
@@ -477,12 +480,15 @@ mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double 
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  // a space that fits in the basis starts complete (the first Rayleigh-Ritz
+  // step is then exact and no restart can shrink the basis below k vectors)
+  const int m0 = n <= mmax ? n : k;
   {
-    std::vector<cd> v0((size_t)k * n, cd(0.0, 0.0));
-    for (int j = 0; j < k; ++j) v0[(size_t)j * n + idx[j]] = 1.0;
+    std::vector<cd> v0((size_t)m0 * n, cd(0.0, 0.0));
+    for (int j = 0; j < m0; ++j) v0[(size_t)j * n + idx[j]] = 1.0;
     DVCHK(dv_copy(V, v0.data(), v0.size() * 16, hipMemcpyHostToDevice, st));
   }
-  int m = k, nnew = k;
+  int m = m0, nnew = m0;
   std::vector<cd> S((size_t)mmax * mmax, cd(0.0, 0.0)), g((size_t)mmax * mmax), Y((size_t)mmax * mmax),
       mh((size_t)mmax * mmax);
   std::vector<double> w(mmax), rn(k);

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name,k", [("s_das", 3), ("s_fc", 2), ("s_single", 1), ("s_tiles", 3), ("c0", 4),
-                                    ("c0", 20), ("c1", 3)])
+                                    ("c0", 12), ("c0", 20), ("c1", 3)])
 def test_davidson_matches_dense_eigh(name, k):
     import paper_2608_11529_amd as M
     pb = problem(name)
