@@ -285,7 +285,7 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (N=%d requested); the multi-GPU "
+        print("bench.py: the library runs on one GPU only (N=%d requested); the multi-GPU "
               "decomposition is a design note, not an implementation" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np  # noqa: F401
