@@ -83,3 +83,61 @@ def test_level_shift_gradient_matches_oracle(name, b):
         assert ok, (name, "dB", t, err, sc)
     ok, err, sc = close(dc.cpu().numpy(), to_plan_order(dc_o, P_o, plan.ref_strings(), pb.n_c))
     assert ok, (name, "dc", err, sc)
+
+
+def test_level_shift_mixed_with_unshifted_instances_in_one_plan():
+    """One batched plan holding an unshifted and a shifted instance (each
+    instance takes its own kernel variants and adjoint passes): energies and
+    gradients equal the single-instance calls, energies match the oracle."""
+    import paper_2608_11529_amd as M
+    cases = [("s_das", 0.0), ("s_fc", 2.0), ("s_tiles", 0.5)]
+    got = [shifted_oracle(nm, b) for nm, b in cases]
+    plan = M.Plan([M.desc_of_problem(g[0], level_shift_b=b) for g, (_, b) in zip(got, cases)])
+    eng = M.Engine(plan)
+    insts = []
+    for i, (g, (nm, b)) in enumerate(zip(got, cases)):
+        pb, _, c_o, P_o = g
+        import torch
+        c = torch.from_numpy(np.ascontiguousarray(to_plan_order(c_o, P_o, plan.ref_strings(i), pb.n_c)))
+        insts.append((SP.one_body(pb).to(eng.device), [B.to(eng.device) for B in SP.factors(pb)],
+                      c.to(eng.device)))
+    print("[gpu] level shift: mixed batch", flush=True)
+    e2 = eng.energy(insts, parts=False).cpu().numpy().copy()
+    outs = eng.backward(insts)[0]
+    for i, (g, (nm, b)) in enumerate(zip(got, cases)):
+        pb, parts_o, _, _ = g
+        assert abs(e2[i] - math.fsum(parts_o.values())) <= 1e-9, (nm, b)
+        p1, e1, h, Bs, c = gpu_setup(pb, b, g[2], g[3])
+        assert float(e1.energy([(h, Bs, c)], parts=False)[0].item()) == e2[i]
+        (dh1, dB1, dc1), = e1.backward([(h, Bs, c)])[0]
+        dh, dB, dc = outs[i]
+        ok, err, sc = close(dh.cpu().numpy(), dh1.cpu().numpy(), rel=1e-12)
+        assert ok, (nm, "dh", err, sc)
+        ok, err, sc = close(dc.cpu().numpy(), dc1.cpu().numpy(), rel=1e-12)
+        assert ok, (nm, "dc", err, sc)
+
+
+def test_level_shift_with_several_states():
+    """E2_m of two reference states under the shift in one call equals the
+    oracle with each state as reference."""
+    import torch
+    import paper_2608_11529_amd as M
+    b = 2.0
+    pb = problem("s_das")
+    h, Bs = SP.one_body(pb).numpy(), [B.numpy() for B in SP.factors(pb)]
+    co = run.class_oracle(pb, h, Bs, SP.weights(pb))
+    H, _ = co.reference(np.ones(len(co.P), dtype=np.complex128))
+    w, v = np.linalg.eigh(H)
+    plan = M.Plan(M.desc_of_problem(pb, level_shift_b=b))
+    eng = M.Engine(plan)
+    cs = []
+    for j in range(2):
+        c = v[:, j] * (abs(v[np.argmax(np.abs(v[:, j])), j]) / v[np.argmax(np.abs(v[:, j])), j])
+        cs.append(c)
+    C = np.stack([to_plan_order(c, co.P, plan.ref_strings(), pb.n_c) for c in cs])
+    print("[gpu] level shift: two states", flush=True)
+    e2, _ = eng.energy_roots([(torch.from_numpy(h).to(eng.device), [torch.from_numpy(x).to(eng.device) for x in Bs],
+                               torch.from_numpy(np.ascontiguousarray(C)).to(eng.device))])
+    for j in range(2):
+        parts, _ = co.e2(cs[j], b=b)
+        assert abs(float(e2[j, 0]) - math.fsum(parts.values())) <= 1e-9, j
