@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(256) k_b_abuild(MRPT2_ARGS) {
   MRPT2_JOB
   abuild_body(I.d, bid);
 }
-__global__ void __launch_bounds__(256) k_b_abuild_f32(MRPT2_ARGS) {
+// two waves per SIMD (252 VGPRs, no AGPR accumulators) instead of one
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_b_abuild_f32(MRPT2_ARGS) {
   MRPT2_JOB
   abuild_f32_body(I.d, bid);
 }

@@ -290,12 +290,19 @@ constexpr int KP32 = KC32 + 1;
 // result D[i][j] sits in lane j + 16 (i/4), register i%4.  Products and the
 // sums over one stage (KC32 complex k) are FP32; every stage's partial sums
 // are added into FP64 accumulators, so the FP32 rounding of a sum grows
-// with the stage length only.  The loaders return two complex FP32 operands
-// (k, k+1) for even k: each stage's loads are issued two stages ahead and
-// complete behind the MFMAs of the stages in between.
+// with the stage length only.
+//
+// Complex FP32 GEMM with three real products per complex product (Gauss):
+// P1 = sum a_re b_re, P2 = sum a_im b_im, P3 = sum (a_re + a_im)(b_re + b_im)
+// over a stage, Re = P1 - P2 and Im = P3 - P1 - P2 formed in FP64 when each
+// stage's partial sums are carried; a quarter fewer MFMAs than the four-product
+// form.  The operands are staged as three real planes (re, im, re + im) per
+// matrix, four complex k per MFMA.  The loaders return two complex FP32
+// operands (k, k+1) for even k; each stage's loads are issued two stages
+// ahead and complete behind the MFMAs of the stages in between.
 template <class FA, class FB>
-__device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, float2* sB,
-                                            double (&accR)[2][2][4], double (&accI)[2][2][4]) {
+__device__ __forceinline__ void cgemm64_f32_3m(FA fa, FB fb, int K, float* sA, float* sB,
+                                               double (&accR)[2][2][4], double (&accI)[2][2][4]) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
 #pragma unroll
@@ -307,11 +314,9 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
         accR[i][j][r] = 0.0;
         accI[i][j][r] = 0.0;
       }
-  const int kq = lane >> 4;
-  const int kcl = kq >> 1, comp = kq & 1;
   constexpr int HP = KC32 / 2;                // operand pairs per staged row
   constexpr int PER = 64 * HP / 256;          // pairs per thread and operand
-  // two register sets: the loads of a stage are issued two stages ahead
+  constexpr int PL = 64 * KP32;               // floats of one plane
   float4 ra0[PER], rb0[PER], ra1[PER], rb1[PER];
   auto fetch = [&](float4 (&ra)[PER], float4 (&rb)[PER], int k0) {
 #pragma unroll
@@ -327,42 +332,48 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
       const int o = (e / HP) * KP32 + 2 * (e % HP);
-      sA[o] = make_float2(ra[u].x, ra[u].y);
-      sA[o + 1] = make_float2(ra[u].z, ra[u].w);
-      sB[o] = make_float2(rb[u].x, rb[u].y);
-      sB[o + 1] = make_float2(rb[u].z, rb[u].w);
+      sA[o] = ra[u].x;
+      sA[o + 1] = ra[u].z;
+      sA[PL + o] = ra[u].y;
+      sA[PL + o + 1] = ra[u].w;
+      sA[2 * PL + o] = ra[u].x + ra[u].y;
+      sA[2 * PL + o + 1] = ra[u].z + ra[u].w;
+      sB[o] = rb[u].x;
+      sB[o + 1] = rb[u].z;
+      sB[PL + o] = rb[u].y;
+      sB[PL + o + 1] = rb[u].w;
+      sB[2 * PL + o] = rb[u].x + rb[u].y;
+      sB[2 * PL + o + 1] = rb[u].z + rb[u].w;
     }
     __syncthreads();
     if (k0 + 2 * KC32 < K) fetch(ra, rb, k0 + 2 * KC32);
-    f4 pR[2][2], pI[2][2];
+    f4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        pR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        pI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        p1[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        p2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        p3[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
-#pragma unroll 4
-    for (int ks = 0; ks < KC32; ks += 2) {
-      const int kc = ks + kcl;
-      float ar[2], ai[2], bb[2];
+#pragma unroll 1
+    for (int ks = 0; ks < KC32; ks += 4) {
+      const int kc = ks + (lane >> 4);
+      float a[3][2], b[3][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float2 v = sA[(wr + i * 16 + (lane & 15)) * KP32 + kc];
-        ar[i] = comp ? -v.y : v.x;
-        ai[i] = comp ? v.x : v.y;
-      }
+      for (int q = 0; q < 3; ++q) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float2 v = sB[(wc + j * 16 + (lane & 15)) * KP32 + kc];
-        bb[j] = comp ? v.y : v.x;
+        for (int i = 0; i < 2; ++i) a[q][i] = sA[q * PL + (wr + i * 16 + (lane & 15)) * KP32 + kc];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[q][j] = sB[q * PL + (wc + j * 16 + (lane & 15)) * KP32 + kc];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          pR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bb[j], pR[i][j], 0, 0, 0);
-          pI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bb[j], pI[i][j], 0, 0, 0);
+          p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][i], b[0][j], p1[i][j], 0, 0, 0);
+          p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1][i], b[1][j], p2[i][j], 0, 0, 0);
+          p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2][i], b[2][j], p3[i][j], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -371,8 +382,9 @@ __device__ __forceinline__ void cgemm64_f32(FA fa, FB fb, int K, float2* sA, flo
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          accR[i][j][r] += (double)pR[i][j][r];
-          accI[i][j][r] += (double)pI[i][j][r];
+          const double x1 = (double)p1[i][j][r], x2 = (double)p2[i][j][r];
+          accR[i][j][r] += x1 - x2;
+          accI[i][j][r] += ((double)p3[i][j][r] - x1) - x2;
         }
     __syncthreads();
   };
@@ -389,10 +401,11 @@ __device__ __forceinline__ int acc_row_f32(int i, int r) {
   return (wv >> 1) * 32 + i * 16 + 4 * (lane >> 4) + r;
 }
 
-// The same FP32-MFMA product for FP64 operands given element by element:
-// each is rounded to FP32 when staged (b with c fastest across threads), the
-// sums over one stage of KC32 complex k are FP32 and are added into FP64
-// accumulators.  Result layout of cgemm64_f32 (acc_row_f32, acc_col).
+// Complex FP32-MFMA product (four real products per complex product) for
+// FP64 operands given element by element: each is rounded to FP32 when
+// staged (b with c fastest across threads), the sums over one stage of KC32
+// complex k are FP32 and are added into FP64 accumulators.  Result layout
+// acc_row_f32, acc_col.
 template <class FA, class FB>
 __device__ __forceinline__ void cgemm64_f32c(FA fa, FB fb, int K, float2* sA, float2* sB,
                                              double (&accR)[2][2][4], double (&accI)[2][2][4]) {
@@ -468,8 +481,8 @@ __device__ __forceinline__ void cgemm64_f32c(FA fa, FB fb, int K, float2* sA, fl
 // Mixed-precision form of k_abuild: the same integrals and output layout,
 // from the FP32 slab.
 __device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {
-  __shared__ float2 sA[64 * KP32];
-  __shared__ float2 sB[64 * KP32];
+  __shared__ float sA[3 * 64 * KP32];
+  __shared__ float sB[3 * 64 * KP32];
   const int64_t tp = bid.x;
   int64_t pr = bid.y;
   int xo = 0;
@@ -502,7 +515,7 @@ __device__ __forceinline__ void abuild_f32_body(const Dev& d, const uint3 bid) {
     return make_float4(-v.x, -v.y, -v.z, -v.w);
   };
   double accR[2][2][4], accI[2][2][4];
-  cgemm64_f32(fa, fb, 2 * nl2, sA, sB, accR, accI);
+  cgemm64_f32_3m(fa, fb, 2 * nl2, sA, sB, accR, accI);
   double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
