@@ -210,11 +210,14 @@ mrpt2_status mrpt2_energy_roots(mrpt2_plan_t plan, const mrpt2_inputs* in, int32
  * host-to-device copy of the instance descriptors from library-owned pinned
  * memory, then one batched launch per stage covering all instances) is
  * enqueued on `stream`, so the call can be captured into a HIP graph and
- * replayed.  Replays reuse the descriptors of the captured call (same input
- * and output pointers).  The device error flag stays in the workspace; read
- * it with mrpt2_check.  Two asynchronous calls with different inputs on one
- * plan must be separated by a stream synchronisation (they share the pinned
- * descriptor buffer). */
+ * replayed.  Replays re-copy the descriptors staged by the captured call
+ * (same input and output pointers); any later call on the same plan restages
+ * them, so a plan whose calls are captured should be reserved for that graph,
+ * and make one ordinary call before the capture (the staging buffer is
+ * allocated on a plan's first call).  The device error flag stays in the
+ * workspace; read it with mrpt2_check.  Two asynchronous calls with different
+ * inputs on one plan must be separated by a stream synchronisation (they
+ * share the pinned descriptor buffer). */
 mrpt2_status mrpt2_energy_async(mrpt2_plan_t plan, const mrpt2_inputs* in,
                                 const void* persistent, void* workspace, size_t workspace_bytes,
                                 hipStream_t stream, double* e2, double* parts);
@@ -309,6 +312,16 @@ mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, co
                                    void* workspace, size_t workspace_bytes, void* grad_workspace,
                                    size_t grad_workspace_bytes, const double* grad_e2,
                                    const mrpt2_grads* grads, hipStream_t stream, double* e2);
+
+/* mrpt2_energy_backward without its final synchronisation: the descriptor
+ * copy and every launch (the forward recomputation included) are enqueued on
+ * `stream`, so one captured HIP graph holds the forward pass and the adjoint
+ * of every instance.  The capture rules of mrpt2_energy_async apply; read the
+ * error flag with mrpt2_check. */
+mrpt2_status mrpt2_energy_backward_async(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                         void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                         size_t grad_workspace_bytes, const double* grad_e2,
+                                         const mrpt2_grads* grads, hipStream_t stream, double* e2);
 
 /* mrpt2_energy_backward with its stages timed by HIP events on `stream`:
  * stage_ms (host, 49 floats) receives milliseconds per stage: 0..22 as in

@@ -216,12 +216,16 @@ class Engine:
         del keep
         return self.e2, self.parts, dict(zip(capi.STAGES, list(ms)))
 
-    def backward(self, insts, grad_e2=None, timed=False):
+    def backward(self, insts, grad_e2=None, timed=False, asynchronous=False, stream=None):
         """Gradients of E2 for every instance: list of (dh, [dB_t], dc)
         complex128 device tensors (dh, dB Hermitian-projected), and the
         device tensor of E2 per instance.  grad_e2: device float64 [n_inst]
         upstream gradients (ones when None).  The gradient workspace is
-        allocated on first use and kept."""
+        allocated on first use and kept.  asynchronous=True enqueues the
+        whole call on `stream` without synchronising (capturable in a HIP
+        graph with the forward recomputation; read the flag with check());
+        the inputs, grad_e2 and the returned tensors must then stay alive
+        until it has run."""
         torch = self.torch
         if getattr(self, "grad_workspace", None) is None:
             self.grad_workspace = torch.empty(max(self.plan.grad_bytes, 256), dtype=torch.uint8,
@@ -241,9 +245,14 @@ class Engine:
                 garr[i].dB[t] = dB.data_ptr()
             garr[i].dc = dc.data_ptr()
             outs.append((dh, dBs, dc))
+        sptr = ctypes.c_void_p((stream or self.stream).cuda_stream) if asynchronous else self._sptr()
         args = (self.plan.handle, arr, self.persistent.data_ptr(), self.workspace.data_ptr(),
                 self.plan.workspace_bytes, self.grad_workspace.data_ptr(), self.plan.grad_bytes,
-                grad_e2.data_ptr(), garr, self._sptr(), self.e2.data_ptr())
+                grad_e2.data_ptr(), garr, sptr, self.e2.data_ptr())
+        if asynchronous:
+            capi.check(capi.lib().mrpt2_energy_backward_async(*args), "mrpt2_energy_backward_async")
+            self._keep = (keep, grad_e2)
+            return outs, self.e2
         if timed:
             ms = (ctypes.c_float * capi.N_STAGE_B)()
             capi.check(capi.lib().mrpt2_energy_backward_timed(*args, ms), "mrpt2_energy_backward_timed")

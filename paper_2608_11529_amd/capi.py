@@ -169,6 +169,8 @@ def lib():
         L.mrpt2_energy_backward.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp,
                                             ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp]
         L.mrpt2_energy_backward.restype = st
+        L.mrpt2_energy_backward_async.argtypes = L.mrpt2_energy_backward.argtypes
+        L.mrpt2_energy_backward_async.restype = st
         L.mrpt2_energy_backward_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp,
                                                   ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp,
                                                   ctypes.POINTER(ctypes.c_float)]
@@ -189,7 +191,7 @@ def check(code, where):
 EXPORTED = [
     "mrpt2_plan", "mrpt2_plan_sizes", "mrpt2_plan_upload", "mrpt2_plan_info",
     "mrpt2_plan_ref_strings", "mrpt2_energy", "mrpt2_energy_roots", "mrpt2_reference_states_size",
-    "mrpt2_reference_states", "mrpt2_hermitian_eigh", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
+    "mrpt2_reference_states", "mrpt2_hermitian_eigh", "mrpt2_energy_backward_async", "mrpt2_energy_timed", "mrpt2_reference_hamiltonian",
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",

@@ -783,6 +783,15 @@ mrpt2_status mrpt2_energy_backward(mrpt2_plan_t plan, const mrpt2_inputs* in, co
   return read_flag(plan->p, workspace, st);
 }
 
+mrpt2_status mrpt2_energy_backward_async(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                         void* workspace, size_t workspace_bytes, void* grad_workspace,
+                                         size_t grad_workspace_bytes, const double* grad_e2,
+                                         const mrpt2_grads* grads, hipStream_t st, double* e2) {
+  Timer tm;
+  return backward_enqueue(plan, in, persistent, workspace, workspace_bytes, grad_workspace, grad_workspace_bytes,
+                          grad_e2, grads, st, e2, tm);
+}
+
 mrpt2_status mrpt2_energy_backward_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
                                          void* workspace, size_t workspace_bytes, void* grad_workspace,
                                          size_t grad_workspace_bytes, const double* grad_e2,

@@ -77,3 +77,55 @@ def test_graph_capture_and_replay():
         assert torch.equal(eng.parts, eager), rep
         other.energy(ins2)
         torch.cuda.synchronize()
+
+
+def test_graph_capture_of_forward_and_adjoint():
+    """One HIP graph holding the batched adjoint (with its forward
+    recomputation) of three instances, replayed three times with unrelated
+    eager work in between: E2 and every gradient match an eager call (the
+    adjoint sums some partials with atomics, hence a relative bound)."""
+    import torch
+    import paper_2608_11529_amd as M
+    names = ["s_fc", "s_tiles", "c0"]
+    plan = M.Plan([M.desc_of_problem(problem(nm)) for nm in names])
+    eng = M.Engine(plan)
+    ins = inputs_for(M, plan, names, eng.device)
+    outs0, e20 = eng.backward(ins)
+    ref = [(dh.clone(), [x.clone() for x in dB], dc.clone()) for dh, dB, dc in outs0]
+    ref_e2 = e20.clone()
+    other = M.Engine(M.Plan([M.desc_of_problem(problem("s_das"))]))
+    ins2 = inputs_for(M, other.plan, ["s_das"], other.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        eng.backward(ins, asynchronous=True, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eng.check()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outs, e2 = eng.backward(ins, asynchronous=True, stream=torch.cuda.current_stream())
+    print("[gpu] captured batched adjoint", flush=True)
+
+    def close(a, b, rel=1e-11):
+        return float((a - b).abs().max()) <= rel * float(b.abs().max()) + 1e-15
+
+    for rep in range(3):
+        for dh, dB, dc in outs:
+            dh.zero_()
+            dc.zero_()
+            for x in dB:
+                x.zero_()
+        e2.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eng.check()
+        assert close(e2, ref_e2, 1e-13), rep
+        for i, ((dh, dB, dc), (rh, rB, rc)) in enumerate(zip(outs, ref)):
+            assert close(dh, rh), (rep, i, "dh")
+            assert close(dc, rc), (rep, i, "dc")
+            for t, (x, rx) in enumerate(zip(dB, rB)):
+                assert close(x, rx), (rep, i, "dB", t)
+        other.energy(ins2)
+        torch.cuda.synchronize()
