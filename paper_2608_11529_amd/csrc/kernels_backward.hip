@@ -1345,6 +1345,139 @@ __device__ __forceinline__ void bagemm_body(const Dev& d, const GradDev& g, cons
       }
 }
 
+// Mixed form of bagemm_body: the same stages, the operands rounded to FP32
+// as staged into three real planes (re, im, re + im) each, the product
+// formed by three real FP32 MFMA products per complex product (Gauss, as in
+// the forward pair-integral build) and each stage's sums carried into FP64.
+__device__ __forceinline__ void bagemm_f32_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  constexpr int PL = 64 * KP;                 // floats of one plane
+  __shared__ float sA[3 * PL];
+  __shared__ float sB[3 * PL];
+  const int nvt = (d.n_v + 63) / 64;
+  const int x = bid.y / nvt;
+  const int I = bid.y % nvt, a0 = I * 64;
+  const int L0 = bid.x * 64;
+  const int nv = d.n_v, nl = d.n_l, no = d.n_o;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  double accR[2][2][4], accI[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accR[i][j][r] = 0.0;
+        accI[i][j][r] = 0.0;
+      }
+  auto tpi = [&](int i0, int j0) -> int64_t {   // tile pair (i0 <= j0)
+    return (int64_t)i0 * nvt - (int64_t)i0 * (i0 - 1) / 2 + (j0 - i0);
+  };
+  for (int y = 0; y < no; ++y) {
+    if (y == x) continue;
+    const int64_t pr = x < y ? occ_pair(x, y, no) : occ_pair(y, x, no);
+    const double sgn = x < y ? 1.0 : -1.0;
+    const double2* Sy = d.slab + ((int64_t)(d.n_fc + y) * d.n_corr + no) * nl;
+    for (int b0 = 0; b0 < nv; b0 += KC) {
+      const int Jb = b0 >> 6, lb0 = b0 & 63;
+      // D = Abar[a][b] - Abar[b][a] in FP64, then rounded once into the planes
+      double2 dv[64 * KC / 256];
+#pragma unroll
+      for (int u = 0; u < 64 * KC / 256; ++u) {
+        const int e = tid + 256 * u;
+        const int r = e / KC, kk = e % KC;
+        const int a = a0 + r, bb = b0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (a < nv && bb < nv) {
+          if (I <= Jb) {
+            const double2 t = g.Ab[(pr * d.n_tp + tpi(I, Jb)) * 4096 + r * 64 + lb0 + kk];
+            v = make_double2(sgn * t.x, sgn * t.y);
+          }
+          if (Jb <= I) {
+            const double2 t = g.Ab[(pr * d.n_tp + tpi(Jb, I)) * 4096 + (lb0 + kk) * 64 + r];
+            v = make_double2(v.x - sgn * t.x, v.y - sgn * t.y);
+          }
+        }
+        dv[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < 64 * KC / 256; ++u) {
+        const int e = tid + 256 * u;
+        const int o = (e / KC) * KP + e % KC;
+        const float re = (float)dv[u].x, im = (float)dv[u].y;
+        sA[o] = re;
+        sA[PL + o] = im;
+        sA[2 * PL + o] = re + im;
+      }
+      // B operand: conj(S_y[b][L]), L fastest
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int c = e & 63, kk = e >> 6;
+        const int L = L0 + c, bb = b0 + kk;
+        const double2 v = (L < nl && bb < nv) ? cconj(Sy[(int64_t)bb * nl + L]) : make_double2(0.0, 0.0);
+        const float re = (float)v.x, im = (float)v.y;
+        const int o = c * KP + kk;
+        sB[o] = re;
+        sB[PL + o] = im;
+        sB[2 * PL + o] = re + im;
+      }
+      __syncthreads();
+      f4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          p1[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          p2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          p3[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 4) {
+        const int kc = ks + (lane >> 4);
+        float av[3][2], bv[3][2];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i) av[q][i] = sA[q * PL + (wr + i * 16 + (lane & 15)) * KP + kc];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) bv[q][j] = sB[q * PL + (wc + j * 16 + (lane & 15)) * KP + kc];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][i], bv[0][j], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][i], bv[1][j], p2[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][i], bv[2][j], p3[i][j], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double x1 = (double)p1[i][j][r], x2 = (double)p2[i][j][r];
+            accR[i][j][r] += x1 - x2;
+            accI[i][j][r] += ((double)p3[i][j][r] - x1) - x2;
+          }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + acc_row_f32(i, r), L = L0 + acc_col(j);
+        if (a < nv && L < nl) {
+          double2* p = g.slabb + ((int64_t)(d.n_fc + x) * d.n_corr + no + a) * nl + L;
+          const double sg = d.sign[L];
+          *p = cadd(*p, make_double2(sg * accR[i][j][r], sg * accI[i][j][r]));
+        }
+      }
+}
+
 // ---- occupied-block integrals: G[m][k] = sum_L w_L P[m][L] Q[k][L] -----------------
 // m = (x, p) over occupied x and active/virtual p, k = (y, q) over occupied y and
 // active q, P[m] = S_x[p], Q[k] = S_y[q].

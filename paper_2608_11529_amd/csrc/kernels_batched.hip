@@ -173,6 +173,11 @@ __global__ void __launch_bounds__(256) k_b_bag(MRPT2_ARGS) {
   MRPT2_JOB
   bagemm_body(I.d, I.g, bid);
 }
+// three waves per SIMD (168 VGPRs, a few spills) beat two at 196 registers
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_b_bagf(MRPT2_ARGS) {
+  MRPT2_JOB
+  bagemm_f32_body(I.d, I.g, bid);
+}
 __global__ void __launch_bounds__(256) k_b_bgg(MRPT2_ARGS) {
   MRPT2_JOB
   bggemm_body(I.d, I.g, jb.arg, bid);

@@ -595,13 +595,16 @@ void build_launches(Plan* P) {
       js.push_back(job(i, cdiv64(cp.n_rows, 256), (int64_t)cp.patterns.size(), k));
     }
   add_launch(P, seq, K_BXB, ST_BXB, js);
-  js.clear();
-  for (int i : all) {
-    const InstancePlan& ip = P->inst[i];
-    if (ip.n_v >= 2 && ip.n_o >= 2)
-      js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
+  // pair-integral adjoint GEMM: FP64, or FP32 (Gauss) in the mixed form
+  for (int prec = 0; prec < 2; ++prec) {
+    js.clear();
+    for (int i : all) {
+      const InstancePlan& ip = P->inst[i];
+      if (ip.n_v >= 2 && ip.n_o >= 2 && (ip.d.precision == MRPT2_MIXED) == (prec == 1))
+        js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
+    }
+    add_launch(P, seq, prec ? K_BAGF : K_BAG, ST_BPAIR, js);
   }
-  add_launch(P, seq, K_BAG, ST_BPAIR, js);
   for (int which = 0; which < 2; ++which) {
     js.clear();
     for (int i : all) {

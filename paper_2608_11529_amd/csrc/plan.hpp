@@ -113,7 +113,7 @@ enum KernelId : int {
   // adjoint
   K_BZERO, K_BROW22, K_BROW12, K_BROW02, K_BROW21, K_BROW11, K_BROW01, K_BROW20, K_BROW10, K_BROW00,
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
-  K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
+  K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BAGF, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
   K_BECOEF, K_BTRANS, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
   K_B12R_20, K_B12S_20
 };
