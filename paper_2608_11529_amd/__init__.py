@@ -140,10 +140,17 @@ class Engine:
     def _sptr(self):
         return ctypes.c_void_p(self.stream.cuda_stream)
 
-    def _inputs(self, insts):
+    def _inputs(self, insts, inst=None):
+        """ctypes input sets: one per instance, or (inst given) the single set
+        of instance inst."""
+        if inst is None and len(insts) != self.plan.n_inst:
+            raise ValueError("the plan holds %d instances, %d input sets given" % (self.plan.n_inst, len(insts)))
+        if inst is not None and (len(insts) != 1 or not 0 <= inst < self.plan.n_inst):
+            raise ValueError("one input set of an instance of the plan expected")
         arr = (capi.Inputs * len(insts))()
         keep = []
         for i, (h, Bs, c) in enumerate(insts):
+            self._check_shapes(i if inst is None else inst, h, Bs, c)
             for x in [h, c, *Bs]:
                 if x is not None:
                     if not x.is_contiguous() or x.device != self.device:
@@ -154,6 +161,25 @@ class Engine:
                 arr[i].B[t] = B.data_ptr()
             arr[i].c = c.data_ptr() if c is not None else None
         return arr, keep
+
+    def _check_shapes(self, i, h, Bs, c):
+        """The kernels read exactly the sizes the plan fixes: h [n][n], B_t
+        [rank_t][n][n], c [N_P] (or [n_roots][N_P]); anything else is refused
+        here, before a device read could run past a tensor."""
+        info, desc = self.plan.info(i), self.plan._descs[i]
+        n = info.n_orb
+        torch = self.torch
+        if h is None or tuple(h.shape) != (n, n) or h.dtype != torch.complex128:
+            raise ValueError("instance %d: h must be complex128 [%d, %d]" % (i, n, n))
+        ranks = [desc.rank[t] for t in range(desc.n_sets)]
+        if len(Bs) != len(ranks):
+            raise ValueError("instance %d: %d factor sets expected" % (i, len(ranks)))
+        for t, (B, r) in enumerate(zip(Bs, ranks)):
+            if tuple(B.shape) != (r, n, n) or B.dtype != torch.complex128:
+                raise ValueError("instance %d: B[%d] must be complex128 [%d, %d, %d]" % (i, t, r, n, n))
+        if c is not None and (c.dtype != torch.complex128 or c.dim() not in (1, 2)
+                              or c.shape[-1] != info.n_ref or c.numel() == 0):
+            raise ValueError("instance %d: c must be complex128 [N_P = %d] (or [n_roots, N_P])" % (i, info.n_ref))
 
     def energy(self, insts, parts=True):
         """insts: list of (h, [B_t], c) complex128 device tensors per
@@ -287,7 +313,7 @@ class Engine:
         C = torch.empty((k, n_p), dtype=torch.complex128, device=self.device)
         e = np.zeros(k)
         its = ctypes.c_int32()
-        arr, keep = self._inputs([(h, Bs, None)])
+        arr, keep = self._inputs([(h, Bs, None)], inst=inst)
         code = capi.lib().mrpt2_reference_states(self.plan.handle, inst, arr, k, tol, max_iter,
                                                  self.persistent.data_ptr(), self.workspace.data_ptr(),
                                                  self.plan.workspace_bytes, dv.data_ptr(), nbytes.value,
@@ -300,7 +326,7 @@ class Engine:
         torch = self.torch
         n_p = self.plan.info(inst).n_ref
         out = torch.empty((n_p, n_p), dtype=torch.complex128, device=self.device)
-        arr, keep = self._inputs([(h, Bs, None)])
+        arr, keep = self._inputs([(h, Bs, None)], inst=inst)
         code = capi.lib().mrpt2_reference_hamiltonian(self.plan.handle, inst, arr, self.persistent.data_ptr(),
                                                       self.workspace.data_ptr(), self.plan.workspace_bytes,
                                                       self._sptr(), out.data_ptr())

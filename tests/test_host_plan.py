@@ -115,3 +115,34 @@ def test_null_arguments_return_status():
     assert L.mrpt2_plan_sizes(None, None, None) == 1
     assert L.mrpt2_energy(None, None, None, None, 0, None, None, None) == 1
     assert L.mrpt2_status_string(6) == b"non-finite input or zero denominator"
+
+
+def test_binding_refuses_inputs_of_the_wrong_shape():
+    """The Python binding checks every tensor against the plan's sizes before
+    a call (the C interface takes plain pointers and reads the plan's sizes)."""
+    import torch
+    M = lib_module()
+    pb = problem("s_das")
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine.__new__(M.Engine)        # shape checks need no device
+    eng.torch, eng.plan = torch, plan
+    info = plan.info()
+    n, n_p = info.n_orb, info.n_ref
+    h = torch.zeros((n, n), dtype=torch.complex128)
+    Bs = [torch.zeros((r, n, n), dtype=torch.complex128) for r, _ in pb.sets]
+    c = torch.zeros(n_p, dtype=torch.complex128)
+    eng._check_shapes(0, h, Bs, c)
+    eng._check_shapes(0, h, Bs, torch.zeros((3, n_p), dtype=torch.complex128))
+    bad = [
+        (torch.zeros((n, n + 1), dtype=torch.complex128), Bs, c),
+        (h.to(torch.complex64), Bs, c),
+        (h, Bs[:-1] if len(Bs) > 1 else [], c),
+        (h, [torch.zeros((Bs[0].shape[0] + 1, n, n), dtype=torch.complex128)] + Bs[1:], c),
+        (h, Bs, torch.zeros(n_p - 1, dtype=torch.complex128)),
+        (h, Bs, torch.zeros((2, n_p + 1), dtype=torch.complex128)),
+    ]
+    for args in bad:
+        with pytest.raises(ValueError):
+            eng._check_shapes(0, *args)
+    with pytest.raises(ValueError):
+        eng._inputs([(h, Bs, c), (h, Bs, c)])
