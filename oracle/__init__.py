@@ -25,4 +25,7 @@ Modules:
   classes    - the same sums organised by excitation class, vectorised over
                virtual spinors (for sizes the literal form cannot reach)
   counting   - closed-form external-space counts per class
+  fullsize   - the class oracle on streamed factor columns, with the sums of
+               the two-virtual classes as plain C loops (vvsum.c), for whole
+               large workloads
 """
