@@ -108,6 +108,13 @@ typedef struct {
                                        (nonzero couplings only; the (2,2) class
                                        has none) */
   double bytes_factors;             /* bytes of all factor sets (one HBM pass) */
+  int32_t n_patterns_class[MRPT2_N_CLASS];  /* distinct coupling patterns per
+      class: for (1,2) the active spinors t of the reference determinants
+      core + alpha' + t it couples to, which sizes the dense-coefficient
+      kernels (up to 8, 16, 24 or 32 patterns; more run the generic kernel) */
+  int32_t kernel_class[MRPT2_N_CLASS];      /* sigma kernel of each class:
+      0 generic (excitation lists), 1 class (2,2) string sums, 2 class (1,2)
+      dense coefficients, 3 class (0,2) string tiles on MFMA */
 } mrpt2_info;
 
 /* Inputs of one instance (device pointers). */

@@ -68,6 +68,8 @@ class Info(ctypes.Structure):
         ("flop_integral", ctypes.c_double),
         ("flop_sigma", ctypes.c_double),
         ("bytes_factors", ctypes.c_double),
+        ("n_patterns_class", ctypes.c_int32 * N_CLASS),
+        ("kernel_class", ctypes.c_int32 * N_CLASS),
     ]
 
 

@@ -1071,6 +1071,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       inf.n_ext_class[k] = cp.n_ext;
       inf.n_strings_class[k] = (int64_t)cp.strings.size();
       inf.n_conn_class[k] = cp.n_conn;
+      inf.n_patterns_class[k] = (int32_t)cp.patterns.size();
+      inf.kernel_class[k] = cp.kernel;
       // complex multiply-adds of the sigma contraction: one per coupling and
       // external determinant (nonzero couplings only); the double core ->
       // virtual class has no contraction (sigma = integral x coefficient)

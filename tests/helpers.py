@@ -44,6 +44,14 @@ SMALL = {
     "s_single": (106, 0, 4, [], 0, 9, [(12, 1.0)], SP.CAS, None),     # single determinant
     "s_nocore": (107, 0, 0, [4], 2, 6, [(10, 1.0)], SP.CAS, None),    # no core spinors
     "s_full": (108, 0, 2, [3], 3, 5, [(8, 1.0)], SP.CAS, None),       # active space full
+    # wide active spaces: class (1,2) couples through 20, 24 and 32 active
+    # spinors, which selects the dense-coefficient kernels sized for up to
+    # 24 and 32 couplings (and the adjoint's 20-, 24- and 32-wide forms);
+    # s_j20 has 190 strings in that class (three 64-string chunks, the last
+    # one partial)
+    "s_j20": (109, 0, 2, [20], 3, 10, [(16, 1.0), (6, -0.02)], SP.CAS, None),
+    "s_j24": (110, 1, 3, [12, 12], 2, 9, [(14, 1.0)], 1, [1, 1]),
+    "s_j32": (111, 0, 2, [32], 2, 8, [(12, 1.0), (4, 0.01)], SP.CAS, None),
 }
 
 

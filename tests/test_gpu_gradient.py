@@ -31,10 +31,18 @@ def gpu_inputs(name, precision=0):
     return pb, plan, eng, h, Bs, cd, c_o, P_o
 
 
-def close(a, b, rel=REL):
+def close(a, b, rel=REL, floor=1e-3):
+    """Element by element: |a - b| <= rel |b| + floor rel max|b| at every
+    entry.  Against the oracle floor = 1e-3, so that small entries (the
+    factor gradients of the weak Gaunt and gauge sets, the couplings of the
+    wide classes) are checked on their own scale and not only against the
+    largest entry; between two GPU results (batched and single, mixed and
+    FP64) floor = 1."""
     scale = max(float(np.abs(b).max()), 1e-300)
-    err = float(np.abs(a - b).max())
-    return err <= rel * scale + 1e-14, err, scale
+    d = np.abs(a - b)
+    err = float(d.max())
+    worst = float((d / (rel * np.abs(b) + floor * rel * scale + 1e-16)).max())
+    return worst <= 1.0, err, scale
 
 
 @pytest.mark.parametrize("name", list(SMALL) + ["c0"])
@@ -100,10 +108,10 @@ def test_batched_backward_matches_single():
     for i, nm in enumerate(names):
         e1 = M.Engine(M.Plan(descs[i]))
         (dh, dB, dc), = e1.backward([ins[i]])[0]
-        assert close(outs[i][0].cpu().numpy(), dh.cpu().numpy(), 1e-12)[0], nm
-        assert close(outs[i][2].cpu().numpy(), dc.cpu().numpy(), 1e-12)[0], nm
+        assert close(outs[i][0].cpu().numpy(), dh.cpu().numpy(), 1e-12, 1.0)[0], nm
+        assert close(outs[i][2].cpu().numpy(), dc.cpu().numpy(), 1e-12, 1.0)[0], nm
         for x, y in zip(outs[i][1], dB):
-            assert close(x.cpu().numpy(), y.cpu().numpy(), 1e-12)[0], nm
+            assert close(x.cpu().numpy(), y.cpu().numpy(), 1e-12, 1.0)[0], nm
 
 
 def herm(gen, shape, dev):
@@ -165,10 +173,10 @@ def test_mixed_precision_gradient_close_to_fp64(name):
     dh, dB, dc = dh.cpu().numpy(), [x.cpu().numpy() for x in dB], dc.cpu().numpy()
     _, _, eng32, _, _, _, _, _ = gpu_inputs(name, precision=1)
     (mh, mB, mc), = eng32.backward([(h, Bs, c)])[0]
-    assert close(mh.cpu().numpy(), dh, 1e-6)[0]
-    assert close(mc.cpu().numpy(), dc, 1e-6)[0]
+    assert close(mh.cpu().numpy(), dh, 1e-6, 1.0)[0]
+    assert close(mc.cpu().numpy(), dc, 1e-6, 1.0)[0]
     for x, y in zip(mB, dB):
-        assert close(x.cpu().numpy(), y, 1e-6)[0]
+        assert close(x.cpu().numpy(), y, 1e-6, 1.0)[0]
 
 
 def _rdot(a, b):

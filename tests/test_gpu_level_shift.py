@@ -15,7 +15,8 @@ from helpers import CLASSES, oracle_reference, problem, to_plan_order
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("s_tiles", 2.0), ("s_fc", 2.0), ("s_das", 0.5), ("s_single", 2.0), ("c0", 0.05), ("c0", 2.0)]
+CASES = [("s_tiles", 2.0), ("s_fc", 2.0), ("s_das", 0.5), ("s_single", 2.0), ("c0", 0.05), ("c0", 2.0),
+         ("s_j20", 0.5), ("s_j32", 2.0)]
 
 
 def shifted_oracle(name, b):
@@ -60,10 +61,14 @@ def test_level_shift_mixed_precision(name, b):
     assert abs(float(e2[0]) - math.fsum(parts_o.values())) <= 1e-6
 
 
-def close(a, b, rel=1e-9):
+def close(a, b, rel=1e-9, floor=1e-3):
+    """Element by element: |a - b| <= rel |b| + floor rel max|b| (floor 1e-3
+    against the oracle, 1 between two GPU results)."""
     scale = max(float(np.abs(b).max()), 1e-300)
-    err = float(np.abs(a - b).max())
-    return err <= rel * scale + 1e-14, err, scale
+    d = np.abs(a - b)
+    err = float(d.max())
+    worst = float((d / (rel * np.abs(b) + floor * rel * scale + 1e-16)).max())
+    return worst <= 1.0, err, scale
 
 
 @pytest.mark.parametrize("name,b", [("s_das", 2.0), ("s_fc", 0.5), ("s_tiles", 2.0), ("c0", 2.0)])
@@ -111,9 +116,9 @@ def test_level_shift_mixed_with_unshifted_instances_in_one_plan():
         assert float(e1.energy([(h, Bs, c)], parts=False)[0].item()) == e2[i]
         (dh1, dB1, dc1), = e1.backward([(h, Bs, c)])[0]
         dh, dB, dc = outs[i]
-        ok, err, sc = close(dh.cpu().numpy(), dh1.cpu().numpy(), rel=1e-12)
+        ok, err, sc = close(dh.cpu().numpy(), dh1.cpu().numpy(), rel=1e-12, floor=1.0)
         assert ok, (nm, "dh", err, sc)
-        ok, err, sc = close(dc.cpu().numpy(), dc1.cpu().numpy(), rel=1e-12)
+        ok, err, sc = close(dc.cpu().numpy(), dc1.cpu().numpy(), rel=1e-12, floor=1.0)
         assert ok, (nm, "dc", err, sc)
 
 

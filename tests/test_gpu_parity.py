@@ -1,8 +1,10 @@
 """GPU parity: the HIP path through the C interface against the CPU oracle,
 class by class, on small problems covering the edge cases (frozen core, DAS
 hop limits, several virtual tiles, single-determinant reference, no core,
-full active space) and on config c0.  Tolerance 1e-9 Eh on E2 and every
-class part (FP64 path)."""
+full active space, wide active spaces that select every width of the
+class (1,2) kernel) and on config c0.  Tolerance 1e-9 Eh on E2 and every
+class part (FP64 path), and each part also within 1e-9 of its own size (the
+parts of the wide problems are as small as 1e-11 Eh)."""
 import sys
 
 import numpy as np
@@ -41,7 +43,9 @@ def test_energy_matches_oracle(name):
     e2, parts, parts_o, E0_o = gpu_energy(name)
     ref = e2_total(parts_o)
     for k, cl in enumerate(CLASSES):
-        assert abs(parts[k] - parts_o.get(cl, 0.0)) <= TOL, (name, cl, parts[k], parts_o.get(cl))
+        want = parts_o.get(cl, 0.0)
+        assert abs(parts[k] - want) <= TOL, (name, cl, parts[k], want)
+        assert abs(parts[k] - want) <= 1e-9 * abs(want) + 1e-15, (name, cl, parts[k], want)
     assert abs(e2 - ref) <= TOL, (name, e2, ref)
     assert abs(parts[9] - e2) <= 1e-15 * max(1.0, abs(e2))
 

@@ -146,3 +146,20 @@ def test_binding_refuses_inputs_of_the_wrong_shape():
             eng._check_shapes(0, *args)
     with pytest.raises(ValueError):
         eng._inputs([(h, Bs, c), (h, Bs, c)])
+
+
+def test_wide_active_spaces_select_every_dense_kernel_width():
+    """Class (1,2) runs the dense-coefficient kernel sized for its pattern
+    count: the small problems with 20, 24 and 32 active spinors select the
+    24- and 32-wide forms (forward) and the 20-, 24- and 32-wide adjoint
+    forms, which the element-wise GPU parity tests then cover; c4 (18
+    active spinors) runs the 24-wide form."""
+    import paper_2608_11529_amd as M
+    from helpers import problem
+    want = {"s_j20": 20, "s_j24": 24, "s_j32": 32, "c4": 18, "c0": 6, "s_das": 6}
+    for name, J in want.items():
+        info = M.Plan(M.desc_of_problem(problem(name))).info()
+        assert info.n_patterns_class[1] == J, (name, info.n_patterns_class[1])
+        assert info.kernel_class[1] == 2, name
+        assert info.kernel_class[0] == 1 and info.kernel_class[2] in (0, 3), name
+    assert M.Plan(M.desc_of_problem(problem("s_j20"))).info().n_strings_class[1] == 190
