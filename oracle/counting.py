@@ -6,7 +6,7 @@ number of external determinants with h core holes and v virtual electrons is
     prod_k C(s_k, m_k).
 For a complete active space (one subspace) the rule reduces to: at most two
 core holes and at most two virtual electrons (the excitation restriction
-stated with the MRCISD comparison in Sec. 3.2), and (h, v) != (0, 0).
+stated with the MRCISD comparison in Sec. 3.3), and (h, v) != (0, 0).
 """
 from math import comb
 

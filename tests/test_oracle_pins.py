@@ -170,7 +170,7 @@ def test_hermiticity_of_matrix_elements():
 # ---------------------------------------------------------- external space
 
 def test_table3_and_hbr_counts():
-    """Sec. 3.2 Table 3 (nDets of 4C-MRPT2) and Sec. 3.1 (HBr external
+    """Sec. 3.3 Table 3 (nDets of 4C-MRPT2) and Sec. 3.1 (HBr external
     space): the class rule with a CAS reference reproduces the printed
     counts; HBr's printed exponent differs by one (see fixture)."""
     with open(os.path.join(GOLDEN, "table3_counts.json")) as f:
