@@ -259,6 +259,9 @@ class Engine:
         if grad_e2 is None:
             grad_e2 = torch.ones(self.plan.n_inst, dtype=torch.float64, device=self.device)
         grad_e2 = grad_e2.to(device=self.device, dtype=torch.float64).contiguous()
+        if grad_e2.numel() != self.plan.n_inst:
+            raise ValueError("grad_e2 must hold one value per instance (%d), got %d"
+                             % (self.plan.n_inst, grad_e2.numel()))
         arr, keep = self._inputs(insts)
         outs = []
         garr = (capi.Grads * len(insts))()

@@ -218,14 +218,11 @@ mrpt2_status ensure_pinned(Plan& P, size_t sets, hipStream_t st) {
 // workspace (asynchronously, on stream).  They are staged in descriptor set
 // `slot`: a multi-state call fills one set per state before the stream has
 // copied the earlier ones.
-mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, char* work, hipStream_t st,
-                          double* e2, double* parts, double* hpp_out, int only, char* gw = nullptr,
-                          const mrpt2_grads* grads = nullptr, const double* grad_e2 = nullptr,
-                          int slot = 0) {
+// Descriptors of every instance written into host memory `stage`.
+mrpt2_status fill_insts(const Plan& P, const mrpt2_inputs* in, const char* pers, char* work, char* stage,
+                        double* e2, double* parts, double* hpp_out, int only, char* gw,
+                        const mrpt2_grads* grads, const double* grad_e2) {
   const size_t bytes = kInstBytes * P.inst.size();
-  mrpt2_status ps = ensure_pinned(P, (size_t)slot + 1, st);
-  if (ps != MRPT2_OK) return ps;
-  char* stage = (char*)P.pinned + bytes * slot;
   std::memset(stage, 0, bytes);
   for (size_t i = 0; i < P.inst.size(); ++i) {
     if (only >= 0 && (int)i != only) continue;
@@ -251,7 +248,35 @@ mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, cha
       for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cg[k] = make_class_grad(ip, k, gw);
     }
   }
+  return MRPT2_OK;
+}
+
+mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, char* work, hipStream_t st,
+                          double* e2, double* parts, double* hpp_out, int only, char* gw = nullptr,
+                          const mrpt2_grads* grads = nullptr, const double* grad_e2 = nullptr,
+                          int slot = 0) {
+  const size_t bytes = kInstBytes * P.inst.size();
+  mrpt2_status ps = ensure_pinned(P, (size_t)slot + 1, st);
+  if (ps != MRPT2_OK) return ps;
+  char* stage = (char*)P.pinned + bytes * slot;
+  // The staging buffer is reused by every call on this plan: before the
+  // first descriptor set of a call is rewritten, the previous call's last
+  // copy from it must have run (an asynchronous call may still have it
+  // queued).  Under stream capture the copy is a graph node that reads the
+  // buffer at every replay, so the captured plan is reserved for its graph
+  // and nothing is waited for or recorded.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (!capturing && slot == 0 && P.staged_recorded) HIPCHK(hipEventSynchronize(P.staged));
+  ps = fill_insts(P, in, pers, work, stage, e2, parts, hpp_out, only, gw, grads, grad_e2);
+  if (ps != MRPT2_OK) return ps;
   HIPCHK(hipMemcpyAsync(work + P.off_insts, stage, bytes, hipMemcpyHostToDevice, st));
+  if (!capturing) {
+    if (!P.staged) HIPCHK(hipEventCreateWithFlags(&P.staged, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(P.staged, st));
+    P.staged_recorded = true;
+  }
   return MRPT2_OK;
 }
 
@@ -262,8 +287,9 @@ mrpt2_status upload_insts(Plan& P, const mrpt2_inputs* in, const char* pers, cha
 bool depends_on_c(int kid) {
   switch (kid) {
     case K_SIGP: case K_E0: case K_CTAB: case K_DCOEF: case K_E02COEF: case K_E22:
-    case K_E12_8: case K_E12_16: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
-    case K_E22S: case K_E12S_8: case K_E12S_16: case K_E12S_24: case K_E12S_32: case K_E02S: case K_E02FS:
+    case K_E12_8: case K_E12_16: case K_E12_20: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
+    case K_E22S: case K_E12S_8: case K_E12S_16: case K_E12S_20: case K_E12S_24: case K_E12S_32: case K_E02S:
+    case K_E02FS:
     case K_SIG22: case K_SIG12: case K_SIG02: case K_SIG21: case K_SIG11: case K_SIG01:
     case K_SIG20: case K_SIG10: case K_SIG00: case K_FINISH:
       return true;
@@ -306,6 +332,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E22: hipLaunchKernelGGL(k_b_e22<false>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_8: hipLaunchKernelGGL((k_b_e12<8, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_16: hipLaunchKernelGGL((k_b_e12<16, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12_20: hipLaunchKernelGGL((k_b_e12<20, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_24: hipLaunchKernelGGL((k_b_e12<24, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_32: hipLaunchKernelGGL((k_b_e12<32, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02: hipLaunchKernelGGL((k_b_e02<false, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
@@ -313,6 +340,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E22S: hipLaunchKernelGGL(k_b_e22<true>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12S_8: hipLaunchKernelGGL((k_b_e12<8, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12S_16: hipLaunchKernelGGL((k_b_e12<16, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12S_20: hipLaunchKernelGGL((k_b_e12<20, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12S_24: hipLaunchKernelGGL((k_b_e12<24, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12S_32: hipLaunchKernelGGL((k_b_e12<32, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02S: hipLaunchKernelGGL((k_b_e02<false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
@@ -911,6 +939,7 @@ mrpt2_status mrpt2_class_partials(mrpt2_plan_t plan, int32_t inst, int32_t cls, 
 void mrpt2_plan_destroy(mrpt2_plan_t plan) {
   if (!plan) return;
   if (plan->p.pinned) (void)hipHostFree(plan->p.pinned);
+  if (plan->p.staged) (void)hipEventDestroy(plan->p.staged);
   delete plan;
 }
 

@@ -115,7 +115,7 @@ enum KernelId : int {
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
   K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BAGF, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
   K_BECOEF, K_BTRANS, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
-  K_B12R_20, K_B12S_20
+  K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20
 };
 
 // Timing slots (mrpt2_energy_timed).
@@ -159,6 +159,8 @@ struct Plan {
   std::vector<char> host_blob;
   void* pinned = nullptr;             // host staging of the instance descriptors
   size_t pinned_bytes = 0;            // its size (one descriptor set per state of a multi-state call)
+  hipEvent_t staged = nullptr;        // recorded after each copy from the pinned staging buffer
+  bool staged_recorded = false;
 };
 
 // Kernel that evaluates a class.
