@@ -491,65 +491,82 @@ __device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd
 // L = core + alpha' + {t} by a_c a_t -> a+_b a+_a:
 //   sigma_K = sum_t <ab||ct> D[alpha'][t],
 //   Delta   = T + eps_c + Uc_c - eps_a - Uv_a - eps_b - Uv_b - W_ab + W_ca + W_cb.
-// One thread per (a, b) of a 16 x 16 sub-tile of a 64 x 64 virtual tile pair,
-// the couplings <ab||ct> of its row in registers; strings are walked in
-// chunks staged in LDS, patterns present in a string selected by a
-// wave-uniform mask, and four fractions |sigma|^2 / Delta merged per
-// reciprocal.  grid (n_c, 16 n_tp), block 256.
+// Each thread owns two (a, b) of a 16 x 32 region of a 64 x 64 virtual tile
+// pair (b and b + 16), the couplings <ab||ct> of both in registers; strings
+// are walked in chunks staged in LDS, patterns present in a string selected
+// by a wave-uniform mask, and four fractions |sigma|^2 / Delta merged per
+// reciprocal.  Every coefficient read from LDS feeds both pairs, which halves
+// the LDS traffic per determinant (the LDS read bandwidth, not the FP64
+// arithmetic, limited the one-pair form).  Partial sums stay per 16 x 16
+// sub-tile.  grid (n_c, 8 n_tp), block 256.
 constexpr int SC12 = 64;
 
 template <int MJ, bool LS>
 __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   __shared__ double sUa[SC12][16];
-  __shared__ double sUb[SC12][16];
+  __shared__ double sUb[SC12][32];
   __shared__ double sG[SC12];
   __shared__ double2 sD[SC12][MJ];
   __shared__ uint32_t sM[SC12];
-  __shared__ double red[256];
-  const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
-  const int tp = tps >> 4, sub = tps & 15;
-  const int sa = sub >> 2, sb = sub & 3;
+  __shared__ double red[2][256];
+  const int tps = bid.y;                    // cores fastest: blocks of one region share its tables
+  const int tp = tps >> 3, reg = tps & 7;
+  const int sa = reg >> 1, sb2 = reg & 1;   // 16-row band sa, 32-column band sb2
   const int c = bid.x;
   const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
-  if (I == Jt && sa > sb) {                    // block entirely below the diagonal
-    if (threadIdx.x == 0) cd.part[(int64_t)c * d.n_tp * 16 + tps] = 0.0;
+  const int64_t pbase = (int64_t)c * d.n_tp * 16 + (int64_t)tp * 16 + sa * 4 + 2 * sb2;
+  if (I == Jt && sa > 2 * sb2 + 1) {        // both sub-tiles entirely below the diagonal
+    if (threadIdx.x < 2) cd.part[pbase + threadIdx.x] = 0.0;
     return;
   }
   const int tid = threadIdx.x;
-  const int la = sa * 16 + (tid >> 4), lb = sb * 16 + (tid & 15);
+  const int la = sa * 16 + (tid >> 4);
   const int nv = d.n_v, nc = d.n_c;
-  int a = I * 64 + la, b = Jt * 64 + lb;
-  const bool valid = (a < b) && (b < nv);
-  if (!valid) {
-    a = 0;
-    b = nv > 1 ? 1 : 0;
-  }
   const int J = cd.n_pat;
   const int64_t gfc = d.n_fc, gv = d.n_fc + d.n_o;
   const double* __restrict__ W = d.W;
-  const double rowc = -d.eps[d.n_o + a] - d.eps[d.n_o + b] - W[(gv + a) * d.n + gv + b] +
-                      W[(gfc + c) * d.n + gv + a] + W[(gfc + c) * d.n + gv + b];
-  double2 X[MJ];
+  const int a0 = I * 64 + la;
+  const int a = a0 < nv ? a0 : 0;
+  int lb[2];
+  bool valid[2];
+  double rowc[2];
+  double2 X[2][MJ];
 #pragma unroll
-  for (int j = 0; j < MJ; ++j) {
-    X[j] = make_double2(0.0, 0.0);
-    if (j < J) {
-      const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
-      X[j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
+  for (int p = 0; p < 2; ++p) {
+    lb[p] = sb2 * 32 + 16 * p + (tid & 15);
+    int b = Jt * 64 + lb[p];
+    valid[p] = (a0 < b) && (b < nv);
+    if (!valid[p]) b = nv > 1 ? 1 : 0;
+    const int aa = valid[p] ? a : 0;
+    rowc[p] = -d.eps[d.n_o + aa] - d.eps[d.n_o + b] - W[(gv + aa) * d.n + gv + b] + W[(gfc + c) * d.n + gv + aa] +
+              W[(gfc + c) * d.n + gv + b];
+#pragma unroll
+    for (int j = 0; j < MJ; ++j) {
+      X[p][j] = make_double2(0.0, 0.0);
+      if (j < J) {
+        const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
+        X[p][j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb[p]];
+      }
     }
   }
   const double epsc = d.eps[c];
   const int64_t S = cd.n_str;
   const double lsb2 = d.ls_b2;
   (void)lsb2;
-  double acc = 0.0;
+  double acc[2] = {0.0, 0.0};
+  const int ia = tid >> 4, ib = tid & 15;
   for (int64_t s0 = 0; s0 < S; s0 += SC12) {
     __syncthreads();
     for (int e = tid; e < SC12 * 16; e += 256) {
       const int sl = e >> 4, l = e & 15;
       const int64_t s = s0 + sl;
-      const int aa = I * 64 + sa * 16 + l, bb = Jt * 64 + sb * 16 + l;
+      const int aa = I * 64 + sa * 16 + l;
       sUa[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
+    }
+    for (int e = tid; e < SC12 * 32; e += 256) {
+      const int sl = e >> 5, l = e & 31;
+      const int64_t s = s0 + sl;
+      const int bb = Jt * 64 + sb2 * 32 + l;
       sUb[sl][l] = (s < S && bb < nv) ? cd.Uv[s * nv + bb] : 0.0;
     }
     for (int e = tid; e < SC12 * MJ; e += 256) {
@@ -563,47 +580,67 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
       sM[tid] = (s < S) ? cd.mask[s] : 0u;
     }
     __syncthreads();
-    const int ia = la - sa * 16, ib = lb - sb * 16;
 #pragma unroll 1
     for (int sl = 0; sl < SC12; sl += 4) {
-      double w[4], dd[4];
-      double2 sg[4];
+      double2 sg[2][4];
       // strings are ordered by pattern mask, so the union of four masks is
       // usually a single mask; absent couplings carry zero coefficients
       const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sg[p][k] = make_double2(0.0, 0.0);
 #pragma unroll
       for (int j = 0; j < MJ; ++j)
         if (um & (1u << j)) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
+          for (int k = 0; k < 4; ++k) {
+            const double2 dv = sD[sl + k][j];
+            sg[0][k] = cfma(dv, X[0][j], sg[0][k]);
+            sg[1][k] = cfma(dv, X[1][j], sg[1][k]);
+          }
         }
+      double g4[4], ua[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        w[k] = cabs2(sg[k]);
-        dd[k] = (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib];
-        if constexpr (LS) {
-          const double d2 = dd[k] * dd[k];
-          w[k] *= dd[k] * d2;
-          dd[k] = fma(d2, d2, lsb2);
-        }
+        g4[k] = sG[sl + k];
+        ua[k] = sUa[sl + k][ia];
       }
-      const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
-      const double q01 = dd[0] * dd[1];
-      const double n23 = fma(w[2], dd[3], w[3] * dd[2]);
-      const double q23 = dd[2] * dd[3];
-      acc = fma(fma(n01, q23, n23 * q01), rcp_nr(q01 * q23), acc);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        double w[4], dd[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          w[k] = cabs2(sg[p][k]);
+          dd[k] = (g4[k] + rowc[p]) - ua[k] - sUb[sl + k][ib + 16 * p];
+          if constexpr (LS) {
+            const double d2 = dd[k] * dd[k];
+            w[k] *= dd[k] * d2;
+            dd[k] = fma(d2, d2, lsb2);
+          }
+        }
+        const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
+        const double q01 = dd[0] * dd[1];
+        const double n23 = fma(w[2], dd[3], w[3] * dd[2]);
+        const double q23 = dd[2] * dd[3];
+        acc[p] = fma(fma(n01, q23, n23 * q01), rcp_nr(q01 * q23), acc[p]);
+      }
     }
   }
-  if (valid && !isfinite(acc)) *flag = 2;
-  red[tid] = valid ? acc : 0.0;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (valid[p] && !isfinite(acc[p])) *flag = 2;
+    red[p][tid] = valid[p] ? acc[p] : 0.0;
+  }
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
+    if (tid < o) {
+      red[0][tid] += red[0][tid + o];
+      red[1][tid] += red[1][tid + o];
+    }
     __syncthreads();
   }
-  if (tid == 0) cd.part[(int64_t)c * d.n_tp * 16 + tps] = red[0];
+  if (tid < 2) cd.part[pbase + tid] = red[tid][0];
 }
 
 

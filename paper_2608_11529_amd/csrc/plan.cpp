@@ -468,7 +468,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
     // (index 1 of each pair: the level-shifted variant)
-    std::vector<JobH> e22[2], e12[2][4], e02[2], e02f[2], gen;
+    std::vector<JobH> e22[2], e12[2][5], e02[2], e02f[2], gen;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -478,8 +478,8 @@ void build_launches(Plan* P) {
         e22[ls].push_back(job(i, cp.n_holes, ip.n_tp, k));
       } else if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
-        const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
-        e12[ls][v].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
+        const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 20 ? 4 : J <= 24 ? 2 : 3;
+        e12[ls][v].push_back(job(i, cp.n_holes, ip.n_tp * 8, k));
       } else if (cp.kernel == KERN_E02) {
         (ip.d.precision == MRPT2_MIXED ? e02f[ls] : e02[ls]).push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
       } else {
@@ -491,6 +491,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12_16, ST_SIGMA0 + k, e12[0][1]);
     add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[0][2]);
     add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[0][3]);
+    add_launch(P, seq, K_E12_20, ST_SIGMA0 + k, e12[0][4]);
     add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02[0]);
     add_launch(P, seq, K_E02F, ST_SIGMA0 + k, e02f[0]);
     add_launch(P, seq, K_E22S, ST_SIGMA0 + k, e22[1]);
@@ -498,6 +499,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12S_16, ST_SIGMA0 + k, e12[1][1]);
     add_launch(P, seq, K_E12S_24, ST_SIGMA0 + k, e12[1][2]);
     add_launch(P, seq, K_E12S_32, ST_SIGMA0 + k, e12[1][3]);
+    add_launch(P, seq, K_E12S_20, ST_SIGMA0 + k, e12[1][4]);
     add_launch(P, seq, K_E02S, ST_SIGMA0 + k, e02[1]);
     add_launch(P, seq, K_E02FS, ST_SIGMA0 + k, e02f[1]);
     add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
