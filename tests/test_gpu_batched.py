@@ -129,3 +129,40 @@ def test_graph_capture_of_forward_and_adjoint():
                 assert close(x, rx), (rep, i, "dB", t)
         other.energy(ins2)
         torch.cuda.synchronize()
+
+
+def test_asynchronous_call_then_synchronous_call_on_one_plan():
+    """An asynchronous evaluation followed at once by a synchronous one on
+    the same plan, workspace and stream, with different reference vectors and
+    output buffers: each returns its own energy (the second call must not
+    rewrite the descriptors the first call's queued copy still reads)."""
+    import torch
+    import paper_2608_11529_amd as M
+    name = "s_tiles"
+    pb = problem(name)
+    plan = M.Plan(M.desc_of_problem(pb))
+    eng = M.Engine(plan)
+    dev = eng.device
+    (h, Bs, c), = inputs_for(M, plan, [name], dev)
+    c2 = c.clone()
+    c2[0] += 0.3
+    ref1 = float(eng.energy([(h, Bs, c)], parts=False)[0].item())
+    ref2 = float(eng.energy([(h, Bs, c2)], parts=False)[0].item())
+    assert ref1 != ref2
+    L = M.capi.lib()
+    out1 = torch.full((1,), float("nan"), dtype=torch.float64, device=dev)
+    out2 = torch.full((1,), float("nan"), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        a1, k1 = eng._inputs([(h, Bs, c)])
+        a2, k2 = eng._inputs([(h, Bs, c2)])
+        # a long queue ahead of the first call keeps its descriptor copy pending
+        big = torch.randn(4096, 4096, dtype=torch.float64, device=dev)
+        for _ in range(4):
+            big = big @ big * 1e-3
+        assert L.mrpt2_energy_async(plan.handle, a1, eng.persistent.data_ptr(), eng.workspace.data_ptr(),
+                                    plan.workspace_bytes, eng._sptr(), out1.data_ptr(), None) == 0
+        assert L.mrpt2_energy(plan.handle, a2, eng.persistent.data_ptr(), eng.workspace.data_ptr(),
+                              plan.workspace_bytes, eng._sptr(), out2.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        assert float(out1[0]) == ref1 and float(out2[0]) == ref2
+        del k1, k2
