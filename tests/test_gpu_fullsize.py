@@ -35,7 +35,10 @@ def golden(name):
     if not os.path.exists(path):
         pytest.skip("oracle values %s not yet written (tests/golden/make_fullsize_golden.py)" % name)
     with open(path) as f:
-        return json.load(f)
+        g = json.load(f)
+    if "instances" not in g and "blocks" not in g:
+        pytest.skip("oracle values %s incomplete (run still in progress)" % name)
+    return g
 
 
 def c_of(g):
@@ -52,8 +55,8 @@ def block_index(plan, k, blk, n_tp):
     b_lo, b_hi = blk["b"]
     I, J = a_lo // 64, b_lo // 64
     tps = {}
-    for tp in range(n_tp):
-        d = plan.class_block(k, tp)
+    for tp in range(n_tp):                    # class (2,2): block tp is core pair 0, tile pair tp
+        d = plan.class_block(0, tp)
         tps[(d.a_lo // 64, d.b_lo // 64)] = tp
     tp = tps[(I, J)]
     nb = plan.class_blocks(k)
@@ -112,7 +115,11 @@ def test_whole_config_matches_oracle(name):
             idx = block_index(plan, k, blk, n_tp)
             got = math.fsum(partials[k][idx].tolist()) / norm
             want = blk["value"]
-            tol = 1e-12 + 1e-9 * abs(want) if prec == 0 else 1e-9 + 1e-6 * abs(want)
+            # the synthetic integrals decay as exp(-|p - q|/8), so blocks far
+            # from the occupied spinors hold values down to 1e-120: FP64 is
+            # checked relative to each block's own size, the mixed form (whose
+            # FP32 integrals underflow there) within 1e-6 relative plus 1e-9 Eh
+            tol = 1e-30 + 1e-9 * abs(want) if prec == 0 else 1e-9 + 1e-6 * abs(want)
             assert abs(got - want) <= tol, (name, prec, blk, got, want)
         del eng, plan
         torch.cuda.empty_cache()
