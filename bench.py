@@ -29,10 +29,6 @@ FP64_MFMA_PEAK = 78.6e12       # FLOP/s, dense FP64 matrix
 FP64_VALU_PEAK = 78.6e12       # FLOP/s, FP64 vector (256 CU x 64 lanes x 2 x 2.4 GHz)
 FP32_MFMA_PEAK = 157.3e12      # FLOP/s, dense FP32 matrix
 HBM_PEAK = 8.0e12              # B/s
-# HBM bytes per launch of k_b_e22 at c4 from rocprofv3 FETCH_SIZE (calibrated
-# against a device copy, profiles/k_e22_c4_hbm_counters.md) plus its written
-# partial sums; valid for the kernel as measured there
-E22_C4_HBM_BYTES = 2.0 * 18.32e6 * 1024 + 378 * 171 * 8
 
 
 def cpu_baseline(pb, seconds=15.0):
@@ -129,6 +125,53 @@ def roofline(dom, ms, cases, precision):
                 "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK, "traffic": None}
     return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
             "traffic": None}
+
+
+def whole_pass_roofline(pb, info, ms, precision, adjoint=False):
+    """Bound of one whole evaluation by the algorithmic work of the path:
+    MFMA F = complex multiply-adds x 8 of the integral builds and of the sigma
+    contractions (nonzero couplings), at the FP64 or FP32 matrix peak; FP64
+    vector work of the Epstein-Nesbet epilogue, 6 instructions per external
+    determinant, at 39.3e12 instructions/s.  The adjoint doubles both counts
+    (every product has two operand adjoints; every determinant's epilogue is
+    recomputed and differentiated).  The bound is the larger time (the two
+    units could overlap), the fraction bound / measured."""
+    mixed = precision == "mixed"
+    k = 2.0 if adjoint else 1.0
+    flop = k * (info.flop_integral + info.flop_sigma)
+    slots = k * 6.0 * info.n_ext
+    t_mfma = flop / (FP32_MFMA_PEAK if mixed else FP64_MFMA_PEAK)
+    t_valu = slots / (FP64_VALU_PEAK / 2.0)
+    t = max(t_mfma, t_valu)
+    return {"bound_s": t, "bound": "mfma" if t_mfma >= t_valu else "alu", "t_mfma_s": t_mfma, "t_valu_s": t_valu,
+            "measured_s": ms * 1e-3, "frac": t / (ms * 1e-3)}
+
+
+def roofline_backward(dom, ms, pb, info, precision):
+    """Roofline of the dominant adjoint stage: the pair-integral adjoint GEMM
+    (two operand adjoints of the forward build: 2 x its flops, on FP32 or FP64
+    MFMA), or a per-class pass on the FP64 vector units counted as twice the
+    forward epilogue plus two complex multiply-adds (8 instructions) per
+    coupling and determinant (the recomputed sigma and its adjoint)."""
+    import paper_2608_11529_amd as M
+    mixed = precision == "mixed"
+    if dom == "bwd_pair_integrals":
+        flop = 2.0 * 8.0 * ((pb.n_c + pb.n_a) * (pb.n_c + pb.n_a - 1) // 2) * pb.n_v * (pb.n_v - 1) * pb.n_l
+        peak = FP32_MFMA_PEAK if mixed else FP64_MFMA_PEAK
+        ach = flop / (ms * 1e-3)
+        return {"kernel": "pair-integral adjoint GEMM", "bound": "mfma", "achieved": ach / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "ms_per_launch": ms}
+    if dom.startswith("bwd_row_") or dom.startswith("bwd_str_"):
+        k = M.CLASSES.index(tuple(int(x) for x in dom[-2:]))
+        n_q = info.n_ext_class[k]
+        per_det = 12.0 + (8.0 * info.n_conn_class[k] / max(1, info.n_strings_class[k]) if k != 0 else 0.0)
+        ops = n_q * per_det
+        ach = ops / (ms * 1e-3)
+        peak = FP64_VALU_PEAK / 2.0
+        return {"kernel": "adjoint pass %s (FP64 vector, %.1f instructions per determinant)" % (dom, per_det),
+                "bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Top/s", "frac": ach / peak,
+                "traffic": None, "ms_per_launch": ms}
+    return {"kernel": dom, "bound": None, "frac": None, "ms_per_launch": ms}
 
 
 def tuning_note(autotune):
@@ -287,7 +330,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["mixed", "fp64"],
+                    help="precision of the headline value (the other form is measured beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--backward-steps", type=int, default=1,
                     help="timed adjoint calls after the forward measurement (0: none)")
@@ -299,6 +343,9 @@ def main():
     ap.add_argument("--davidson", type=int, default=3, metavar="K",
                     help="also time the device Davidson solver for the 1 and K lowest reference states against "
                          "the host eigensolver path; 0: skip")
+    ap.add_argument("--c3-steps", type=int, default=2, metavar="K",
+                    help="after the c4 measurement also time the 64-instance batch c3 (one batched call "
+                         "against 64 one-instance calls, K steps each); 0: skip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -372,8 +419,9 @@ def main():
     roof = roofline(dom, stage[dom], [(pb, info)], args.precision)
     n_v, n_l = pb.n_v, pb.n_l
     roof["ms_per_launch"] = stage[dom]
-    if dom == "sigma_22" and args.config == "c4":
-        roof["traffic"] = E22_C4_HBM_BYTES
+    # HBM bytes need the profiler's counters (FETCH_SIZE, WRITE_SIZE), which a
+    # timed run does not collect: traffic stays null here and the counter
+    # figures of the kernels are kept with their commands under profiles/
     other = "fp64" if args.precision == "mixed" else "mixed"
     out = {
         "metric": "external dets/sec + E2 evals/sec (mixed vs FP64, |dE2| Eh), 1 MI355X",
@@ -395,10 +443,14 @@ def main():
         "e2": head["e2"],
         "compare": {"precision": other, "value": info.n_ext / (res[other]["ms"] * 1e-3),
                     "ms_per_step": res[other]["ms"], "e2": res[other]["e2"],
+                    "e2_evals_per_s": 1000.0 / res[other]["ms"],
+                    "stages_ms": {k: round(v, 3) for k, v in res[other]["stage"].items() if v > 0},
+                    "roofline": whole_pass_roofline(pb, info, res[other]["ms"], other),
                     "abs_dE2_mixed_vs_fp64": abs(res["mixed"]["e2"] - res["fp64"]["e2"]),
                     "abs_dE2_per_class": [abs(x - y) for x, y in zip(res["mixed"]["parts"][:9], res["fp64"]["parts"][:9])]},
         "stages_ms": {k: round(v, 3) for k, v in stage.items() if v > 0},
         "roofline": roof,
+        "roofline_whole_pass": whole_pass_roofline(pb, info, ms_per_step, args.precision),
     }
 
     def guarded(key, fn):
@@ -506,7 +558,10 @@ def main():
         bwd_ms = (time.perf_counter() - t0) * 1000.0 / args.backward_steps
         (dh, dBs, dc), = outs
         bst = {k: v / args.backward_steps for k, v in bsum.items()}
+        bdom = max((k for k in bst if k.startswith("bwd_")), key=lambda k: bst[k])
         out["backward"] = {
+            "roofline": roofline_backward(bdom, bst[bdom], pb, info, args.precision),
+            "roofline_whole_pass": whole_pass_roofline(pb, info, bwd_ms, args.precision, adjoint=True),
             "precision": args.precision, "steps": args.backward_steps, "ms_per_step": bwd_ms,
             "grad_evals_per_s": 1000.0 / bwd_ms, "dets_per_s": info.n_ext / (bwd_ms * 1e-3),
             "ratio_to_forward": bwd_ms / ms_per_step,
@@ -518,9 +573,20 @@ def main():
               file=sys.stderr, flush=True)
         del outs, dh, dBs, dc
         eng.grad_workspace = None
-    if not args.no_cpu_baseline:
-        del Bs, h, engs, eng
+    if not args.no_cpu_baseline or args.c3_steps > 0:
+        del Bs, h, engs
+        eng = None
         torch.cuda.empty_cache()
+    if args.c3_steps > 0 and args.config == "c4":
+        # the batched form on its own workload, beside the headline
+        def measure_c3():
+            c3 = bench_batched(argparse.Namespace(steps=args.c3_steps, warmup=1, precision=args.precision,
+                                                  backward_steps=0))
+            out["batched_c3"] = {k: c3[k] for k in ("value", "unit", "ms_per_step", "e2_evals_per_s", "dtype",
+                                                     "config", "compare", "roofline", "stages_ms")}
+            torch.cuda.empty_cache()
+        guarded("batched_c3", measure_c3)
+    if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)
 
