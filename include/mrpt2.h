@@ -374,6 +374,29 @@ mrpt2_status mrpt2_plan_class_strings(mrpt2_plan_t plan, int32_t inst, int32_t c
 mrpt2_status mrpt2_class_partials(mrpt2_plan_t plan, int32_t inst, int32_t cls, const void* workspace,
                                   hipStream_t stream, double* out);
 
+/* ---- energy without caller-provided workspace ------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * mrpt2_energy with the workspace replaced by a device array the library
+ * owns, MRPT2_STATIC_WORKSPACE_BYTES per GPU, held from the library's load
+ * until the process ends.  The call allocates nothing (no device, pinned or
+ * heap memory): plan tables (persistent region, uploaded by
+ * mrpt2_plan_upload), inputs and outputs are the caller's, as for
+ * mrpt2_energy, and the instance descriptors are staged in host memory the
+ * plan reserved when it was built.  Plans whose workspace (mrpt2_plan_sizes)
+ * exceeds the array are rejected with MRPT2_ERR_WORKSPACE before any work.
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents (nothing in the energy sequence reads it before writing it):
+ * calls that overlap on one GPU race, so calls on one device must be
+ * serialised by the caller (one stream, or synchronisation between streams).
+ * The call ends with a synchronisation of stream (error flag), like
+ * mrpt2_energy.  Outputs: e2 [n_inst], parts [n_inst][12] (nullable), device
+ * pointers.  mrpt2_static_workspace_bytes reports the array's size. */
+#define MRPT2_STATIC_WORKSPACE_BYTES (64ull << 20)
+mrpt2_status mrpt2_energy_static(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                 hipStream_t stream, double* e2, double* parts);
+mrpt2_status mrpt2_static_workspace_bytes(size_t* bytes);
+
 void mrpt2_plan_destroy(mrpt2_plan_t plan);
 const char* mrpt2_status_string(mrpt2_status s);
 

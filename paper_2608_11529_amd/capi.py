@@ -177,6 +177,10 @@ def lib():
                                                   ctypes.c_size_t, vp, ctypes.POINTER(Grads), vp, vp,
                                                   ctypes.POINTER(ctypes.c_float)]
         L.mrpt2_energy_backward_timed.restype = st
+        L.mrpt2_energy_static.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, vp, vp]
+        L.mrpt2_energy_static.restype = st
+        L.mrpt2_static_workspace_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.mrpt2_static_workspace_bytes.restype = st
         L.mrpt2_plan_destroy.argtypes = [vp]
         L.mrpt2_plan_destroy.restype = None
         L.mrpt2_status_string.argtypes = [st]
@@ -197,4 +201,5 @@ EXPORTED = [
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",
+    "mrpt2_energy_static", "mrpt2_static_workspace_bytes",
 ]

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -653,6 +654,38 @@ mrpt2_status energy_enqueue(mrpt2_plan_t plan, const mrpt2_inputs* in, const voi
 
 }  // namespace
 
+// ---- a workspace the library owns, for callers that cannot allocate --------
+// File-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  In host code its name is not a device address;
+// the address is taken once per device with hipGetSymbolAddress and used
+// wherever the array's memory is needed.
+static __device__ __align__(256) char scratch[MRPT2_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's array (taken on the first call
+// on that device, with that device current).
+mrpt2_status scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return MRPT2_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return MRPT2_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MRPT2_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out) {
@@ -714,6 +747,35 @@ mrpt2_status mrpt2_energy(mrpt2_plan_t plan, const mrpt2_inputs* in, const void*
   mrpt2_status s = energy_enqueue(plan, in, persistent, workspace, workspace_bytes, st, e2, parts, tm);
   if (s != MRPT2_OK) return s;
   return read_flag(plan->p, workspace, st);
+}
+
+mrpt2_status mrpt2_energy_static(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent,
+                                 hipStream_t st, double* e2, double* parts) {
+  if (!plan || !in || !e2 || !persistent) return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  if (P.workspace_bytes > (size_t)MRPT2_STATIC_WORKSPACE_BYTES) return MRPT2_ERR_WORKSPACE;
+  if ((uintptr_t)persistent & 255) return MRPT2_ERR_ARG;
+  void* work = nullptr;
+  mrpt2_status s = scratch_address(&work);
+  if (s != MRPT2_OK) return s;
+  // descriptors staged in the plan's host buffer (sized when the plan was
+  // built) and copied from there; the call ends with a stream
+  // synchronisation, so the next call finds the buffer free
+  s = fill_insts(P, in, (const char*)persistent, (char*)work, P.static_stage.data(), e2, parts, nullptr, -1,
+                 nullptr, nullptr, nullptr);
+  if (s != MRPT2_OK) return s;
+  HIPCHK(hipMemcpyAsync((char*)work + P.off_insts, P.static_stage.data(), kInstBytes * P.inst.size(),
+                        hipMemcpyHostToDevice, st));
+  Timer tm;
+  s = run(P, P.energy, (const char*)persistent, (char*)work, st, tm);
+  if (s != MRPT2_OK) return s;
+  return read_flag(P, work, st);
+}
+
+mrpt2_status mrpt2_static_workspace_bytes(size_t* bytes) {
+  if (!bytes) return MRPT2_ERR_ARG;
+  *bytes = (size_t)MRPT2_STATIC_WORKSPACE_BYTES;
+  return MRPT2_OK;
 }
 
 mrpt2_status mrpt2_energy_roots(mrpt2_plan_t plan, const mrpt2_inputs* in, int32_t n_roots,

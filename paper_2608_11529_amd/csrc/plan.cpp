@@ -1103,6 +1103,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
   out->persistent_bytes = pers;
   out->workspace_bytes = work;
   out->host_blob.assign(pers, 0);
+  out->static_stage.assign(kInstBytes * (size_t)n_inst, 0);
   for (auto& ip : out->inst)
     std::memcpy(out->host_blob.data() + ip.persistent_base, ip.host_blob.data(), ip.persistent_bytes);
   if (!out->jobs.empty())

@@ -157,6 +157,7 @@ struct Plan {
   size_t grad_bytes = 0;              // gradient workspace of mrpt2_energy_backward
   std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
   std::vector<char> host_blob;
+  std::vector<char> static_stage;     // host staging of the descriptors for mrpt2_energy_static
   void* pinned = nullptr;             // host staging of the instance descriptors
   size_t pinned_bytes = 0;            // its size (one descriptor set per state of a multi-state call)
   hipEvent_t staged = nullptr;        // recorded after each copy from the pinned staging buffer
