@@ -112,9 +112,13 @@ typedef struct {
       class: for (1,2) the active spinors t of the reference determinants
       core + alpha' + t it couples to, which sizes the dense-coefficient
       kernels (up to 8, 16, 24 or 32 patterns; more run the generic kernel) */
+  int64_t n_ref_couplings;          /* off-diagonal entries of the excitation
+      lists of P (pairs of reference determinants one or two active
+      replacements apart), which the direct sigma-build in P applies */
   int32_t kernel_class[MRPT2_N_CLASS];      /* sigma kernel of each class:
       0 generic (excitation lists), 1 class (2,2) string sums, 2 class (1,2)
-      dense coefficients, 3 class (0,2) string tiles on MFMA */
+      dense coefficients, 3 class (0,2) string tiles on MFMA, 4 class (2,1)
+      dense coefficients */
 } mrpt2_info;
 
 /* Inputs of one instance (device pointers). */
@@ -281,6 +285,31 @@ mrpt2_status mrpt2_reference_states(mrpt2_plan_t plan, int32_t inst, const mrpt2
                                     double tol, int32_t max_iter, const void* persistent, void* workspace,
                                     size_t workspace_bytes, void* dv, size_t dv_bytes, hipStream_t stream,
                                     double* c_out, double* e_out, int32_t* iterations);
+
+/* Direct sigma-build in P (Sec. 2.4, the sigma of eq. sumsigma restricted
+ * to the primary space): Y = (H_PP - E_core) X for n_vec vectors without
+ * storing H_PP.  The plan keeps, for every reference determinant, the list
+ * of reference determinants reached from it by one or two replacements of
+ * active spinors (mrpt2_info.n_ref_couplings entries in all); each row
+ * applies its list with elements from the Slater-Condon rules on the
+ * integral tables (the same rules as mrpt2_reference_hamiltonian) and adds
+ * its diagonal.  x, y: device complex [n_vec][N_P] (plan order), distinct.
+ * The tables are rebuilt from h and B in workspace first.  Synchronises
+ * stream; MRPT2_ERR_NUMERIC on non-finite tables. */
+mrpt2_status mrpt2_reference_sigma(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in, int32_t n_vec,
+                                   const double* x, const void* persistent, void* workspace,
+                                   size_t workspace_bytes, hipStream_t stream, double* y);
+
+/* mrpt2_reference_states with the direct sigma-build in P instead of a
+ * stored H_PP: the solver region (mrpt2_reference_states_direct_size) holds
+ * only the search space, its image, their restart copies, Ritz vectors,
+ * residuals and small matrices, O(N_P) per vector, so reference spaces far
+ * beyond a dense H_PP fit.  Same arguments, results and errors. */
+mrpt2_status mrpt2_reference_states_direct_size(mrpt2_plan_t plan, int32_t inst, int32_t n_states, size_t* bytes);
+mrpt2_status mrpt2_reference_states_direct(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
+                                           int32_t n_states, double tol, int32_t max_iter, const void* persistent,
+                                           void* workspace, size_t workspace_bytes, void* dv, size_t dv_bytes,
+                                           hipStream_t stream, double* c_out, double* e_out, int32_t* iterations);
 
 /* Eigenpairs of a complex Hermitian n x n matrix (host memory, row-major,
  * interleaved complex; only its Hermitian part is used) by cyclic Jacobi

@@ -302,28 +302,50 @@ class Engine:
                    "mrpt2_class_partials")
         return out[:n]
 
-    def reference_states(self, h, Bs, k=1, tol=1e-10, max_iter=500, inst=0):
+    def reference_states(self, h, Bs, k=1, tol=1e-10, max_iter=500, inst=0, direct=False):
         """The k lowest eigenpairs of H_PP - E_core by the library's block
         Davidson solver on the device: C [k, N_P] complex128 device tensor in
         plan order (unit norm, largest component real positive), energies
-        (host numpy, ascending) and the iteration count."""
+        (host numpy, ascending) and the iteration count.  direct=True applies
+        H_PP by the direct sigma-build in P (excitation lists, no stored
+        H_PP) instead of a dense H_PP."""
         torch = self.torch
         n_p = self.plan.info(inst).n_ref
         nbytes = ctypes.c_size_t()
-        capi.check(capi.lib().mrpt2_reference_states_size(self.plan.handle, inst, k, ctypes.byref(nbytes)),
-                   "mrpt2_reference_states_size")
+        size_fn = "mrpt2_reference_states_direct_size" if direct else "mrpt2_reference_states_size"
+        capi.check(getattr(capi.lib(), size_fn)(self.plan.handle, inst, k, ctypes.byref(nbytes)), size_fn)
         dv = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
         C = torch.empty((k, n_p), dtype=torch.complex128, device=self.device)
         e = np.zeros(k)
         its = ctypes.c_int32()
         arr, keep = self._inputs([(h, Bs, None)], inst=inst)
-        code = capi.lib().mrpt2_reference_states(self.plan.handle, inst, arr, k, tol, max_iter,
-                                                 self.persistent.data_ptr(), self.workspace.data_ptr(),
-                                                 self.plan.workspace_bytes, dv.data_ptr(), nbytes.value,
-                                                 self._sptr(), C.data_ptr(), e.ctypes.data, ctypes.byref(its))
-        capi.check(code, "mrpt2_reference_states")
+        fn = "mrpt2_reference_states_direct" if direct else "mrpt2_reference_states"
+        code = getattr(capi.lib(), fn)(self.plan.handle, inst, arr, k, tol, max_iter,
+                                       self.persistent.data_ptr(), self.workspace.data_ptr(),
+                                       self.plan.workspace_bytes, dv.data_ptr(), nbytes.value,
+                                       self._sptr(), C.data_ptr(), e.ctypes.data, ctypes.byref(its))
+        capi.check(code, fn)
         del keep, dv
         return C, e, its.value
+
+    def reference_sigma(self, h, Bs, X, inst=0):
+        """(H_PP - E_core) X for the rows of X (complex128 [m, N_P] device
+        tensor, plan order) by the direct sigma-build in P: excitation lists
+        of the reference space, elements from the Slater-Condon rules, no
+        stored H_PP."""
+        torch = self.torch
+        n_p = self.plan.info(inst).n_ref
+        X = X.reshape(-1, n_p) if X.dim() == 1 else X
+        if X.dtype != torch.complex128 or X.shape[-1] != n_p or not X.is_contiguous() or X.device != self.device:
+            raise ValueError("X must be a contiguous complex128 [m, %d] tensor on the engine's device" % n_p)
+        Y = torch.empty_like(X)
+        arr, keep = self._inputs([(h, Bs, None)], inst=inst)
+        code = capi.lib().mrpt2_reference_sigma(self.plan.handle, inst, arr, X.shape[0], X.data_ptr(),
+                                                self.persistent.data_ptr(), self.workspace.data_ptr(),
+                                                self.plan.workspace_bytes, self._sptr(), Y.data_ptr())
+        capi.check(code, "mrpt2_reference_sigma")
+        del keep
+        return Y
 
     def reference_hamiltonian(self, h, Bs, inst=0):
         torch = self.torch

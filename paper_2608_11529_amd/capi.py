@@ -69,6 +69,7 @@ class Info(ctypes.Structure):
         ("flop_sigma", ctypes.c_double),
         ("bytes_factors", ctypes.c_double),
         ("n_patterns_class", ctypes.c_int32 * N_CLASS),
+        ("n_ref_couplings", ctypes.c_int64),
         ("kernel_class", ctypes.c_int32 * N_CLASS),
     ]
 
@@ -149,6 +150,13 @@ def lib():
                                              ctypes.c_int32, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp, vp,
                                              ctypes.POINTER(ctypes.c_int32)]
         L.mrpt2_reference_states.restype = st
+        L.mrpt2_reference_sigma.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Inputs), ctypes.c_int32, vp, vp, vp,
+                                            ctypes.c_size_t, vp, vp]
+        L.mrpt2_reference_sigma.restype = st
+        L.mrpt2_reference_states_direct_size.argtypes = L.mrpt2_reference_states_size.argtypes
+        L.mrpt2_reference_states_direct_size.restype = st
+        L.mrpt2_reference_states_direct.argtypes = L.mrpt2_reference_states.argtypes
+        L.mrpt2_reference_states_direct.restype = st
         L.mrpt2_hermitian_eigh.argtypes = [ctypes.c_int32, vp, vp, vp]
         L.mrpt2_hermitian_eigh.restype = st
         L.mrpt2_energy_timed.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, vp, vp,
@@ -201,5 +209,6 @@ EXPORTED = [
     "mrpt2_plan_destroy", "mrpt2_status_string", "mrpt2_plan_class_blocks", "mrpt2_plan_class_block",
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",
-    "mrpt2_energy_static", "mrpt2_static_workspace_bytes",
+    "mrpt2_energy_static", "mrpt2_static_workspace_bytes", "mrpt2_reference_sigma",
+    "mrpt2_reference_states_direct_size", "mrpt2_reference_states_direct",
 ]

@@ -71,6 +71,8 @@ struct Dev {
   const double* sign;        // [n_l]
   const double* scale;       // [n_l]
   const uint64_t* pstrings;  // [n_p]
+  const int64_t* plist_ptr;  // [n_p + 1] excitation lists of P (CSR)
+  const int32_t* plist_col;  // reference strings one or two active replacements away
   const int32_t* hole_pairs; // [C(n_c,2)][2]
   const int32_t* tile_pairs; // [n_tp][2]
   double* dg;                // [n_l][n]   scale * Re B[L][p][p]

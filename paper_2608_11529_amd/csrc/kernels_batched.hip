@@ -84,6 +84,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
   e22_body<LS>(I.d, I.cls[0], flag, bid);
 }
 template <int MJ, bool LS>
+__global__ void __launch_bounds__(256) k_b_e21(MRPT2_ARGS) {
+  MRPT2_JOB
+  e21_body<MJ, LS>(I.d, I.cls[3], flag, bid);
+}
+template <int MJ, bool LS>
 __global__ void __launch_bounds__(256) k_b_e12(MRPT2_ARGS) {
   MRPT2_JOB
   e12_body<MJ, LS>(I.d, I.cls[1], flag, bid);

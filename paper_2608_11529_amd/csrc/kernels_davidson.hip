@@ -105,4 +105,59 @@ __global__ void __launch_bounds__(256) k_dv_diag(const double2* __restrict__ H, 
   if (i < n) d[i] = H[(int64_t)i * n + i].x;
 }
 
+// Direct sigma-build in P: W[c0 + j] = (H_PP - E_core) X[c0 + j], j < nc,
+// without a stored H_PP.  Row i applies its excitation list (the reference
+// strings one or two active replacements away) with elements from the
+// Slater-Condon rules (hpp_element, as the dense H_PP) and adds its diagonal
+// (the active-space energy).  One wave per row, the list entries spread over
+// the lanes; every element serves all nc vectors.  grid (ceil(n / 4)),
+// block 256.
+__global__ void __launch_bounds__(256) k_dv_hx_direct(const Inst* __restrict__ insts, int inst,
+                                                       const double2* __restrict__ X, double2* __restrict__ W,
+                                                       int n, int c0, int nc) {
+  const Dev& d = inst_at(insts, inst).d;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  if (i >= n) return;                     // whole wave
+  const uint64_t bi = d.pstrings[i];
+  double2 acc[DV_COLS];
+#pragma unroll
+  for (int j = 0; j < DV_COLS; ++j) acc[j] = make_double2(0.0, 0.0);
+  const int64_t e1 = d.plist_ptr[i + 1];
+  for (int64_t e = d.plist_ptr[i] + lane; e < e1; e += 64) {
+    const int t = d.plist_col[e];
+    const double2 hv = hpp_element(d, bi, d.pstrings[t]);
+#pragma unroll
+    for (int j = 0; j < DV_COLS; ++j)
+      if (j < nc) acc[j] = cfma(hv, X[(int64_t)(c0 + j) * n + t], acc[j]);
+  }
+  if (lane == 0) {
+    const double e = act_energy(d, bi);
+#pragma unroll
+    for (int j = 0; j < DV_COLS; ++j)
+      if (j < nc) {
+        const double2 x = X[(int64_t)(c0 + j) * n + i];
+        acc[j] = make_double2(fma(e, x.x, acc[j].x), fma(e, x.y, acc[j].y));
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < DV_COLS; ++j) {
+    double x = acc[j].x, y = acc[j].y;
+    for (int off = 32; off > 0; off >>= 1) {
+      x += __shfl_down(x, off, 64);
+      y += __shfl_down(y, off, 64);
+    }
+    if (lane == 0 && j < nc) W[(int64_t)(c0 + j) * n + i] = make_double2(x, y);
+  }
+}
+
+// Diagonal of H_PP - E_core (the active-space energies), for the direct
+// solver's starting vectors and preconditioner.  grid (ceil(n / 256)).
+__global__ void __launch_bounds__(256) k_dv_diag_direct(const Inst* __restrict__ insts, int inst, double* dg,
+                                                         int n) {
+  const Dev& d = inst_at(insts, inst).d;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dg[i] = act_energy(d, d.pstrings[i]);
+}
+
 }  // namespace mrpt2

@@ -30,15 +30,10 @@ __device__ double act_energy(const Dev& d, uint64_t al) {
   return e;
 }
 
-// Dense reference-space Hamiltonian minus the core energy, by the
-// Slater-Condon rules within the active space (core and frozen core folded
-// into f).  Row i = bra, column j = ket.  grid (ceil(np/16), ceil(np/16)),
-// block (16, 16).
-__device__ __forceinline__ void hpp_body(const Dev& d, double2* __restrict__ out, const uint3 bid) {
-  const int j = bid.x * 16 + (threadIdx.x & 15);
-  const int i = bid.y * 16 + (threadIdx.x >> 4);
-  if (i >= d.n_p || j >= d.n_p) return;
-  const uint64_t bi = d.pstrings[i], bj = d.pstrings[j];
+// Element <bi|H|bj> of the reference-space Hamiltonian minus the core
+// energy, by the Slater-Condon rules within the active space (core and frozen
+// core folded into f).  bi = bra, bj = ket (active strings).
+__device__ __forceinline__ double2 hpp_element(const Dev& d, uint64_t bi, uint64_t bj) {
   const uint64_t cre = bi & ~bj, ann = bj & ~bi;
   const int nd = popc64(cre);
   double2 v = make_double2(0.0, 0.0);
@@ -74,7 +69,16 @@ __device__ __forceinline__ void hpp_body(const Dev& d, double2* __restrict__ out
     v = csub(Gv(d, nc + q1, p2, nc + q2, p1), Gv(d, nc + q2, p2, nc + q1, p1));
     if (par) v = make_double2(-v.x, -v.y);
   }
-  out[(int64_t)i * d.n_p + j] = v;
+  return v;
+}
+
+// Dense reference-space Hamiltonian minus the core energy.  Row i = bra,
+// column j = ket.  grid (ceil(np/16), ceil(np/16)), block (16, 16).
+__device__ __forceinline__ void hpp_body(const Dev& d, double2* __restrict__ out, const uint3 bid) {
+  const int j = bid.x * 16 + (threadIdx.x & 15);
+  const int i = bid.y * 16 + (threadIdx.x >> 4);
+  if (i >= d.n_p || j >= d.n_p) return;
+  out[(int64_t)i * d.n_p + j] = hpp_element(d, d.pstrings[i], d.pstrings[j]);
 }
 
 // sigma_P = H~ C, one wavefront per row.  grid (np), block 64.
@@ -299,7 +303,9 @@ __device__ __forceinline__ void sigma_body(const Dev& d, const ClassDev& cd, int
     if (e1 > e0) {
       const double t = cabs2(sig) * en_weight(del, b2);
       if (valid) {
-        if (!(del != 0.0) || !isfinite(t)) bad = true;
+        // an exactly vanishing denominator leaves eq. pt2en undefined; under
+        // the level shift the weight Delta^3/(Delta^4 + b^2) is 0 there
+        if ((b2 == 0.0 && !(del != 0.0)) || !isfinite(t)) bad = true;
         acc += t;
       }
     }
@@ -641,6 +647,106 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
     __syncthreads();
   }
   if (tid < 2) cd.part[pbase + tid] = red[tid][0];
+}
+
+
+// Class (2,1): K = core - {c, c'} + alpha + {a}, reached from
+// L = core + alpha - {u} by a_c a_c' -> a+_a a+_u:
+//   sigma_K = sum_u X[u][(c c', a)] D[alpha][u]   (X = <au||cc'>, xbuild),
+//   Delta   = T + eps_c + Uc_c + eps_c' + Uc_c' - W_cc' - eps_a - Uv_a + W_ca + W_c'a.
+// One thread per (core pair, a) with the couplings of its row in registers;
+// strings walked in chunks staged in LDS, the patterns present in four
+// strings selected by a wave-uniform mask (strings ordered by pattern mask),
+// four fractions merged per reciprocal.  The generic kernel read every
+// coupling of every determinant from memory.  grid (C(n_c, 2), ceil(n_v / 256)),
+// block 256: core pairs fastest, so that the blocks sharing a range of
+// virtual spinors (the same string-table columns) run together.
+constexpr int SC21 = 16;
+
+template <int MJ, bool LS>
+__device__ __forceinline__ void e21_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
+  __shared__ double sUv[SC21][256];
+  __shared__ double2 sD[SC21][MJ];
+  __shared__ double sG[SC21];
+  __shared__ uint32_t sM[SC21];
+  __shared__ double red[256];
+  const int hp = bid.x, at = bid.y;
+  const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
+  const int tid = threadIdx.x;
+  const int nv = d.n_v, nc = d.n_c;
+  const int a0 = at * 256 + tid;
+  const bool valid = a0 < nv;
+  const int a = valid ? a0 : 0;
+  const int64_t r = (int64_t)hp * nv + a;
+  const int J = cd.n_pat;
+  const int64_t gfc = d.n_fc, gv = d.n_fc + d.n_o;
+  const double* __restrict__ W = d.W;
+  const double rowc = -d.eps[d.n_o + a] + W[(gfc + c0) * d.n + gv + a] + W[(gfc + c1) * d.n + gv + a];
+  const double gconst = d.eps[c0] + d.eps[c1] - W[(gfc + c0) * d.n + gfc + c1];
+  double2 X[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j) X[j] = (j < J) ? cd.X[(int64_t)j * cd.n_rows + r] : make_double2(0.0, 0.0);
+  const int64_t S = cd.n_str;
+  const double lsb2 = d.ls_b2;
+  (void)lsb2;
+  double acc = 0.0;
+  for (int64_t s0 = 0; s0 < S; s0 += SC21) {
+    __syncthreads();
+    for (int e = tid; e < SC21 * 256; e += 256) {
+      const int sl = e >> 8, l = e & 255;
+      const int64_t s = s0 + sl;
+      const int aa = at * 256 + l;
+      sUv[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
+    }
+    for (int e = tid; e < SC21 * MJ; e += 256) {
+      const int sl = e / MJ, j = e % MJ;
+      const int64_t s = s0 + sl;
+      sD[sl][j] = (s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
+    }
+    if (tid < SC21) {
+      const int64_t s = s0 + tid;
+      sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c0] + cd.Uc[s * nc + c1] + gconst : (LS ? 1e6 : 1e30);
+      sM[tid] = (s < S) ? cd.mask[s] : 0u;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int sl = 0; sl < SC21; sl += 4) {
+      double2 sg[4];
+      const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < MJ; ++j)
+        if (um & (1u << j)) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
+        }
+      double w[4], dd[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        w[k] = cabs2(sg[k]);
+        dd[k] = (sG[sl + k] + rowc) - sUv[sl + k][tid];
+        if constexpr (LS) {
+          const double d2 = dd[k] * dd[k];
+          w[k] *= dd[k] * d2;
+          dd[k] = fma(d2, d2, lsb2);
+        }
+      }
+      const double n01 = fma(w[0], dd[1], w[1] * dd[0]);
+      const double q01 = dd[0] * dd[1];
+      const double n23 = fma(w[2], dd[3], w[3] * dd[2]);
+      const double q23 = dd[2] * dd[3];
+      acc = fma(fma(n01, q23, n23 * q01), rcp_nr(q01 * q23), acc);
+    }
+  }
+  if (valid && !isfinite(acc)) *flag = 2;
+  red[tid] = valid ? acc : 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) cd.part[(int64_t)at * cd.n_holes + hp] = red[0];
 }
 
 

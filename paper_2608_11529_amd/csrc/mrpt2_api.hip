@@ -64,6 +64,8 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.sign = (const double*)(P + ip.off_sign);
   d.scale = (const double*)(P + ip.off_scale);
   d.pstrings = (const uint64_t*)(P + ip.off_pstrings);
+  d.plist_ptr = (const int64_t*)(P + ip.off_plist_ptr);
+  d.plist_col = (const int32_t*)(P + ip.off_plist_col);
   d.hole_pairs = (const int32_t*)(P + ip.off_hole_pairs);
   d.tile_pairs = (const int32_t*)(P + ip.off_tile_pairs);
   d.dg = (double*)(W + ip.off_dg);
@@ -290,7 +292,8 @@ bool depends_on_c(int kid) {
     case K_SIGP: case K_E0: case K_CTAB: case K_DCOEF: case K_E02COEF: case K_E22:
     case K_E12_8: case K_E12_16: case K_E12_20: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
     case K_E22S: case K_E12S_8: case K_E12S_16: case K_E12S_20: case K_E12S_24: case K_E12S_32: case K_E02S:
-    case K_E02FS:
+    case K_E02FS: case K_E21_8: case K_E21_16: case K_E21_20: case K_E21_24: case K_E21_32: case K_E21S_8:
+    case K_E21S_16: case K_E21S_20: case K_E21S_24: case K_E21S_32:
     case K_SIG22: case K_SIG12: case K_SIG02: case K_SIG21: case K_SIG11: case K_SIG01:
     case K_SIG20: case K_SIG10: case K_SIG00: case K_FINISH:
       return true;
@@ -334,6 +337,16 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E12_8: hipLaunchKernelGGL((k_b_e12<8, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_16: hipLaunchKernelGGL((k_b_e12<16, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_20: hipLaunchKernelGGL((k_b_e12<20, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21_8: hipLaunchKernelGGL((k_b_e21<8, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21_16: hipLaunchKernelGGL((k_b_e21<16, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21_20: hipLaunchKernelGGL((k_b_e21<20, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21_24: hipLaunchKernelGGL((k_b_e21<24, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21_32: hipLaunchKernelGGL((k_b_e21<32, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21S_8: hipLaunchKernelGGL((k_b_e21<8, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21S_16: hipLaunchKernelGGL((k_b_e21<16, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21S_20: hipLaunchKernelGGL((k_b_e21<20, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21S_24: hipLaunchKernelGGL((k_b_e21<24, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E21S_32: hipLaunchKernelGGL((k_b_e21<32, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_24: hipLaunchKernelGGL((k_b_e12<24, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_32: hipLaunchKernelGGL((k_b_e12<32, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02: hipLaunchKernelGGL((k_b_e02<false, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
@@ -439,7 +452,7 @@ struct DvLayout {
   size_t H = 0, V = 0, W = 0, Vt = 0, Wt = 0, X = 0, R = 0, G = 0, M = 0, th = 0, sc = 0, dg = 0, total = 0;
 };
 
-DvLayout dv_layout(int64_t n, int k) {
+DvLayout dv_layout(int64_t n, int k, bool dense = true) {
   DvLayout L;
   L.mmax = (int)std::min<int64_t>(n, std::max(6 * k, 30));
   size_t off = 0;
@@ -449,7 +462,7 @@ DvLayout dv_layout(int64_t n, int k) {
     return o;
   };
   const size_t vec = (size_t)n * 16, mm = (size_t)L.mmax;
-  L.H = take((size_t)n * vec);
+  L.H = take(dense ? (size_t)n * vec : 0);
   L.V = take(mm * vec);
   L.W = take(mm * vec);
   L.Vt = take(mm * vec);
@@ -485,8 +498,11 @@ mrpt2_status dv_copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kin
 // With n > mmax = max(6k, 30), a restart keeps q >= 2k Ritz vectors (the
 // restart happens at m > mmax - k >= 5k), so the basis never holds fewer
 // than k vectors.
+// dinst: the instance descriptors for the direct sigma-build in P (H_PP not
+// stored), or null for the dense H_PP in the solver region.
 mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double tol, int max_iter,
-                      hipStream_t st, double* c_out, double* e_out, int32_t* iters) {
+                      hipStream_t st, double* c_out, double* e_out, int32_t* iters, const Inst* dinst = nullptr,
+                      int di = 0) {
   using cd = std::complex<double>;
   const int n = (int)n64, mmax = L.mmax;
   double2* H = (double2*)(base + L.H);
@@ -504,7 +520,8 @@ mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double 
   const dim3 b256(256);
   const unsigned nb = (unsigned)cdiv(n, 256);
   // initial basis: unit vectors at the k lowest diagonal elements
-  hipLaunchKernelGGL(k_dv_diag, dim3(nb), b256, 0, st, H, dg, n);
+  if (dinst) hipLaunchKernelGGL(k_dv_diag_direct, dim3(nb), b256, 0, st, dinst, di, dg, n);
+  else hipLaunchKernelGGL(k_dv_diag, dim3(nb), b256, 0, st, H, dg, n);
   std::vector<double> d(n);
   DVCHK(dv_copy(d.data(), dg, (size_t)n * 8, hipMemcpyDeviceToHost, st));
   std::vector<int> idx(n);
@@ -525,8 +542,13 @@ mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double 
   bool conv = false;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    for (int c = m - nnew; c < m; c += DV_COLS)
-      hipLaunchKernelGGL(k_dv_hx, dim3((unsigned)cdiv(n, 4)), b256, 0, st, H, V, W, n, c, std::min(DV_COLS, m - c));
+    for (int c = m - nnew; c < m; c += DV_COLS) {
+      if (dinst)
+        hipLaunchKernelGGL(k_dv_hx_direct, dim3((unsigned)cdiv(n, 4)), b256, 0, st, dinst, di, V, W, n, c,
+                           std::min(DV_COLS, m - c));
+      else
+        hipLaunchKernelGGL(k_dv_hx, dim3((unsigned)cdiv(n, 4)), b256, 0, st, H, V, W, n, c, std::min(DV_COLS, m - c));
+    }
     hipLaunchKernelGGL(k_dv_dots, dim3((unsigned)(m * nnew)), b256, 0, st, V, 0, W, m - nnew, nnew, n, G);
     HIPCHK(hipGetLastError());
     DVCHK(dv_copy(g.data(), G, (size_t)m * nnew * 16, hipMemcpyDeviceToHost, st));
@@ -955,6 +977,67 @@ mrpt2_status mrpt2_reference_states(mrpt2_plan_t plan, int32_t inst, const mrpt2
   s = read_flag(P, workspace, st);
   if (s != MRPT2_OK) return s;
   return davidson(base, L, n, n_states, tol, max_iter, st, c_out, e_out, iterations);
+}
+
+// Tables of one instance (factor pass, orbital energies, pair energies,
+// occupied-block integrals; no H_PP) for the direct sigma-build in P.
+static mrpt2_status reference_tables(Plan& P, int32_t inst, const mrpt2_inputs* in, const void* persistent,
+                                     void* workspace, size_t workspace_bytes, hipStream_t st) {
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, nullptr, nullptr, nullptr, inst);
+  if (s != MRPT2_OK) return s;
+  Timer tm;
+  s = run(P, P.reference_tables[inst], (const char*)persistent, (char*)workspace, st, tm);
+  if (s != MRPT2_OK) return s;
+  return read_flag(P, workspace, st);
+}
+
+mrpt2_status mrpt2_reference_sigma(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in, int32_t n_vec,
+                                   const double* x, const void* persistent, void* workspace,
+                                   size_t workspace_bytes, hipStream_t st, double* y) {
+  if (!plan || !in || !x || !y || x == y || n_vec < 1 || inst < 0 || inst >= (int)plan->p.inst.size())
+    return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  const int64_t n = (int64_t)P.inst[inst].pstrings.size();
+  if (n > INT32_MAX / 4) return MRPT2_ERR_ARG;
+  mrpt2_status s = reference_tables(P, inst, in, persistent, workspace, workspace_bytes, st);
+  if (s != MRPT2_OK) return s;
+  const Inst* insts = (const Inst*)((const char*)workspace + P.off_insts);
+  for (int c = 0; c < n_vec; c += DV_COLS)
+    hipLaunchKernelGGL(k_dv_hx_direct, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, st, insts, inst, (const double2*)x,
+                       (double2*)y, (int)n, c, std::min(DV_COLS, n_vec - c));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_reference_states_direct_size(mrpt2_plan_t plan, int32_t inst, int32_t n_states,
+                                                size_t* bytes) {
+  if (!plan || !bytes || inst < 0 || inst >= (int)plan->p.inst.size() || n_states < 1) return MRPT2_ERR_ARG;
+  const int64_t n = (int64_t)plan->p.inst[inst].pstrings.size();
+  if (n_states > n) return MRPT2_ERR_ARG;
+  *bytes = dv_layout(n, n_states, false).total;
+  return MRPT2_OK;
+}
+
+mrpt2_status mrpt2_reference_states_direct(mrpt2_plan_t plan, int32_t inst, const mrpt2_inputs* in,
+                                           int32_t n_states, double tol, int32_t max_iter, const void* persistent,
+                                           void* workspace, size_t workspace_bytes, void* dv, size_t dv_bytes,
+                                           hipStream_t st, double* c_out, double* e_out, int32_t* iterations) {
+  if (!plan || !in || !dv || !c_out || !e_out || inst < 0 || inst >= (int)plan->p.inst.size() || n_states < 1 ||
+      max_iter < 1 || !(tol > 0.0))
+    return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  const int64_t n = (int64_t)P.inst[inst].pstrings.size();
+  if (n_states > n || n > INT32_MAX / 4) return MRPT2_ERR_ARG;
+  const DvLayout L = dv_layout(n, n_states, false);
+  if (dv_bytes < L.total) return MRPT2_ERR_WORKSPACE;
+  if ((uintptr_t)dv & 255) return MRPT2_ERR_ARG;
+  mrpt2_status s = reference_tables(P, inst, in, persistent, workspace, workspace_bytes, st);
+  if (s != MRPT2_OK) return s;
+  const Inst* insts = (const Inst*)((const char*)workspace + P.off_insts);
+  return davidson((char*)dv, L, n, n_states, tol, max_iter, st, c_out, e_out, iterations, insts, inst);
 }
 
 mrpt2_status mrpt2_plan_class_blocks(mrpt2_plan_t plan, int32_t inst, int32_t cls, int64_t* n_blocks) {

@@ -233,7 +233,10 @@ void sort_by_pattern_mask(InstancePlan& ip, ClassPlan& cp) {
   for (size_t s = 0; s < S; ++s)
     for (int e = cp.conn_ptr[s]; e < cp.conn_ptr[s + 1]; ++e) {
       const Pattern& p = cp.patterns[cp.conn[2 * e + 1]];
-      if (p.a0 >= 0) key[s] |= 1ull << p.a0;
+      // the orbital a pattern is indexed by: the annihilated active spinor
+      // (class (1,2)) or the created one (class (2,1))
+      const int o = p.a0 >= 0 ? p.a0 : p.r0;
+      if (o >= 0) key[s] |= 1ull << o;
     }
   std::vector<size_t> ord(S);
   for (size_t s = 0; s < S; ++s) ord[s] = s;
@@ -456,7 +459,7 @@ void build_launches(Plan* P) {
     js.clear();
     for (int i : all) {
       const ClassPlan& cp = P->inst[i].cls[k];
-      if (cp.kernel == KERN_E12 && !cp.strings.empty() && cp.n_rows > 0)
+      if ((cp.kernel == KERN_E12 || cp.kernel == KERN_E21) && !cp.strings.empty() && cp.n_rows > 0)
         js.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), 1, k));
     }
     add_launch(P, seq, K_DCOEF, ST_PREP0 + k, js);
@@ -468,7 +471,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
     // (index 1 of each pair: the level-shifted variant)
-    std::vector<JobH> e22[2], e12[2][5], e02[2], e02f[2], gen;
+    std::vector<JobH> e22[2], e12[2][5], e21[2][5], e02[2], e02f[2], gen;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -480,6 +483,10 @@ void build_launches(Plan* P) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 20 ? 4 : J <= 24 ? 2 : 3;
         e12[ls][v].push_back(job(i, cp.n_holes, ip.n_tp * 8, k));
+      } else if (cp.kernel == KERN_E21) {
+        const size_t J = cp.patterns.size();
+        const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 20 ? 2 : J <= 24 ? 3 : 4;
+        e21[ls][v].push_back(job(i, cp.n_holes, cdiv64(ip.n_v, 256), k));
       } else if (cp.kernel == KERN_E02) {
         (ip.d.precision == MRPT2_MIXED ? e02f[ls] : e02[ls]).push_back(job(i, cp.n_tiles, ip.n_tp * 64, k));
       } else {
@@ -502,6 +509,10 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12S_20, ST_SIGMA0 + k, e12[1][4]);
     add_launch(P, seq, K_E02S, ST_SIGMA0 + k, e02[1]);
     add_launch(P, seq, K_E02FS, ST_SIGMA0 + k, e02f[1]);
+    for (int v = 0; v < 5; ++v) {
+      add_launch(P, seq, K_E21_8 + v, ST_SIGMA0 + k, e21[0][v]);
+      add_launch(P, seq, K_E21S_8 + v, ST_SIGMA0 + k, e21[1][v]);
+    }
     add_launch(P, seq, K_SIG22 + k, ST_SIGMA0 + k, gen);
   }
   js.clear();
@@ -658,6 +669,13 @@ void build_launches(Plan* P) {
     const int np = (int)P->inst[i].pstrings.size();
     add_launch(P, r, K_HPP, ST_REF, {job(i, cdiv64(np, 16), cdiv64(np, 16))}, 0, 1);
   }
+  // the same tables without H_PP (the direct sigma-build in P)
+  P->reference_tables.resize(ni);
+  for (int i = 0; i < ni; ++i) {
+    std::vector<Launch>* r = &P->reference_tables[i];
+    add_launch(P, r, K_CLEAR, ST_NONE, {job(0, 1, 1)});
+    table_launches(P, r, {i});
+  }
 }
 
 void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
@@ -692,6 +710,13 @@ void class_block(const InstancePlan& ip, int k, int64_t b, mrpt2_block* o) {
     const int I = ip.tile_pairs[2 * tp], J = ip.tile_pairs[2 * tp + 1];
     o->a_lo = clampv(I * 64 + sa * 16); o->a_hi = clampv(I * 64 + sa * 16 + 16);
     o->b_lo = clampv(J * 64 + sb * 16); o->b_hi = clampv(J * 64 + sb * 16 + 16);
+    return;
+  }
+  if (cp.kernel == KERN_E21) {
+    const int64_t hp = b % cp.n_holes, at = b / cp.n_holes;
+    set_holes(hp);
+    o->a_lo = clampv((int)(at * 256));
+    o->a_hi = clampv((int)(at * 256 + 256));
     return;
   }
   if (cp.kernel == KERN_E02) {
@@ -811,6 +836,37 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       return MRPT2_ERR_SHAPE;
     }
     for (size_t i = 0; i < ip.pstrings.size(); ++i) ip.pindex[ip.pstrings[i]] = (int32_t)i;
+    // excitation lists of the reference space: for every reference string,
+    // the reference strings reached from it by one or two replacements of
+    // active spinors, in ascending order (the off-diagonal couplings of H_PP,
+    // which the sigma-build in P applies without storing H_PP)
+    {
+      const uint64_t act = ip.n_a >= 64 ? ~0ull : ((1ull << ip.n_a) - 1);
+      ip.plist_ptr.assign(1, 0);
+      std::vector<int> occ, emp;
+      std::vector<int32_t> row;
+      for (size_t i = 0; i < ip.pstrings.size(); ++i) {
+        const uint64_t b = ip.pstrings[i];
+        occ.clear();
+        emp.clear();
+        for (int t = 0; t < ip.n_a; ++t) (b >> t & 1 ? occ : emp).push_back(t);
+        row.clear();
+        auto add = [&](uint64_t bj) {
+          auto it = ip.pindex.find(bj & act);
+          if (it != ip.pindex.end()) row.push_back(it->second);
+        };
+        for (int q : occ)
+          for (int p : emp) add(b ^ (1ull << q) ^ (1ull << p));
+        for (size_t x = 0; x < occ.size(); ++x)
+          for (size_t y = x + 1; y < occ.size(); ++y)
+            for (size_t u = 0; u < emp.size(); ++u)
+              for (size_t w = u + 1; w < emp.size(); ++w)
+                add(b ^ (1ull << occ[x]) ^ (1ull << occ[y]) ^ (1ull << emp[u]) ^ (1ull << emp[w]));
+        std::sort(row.begin(), row.end());
+        ip.plist_col.insert(ip.plist_col.end(), row.begin(), row.end());
+        ip.plist_ptr.push_back((int64_t)ip.plist_col.size());
+      }
+    }
     // external space by class: level = v + min over P categories of the
     // surplus sum_k max(0, m_k - m'_k) must not exceed 2
     int64_t n_ext = 0;
@@ -850,7 +906,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.n_ext = cp.n_holes * binom(ip.n_v, cp.v) * (int64_t)cp.strings.size();
       n_ext += cp.n_ext;
       if (!cp.strings.empty()) build_class(ip, cp);
-      if (k == 1 && !cp.strings.empty() && cp.patterns.size() <= (size_t)kMaxDenseJ)
+      if ((k == 1 || k == 3) && !cp.strings.empty() && cp.patterns.size() <= (size_t)kMaxDenseJ)
         sort_by_pattern_mask(ip, cp);
       if (k == 2 && !cp.strings.empty() && !tile_by_support(ip, cp, ss, off)) {
         cp.n_tiles = 0;
@@ -889,6 +945,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
     // ---- persistent layout (plan tables) ----
     Layout P;
     ip.off_pstrings = P.take(ip.pstrings.size() * 8);
+    ip.off_plist_ptr = P.take(ip.plist_ptr.size() * 8);
+    ip.off_plist_col = P.take(std::max<size_t>(ip.plist_col.size(), 1) * 4);
     ip.off_hole_pairs = P.take(std::max<size_t>(ip.hole_pairs.size(), 2) * 4);
     ip.off_tile_pairs = P.take(std::max<size_t>(ip.tile_pairs.size(), 2) * 4);
     ip.off_sign = P.take(ip.n_l * 8);
@@ -929,6 +987,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       if (bytes) std::memcpy(ip.host_blob.data() + o, src, bytes);
     };
     put(ip.off_pstrings, ip.pstrings.data(), ip.pstrings.size() * 8);
+    put(ip.off_plist_ptr, ip.plist_ptr.data(), ip.plist_ptr.size() * 8);
+    put(ip.off_plist_col, ip.plist_col.data(), ip.plist_col.size() * 4);
     put(ip.off_hole_pairs, ip.hole_pairs.data(), ip.hole_pairs.size() * 4);
     put(ip.off_tile_pairs, ip.tile_pairs.data(), ip.tile_pairs.size() * 4);
     put(ip.off_sign, ip.set_sign.data(), ip.n_l * 8);
@@ -973,7 +1033,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       // kernels have shifted variants, the adjoint then runs on the generic
       // passes (the only ones that carry the shifted weight's derivative)
       const bool shifted = ip.d.level_shift_b != 0.0;
-      cp.dense_coef = (k == 1) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
+      cp.dense_coef = (k == 1 || k == 3) && S && cp.patterns.size() <= (size_t)kMaxDenseJ;
       cp.off_D = W.take(cp.dense_coef ? S * cp.patterns.size() * 16 : 0);
       cp.off_mask = W.take(cp.dense_coef ? S * 4 : 0);
       // kernel choice and partial-sum blocks: the dedicated kernels' grids
@@ -984,12 +1044,15 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
         if (k == 0) cp.kernel = KERN_E22;
         else if (k == 1 && cp.dense_coef) cp.kernel = KERN_E12;
         else if (k == 2 && cp.n_tiles > 0) cp.kernel = KERN_E02;
+        else if (k == 3 && cp.dense_coef) cp.kernel = KERN_E21;
       }
-      cp.kernel_bwd = shifted ? KERN_GENERIC : cp.kernel;
+      // class (2,1) has no dedicated adjoint: its generic passes serve
+      cp.kernel_bwd = (shifted || cp.kernel == KERN_E21) ? KERN_GENERIC : cp.kernel;
       cp.off_Md = W.take(cp.kernel == KERN_E02 ? (size_t)kStrTile * cp.tile_k0.back() * 16 : 0);
       cp.n_blocks = (cp.kernel == KERN_E22)   ? ip.n_tp * cp.n_holes
                     : (cp.kernel == KERN_E12) ? ip.n_tp * 16 * cp.n_holes
                     : (cp.kernel == KERN_E02) ? ip.n_tp * 64 * cp.n_tiles
+                    : (cp.kernel == KERN_E21) ? cp.n_holes * cdiv64(ip.n_v, 256)
                                               : sigma_blocks(ip, k);
       ip.n_part_class[k] = cp.n_blocks;
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
@@ -1067,6 +1130,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
     inf.n_chol = ip.n_l;
     inf.n_ref = (int64_t)NP;
     inf.n_ext = n_ext;
+    inf.n_ref_couplings = (int64_t)ip.plist_col.size();
     double fs = 0;
     for (int k = 0; k < MRPT2_N_CLASS; ++k) {
       const ClassPlan& cp = ip.cls[k];

@@ -80,12 +80,15 @@ struct InstancePlan {
   std::vector<std::vector<int>> pcats;
   std::vector<uint64_t> pstrings;
   std::unordered_map<uint64_t, int32_t> pindex;
+  std::vector<int64_t> plist_ptr;     // [N_P + 1] excitation lists of P (CSR)
+  std::vector<int32_t> plist_col;     // reference strings one or two replacements away
   ClassPlan cls[MRPT2_N_CLASS];
   std::vector<int32_t> hole_pairs;    // (c, c') for c < c'
   std::vector<int32_t> tile_pairs;    // (I, J) for I <= J
   std::vector<double> set_sign;       // per Cholesky vector: sign of its weight
   std::vector<double> set_scale;      // per Cholesky vector: sqrt|weight|
   // persistent layout
+  size_t off_plist_ptr = 0, off_plist_col = 0;
   size_t off_pstrings = 0, off_hole_pairs = 0, off_tile_pairs = 0, off_sign = 0, off_scale = 0;
   size_t persistent_bytes = 0, persistent_base = 0;
   // workspace layout
@@ -115,7 +118,9 @@ enum KernelId : int {
   K_BSTR22, K_BSTR12, K_BSTR02, K_BSTR21, K_BSTR11, K_BSTR01, K_BSTR20, K_BSTR10, K_BSTR00,
   K_BSFIN, K_BHPP, K_BXB, K_BAG, K_BAGF, K_BGG, K_BFOCK, K_BDSUM, K_BHFE, K_BWSYM, K_BDG, K_BDB, K_BDH, K_BDC,
   K_BECOEF, K_BTRANS, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
-  K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20
+  K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20,
+  // class (2,1) dense-coefficient kernel, pattern widths 8, 16, 20, 24, 32 (then level-shifted)
+  K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32
 };
 
 // Timing slots (mrpt2_energy_timed).
@@ -156,6 +161,7 @@ struct Plan {
   std::vector<Launch> backward;       // launch sequence of mrpt2_energy_backward
   size_t grad_bytes = 0;              // gradient workspace of mrpt2_energy_backward
   std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
+  std::vector<std::vector<Launch>> reference_tables;  // per instance: tables only
   std::vector<char> host_blob;
   std::vector<char> static_stage;     // host staging of the descriptors for mrpt2_energy_static
   void* pinned = nullptr;             // host staging of the instance descriptors
@@ -165,7 +171,7 @@ struct Plan {
 };
 
 // Kernel that evaluates a class.
-enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3 };
+enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3, KERN_E21 = 4 };
 constexpr int kStrTile = 64;                // strings per tile of the (0,2) contraction kernel
 
 struct Plan;

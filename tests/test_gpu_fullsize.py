@@ -65,8 +65,13 @@ def block_index(plan, k, blk, n_tp):
         hp = next(i for i in range(n_hp) if tuple(plan.class_block(k, i * n_tp).hole[:2]) == holes)
         idx = [hp * n_tp + tp]
     elif k == 1:
-        sa, sb = (a_lo - I * 64) // 16, (b_lo - J * 64) // 16
-        idx = [holes[0] * n_tp * 16 + tp * 16 + sa * 4 + sb]
+        # 16 x 16 sub-tile (sa, sb) of the tile pair; ranges clamped at the
+        # end of the virtual block may be empty, so match the described ranges
+        base = holes[0] * n_tp * 16 + tp * 16
+        subs = [base + q for q in range(16)
+                if (lambda d: (d.a_lo, d.a_hi, d.b_lo, d.b_hi))(plan.class_block(k, base + q)) == (a_lo, a_hi, b_lo, b_hi)]
+        assert subs, (k, blk)
+        idx = subs[:1]
     else:
         n_tiles = nb // (n_tp * 64)
         la = a_lo - I * 64

@@ -162,4 +162,23 @@ def test_wide_active_spaces_select_every_dense_kernel_width():
         assert info.n_patterns_class[1] == J, (name, info.n_patterns_class[1])
         assert info.kernel_class[1] == 2, name
         assert info.kernel_class[0] == 1 and info.kernel_class[2] in (0, 3), name
+        assert info.kernel_class[3] == (4 if info.n_patterns_class[3] <= 32 else 0), name
     assert M.Plan(M.desc_of_problem(problem("s_j20"))).info().n_strings_class[1] == 190
+
+
+def test_reference_excitation_lists_count():
+    """The plan's excitation lists of P hold exactly the ordered pairs of
+    reference determinants one or two active replacements apart (bit strings
+    differing in two or four positions), by brute force over P."""
+    import numpy as np
+    import paper_2608_11529_amd as M
+    from helpers import problem
+    for name in ("s_das", "s_fc", "s_hop0", "s_j24", "c0", "c1"):
+        plan = M.Plan(M.desc_of_problem(problem(name)))
+        b = [int(x) for x in plan.ref_strings()]
+        n = 0
+        for i in range(len(b)):
+            for j in range(len(b)):
+                if i != j and bin(b[i] ^ b[j]).count("1") in (2, 4):
+                    n += 1
+        assert plan.info().n_ref_couplings == n, (name, plan.info().n_ref_couplings, n)
