@@ -85,6 +85,7 @@ struct Dev {
   double* W;                 // [n][n]
   double* eps;               // [n_corr]
   double2* f;                // [n_a+n_v][n_o]
+  double2* fx;               // [n_fc+n_c][n_a+n_v][n_o] exchange partials of f per core spinor
   double2* G;                // [n_o][n_a+n_v][n_o][n_a]
   double2* A;                // [n_pairs][n_tp][64][64]
   double2* hpp;              // [n_p][n_p]

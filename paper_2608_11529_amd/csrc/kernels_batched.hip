@@ -35,6 +35,10 @@ __global__ void __launch_bounds__(256) k_b_dsum(MRPT2_ARGS) {
   MRPT2_JOB
   dsum_body(I.d, bid);
 }
+__global__ void __launch_bounds__(256) k_b_fockx(MRPT2_ARGS) {
+  MRPT2_JOB
+  fockx_body(I.d, bid);
+}
 __global__ void __launch_bounds__(64) k_b_fock(MRPT2_ARGS) {
   MRPT2_JOB
   fock_body(I.d, bid);

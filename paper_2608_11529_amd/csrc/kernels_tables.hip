@@ -124,7 +124,9 @@ __device__ __forceinline__ void dsum_body(const Dev& d, const uint3 bid) {
 
 // Core Fock matrix f_pq = h_pq + sum_{j in core} [(pq|jj) - (pj|jq)] for p
 // active or virtual and q core or active (frozen-core fold of Sec. 2 plus the
-// correlated core).  grid (n_o, n_a + n_v), one wavefront per entry.
+// correlated core): the Coulomb part sum_L w_L B_pq^L dsum_L per entry, the
+// exchange part from the per-core-spinor partials fx (fockx_body), summed in
+// core order.  grid (n_o, n_a + n_v), one wavefront per entry.
 __device__ __forceinline__ void fock_body(const Dev& d, const uint3 bid) {
   const double2* __restrict__ h = d.h;
   const int qo = bid.x;
@@ -138,21 +140,17 @@ __device__ __forceinline__ void fock_body(const Dev& d, const uint3 bid) {
     acc.x = fma(s, Bq[L].x, acc.x);
     acc.y = fma(s, Bq[L].y, acc.y);
   }
-  for (int j = 0; j < d.n_fc + d.n_c; ++j) {
-    const double2* Bp = d.slab + ((int64_t)j * d.n_corr + pcorr) * d.n_l;
-    const double2* Bc = d.slab + ((int64_t)j * d.n_corr + qo) * d.n_l;
-    for (int L = lane; L < d.n_l; L += 64) {
-      const double s = d.sign[L];
-      const double2 a = Bp[L], b = Bc[L];   // B_pj and conj(B_jq) = B_qj
-      acc.x -= s * (a.x * b.x + a.y * b.y);
-      acc.y -= s * (a.y * b.x - a.x * b.y);
-    }
-  }
   for (int off = 32; off > 0; off >>= 1) {
     acc.x += __shfl_down(acc.x, off, 64);
     acc.y += __shfl_down(acc.y, off, 64);
   }
   if (lane == 0) {
+    const int np = d.n_a + d.n_v;
+    for (int j = 0; j < d.n_fc + d.n_c; ++j) {
+      const double2 x = d.fx[((int64_t)j * np + pr) * d.n_o + qo];
+      acc.x -= x.x;
+      acc.y -= x.y;
+    }
     const int gp = d.n_fc + pcorr, gq = d.n_fc + qo;
     const double2 hv = h[(int64_t)gp * d.n + gq];
     d.f[(int64_t)pr * d.n_o + qo] = make_double2(hv.x + acc.x, hv.y + acc.y);
@@ -190,11 +188,6 @@ __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double
       sA[r * KP + kk] = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
       if (!BCOL) sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
     }
-    if (BCOL)
-      for (int e = tid; e < 64 * KC; e += 256) {
-        const int c = e & 63, kk = e >> 6;
-        sB[c * KP + kk] = (k0 + kk) < K ? fb(c, k0 + kk) : make_double2(0.0, 0.0);
-      }
     __syncthreads();
 #pragma unroll 2
     for (int ks = 0; ks < KC; ks += 2) {
@@ -231,6 +224,48 @@ __device__ __forceinline__ int acc_row(int i, int r) {
 __device__ __forceinline__ int acc_col(int j) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   return (wv & 1) * 32 + j * 16 + (lane & 15);
+}
+
+// Exchange part of the core Fock block, one core spinor j (frozen or
+// correlated) at a time: fx[j][p][q] = sum_L w_L B_pj^L B_jq^L
+// = sum_L sign_L slab[j][p][L] conj(slab[j][q][L]) (B Hermitian), for p active
+// or virtual and q core or active: a complex GEMM with K = n_l on FP64 MFMA.
+// grid (ceil((n_a + n_v)/64) * ceil(n_o/64), n_fc + n_c), block 256.
+__device__ __forceinline__ void fockx_body(const Dev& d, const uint3 bid) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int np = d.n_a + d.n_v;
+  const int npt = (np + 63) / 64;
+  const int p0 = (int)(bid.x % npt) * 64, q0 = (int)(bid.x / npt) * 64;
+  const int j = bid.y;
+  const int nl = d.n_l;
+  const double2* Sp = d.slab + ((int64_t)j * d.n_corr + d.n_c) * nl;   // rows p (correlated n_c + p)
+  const double2* Sq = d.slab + (int64_t)j * d.n_corr * nl;             // rows q (correlated q)
+  const double* sg = d.sign;
+  auto fa = [&](int r, int k) -> double2 {
+    const int p = p0 + r;
+    if (p >= np) return make_double2(0.0, 0.0);
+    const double2 v = Sp[(int64_t)p * nl + k];
+    return make_double2(sg[k] * v.x, sg[k] * v.y);
+  };
+  auto fb = [&](int c, int k) -> double2 {
+    const int q = q0 + c;
+    if (q >= d.n_o) return make_double2(0.0, 0.0);
+    const double2 v = Sq[(int64_t)q * nl + k];
+    return make_double2(v.x, -v.y);
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, nl, sA, sB, accR, accI);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + acc_row(i, r), q = q0 + acc_col(jj);
+        if (p < np && q < d.n_o)
+          d.fx[((int64_t)j * np + p) * d.n_o + q] = make_double2(accR[i][jj][r], accI[i][jj][r]);
+      }
 }
 
 // Antisymmetrised virtual-pair integrals for every occupied pair x < y

@@ -75,6 +75,7 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.W = (double*)(W + ip.off_W);
   d.eps = (double*)(W + ip.off_eps);
   d.f = (double2*)(W + ip.off_f);
+  d.fx = (double2*)(W + ip.off_fx);
   d.G = (double2*)(W + ip.off_G);
   d.A = (double2*)(W + ip.off_A);
   d.hpp = (double2*)(W + ip.off_hpp);
@@ -324,6 +325,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_EPS: hipLaunchKernelGGL(k_b_eps, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_DSUM: hipLaunchKernelGGL(k_b_dsum, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_FOCK: hipLaunchKernelGGL(k_b_fock, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_FOCKX: hipLaunchKernelGGL(k_b_fockx, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_GBUILD: hipLaunchKernelGGL(k_b_gbuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_HPP: hipLaunchKernelGGL(k_b_hpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIGP: hipLaunchKernelGGL(k_b_sigp, g, b64, 0, st, insts, jobs, nj, flag, ka); break;

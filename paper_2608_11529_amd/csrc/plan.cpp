@@ -322,6 +322,13 @@ void table_launches(Plan* P, std::vector<Launch>* seq, const std::vector<int>& w
   for (int i : which) js.push_back(job(i, cdiv64(P->inst[i].n_l, 256), 1));
   add_launch(P, seq, K_DSUM, ST_TABLES, js);
   js.clear();
+  for (int i : which) {
+    const InstancePlan& ip = P->inst[i];
+    if (ip.n_fc + ip.n_c > 0)
+      js.push_back(job(i, cdiv64(ip.n_a + ip.n_v, 64) * cdiv64(ip.n_o, 64), ip.n_fc + ip.n_c));
+  }
+  add_launch(P, seq, K_FOCKX, ST_TABLES, js);
+  js.clear();
   for (int i : which) js.push_back(job(i, P->inst[i].n_o, P->inst[i].n_a + P->inst[i].n_v));
   add_launch(P, seq, K_FOCK, ST_TABLES, js);
   js.clear();
@@ -1015,6 +1022,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
     ip.off_W = W.take((size_t)ip.n * ip.n * 8);
     ip.off_eps = W.take((size_t)ip.n * 8);
     ip.off_f = W.take((size_t)(ip.n_a + ip.n_v) * ip.n_o * 16);
+    ip.off_fx = W.take((size_t)(ip.n_fc + ip.n_c) * (ip.n_a + ip.n_v) * ip.n_o * 16);
     ip.off_G = W.take((size_t)ip.n_o * (ip.n_a + ip.n_v) * ip.n_o * std::max(ip.n_a, 1) * 16);
     ip.off_A = W.take(ip.n_v >= 2 ? (size_t)ip.n_pairs * ip.n_tp * kTile * kTile * 16 : 0);
     ip.off_hpp = W.take(NP * NP * 16);

@@ -92,6 +92,7 @@ struct InstancePlan {
   size_t off_pstrings = 0, off_hole_pairs = 0, off_tile_pairs = 0, off_sign = 0, off_scale = 0;
   size_t persistent_bytes = 0, persistent_base = 0;
   // workspace layout
+  size_t off_fx = 0;
   size_t off_dg = 0, off_slab = 0, off_slab32 = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
   size_t off_hpp = 0, off_sigp = 0, off_scal = 0, off_dsum = 0, off_part = 0;
   size_t workspace_bytes = 0, workspace_base = 0;
@@ -120,7 +121,8 @@ enum KernelId : int {
   K_BECOEF, K_BTRANS, K_B22A, K_B22B, K_B22WR, K_B22FIN, K_B12R_8, K_B12R_16, K_B12R_24, K_B12R_32, K_B12S_8, K_B12S_16, K_B12S_24, K_B12S_32,
   K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20,
   // class (2,1) dense-coefficient kernel, pattern widths 8, 16, 20, 24, 32 (then level-shifted)
-  K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32
+  K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32,
+  K_FOCKX
 };
 
 // Timing slots (mrpt2_energy_timed).
