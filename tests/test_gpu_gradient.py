@@ -387,3 +387,37 @@ def test_finite_differences_batched_c3_instances():
             print(f"[gpu] c3 instance {i} direction {k}: analytic {ana:.12e} fd {num:.12e} (fd spread {err:.2e})",
                   flush=True)
             assert abs(num - ana) <= 1e-6 * abs(ana), (i, k, num, ana)
+
+
+def test_mixed_precision_gradient_c1():
+    """The mixed form at c1 (FP32-MFMA pair integrals with a per-stage FP64
+    carry, FP64 elsewhere): its adjoint against the FP64 adjoint element by
+    element (1e-5 of each entry plus 1e-8 of the largest), and against central
+    differences of the mixed energy itself along the largest entries of dh
+    and dC (1e-5 of the entry)."""
+    import paper_2608_11529_amd as M
+    from paper_2608_11529_amd.reference import ground_state
+    pb = problem("c1")
+    e64 = M.Engine(M.Plan(M.desc_of_problem(pb, precision=0)))
+    dev = e64.device
+    h, Bs = SP.one_body(pb, dev), SP.factors(pb, dev)
+    c, _ = ground_state(e64, h, Bs)
+    (gh, gB, gc), = e64.backward([(h, Bs, c)])[0]
+    gh, gB, gc = gh.cpu().numpy(), [x.cpu().numpy() for x in gB], gc.cpu().numpy()
+    e32 = M.Engine(M.Plan(M.desc_of_problem(pb, precision=1)))
+    print("[gpu] c1 mixed backward", flush=True)
+    (mh, mB, mc), = e32.backward([(h, Bs, c)])[0]
+    mh_d, mc_d = mh.clone(), mc.clone()
+    assert close(mh.cpu().numpy(), gh, 1e-5, 1e-3)[0]
+    assert close(mc.cpu().numpy(), gc, 1e-5, 1e-3)[0]
+    for x, y in zip(mB, gB):
+        assert close(x.cpu().numpy(), y, 1e-5, 1e-3)[0]
+
+    def E():
+        return float(e32.energy([(h, Bs, c)], parts=False)[0].item())
+
+    for label, target, g, herm_ in (("dh", h, mh_d, True), ("dC", c, mc_d, False)):
+        idx = _entry_directions(g, 1)[0]
+        gv = complex(g.view(-1)[idx].item())
+        for num, ana, err in _coord_check(E, target, idx, gv, herm_, "c1 mixed " + label, h0=1e-3, levels=4):
+            assert abs(num - ana) <= 1e-5 * abs(gv) * (2.0 if herm_ else 1.0) + 1e-10, (label, idx, num, ana)
