@@ -188,6 +188,11 @@ __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double
       sA[r * KP + kk] = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
       if (!BCOL) sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
     }
+    if (BCOL)
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int c = e & 63, kk = e >> 6;
+        sB[c * KP + kk] = (k0 + kk) < K ? fb(c, k0 + kk) : make_double2(0.0, 0.0);
+      }
     __syncthreads();
 #pragma unroll 2
     for (int ks = 0; ks < KC; ks += 2) {
