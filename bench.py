@@ -103,8 +103,8 @@ def roofline(dom, ms, cases, precision):
                    for pb, _ in cases)
         peak = FP32_MFMA_PEAK if mixed else FP64_MFMA_PEAK
         ach = flop / (ms * 1e-3)
-        return {"kernel": "k_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
-                          % ("_f32" if mixed else "", "FP32" if mixed else "FP64"),
+        return {"kernel": "k_b_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
+                          % ("_f32" if mixed else "128", "FP32" if mixed else "FP64"),
                 "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": None}
     if dom == "sigma_22":

@@ -60,11 +60,11 @@ __global__ void __launch_bounds__(256) k_b_e0(MRPT2_ARGS) {
   (void)bid;
   e0_body(I.d, flag);
 }
-__global__ void __launch_bounds__(256) k_b_abuild(MRPT2_ARGS) {
-  MRPT2_JOB
-  abuild_body(I.d, bid);
-}
 // two waves per SIMD (252 VGPRs, no AGPR accumulators) instead of one
+__global__ void __launch_bounds__(512) k_b_abuild128(MRPT2_ARGS) {
+  MRPT2_JOB
+  abuild128_body(I.d, bid);
+}
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_b_abuild_f32(MRPT2_ARGS) {
   MRPT2_JOB
   abuild_f32_body(I.d, bid);

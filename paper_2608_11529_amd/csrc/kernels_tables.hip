@@ -276,12 +276,31 @@ __device__ __forceinline__ void fockx_body(const Dev& d, const uint3 bid) {
 // Antisymmetrised virtual-pair integrals for every occupied pair x < y
 // (core or active):  A[xy][a][b] = <ab||xy> = (ax|by) - (ay|bx)
 //   = sum_L w_L (B_ax B_by - B_ay B_bx),
-// one 64 x 64 tile (I, J), I <= J, of virtual pairs per block, K = 2 n_l.
-// grid (n_tp, n_pairs), block 256.
-__device__ __forceinline__ void abuild_body(const Dev& d, const uint3 bid) {
-  __shared__ double2 sA[64 * KP];
-  __shared__ double2 sB[64 * KP];
-  const int64_t tp = bid.x;
+// stored per 64 x 64 tile (I, J), I <= J, of virtual pairs, K = 2 n_l.
+// They are built in 128 x 128 blocks of virtual pairs: the block covers
+// the four tiles (I, J) = (2 I2 + u, 2 J2 + v), u, v in {0, 1}, I2 <= J2, and
+// each of its eight waves computes a 64 x 32 half of one tile on FP64 MFMA
+// (four by two 16 x 16 products, real and imaginary parts).  Twice the
+// arithmetic per staged operand of the 64 x 64 form: each stage of AK complex
+// k stages 256 rows for 128 x 128 products.  The next stage's operands are
+// fetched into registers while the current one is multiplied, so the global
+// latency hides behind the MFMA work; waves whose tile lies below the diagonal
+// (I > J) or past the last virtual tile only help to stage.
+// grid (n2 (n2 + 1) / 2 with n2 = ceil(n_vt / 2), n_pairs), block 512.
+constexpr int AK = 16;              // complex k per stage
+constexpr int AKP = AK + 1;         // padded LDS row (double2)
+
+__device__ __forceinline__ void abuild128_body(const Dev& d, const uint3 bid) {
+  __shared__ double2 sA[128 * AKP];
+  __shared__ double2 sB[128 * AKP];
+  const int nvt = d.n_vt, nvt2 = (nvt + 1) >> 1;
+  int I2 = 0;
+  int64_t rem = bid.x;
+  while (rem >= nvt2 - I2) {
+    rem -= nvt2 - I2;
+    ++I2;
+  }
+  const int J2 = I2 + (int)rem;
   int64_t pr = bid.y;
   int xo = 0;
   while (pr >= d.n_o - 1 - xo) {
@@ -289,36 +308,98 @@ __device__ __forceinline__ void abuild_body(const Dev& d, const uint3 bid) {
     ++xo;
   }
   const int yo = xo + 1 + (int)pr;
-  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
-  const int nl = d.n_l;
-  const double2* Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
-  const double2* Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
-  const double* sg = d.sign;
-  const int nv = d.n_v;
-  auto fa = [&](int r, int k) -> double2 {
-    const int a = I * 64 + r;
-    if (a >= nv) return make_double2(0.0, 0.0);
-    const int L = k < nl ? k : k - nl;
-    const double2 v = (k < nl ? Sx : Sy)[(int64_t)a * nl + L];
-    return make_double2(sg[L] * v.x, sg[L] * v.y);
-  };
-  auto fb = [&](int r, int k) -> double2 {
-    const int b = J * 64 + r;
-    if (b >= nv) return make_double2(0.0, 0.0);
-    if (k < nl) return Sy[(int64_t)b * nl + k];
-    const double2 v = Sx[(int64_t)b * nl + (k - nl)];
-    return make_double2(-v.x, -v.y);
-  };
-  d4 accR[2][2], accI[2][2];
-  cgemm64(fa, fb, 2 * nl, sA, sB, accR, accI);
-  double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int u = wv >> 2, cq = wv & 3;                 // row half, column quarter of the block
+  const int I = 2 * I2 + u, J = 2 * J2 + (cq >> 1);
+  const bool active = (I <= J) && (J < nvt);
+  const int nl = d.n_l, nv = d.n_v;
+  const int K = 2 * nl;
+  const double2* __restrict__ Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
+  const double2* __restrict__ Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
+  const double* __restrict__ sg = d.sign;
+  const int a0 = I2 * 128, b0 = J2 * 128;
+  // staging: element e = tid + 512 q (q < 4) of each operand is row e / AK,
+  // k e % AK.  The raw values are fetched into registers and scaled (sign of
+  // the factor, minus of the exchange half) only when stored, so nothing
+  // waits for the fetch before the stage's products.
+  double2 ra[4], rb[4];
+  double rs[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 512 * q;
+      const int r = e / AK, k = k0 + e % AK;
+      const bool first = k < nl;
+      const int L = first ? k : k - nl;
+      const int a = a0 + r, b = b0 + r;
+      ra[q] = make_double2(0.0, 0.0);
+      rb[q] = make_double2(0.0, 0.0);
+      rs[q] = 0.0;
+      if (k < K) {
+        rs[q] = sg[L];
+        if (a < nv) ra[q] = (first ? Sx : Sy)[(int64_t)a * nl + L];
+        if (b < nv) rb[q] = (first ? Sy : Sx)[(int64_t)b * nl + L];
+      }
+    }
+  };
+  d4 accR[4][2], accI[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int kq = lane >> 4, kcl = kq >> 1, comp = kq & 1;
+  const int rowA = u * 64 + (lane & 15), rowB = cq * 32 + (lane & 15);
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += AK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 512 * q;
+      const double m = (k0 + e % AK) < nl ? 1.0 : -1.0;
+      sA[(e / AK) * AKP + e % AK] = make_double2(rs[q] * ra[q].x, rs[q] * ra[q].y);
+      sB[(e / AK) * AKP + e % AK] = make_double2(m * rb[q].x, m * rb[q].y);
+    }
+    __syncthreads();
+    if (k0 + AK < K) fetch(k0 + AK);
+    if (active) {
+#pragma unroll 2
+      for (int ks = 0; ks < AK; ks += 2) {
+        const int kc = ks + kcl;
+        double ar[4], ai[4], bb[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sA[(rowA + i * 16) * AKP + kc];
+          ar[i] = comp ? -v.y : v.x;
+          ai[i] = comp ? v.x : v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double2 v = sB[(rowB + j * 16) * AKP + kc];
+          bb[j] = comp ? v.y : v.x;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bb[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bb[j], accI[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+  if (!active) return;
+  const int64_t tp = (int64_t)I * nvt - (int64_t)I * (I - 1) / 2 + (J - I);
+  double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096 + (cq & 1) * 32;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[acc_row(i, r) * 64 + acc_col(j)] = make_double2(accR[i][j][r], accI[i][j][r]);
+        out[(i * 16 + (lane >> 4) + 4 * r) * 64 + j * 16 + (lane & 15)] = make_double2(accR[i][j][r], accI[i][j][r]);
 }
 
 // ---- mixed precision: complex FP32 MFMA with FP64 carry ---------------------

@@ -442,8 +442,10 @@ void build_launches(Plan* P) {
     js.clear();
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
-      if (ip.n_v >= 2 && ip.n_pairs > 0 && (ip.d.precision == MRPT2_MIXED) == (prec == 1))
-        js.push_back(job(i, ip.n_tp, ip.n_pairs));
+      if (ip.n_v >= 2 && ip.n_pairs > 0 && (ip.d.precision == MRPT2_MIXED) == (prec == 1)) {
+        const int64_t n2 = (ip.n_vt + 1) / 2;   // FP64: 128 x 128 blocks of virtual pairs
+        js.push_back(prec ? job(i, ip.n_tp, ip.n_pairs) : job(i, n2 * (n2 + 1) / 2, ip.n_pairs));
+      }
     }
     add_launch(P, seq, prec ? K_ABUILD32 : K_ABUILD, ST_ABUILD, js);
   }
