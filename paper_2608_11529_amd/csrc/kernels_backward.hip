@@ -757,9 +757,12 @@ __device__ __forceinline__ void b22fin_body(const Dev& d, const ClassDev& cd, co
 //   Delta = T + eps_c + Uc_c - eps_a - Uv_a - eps_b - Uv_b - W_ab + W_ca + W_cb.
 // Row pass (the forward kernel's layout, one thread per (a, b) of a 16 x 16
 // sub-tile, couplings and their adjoints in registers): Abar for the core-active
-// pairs, the row constants, and the Uv tables (per-string sums over b and over a
-// reduced across lanes, contracted with the string occupations per chunk).
-// grid (n_c, 16 n_tp), block 256.
+// pairs, the row constants, and the Uv tables.  For the tables each thread
+// keeps y[t] = sum over the strings containing active spinor t of its
+// Delta-bar (YREG: in registers, else in its own LDS column; the string's
+// occupation is wave-uniform, so the update loop is scalar); the sums over b
+// (table of a) and over a (table of b) are taken once per block at the end.
+// grid (n_c, 16 n_tp), block 256, dynamic LDS n_a * 256 doubles.
 constexpr int B12C = 32;
 
 __device__ __forceinline__ double xsum16(double v) {   // sum over the 16 lanes sharing tid >> 4
@@ -774,18 +777,22 @@ __device__ __forceinline__ double xsum4(double v) {    // sum over lanes l, l^16
   v += __shfl_xor(v, 32, 64);
   return v;
 }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {   // a wave-uniform value into scalar registers
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 
-template <int MJ, int GS>
+template <int MJ, int GS, bool YREG>
 __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
+  extern __shared__ double sY[];            // [n_a][256]
   __shared__ double sUa[B12C][16];
   __shared__ double sUb[B12C][16];
   __shared__ double sG[B12C];
   __shared__ double2 sD[B12C][MJ];
   __shared__ uint32_t sM[B12C];
   __shared__ uint64_t sStr[B12C];
-  __shared__ double sVa[B12C][16];
-  __shared__ double sVb[B12C][16];
   __shared__ double sRow[16], sCol[16];
   const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
   const int tp = tps >> 4, sub = tps & 15;
@@ -818,9 +825,13 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       X[j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
     }
   }
+  constexpr int NY = YREG ? MJ : 1;
+  double y[NY];
+#pragma unroll
+  for (int t = 0; t < NY; ++t) y[t] = 0.0;
+  if (!YREG)
+    for (int t = 0; t < na; ++t) sY[t * 256 + tid] = 0.0;
   const double epsc = d.eps[c];
-  const int cx = tid & 15, tg = tid >> 4;
-  double Ya[4] = {0.0, 0.0, 0.0, 0.0}, Yb[4] = {0.0, 0.0, 0.0, 0.0};
   double q = 0.0;
   const int64_t S = cd.n_str;
   for (int64_t s0 = 0; s0 < S; s0 += B12C) {
@@ -831,8 +842,6 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       const int aa = I * 64 + sa * 16 + l, bb = Jt * 64 + sb * 16 + l;
       sUa[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
       sUb[sl][l] = (s < S && bb < nv) ? cd.Uv[s * nv + bb] : 0.0;
-      sVa[sl][l] = 0.0;
-      sVb[sl][l] = 0.0;
     }
     for (int e = tid; e < B12C * MJ; e += 256) {
       const int sl = e / MJ, j = e % MJ;
@@ -851,6 +860,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       uint32_t um = 0;
 #pragma unroll
       for (int k = 0; k < GS; ++k) um |= sM[sl + k];
+      um = __builtin_amdgcn_readfirstlane(um);
       double2 sg[GS];
 #pragma unroll
       for (int k = 0; k < GS; ++k) sg[k] = make_double2(0.0, 0.0);
@@ -886,30 +896,31 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
         dl[k] = valid ? -oneN * cabs2(t) : 0.0;
         q += dl[k];
       }
+      // Xbar_j += sigma-bar conj(D_j)
 #pragma unroll
       for (int j = 0; j < MJ; ++j)
         if (um & (1u << j)) {
 #pragma unroll
-          for (int k = 0; k < GS; ++k) Xb[j] = cadd(Xb[j], cmul(sbv[k], cconj(sD[sl + k][j])));
+          for (int k = 0; k < GS; ++k) {
+            const double2 dv = sD[sl + k][j];
+            Xb[j].x = fma(sbv[k].x, dv.x, fma(sbv[k].y, dv.y, Xb[j].x));
+            Xb[j].y = fma(sbv[k].y, dv.x, fma(-sbv[k].x, dv.y, Xb[j].y));
+          }
         }
 #pragma unroll
       for (int k = 0; k < GS; ++k) {
-        const double va = xsum16(dl[k]);
-        if (ib == 0) sVa[sl + k][ia] = va;
-        const double vb = xsum4(dl[k]);
-        if ((tid & 63) < 16) atomicAdd(&sVb[sl + k][ib], vb);
-      }
-    }
-    __syncthreads();
-    for (int sl = 0; sl < B12C; ++sl) {
-      const uint64_t str = sStr[sl];
-      const double va = sVa[sl][cx], vb = sVb[sl][cx];
+        const uint64_t str = uniform64(sStr[sl + k]);
+        if (YREG) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int t = tg + 16 * m;
-        if (t < na && ((str >> t) & 1ull)) {
-          Ya[m] += va;
-          Yb[m] += vb;
+          for (int t = 0; t < NY; ++t)
+            if ((str >> t) & 1ull) y[t] += dl[k];
+        } else {
+          uint64_t x = str;
+          while (x) {
+            const int t = __builtin_ctzll(x);
+            x &= x - 1;
+            atomicAdd(&sY[t * 256 + tid], dl[k]);
+          }
         }
       }
     }
@@ -923,6 +934,11 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
         g.Ab[(pr * d.n_tp + tp) * 4096 + la * 64 + lb] = Xb[j];
       }
     atomicAdd(&g.Wb[(gv + a) * n + gv + b], -q);
+  }
+  if (YREG) {
+#pragma unroll
+    for (int t = 0; t < NY; ++t)
+      if (t < na) sY[t * 256 + tid] = y[t];
   }
   // row constants: eps and W of c, a, b
   __syncthreads();
@@ -951,14 +967,20 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       atomicAdd(&g.epsb[c], tot);
     }
   }
-  // Uv tables of the sub-tile's a and b
-  const int av = I * 64 + sa * 16 + cx, bv = Jt * 64 + sb * 16 + cx;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int t = tg + 16 * m;
-    if (t >= na) continue;
-    if (av < nv && Ya[m] != 0.0) atomicAdd(&g.Wb[(gv + av) * n + ga + t], -Ya[m]);
-    if (bv < nv && Yb[m] != 0.0) atomicAdd(&g.Wb[(gv + bv) * n + ga + t], -Yb[m]);
+  // Uv tables of the sub-tile's a (sum over b) and b (sum over a)
+  for (int e = tid; e < na * 32; e += 256) {
+    const int t = e >> 5, x = e & 31;
+    const double* yt = sY + t * 256;
+    double v = 0.0;
+    int vv;
+    if (x < 16) {
+      for (int y = 0; y < 16; ++y) v += yt[x * 16 + y];
+      vv = I * 64 + sa * 16 + x;
+    } else {
+      for (int y = 0; y < 16; ++y) v += yt[y * 16 + x - 16];
+      vv = Jt * 64 + sb * 16 + x - 16;
+    }
+    if (vv < nv && v != 0.0) atomicAdd(&g.Wb[(gv + vv) * n + ga + t], -v);
   }
 }
 
@@ -996,6 +1018,7 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
   }
   uint32_t um = live ? cd.mask[s] : 0u;
   for (int o = 1; o < 64; o <<= 1) um |= __shfl_xor(um, o, 64);
+  um = __builtin_amdgcn_readfirstlane(um);   // wave-uniform: scalar branches below
   const double Gs = cd.T[s] + cd.Uc[s * nc + c] + d.eps[c];
   const double* Uvs = cd.Uv + s * nv;
   double tq = 0.0;
@@ -1056,7 +1079,11 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
           tq -= oneN * cabs2(t);
 #pragma unroll
           for (int j = 0; j < MJ; ++j)
-            if (um & (1u << j)) Db[j] = cadd(Db[j], cmul(sbv, cconj(sX[lb + k][j])));
+            if (um & (1u << j)) {   // Dbar_j += sigma-bar conj(X_j)
+              const double2 xv = sX[lb + k][j];
+              Db[j].x = fma(sbv.x, xv.x, fma(sbv.y, xv.y, Db[j].x));
+              Db[j].y = fma(sbv.y, xv.x, fma(-sbv.x, xv.y, Db[j].y));
+            }
         }
       }
     }

@@ -407,12 +407,21 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_B22B: hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka); break;
       case K_BTRANS: hipLaunchKernelGGL(k_b_btrans, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B12R_8: hipLaunchKernelGGL((k_b_b12r<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B12R_16: hipLaunchKernelGGL((k_b_b12r<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B12R_24: hipLaunchKernelGGL((k_b_b12r<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B12R_20: hipLaunchKernelGGL((k_b_b12r<20>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+#define MRPT2_B12R(ID, MJ)                                                                         \
+  case ID:                                                                                        \
+    if (L.dyn_lds > 65536 &&                                                                      \
+        hipFuncSetAttribute((const void*)k_b_b12r<MJ>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)L.dyn_lds) != hipSuccess)                                        \
+      return MRPT2_ERR_HIP;                                                                       \
+    hipLaunchKernelGGL((k_b_b12r<MJ>), g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);        \
+    break;
+      MRPT2_B12R(K_B12R_8, 8)
+      MRPT2_B12R(K_B12R_16, 16)
+      MRPT2_B12R(K_B12R_24, 24)
+      MRPT2_B12R(K_B12R_20, 20)
       case K_B12S_20: hipLaunchKernelGGL((k_b_b12s<20>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B12R_32: hipLaunchKernelGGL((k_b_b12r<32>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      MRPT2_B12R(K_B12R_32, 32)
+#undef MRPT2_B12R
       case K_B12S_8: hipLaunchKernelGGL((k_b_b12s<8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12S_16: hipLaunchKernelGGL((k_b_b12s<16>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B12S_24: hipLaunchKernelGGL((k_b_b12s<24>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;

@@ -547,7 +547,7 @@ void build_launches(Plan* P) {
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
     std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[5], j12s[5];
-    size_t lds = 0;
+    size_t lds = 0, lds12 = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -571,6 +571,7 @@ void build_launches(Plan* P) {
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         const int vs = (J > 16 && J <= 20) ? 4 : v;
         j12r[vs].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
+        lds12 = std::max(lds12, (size_t)ip.n_a * 256 * 8);
         j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
@@ -583,10 +584,10 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_B22B, ST_BSTR0 + k, j22b);
     add_launch(P, seq, K_B22WR, ST_BSTR0 + k, j22w);
     for (int v = 0; v < 4; ++v) {
-      add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v]);
+      add_launch(P, seq, K_B12R_8 + v, ST_BROW0 + k, j12r[v], lds12);
       add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
     }
-    add_launch(P, seq, K_B12R_20, ST_BROW0 + k, j12r[4]);
+    add_launch(P, seq, K_B12R_20, ST_BROW0 + k, j12r[4], lds12);
     add_launch(P, seq, K_B12S_20, ST_BSTR0 + k, j12s[4]);
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
