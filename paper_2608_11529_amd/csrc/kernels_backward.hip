@@ -498,8 +498,8 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
 }
 
 // String-owned (one thread per reference string alpha; the block walks all
-// tile pairs for a group of core pairs, in 32 x 32 sub-tiles whose |A|^2 and
-// W_ab are staged in LDS and read by every thread):
+// tile pairs for a group of core pairs, in sub-tiles whose |A|^2 and W_ab are
+// staged in LDS and read by every thread):
 //   R1(alpha) = sum |A|^2 w        -> Cbar_alpha = (2/N) C_alpha R1,
 //   Tbar(alpha) = -(1/N) cw sum |A|^2 w^2,
 //   Uv tables: per virtual a (b), x(alpha, a) = cw sum_{c c', b (a)} |A|^2 w^2
@@ -507,29 +507,33 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
 //   occupations, W[a][t] += (1/N) sum_alpha [t in alpha] x(alpha, a), into a
 //   per-block partial of W (reduced by the next kernel);
 //   Uc: per core pair likewise with -1/N, straight into W.
-// grid (ceil(n_p / 128), ceil(C(n_c,2) / group)), block 128 (B22T), dynamic
-// LDS 2 * 32 * B22T doubles.
-constexpr int B22T = 128;
+// The sub-tiles are B22S x B22S; blocks of B22T threads keep the LDS slab of
+// per-thread values small enough for four blocks (sixteen waves) per CU.
+// grid (ceil(n_p / B22T), ceil(C(n_c,2) / group)), block B22T.
+constexpr int B22T = 256;
+constexpr int B22S = 16;
 
-// Contract one 32-row slab of per-thread values with the string occupations:
-// wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < 32, t < n_a.
+// Contract one B22S-row slab of per-thread values with the string occupations:
+// wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < B22S, t < n_a.
 __device__ __forceinline__ void b22_contract(const double* buf, const uint64_t* sStr, double* wpart, int v0, int nv,
                                              int na) {
-  const int tid = threadIdx.x, cx = tid & 31, tq = tid >> 5;
-  double acc[16];
+  constexpr int TQ = B22T / B22S;           // threads per row: spinors t = tq + TQ m
+  constexpr int NM = 64 / TQ;
+  const int tid = threadIdx.x, cx = tid % B22S, tq = tid / B22S;
+  double acc[NM];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+  for (int m = 0; m < NM; ++m) acc[m] = 0.0;
   for (int l = 0; l < B22T; ++l) {
     const double v = buf[cx * B22T + l];
     const uint64_t x = sStr[l] >> tq;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) acc[m] += ((x >> (4 * m)) & 1ull) ? v : 0.0;
+    for (int m = 0; m < NM; ++m) acc[m] += ((x >> (TQ * m)) & 1ull) ? v : 0.0;
   }
   const int vv = v0 + cx;
   if (vv < nv) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int t = tq + 4 * m;
+    for (int m = 0; m < NM; ++m) {
+      const int t = tq + TQ * m;
       if (t < na) wpart[(int64_t)vv * na + t] += acc[m];
     }
   }
@@ -567,9 +571,9 @@ __device__ __forceinline__ void btrans_body(const Dev& d, const ClassDev& cd, co
 
 __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid, int64_t nsblk) {
-  __shared__ double sBuf[32 * B22T];   // per-thread column: a side, then b side of a sub-tile
-  __shared__ double sA2[32][32];
-  __shared__ double sWab[32][32];
+  __shared__ double sBuf[B22S * B22T];   // per-thread column: a side, then b side of a sub-tile
+  __shared__ double sA2[B22S][B22S];
+  __shared__ double sWab[B22S][B22S];
   __shared__ double sUc[64];
   __shared__ uint64_t sStr[B22T];
   const int tid = threadIdx.x;
@@ -590,17 +594,17 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
   const double* Ucs = cd.Uc + (int64_t)s * nc;
   double* wpart = cg.wpart + ((int64_t)bid.y * nsblk + bid.x) * nv * na;
   double R1 = 0.0, T2 = 0.0;
-  constexpr int NB = 32;
+  constexpr int NB = B22S;
   for (int64_t tp = 0; tp < d.n_tp; ++tp) {
     const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
-    for (int ha = 0; ha < 64; ha += 32) {
+    for (int ha = 0; ha < 64; ha += B22S) {
       const int a0 = I * 64 + ha;
       if (a0 >= nv || J * 64 + 63 <= a0) continue;
       for (int hb = 0; hb < 64; hb += NB) {
         const int b0 = J * 64 + hb;
         if (b0 >= nv || b0 + NB - 1 <= a0) continue;
 #pragma unroll
-        for (int la = 0; la < 32; ++la) sBuf[la * B22T + tid] = 0.0;
+        for (int la = 0; la < B22S; ++la) sBuf[la * B22T + tid] = 0.0;
         double vb[NB];
 #pragma unroll
         for (int lb = 0; lb < NB; ++lb) vb[lb] = 0.0;
@@ -608,8 +612,8 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
           const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
           const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
           __syncthreads();
-          for (int e = tid; e < 32 * 32; e += B22T) {
-            const int la = e >> 5, lb = e & 31;
+          for (int e = tid; e < B22S * NB; e += B22T) {
+            const int la = e / NB, lb = e % NB;
             const int a = a0 + la, b = b0 + lb;
             const bool ok = (a < b) && (b < nv);
             sA2[la][lb] = ok ? cabs2(Ablk[(ha + la) * 64 + hb + lb]) : 0.0;
@@ -626,7 +630,7 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
                               : 0.0;
           }
           double q2c = 0.0;
-          for (int la = 0; la < 32; ++la) {
+          for (int la = 0; la < B22S; ++la) {
             const int a = a0 + la;
             if (a >= nv || b0 + NB - 1 <= a) break;
             const double base =

@@ -404,7 +404,10 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BECOEF: hipLaunchKernelGGL(k_b_becoef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22A: hipLaunchKernelGGL(k_b_b22a, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22WR: hipLaunchKernelGGL(k_b_b22w, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-      case K_B22B: hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B22B:
+        static_assert(B22T == kB22Threads, "(2,2) string-pass block size");
+        hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka);
+        break;
       case K_BTRANS: hipLaunchKernelGGL(k_b_btrans, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
 #define MRPT2_B12R(ID, MJ)                                                                         \

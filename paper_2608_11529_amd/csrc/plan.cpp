@@ -561,7 +561,7 @@ void build_launches(Plan* P) {
       }
       if (cp.kernel_bwd == KERN_E22) {
         j22a.push_back(job(i, cp.n_holes, ip.n_tp, k));
-        j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), 128), cp.parts, k));
+        j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), kB22Threads), cp.parts, k));
 
         j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
         continue;
@@ -1125,7 +1125,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_r1 = Gw.take(b22 ? (size_t)cp.parts * S * 8 : 0);
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
       cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
-      cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + 127) / 128) * ip.n_v * ip.n_a * 8 : 0);
+      cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + kB22Threads - 1) / kB22Threads) * ip.n_v * ip.n_a * 8 : 0);
       // string tables transposed for the generic string-owned pass of the
       // one-virtual classes (lanes = strings)
       const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_GENERIC && cp.v <= 1;
