@@ -61,6 +61,10 @@ __global__ void __launch_bounds__(256) k_b_e0(MRPT2_ARGS) {
   e0_body(I.d, flag);
 }
 // two waves per SIMD (252 VGPRs, no AGPR accumulators) instead of one
+__global__ void __launch_bounds__(256) k_b_abuild(MRPT2_ARGS) {
+  MRPT2_JOB
+  abuild_body(I.d, bid);
+}
 __global__ void __launch_bounds__(512) k_b_abuild128(MRPT2_ARGS) {
   MRPT2_JOB
   abuild128_body(I.d, bid);

@@ -277,6 +277,52 @@ __device__ __forceinline__ void fockx_body(const Dev& d, const uint3 bid) {
 // (core or active):  A[xy][a][b] = <ab||xy> = (ax|by) - (ay|bx)
 //   = sum_L w_L (B_ax B_by - B_ay B_bx),
 // stored per 64 x 64 tile (I, J), I <= J, of virtual pairs, K = 2 n_l.
+// One tile per block (instances with few virtual tiles, where the 128 x 128
+// form below would leave many of its waves idle).
+// grid (n_tp, n_pairs), block 256.
+__device__ __forceinline__ void abuild_body(const Dev& d, const uint3 bid) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  const int64_t tp = bid.x;
+  int64_t pr = bid.y;
+  int xo = 0;
+  while (pr >= d.n_o - 1 - xo) {
+    pr -= d.n_o - 1 - xo;
+    ++xo;
+  }
+  const int yo = xo + 1 + (int)pr;
+  const int I = d.tile_pairs[2 * tp], J = d.tile_pairs[2 * tp + 1];
+  const int nl = d.n_l;
+  const double2* Sx = d.slab + ((int64_t)(d.n_fc + xo) * d.n_corr + d.n_o) * nl;
+  const double2* Sy = d.slab + ((int64_t)(d.n_fc + yo) * d.n_corr + d.n_o) * nl;
+  const double* sg = d.sign;
+  const int nv = d.n_v;
+  auto fa = [&](int r, int k) -> double2 {
+    const int a = I * 64 + r;
+    if (a >= nv) return make_double2(0.0, 0.0);
+    const int L = k < nl ? k : k - nl;
+    const double2 v = (k < nl ? Sx : Sy)[(int64_t)a * nl + L];
+    return make_double2(sg[L] * v.x, sg[L] * v.y);
+  };
+  auto fb = [&](int r, int k) -> double2 {
+    const int b = J * 64 + r;
+    if (b >= nv) return make_double2(0.0, 0.0);
+    if (k < nl) return Sy[(int64_t)b * nl + k];
+    const double2 v = Sx[(int64_t)b * nl + (k - nl)];
+    return make_double2(-v.x, -v.y);
+  };
+  d4 accR[2][2], accI[2][2];
+  cgemm64(fa, fb, 2 * nl, sA, sB, accR, accI);
+  double2* out = d.A + ((int64_t)bid.y * d.n_tp + tp) * 4096;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[acc_row(i, r) * 64 + acc_col(j)] = make_double2(accR[i][j][r], accI[i][j][r]);
+}
+
 // They are built in 128 x 128 blocks of virtual pairs: the block covers
 // the four tiles (I, J) = (2 I2 + u, 2 J2 + v), u, v in {0, 1}, I2 <= J2, and
 // each of its eight waves computes a 64 x 32 half of one tile on FP64 MFMA

@@ -331,6 +331,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_SIGP: hipLaunchKernelGGL(k_b_sigp, g, b64, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E0: hipLaunchKernelGGL(k_b_e0, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_ABUILD: hipLaunchKernelGGL(k_b_abuild128, g, dim3(512), 0, st, insts, jobs, nj, flag, ka); break;
+      case K_ABUILD64: hipLaunchKernelGGL(k_b_abuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_ABUILD32: hipLaunchKernelGGL(k_b_abuild_f32, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_CTAB: hipLaunchKernelGGL(k_b_class_tables, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_XBUILD: hipLaunchKernelGGL(k_b_xbuild, g, b256, 0, st, insts, jobs, nj, flag, ka); break;

@@ -438,16 +438,22 @@ void build_launches(Plan* P) {
   js.clear();
   for (int i : all) js.push_back(job(i, 1, 1));
   add_launch(P, seq, K_E0, ST_REF, js);
-  for (int prec = 0; prec < 2; ++prec) {
-    js.clear();
+  {
+    // FP64: 128 x 128 blocks of virtual pairs where at least 90 % of their
+    // waves have a tile to compute (n_tp tiles over 4 n2 (n2 + 1) / 2 wave
+    // pairs), else one 64 x 64 tile per block; mixed form: its own kernel
+    std::vector<JobH> j128, j64, j32;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
-      if (ip.n_v >= 2 && ip.n_pairs > 0 && (ip.d.precision == MRPT2_MIXED) == (prec == 1)) {
-        const int64_t n2 = (ip.n_vt + 1) / 2;   // FP64: 128 x 128 blocks of virtual pairs
-        js.push_back(prec ? job(i, ip.n_tp, ip.n_pairs) : job(i, n2 * (n2 + 1) / 2, ip.n_pairs));
-      }
+      if (ip.n_v < 2 || ip.n_pairs == 0) continue;
+      const int64_t n2 = (ip.n_vt + 1) / 2, nstp = n2 * (n2 + 1) / 2;
+      if (ip.d.precision == MRPT2_MIXED) j32.push_back(job(i, ip.n_tp, ip.n_pairs));
+      else if (10 * ip.n_tp >= 9 * 4 * nstp) j128.push_back(job(i, nstp, ip.n_pairs));
+      else j64.push_back(job(i, ip.n_tp, ip.n_pairs));
     }
-    add_launch(P, seq, prec ? K_ABUILD32 : K_ABUILD, ST_ABUILD, js);
+    add_launch(P, seq, K_ABUILD, ST_ABUILD, j128);
+    add_launch(P, seq, K_ABUILD64, ST_ABUILD, j64);
+    add_launch(P, seq, K_ABUILD32, ST_ABUILD, j32);
   }
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
     js.clear();

@@ -122,7 +122,7 @@ enum KernelId : int {
   K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20,
   // class (2,1) dense-coefficient kernel, pattern widths 8, 16, 20, 24, 32 (then level-shifted)
   K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32,
-  K_FOCKX
+  K_FOCKX, K_ABUILD64
 };
 
 // Timing slots (mrpt2_energy_timed).

@@ -19,7 +19,8 @@ def uniform(**kv):
 
 def generic_classes(plan):
     """Classes of the generic sigma kernel: partial blocks = row blocks x string chunks."""
-    return [k for k, (h, v) in enumerate(CLASSES) if v < 2 and plan.class_blocks(k) > 0]
+    kc = plan.info().kernel_class
+    return [k for k, (h, v) in enumerate(CLASSES) if kc[k] == 0 and plan.class_blocks(k) > 0]
 
 
 def test_sigma_target_sets_string_chunks():
