@@ -174,6 +174,7 @@ struct ClassGrad {
   double* wpart;       // class (2,2): per-block partials of the Uv adjoint [blocks][n_v][n_a]
   double* UvT;         // generic one-virtual classes: string tables transposed for the
   double* UcT;         // string-owned pass, Uv^T [n_v][S] (v = 1), Uc^T [n_c][S] (h >= 1)
+  double* u2;          // class (0,2): per part, per string and virtual spinor, sums of Delta-bar [parts][S][n_v]
   int64_t wblocks;     // number of those blocks (string blocks x parts)
   int row_split;       // string chunks of the row-owned pass (> 1: shared rows, atomics)
   int parts;           // row parts of the string-owned pass

@@ -1109,6 +1109,334 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
   if (tid < na && sZ[tid] != 0.0) atomicAdd(&g.Wb[(gfc + c) * n + ga + tid], sZ[tid]);
 }
 
+// ---- class (0,2) ---------------------------------------------------------------------
+// sigma[s][b] = sum_k Md[s][k] A[sup_k][a][b] over a tile of at most 64 strings
+// and the 64 b of a tile pair (the forward contraction on FP64 MFMA), with
+//   Delta = T[s] - eps_a - eps_b - W_ab - Uv[s][a] - Uv[s][b].
+// Two passes recompute sigma block by block; both keep every sum in a fixed
+// order and write only entries they own, so the result repeats bit for bit:
+//   row pass    (block: one a of a tile pair, every string tile):
+//               Abar[sup_k][a][b] += sum_s conj(Md[s][k]) sigma-bar[s][b], a second
+//               complex MFMA product with sigma-bar staged in LDS, added into
+//               the block's own entries of Abar; the row constants (eps_a,
+//               eps_b, W_ab) from the column sums of Delta-bar;
+//   string pass (block: one string tile, 64 of its support columns, one part
+//               of the (tile pair, a) rows): Mbar[s][k] = sum_b sigma-bar[s][b]
+//               conj(A[sup_k][a][b]) accumulated on MFMA over the part's rows,
+//               then per coupling cbe[e] = sign_e Mbar[s][ccol_e]; Tbar[s]; and
+//               u[s][v] = sum of Delta-bar over the string's determinants with
+//               virtual spinor v (a or b), for the Uv tables (b02w_body).
+
+// sigma of one (string tile t, row (tp, la)) block on MFMA, then in place the
+// adjoint sigma-bar = (2/N) sigma / Delta and dl = Delta-bar = -|sigma|^2 /
+// (N Delta^2), zero outside the valid (string, a < b < n_v) entries.  Ends
+// with a barrier (the MFMA staging's last).
+__device__ __forceinline__ void b02_tile(const Dev& d, const ClassDev& cd, int64_t t, int64_t tp, int la,
+                                         double2* sA, double2* sB, d4 (&aR)[2][2], d4 (&aI)[2][2],
+                                         double (&dl)[2][2][4]) {
+  const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
+  const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
+  const double2* M = cd.Md + (int64_t)64 * k0;
+  const int32_t* sup = cd.tile_sup + k0;
+  const double2* Ar = d.A + tp * 4096 + la * 64;
+  auto fa = [&](int r, int k) -> double2 { return M[r * K + k]; };
+  auto fb = [&](int r, int k) -> double2 {
+    const int pr = sup[k];
+    return pr < 0 ? make_double2(0.0, 0.0) : Ar[(int64_t)pr * d.n_tp * 4096 + r];
+  };
+  cgemm64<true>(fa, fb, K, sA, sB, aR, aI);
+  const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+  const int nv = d.n_v;
+  const int a = I * 64 + la;
+  const int64_t gv = d.n_fc + d.n_o;
+  const double ea = d.eps[d.n_o + a];
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  double rowc[2];
+  bool bok[2];
+  int bb[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int b = Jt * 64 + acc_col(j);
+    bok[j] = (a < b) && (b < nv);
+    bb[j] = bok[j] ? b : a;
+    rowc[j] = bok[j] ? -ea - d.eps[d.n_o + b] - d.W[(gv + a) * d.n + gv + b] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = s0 + acc_row(i, r);
+      const bool sok = s < s1;
+      const int64_t so = (int64_t)(sok ? s : s0) * nv;
+      const double Ts = cd.T[sok ? s : s0], ua = cd.Uv[so + a];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bool ok = sok && bok[j];
+        const double del = (Ts + rowc[j]) - ua - cd.Uv[so + bb[j]];
+        const double gw = ok ? rcp_nr(del) : 0.0;
+        const double sx = aR[i][j][r], sy = aI[i][j][r];
+        aR[i][j][r] = twoN * gw * sx;
+        aI[i][j][r] = twoN * gw * sy;
+        dl[i][j][r] = -oneN * gw * gw * fma(sx, sx, sy * sy);
+      }
+    }
+}
+
+// Row pass.  grid (64 n_tp) (block = tp * 64 + la), block 256.
+__device__ __forceinline__ void b02r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const uint3 bid) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  __shared__ double2 sS[64 * 65];          // sigma-bar [string][b]
+  __shared__ double sQ[2][64];
+  const int64_t tp = bid.x >> 6;
+  const int la = bid.x & 63;
+  const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+  const int nv = d.n_v;
+  const int a = I * 64 + la;
+  if (a + 1 >= nv || a >= Jt * 64 + 63) return;   // no valid (a, b) in this block
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t n = d.n, gv = d.n_fc + d.n_o;
+  double2* Abr = g.Ab + tp * 4096 + la * 64;
+  double q[2] = {0.0, 0.0};
+  for (int64_t t = 0; t < cd.n_tiles; ++t) {
+    const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
+    if (K == 0) continue;
+    d4 aR[2][2], aI[2][2];
+    double dl[2][2][4];
+    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          sS[acc_row(i, r) * 65 + acc_col(j)] = make_double2(aR[i][j][r], aI[i][j][r]);
+          q[j] += dl[i][j][r];
+        }
+    __syncthreads();
+    const double2* M = cd.Md + (int64_t)64 * k0;
+    const int32_t* sup = cd.tile_sup + k0;
+    for (int kt0 = 0; kt0 < K; kt0 += 64) {
+      auto fa = [&](int r, int s) -> double2 {   // conj(Md[s][kt0 + r])
+        const int k = kt0 + r;
+        if (k >= K) return make_double2(0.0, 0.0);
+        const double2 v = M[s * K + k];
+        return make_double2(v.x, -v.y);
+      };
+      auto fb = [&](int c, int s) -> double2 { return sS[s * 65 + c]; };
+      d4 oR[2][2], oI[2][2];
+      cgemm64<true>(fa, fb, 64, sA, sB, oR, oI);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kt0 + acc_row(i, r);
+          const int pr = k < K ? sup[k] : -1;
+          if (pr < 0) continue;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int lb = acc_col(j), b = Jt * 64 + lb;
+            if (a < b && b < nv) {
+              double2* p = Abr + (int64_t)pr * d.n_tp * 4096 + lb;
+              const double2 o = *p;
+              *p = make_double2(o.x + oR[i][j][r], o.y + oI[i][j][r]);
+            }
+          }
+        }
+    }
+  }
+  // row constants: per column b the sum over strings of Delta-bar
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double v = xsum4(q[j]);
+    if ((lane >> 4) == 0) sQ[wv >> 1][acc_col(j)] = v;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int b = Jt * 64 + tid;
+    double qb = sQ[0][tid] + sQ[1][tid];
+    if (!(a < b && b < nv)) qb = 0.0;
+    if (qb != 0.0) {
+      atomicAdd(&g.epsb[d.n_o + b], -qb);
+      atomicAdd(&g.Wb[(gv + a) * n + gv + b], -qb);
+    }
+    double tot = qb;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if (tid == 0 && tot != 0.0) atomicAdd(&g.epsb[d.n_o + a], -tot);
+  }
+}
+
+// String pass.  grid (n_tiles * nkb (tile, block of 64 support columns), parts),
+// nkb = the widest tile's support in 64-column blocks; block 256.
+__device__ __forceinline__ void b02s_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid, int nkb) {
+  __shared__ double2 sA[64 * KP];
+  __shared__ double2 sB[64 * KP];
+  __shared__ double2 sS[64 * 65];          // sigma-bar [string][b], at the end Mbar [string][column]
+  __shared__ double sRow[2][64];
+  const int64_t t = bid.x / nkb;
+  const int kt0 = (int)(bid.x % nkb) * 64;
+  const bool first = kt0 == 0;             // the first column block also owns Tbar and u
+  const int part = bid.y;
+  const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
+  const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
+  if (kt0 > 0 && kt0 >= K) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nv = d.n_v;
+  const int64_t S = cd.n_str;
+  const int64_t nrow = 64 * d.n_tp;
+  const int64_t r0 = (int64_t)part * cg.rows_per_part, r1 = min(nrow, r0 + cg.rows_per_part);
+  const int32_t* sup = cd.tile_sup + k0;
+  double* u2 = cg.u2 + (int64_t)part * S * nv;
+  d4 mR[2][2], mI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      mR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      mI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  double tq[2][4], ub[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tq[i][r] = 0.0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) ub[i][j][r] = 0.0;
+    }
+  // b side of u: sums over the rows of one tile pair, added when the tile pair changes
+  auto flush_ub = [&](int64_t tpc) {
+    const int Jc = d.tile_pairs[2 * tpc + 1];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = s0 + acc_row(i, r);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int b = Jc * 64 + acc_col(j);
+          if (s < s1 && b < nv && ub[i][j][r] != 0.0) u2[(int64_t)s * nv + b] += ub[i][j][r];
+          ub[i][j][r] = 0.0;
+        }
+      }
+  };
+  int64_t cur = -1;
+  for (int64_t row = r0; row < r1; ++row) {
+    const int64_t tp = row >> 6;
+    const int la = (int)(row & 63);
+    const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+    const int a = I * 64 + la;
+    if (a + 1 >= nv || a >= Jt * 64 + 63 || K == 0) continue;
+    if (first && tp != cur) {
+      if (cur >= 0) flush_ub(cur);
+      cur = tp;
+    }
+    d4 aR[2][2], aI[2][2];
+    double dl[2][2][4];
+    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = dl[i][0][r] + dl[i][1][r];
+        if (first) {
+          tq[i][r] += v;
+          const double va = xsum16(v);   // a side: the string's sum over this wave's 32 columns
+          if ((lane & 15) == 0) sRow[wv & 1][acc_row(i, r)] = va;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          sS[acc_row(i, r) * 65 + acc_col(j)] = make_double2(aR[i][j][r], aI[i][j][r]);
+          if (first) ub[i][j][r] += dl[i][j][r];
+        }
+      }
+    __syncthreads();
+    if (first && tid < 64) {
+      const int s = s0 + tid;
+      const double va = sRow[0][tid] + sRow[1][tid];
+      if (s < s1 && va != 0.0) u2[(int64_t)s * nv + a] += va;
+    }
+    const double2* Ar = d.A + tp * 4096 + la * 64;
+    auto fa = [&](int r, int b) -> double2 { return sS[r * 65 + b]; };
+    auto fb = [&](int c, int b) -> double2 {   // conj(A[sup_{kt0 + c}][a][b])
+      const int k = kt0 + c;
+      const int pr = k < K ? sup[k] : -1;
+      if (pr < 0) return make_double2(0.0, 0.0);
+      const double2 v = Ar[(int64_t)pr * d.n_tp * 4096 + b];
+      return make_double2(v.x, -v.y);
+    };
+    cgemm64<false, false>(fa, fb, 64, sA, sB, mR, mI);
+  }
+  if (first) {
+    if (cur >= 0) flush_ub(cur);
+    // Tbar: per string the sum over the part's determinants
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = xsum16(tq[i][r]);
+        if ((lane & 15) == 0) sRow[wv & 1][acc_row(i, r)] = v;
+      }
+    __syncthreads();
+    if (tid < 64 && s0 + tid < s1) cg.Tb[(int64_t)part * S + s0 + tid] = sRow[0][tid] + sRow[1][tid];
+  }
+  // coupling adjoints of the tile's strings through the columns of this block
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sS[acc_row(i, r) * 65 + acc_col(j)] = make_double2(mR[i][j][r], mI[i][j][r]);
+  __syncthreads();
+  double2* cbe = cg.cbe + (int64_t)part * cd.n_conn;
+  for (int sl = tid >> 2; sl < 64; sl += 64) {
+    const int s = s0 + sl;
+    if (s >= s1) continue;
+    for (int e = cd.conn_ptr[s] + (tid & 3); e < cd.conn_ptr[s + 1]; e += 4) {
+      const int c = cd.ccol[e] - kt0;
+      if (c < 0 || c >= 64) continue;
+      const double2 v = sS[sl * 65 + c];
+      cbe[e] = cd.conn[2 * e] < 0 ? make_double2(-v.x, -v.y) : v;
+    }
+  }
+}
+
+// Uv tables of class (0,2): W[v][t] -= sum_s [t in s] sum_parts u[s][v].
+// grid (ceil(n_v / 256), string chunks), block 256, dynamic LDS n_a * 256 doubles.
+__device__ __forceinline__ void b02w_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid, int nchunk) {
+  extern __shared__ double sY[];
+  const int tid = threadIdx.x;
+  const int nv = d.n_v, na = d.n_a;
+  const int v = bid.x * 256 + tid;
+  const bool live = v < nv;
+  const int64_t S = cd.n_str;
+  for (int t = 0; t < na; ++t) sY[t * 256 + tid] = 0.0;
+  const int64_t chunk = (S + nchunk - 1) / nchunk;
+  const int64_t s_lo = (int64_t)bid.y * chunk, s_hi = min(S, s_lo + chunk);
+  const int64_t per = S * nv;
+  for (int64_t s = s_lo; s < s_hi; ++s) {
+    double u = 0.0;
+    if (live)
+      for (int p = 0; p < cg.parts; ++p) u += cg.u2[p * per + s * nv + v];
+    uint64_t x = uniform64(cd.strings[s]);
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      sY[t * 256 + tid] += u;
+    }
+  }
+  if (!live) return;
+  const int64_t gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  for (int t = 0; t < na; ++t) {
+    const double y = sY[t * 256 + tid];
+    if (y != 0.0) atomicAdd(&g.Wb[(gv + v) * d.n + ga + t], -y);
+  }
+}
+
 // ---- per-string adjoints -------------------------------------------------------
 // T[s] = (E0 - E_core) - E_act(s):  dE0 += Tbar[s];  E_act(s) = sum_{t in s} eps_t
 // + sum_{t<u in s} W_tu receives -Tbar[s].  Coupling adjoints go to C.

@@ -172,6 +172,18 @@ __global__ void __launch_bounds__(256) k_b_b12s(MRPT2_ARGS) {
   MRPT2_JOB
   b12s_body<MJ>(I.d, I.cls[1], I.g, I.cg[1], bid);
 }
+__global__ void __launch_bounds__(256) k_b_b02r(MRPT2_ARGS) {
+  MRPT2_JOB
+  b02r_body(I.d, I.cls[2], I.g, bid);
+}
+__global__ void __launch_bounds__(256) k_b_b02s(MRPT2_ARGS) {
+  MRPT2_JOB
+  b02s_body(I.d, I.cls[2], I.g, I.cg[2], bid, (int)(jb.gx / I.cls[2].n_tiles));
+}
+__global__ void __launch_bounds__(256) k_b_b02w(MRPT2_ARGS) {
+  MRPT2_JOB
+  b02w_body(I.d, I.cls[2], I.g, I.cg[2], bid, jb.gy);
+}
 __global__ void __launch_bounds__(256) k_b_bsfin(MRPT2_ARGS) {
   MRPT2_JOB
   bstrfin_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);

@@ -167,18 +167,21 @@ constexpr int KP = KC + 1;
 // A complex product uses two real MFMAs per pair of complex k:
 //   Re += [ar, -ai] . [br; bi],   Im += [ai, ar] . [br; bi].
 // BCOL: b(c, k) is read with c fastest across threads (operands stored k-major).
-template <bool BCOL = false, class FA, class FB>
+// ZERO = false adds to the accumulators instead of starting from zero.
+template <bool BCOL = false, bool ZERO = true, class FA, class FB>
 __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double2* sB,
                                         d4 (&accR)[2][2], d4 (&accI)[2][2]) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  if (ZERO) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+      for (int j = 0; j < 2; ++j) {
+        accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+  }
   const int kq = lane >> 4;           // 0..3
   const int kcl = kq >> 1, comp = kq & 1;
   for (int k0 = 0; k0 < K; k0 += KC) {

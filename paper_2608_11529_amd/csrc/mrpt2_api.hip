@@ -169,6 +169,7 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   c.row_split = cp.row_split;
   c.ecoef = (double2*)(G + cp.off_ecoef);
   c.wpart = (double*)(G + cp.off_wpart);
+  c.u2 = (double*)(G + cp.off_u2);
   c.UvT = (double*)(G + cp.off_UvT);
   c.UcT = (double*)(G + cp.off_UcT);
   c.wblocks = cp.kernel_bwd == KERN_E22 ? (int64_t)cp.parts * ((int64_t)(cp.strings.size() + B22T - 1) / B22T) : 0;
@@ -405,6 +406,15 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BECOEF: hipLaunchKernelGGL(k_b_becoef, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22A: hipLaunchKernelGGL(k_b_b22a, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22WR: hipLaunchKernelGGL(k_b_b22w, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B02R: hipLaunchKernelGGL(k_b_b02r, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B02S: hipLaunchKernelGGL(k_b_b02s, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_B02W:
+        if (L.dyn_lds > 65536 &&
+            hipFuncSetAttribute((const void*)k_b_b02w, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.dyn_lds) !=
+                hipSuccess)
+          return MRPT2_ERR_HIP;
+        hipLaunchKernelGGL(k_b_b02w, g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);
+        break;
       case K_B22B:
         static_assert(B22T == kB22Threads, "(2,2) string-pass block size");
         hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka);

@@ -552,8 +552,8 @@ void build_launches(Plan* P) {
     }
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[5], j12s[5];
-    size_t lds = 0, lds12 = 0;
+    std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[5], j12s[5], j02r, j02s, j02w;
+    size_t lds = 0, lds12 = 0, lds02 = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -570,6 +570,16 @@ void build_launches(Plan* P) {
         j22b.push_back(job(i, cdiv64((int64_t)cp.strings.size(), kB22Threads), cp.parts, k));
 
         j22w.push_back(job(i, cdiv64((int64_t)ip.n_v * ip.n_a, 256), 1, k));
+        continue;
+      }
+      if (cp.kernel_bwd == KERN_E02) {
+        j02r.push_back(job(i, 64 * ip.n_tp, 1, k));
+        int64_t nkb = 1;   // the widest tile's support in blocks of 64 columns
+        for (int64_t t = 0; t < cp.n_tiles; ++t) nkb = std::max<int64_t>(nkb, cdiv64(cp.tile_k0[t + 1] - cp.tile_k0[t], 64));
+        j02s.push_back(job(i, nkb * cp.n_tiles, cp.parts, k));
+        const int64_t vb = cdiv64(ip.n_v, 256);
+        j02w.push_back(job(i, vb, std::min<int64_t>((int64_t)cp.strings.size(), cdiv64(1024, vb)), k));
+        lds02 = std::max(lds02, (size_t)ip.n_a * 256 * 8);
         continue;
       }
       if (cp.kernel_bwd == KERN_E12) {
@@ -595,6 +605,9 @@ void build_launches(Plan* P) {
     }
     add_launch(P, seq, K_B12R_20, ST_BROW0 + k, j12r[4], lds12);
     add_launch(P, seq, K_B12S_20, ST_BSTR0 + k, j12s[4]);
+    add_launch(P, seq, K_B02R, ST_BROW0 + k, j02r);
+    add_launch(P, seq, K_B02S, ST_BSTR0 + k, j02s);
+    add_launch(P, seq, K_B02W, ST_BSTR0 + k, j02w, lds02);
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
   }
@@ -1097,8 +1110,8 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.row_split = 1;
       const int64_t bt = cp.bwd_target > 0 ? cp.bwd_target : 2048;
       if (S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_E22) {
-        // (2,2) string-owned adjoint kernel (128 strings per block): parts = groups of core pairs
-        const int64_t sblk = (S + 127) / 128;
+        // (2,2) string-owned adjoint kernel (kB22Threads strings per block): parts = groups of core pairs
+        const int64_t sblk = (S + kB22Threads - 1) / kB22Threads;
         int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (bt + sblk - 1) / sblk));
         const int64_t grp = (cp.n_holes + parts - 1) / parts;
         cp.rows_per_part = grp;
@@ -1111,6 +1124,13 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
         ngr = (ip.n_tp + tpg - 1) / tpg;
         cp.rows_per_part = tpg;
         cp.parts = (int)(cp.n_holes * ngr);
+      } else if (S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_E02) {
+        // (0,2) string pass: parts = groups of (tile pair, a) rows, enough
+        // (string tile, part) blocks to fill the device
+        const int64_t nrow = 64 * ip.n_tp;
+        const int64_t parts = std::min<int64_t>(nrow, std::max<int64_t>(1, (bt + cp.n_tiles - 1) / std::max<int64_t>(cp.n_tiles, 1)));
+        cp.rows_per_part = (nrow + parts - 1) / parts;
+        cp.parts = (int)((nrow + cp.rows_per_part - 1) / cp.rows_per_part);
       } else if (S > 0 && cp.n_rows > 0) {
         // string-owned pass: enough (string block, row part) blocks to fill the
         // device, partial coupling adjoints bounded to 256 MB
@@ -1132,6 +1152,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_dbp = Gw.take(b12 ? (size_t)cp.parts * S * cp.patterns.size() * 16 : 0);
       cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
       cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + kB22Threads - 1) / kB22Threads) * ip.n_v * ip.n_a * 8 : 0);
+      cp.off_u2 = Gw.take((cp.kernel_bwd == KERN_E02 && S > 0 && cp.n_rows > 0) ? (size_t)cp.parts * S * ip.n_v * 8 : 0);
       // string tables transposed for the generic string-owned pass of the
       // one-virtual classes (lanes = strings)
       const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_GENERIC && cp.v <= 1;

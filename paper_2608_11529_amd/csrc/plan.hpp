@@ -49,7 +49,7 @@ struct ClassPlan {
   size_t off_T = 0, off_Uc = 0, off_Uv = 0, off_X = 0, off_D = 0, off_mask = 0;
   // gradient workspace offsets (adjoint): coupling adjoints, string-pass partials
   size_t off_Xb = 0, off_Tb = 0, off_cbe = 0, off_r1 = 0, off_dbp = 0, off_ecoef = 0, off_wpart = 0;
-  size_t off_UvT = 0, off_UcT = 0;
+  size_t off_UvT = 0, off_UcT = 0, off_u2 = 0;
   int parts = 1;                       // row parts of the string-owned adjoint pass
   int64_t rows_per_part = 0;           // rows per part (tile pairs per part for the (1,2) kernels)
   int row_split = 1;                   // string chunks of the generic row-owned adjoint pass
@@ -122,7 +122,9 @@ enum KernelId : int {
   K_B12R_20, K_B12S_20, K_E12_20, K_E12S_20,
   // class (2,1) dense-coefficient kernel, pattern widths 8, 16, 20, 24, 32 (then level-shifted)
   K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32,
-  K_FOCKX, K_ABUILD64
+  K_FOCKX, K_ABUILD64,
+  // class (0,2) adjoint on MFMA: row pass, string pass, Uv tables
+  K_B02R, K_B02S, K_B02W
 };
 
 // Timing slots (mrpt2_energy_timed).
