@@ -1704,6 +1704,111 @@ __device__ __forceinline__ void bagemm_body(const Dev& d, const GradDev& g, cons
       }
 }
 
+// The same GEMM in 128 x 128 blocks (the 128 virtual a of two tiles, 128
+// Cholesky columns), eight waves each computing a 64 x 32 part on FP64 MFMA:
+// twice the products per staged operand of the 64 x 64 block.  Used where the
+// blocks are nearly full (large n_v and N_L).
+// grid (ceil(n_l/128), ceil(n_vt/2) * n_o), block 512.
+__device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, const uint3 bid) {
+  __shared__ double2 sA[128 * KP];
+  __shared__ double2 sB[128 * KP];
+  const int nvt = (d.n_v + 63) / 64, nvt2 = (nvt + 1) / 2;
+  const int x = bid.y / nvt2;
+  const int I2 = bid.y % nvt2, a0 = I2 * 128;
+  const int L0 = bid.x * 128;
+  const int nv = d.n_v, nl = d.n_l, no = d.n_o;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int u = wv >> 2, cq = wv & 3;       // row half (64 a), column quarter (32 L)
+  const int kq = lane >> 4, kcl = kq >> 1, comp = kq & 1;
+  const int rowA = u * 64 + (lane & 15), rowB = cq * 32 + (lane & 15);
+  d4 accR[4][2], accI[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto tpi = [&](int i0, int j0) -> int64_t {   // tile pair (i0 <= j0)
+    return (int64_t)i0 * nvt - (int64_t)i0 * (i0 - 1) / 2 + (j0 - i0);
+  };
+  for (int y = 0; y < no; ++y) {
+    if (y == x) continue;
+    const int64_t pr = x < y ? occ_pair(x, y, no) : occ_pair(y, x, no);
+    const double sgn = x < y ? 1.0 : -1.0;
+    const double2* Sy = d.slab + ((int64_t)(d.n_fc + y) * d.n_corr + no) * nl;
+    const double2* Abp = g.Ab + pr * d.n_tp * 4096;
+    for (int b0 = 0; b0 < nv; b0 += KC) {
+      const int Jb = b0 >> 6, lb0 = b0 & 63;    // the 16 b lie in one tile
+      // D term 1: Abar[a][b] from tile (I, Jb), I <= Jb, 16 consecutive b per row
+      for (int e = tid; e < 128 * KC; e += 512) {
+        const int r = e / KC, kk = e % KC;
+        const int a = a0 + r, I = a >> 6, bb = b0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (I <= Jb && a < nv && bb < nv) v = Abp[tpi(I, Jb) * 4096 + (r & 63) * 64 + lb0 + kk];
+        sA[r * KP + kk] = make_double2(sgn * v.x, sgn * v.y);
+      }
+      // B operand: conj(S_y[b][L]), L fastest
+      for (int e = tid; e < 128 * KC; e += 512) {
+        const int c = e & 127, kk = e >> 7;
+        const int L = L0 + c, bb = b0 + kk;
+        sB[c * KP + kk] = (L < nl && bb < nv) ? cconj(Sy[(int64_t)bb * nl + L]) : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      // D term 2: - Abar[b][a] from tile (Jb, I), Jb <= I, a fastest
+      if (Jb <= 2 * I2 + 1) {
+        for (int e = tid; e < 128 * KC; e += 512) {
+          const int r = e & 127, kk = e >> 7;
+          const int a = a0 + r, I = a >> 6, bb = b0 + kk;
+          if (Jb <= I && a < nv && bb < nv) {
+            const double2 v = Abp[tpi(Jb, I) * 4096 + (lb0 + kk) * 64 + (r & 63)];
+            const double2 w = sA[r * KP + kk];
+            sA[r * KP + kk] = make_double2(w.x - sgn * v.x, w.y - sgn * v.y);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll 2
+      for (int ks = 0; ks < KC; ks += 2) {
+        const int kc = ks + kcl;
+        double ar[4], ai[4], bq[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double2 v = sA[(rowA + i * 16) * KP + kc];
+          ar[i] = comp ? -v.y : v.x;
+          ai[i] = comp ? v.x : v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double2 v = sB[(rowB + j * 16) * KP + kc];
+          bq[j] = comp ? v.y : v.x;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bq[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bq[j], accI[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + u * 64 + i * 16 + (lane >> 4) + 4 * r, L = L0 + cq * 32 + j * 16 + (lane & 15);
+        if (a < nv && L < nl) {
+          double2* p = g.slabb + ((int64_t)(d.n_fc + x) * d.n_corr + no + a) * nl + L;
+          const double sg = d.sign[L];
+          *p = cadd(*p, make_double2(sg * accR[i][j][r], sg * accI[i][j][r]));
+        }
+      }
+}
+
 // Mixed form of bagemm_body: the same stages, the operands rounded to FP32
 // as staged into three real planes (re, im, re + im) each, the product
 // formed by three real FP32 MFMA products per complex product (Gauss, as in

@@ -443,6 +443,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BHPP: hipLaunchKernelGGL(k_b_bhpp, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BXB: hipLaunchKernelGGL(k_b_bxb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAG: hipLaunchKernelGGL(k_b_bag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BAG128: hipLaunchKernelGGL(k_b_bag128, g, dim3(512), 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAGF: hipLaunchKernelGGL(k_b_bagf, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BGG: hipLaunchKernelGGL(k_b_bgg, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BFOCK: hipLaunchKernelGGL(k_b_bfock, g, b64, 0, st, insts, jobs, nj, flag, ka); break;

@@ -637,15 +637,21 @@ void build_launches(Plan* P) {
       js.push_back(job(i, cdiv64(cp.n_rows, 256), (int64_t)cp.patterns.size(), k));
     }
   add_launch(P, seq, K_BXB, ST_BXB, js);
-  // pair-integral adjoint GEMM: FP64, or FP32 (Gauss) in the mixed form
-  for (int prec = 0; prec < 2; ++prec) {
-    js.clear();
+  // pair-integral adjoint GEMM: FP64 (128 x 128 blocks for large n_v and
+  // N_L, else 64 x 64), or FP32 (Gauss) in the mixed form
+  {
+    std::vector<JobH> j64, j128, j32;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
-      if (ip.n_v >= 2 && ip.n_o >= 2 && (ip.d.precision == MRPT2_MIXED) == (prec == 1))
-        js.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
+      if (ip.n_v < 2 || ip.n_o < 2) continue;
+      if (ip.d.precision == MRPT2_MIXED) j32.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
+      else if (ip.n_v >= 512 && ip.n_l >= 512)
+        j128.push_back(job(i, cdiv64(ip.n_l, 128), cdiv64(ip.n_vt, 2) * ip.n_o));
+      else j64.push_back(job(i, cdiv64(ip.n_l, 64), cdiv64(ip.n_v, 64) * ip.n_o));
     }
-    add_launch(P, seq, prec ? K_BAGF : K_BAG, ST_BPAIR, js);
+    add_launch(P, seq, K_BAG128, ST_BPAIR, j128);
+    add_launch(P, seq, K_BAG, ST_BPAIR, j64);
+    add_launch(P, seq, K_BAGF, ST_BPAIR, j32);
   }
   for (int which = 0; which < 2; ++which) {
     js.clear();

@@ -124,7 +124,8 @@ enum KernelId : int {
   K_E21_8, K_E21_16, K_E21_20, K_E21_24, K_E21_32, K_E21S_8, K_E21S_16, K_E21S_20, K_E21S_24, K_E21S_32,
   K_FOCKX, K_ABUILD64,
   // class (0,2) adjoint on MFMA: row pass, string pass, Uv tables
-  K_B02R, K_B02S, K_B02W
+  K_B02R, K_B02S, K_B02W,
+  K_BAG128
 };
 
 // Timing slots (mrpt2_energy_timed).
