@@ -512,6 +512,7 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
 // grid (ceil(n_p / B22T), ceil(C(n_c,2) / group)), block B22T.
 constexpr int B22T = 256;
 constexpr int B22S = 16;
+constexpr int B22HP = 8;                   // at most this many core pairs per part (LDS slab of the Uc sums)
 
 // Contract one B22S-row slab of per-thread values with the string occupations:
 // wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < B22S, t < n_a.
@@ -574,7 +575,9 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
   __shared__ double sBuf[B22S * B22T];   // per-thread column: a side, then b side of a sub-tile
   __shared__ double sA2[B22S][B22S];
   __shared__ double sWab[B22S][B22S];
-  __shared__ double sUc[64];
+  __shared__ double sWc[2][B22S];        // W[c][v] + W[c'][v] of the sub-tile's a (0) and b (1)
+  __shared__ double sEa[B22S];           // eps of the sub-tile's a
+  __shared__ double sQ2[B22HP][B22T];    // per core pair of the part and string: sum of |A|^2 w^2 (Uc tables)
   __shared__ uint64_t sStr[B22T];
   const int tid = threadIdx.x;
   const int np = d.n_p, nv = d.n_v, nc = d.n_c, na = d.n_a;
@@ -589,6 +592,8 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
   const double cw = live ? cabs2(d.c[s]) : 0.0;
   const uint64_t str = live ? d.pstrings[s] : 0ull;
   sStr[tid] = str;
+#pragma unroll
+  for (int h = 0; h < B22HP; ++h) sQ2[h][tid] = 0.0;
   const double Ts = cd.T[s];
   const double* Uvs = cd.Uv + (int64_t)s * nv;
   const double* Ucs = cd.Uc + (int64_t)s * nc;
@@ -605,9 +610,13 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
         if (b0 >= nv || b0 + NB - 1 <= a0) continue;
 #pragma unroll
         for (int la = 0; la < B22S; ++la) sBuf[la * B22T + tid] = 0.0;
-        double vb[NB];
+        double vb[NB], ybs[NB];
 #pragma unroll
-        for (int lb = 0; lb < NB; ++lb) vb[lb] = 0.0;
+        for (int lb = 0; lb < NB; ++lb) {
+          vb[lb] = 0.0;
+          const int b = b0 + lb;
+          ybs[lb] = (b < nv) ? -d.eps[d.n_o + b] - Uvs[b] : 0.0;   // the string's part of the b side
+        }
         for (int64_t hp = hp0; hp < hp1; ++hp) {
           const int c0 = d.hole_pairs[2 * hp], c1 = d.hole_pairs[2 * hp + 1];
           const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
@@ -619,22 +628,22 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
             sA2[la][lb] = ok ? cabs2(Ablk[(ha + la) * 64 + hb + lb]) : 0.0;
             sWab[la][lb] = ok ? W[(gv + a) * n + gv + b] : 0.0;
           }
-          if (tid < 64) sUc[tid] = 0.0;
+          if (tid < 2 * B22S) {
+            const int side = tid / B22S, l = tid % B22S;
+            const int v = (side ? b0 : a0) + l;
+            sWc[side][l] = v < nv ? W[(gfc + c0) * n + gv + v] + W[(gfc + c1) * n + gv + v] : 0.0;
+            if (side == 0) sEa[l] = v < nv ? d.eps[d.n_o + v] : 0.0;
+          }
           __syncthreads();
           const double Gc = Ts + Ucs[c0] + Ucs[c1] + d.eps[c0] + d.eps[c1] - W[(gfc + c0) * n + gfc + c1];
           double yb[NB];
 #pragma unroll
-          for (int lb = 0; lb < NB; ++lb) {
-            const int b = b0 + lb;
-            yb[lb] = (b < nv) ? -d.eps[d.n_o + b] - Uvs[b] + W[(gfc + c0) * n + gv + b] + W[(gfc + c1) * n + gv + b]
-                              : 0.0;
-          }
+          for (int lb = 0; lb < NB; ++lb) yb[lb] = ybs[lb] + sWc[1][lb];
           double q2c = 0.0;
           for (int la = 0; la < B22S; ++la) {
             const int a = a0 + la;
             if (a >= nv || b0 + NB - 1 <= a) break;
-            const double base =
-                Gc - d.eps[d.n_o + a] - Uvs[a] + W[(gfc + c0) * n + gv + a] + W[(gfc + c1) * n + gv + a];
+            const double base = Gc - sEa[la] - Uvs[a] + sWc[0][la];
             double va = 0.0;
 #pragma unroll
             for (int lb = 0; lb < NB; lb += 4) {
@@ -668,20 +677,7 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
             sBuf[la * B22T + tid] += cw * va;
           }
           T2 += q2c;
-          // Uc of this core pair: W[c][t] -= (1/N) sum_alpha [t in alpha] cw q2c
-          if (live && q2c != 0.0) {
-            uint64_t x = str;
-            while (x) {
-              const int t = __builtin_ctzll(x);
-              x &= x - 1;
-              atomicAdd(&sUc[t], cw * q2c);
-            }
-          }
-          __syncthreads();
-          if (tid < na && sUc[tid] != 0.0) {
-            atomicAdd(&g.Wb[(gfc + c0) * n + ga + tid], -oneN * sUc[tid]);
-            atomicAdd(&g.Wb[(gfc + c1) * n + ga + tid], -oneN * sUc[tid]);
-          }
+          sQ2[hp - hp0][tid] += cw * q2c;   // own column
         }
         // the sub-tile's a side, then its b side, contracted with the occupations
         __syncthreads();
@@ -698,6 +694,21 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
   if (live) {
     cg.Tb[(int64_t)bid.y * np + s] = -oneN * cw * T2;
     cg.r1[(int64_t)bid.y * np + s] = R1;
+  }
+  // Uc tables of the part's core pairs: W[c][t] -= (1/N) sum_alpha [t in alpha] cw q2
+  __syncthreads();
+  const int nh = (int)(hp1 - hp0);
+  for (int e = tid; e < nh * 64; e += B22T) {
+    const int h = e >> 6, t = e & 63;
+    if (t >= na) continue;
+    double v = 0.0;
+    for (int l = 0; l < B22T; ++l)
+      if ((sStr[l] >> t) & 1ull) v += sQ2[h][l];
+    if (v != 0.0) {
+      const int c0 = d.hole_pairs[2 * (hp0 + h)], c1 = d.hole_pairs[2 * (hp0 + h) + 1];
+      atomicAdd(&g.Wb[(gfc + c0) * n + ga + t], -oneN * v);
+      atomicAdd(&g.Wb[(gfc + c1) * n + ga + t], -oneN * v);
+    }
   }
 }
 

@@ -416,7 +416,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
         hipLaunchKernelGGL(k_b_b02w, g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);
         break;
       case K_B22B:
-        static_assert(B22T == kB22Threads, "(2,2) string-pass block size");
+        static_assert(B22T == kB22Threads && B22HP == kB22PairsPerPart, "(2,2) string-pass shape");
         hipLaunchKernelGGL(k_b_b22b, g, dim3(B22T), 0, st, insts, jobs, nj, flag, ka);
         break;
       case K_BTRANS: hipLaunchKernelGGL(k_b_btrans, g, b256, 0, st, insts, jobs, nj, flag, ka); break;

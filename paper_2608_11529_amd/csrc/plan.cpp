@@ -1119,6 +1119,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
         // (2,2) string-owned adjoint kernel (kB22Threads strings per block): parts = groups of core pairs
         const int64_t sblk = (S + kB22Threads - 1) / kB22Threads;
         int64_t parts = std::min<int64_t>(cp.n_holes, std::max<int64_t>(1, (bt + sblk - 1) / sblk));
+        parts = std::max<int64_t>(parts, (cp.n_holes + kB22PairsPerPart - 1) / kB22PairsPerPart);
         const int64_t grp = (cp.n_holes + parts - 1) / parts;
         cp.rows_per_part = grp;
         cp.parts = (int)((cp.n_holes + grp - 1) / grp);

@@ -179,6 +179,7 @@ struct Plan {
 enum ClassKernel : int { KERN_GENERIC = 0, KERN_E22 = 1, KERN_E12 = 2, KERN_E02 = 3, KERN_E21 = 4 };
 constexpr int kStrTile = 64;                // strings per tile of the (0,2) contraction kernel
 constexpr int kB22Threads = 256;            // strings per block of the (2,2) string-owned adjoint kernel
+constexpr int kB22PairsPerPart = 8;         // its largest group of core pairs per block
 
 struct Plan;
 // Launch sequences and job table of a plan whose instances are built.
