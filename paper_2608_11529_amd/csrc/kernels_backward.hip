@@ -42,6 +42,20 @@ __device__ __forceinline__ void bzero_body(const GradDev& g, const uint3 bid, in
   for (int64_t i = (int64_t)bid.x * 256 + threadIdx.x; i < g.n_zero; i += nblk * 256) g.zero[i] = z;
 }
 
+// Sum of v over a block of 256 threads in a fixed order (each wave by a fixed
+// butterfly, then the four waves in order); every thread of the block must
+// call it.  The adjoint's row passes write E2 per block with it, so the E2 of
+// the adjoint call repeats bit for bit.
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double sw[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = ((sw[0] + sw[1]) + sw[2]) + sw[3];
+  __syncthreads();
+  return t;
+}
+
 // ---- row decoding shared by the two passes ----------------------------------
 struct Row {
   int c0, c1, a, b;
@@ -188,7 +202,7 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
   const double2* X = (V == 2) ? d.A : cd.X;
   const double2* __restrict__ ec = cg.ecoef;
   const int32_t* __restrict__ ek = cd.ekey;
-  double q = 0.0;
+  double q = 0.0, e2 = 0.0;
   const double b2 = d.ls_b2;
   const int64_t S = cd.n_str;
   // strings [s_lo, s_hi) of this block; with several string chunks the
@@ -216,6 +230,7 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     const double2 sb = make_double2(twoN * gw * sig.x, twoN * gw * sig.y);
     const double dl = oneN * gp * cabs2(sig);
     if (w.valid) {
+      e2 = fma(gw, cabs2(sig), e2);
       for (e = e0; e < e1; ++e) {
         double2* p = Xb + coupling_off<H, V>(d, cd, ek[e], w, rr);
         const double2 v = cmul(sb, cconj(ec[e]));
@@ -231,6 +246,8 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
       }
     }
   }
+  const double e2b = block_sum256(e2);
+  if (tid == 0) cd.part[(int64_t)bid.y * ((cd.n_rows + 255) / 256) + bid.x] = e2b;
   if (!w.valid) return;
   const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
   double* Wb = g.Wb;
@@ -453,6 +470,7 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
   const double2* Ablk = d.A + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
   double2* Ab = g.Ab + ((int64_t)occ_pair(c0, c1, d.n_o) * d.n_tp + tp) * 4096;
   double rowa[4] = {0.0, 0.0, 0.0, 0.0}, colb[4] = {0.0, 0.0, 0.0, 0.0};
+  double e2 = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -460,6 +478,7 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
       if (ok[i][j]) {
         const int li = (ta + 16 * i) * 64 + tb + 16 * j;
         const double2 av = Ablk[li];
+        e2 = fma(cabs2(av), S1[i][j], e2);
         Ab[li] = make_double2(twoN * S1[i][j] * av.x, twoN * S1[i][j] * av.y);
         const double gq = -oneN * cabs2(av) * S2[i][j];   // sum over alpha of Delta-bar
         const int a = I * 64 + ta + 16 * i, b = J * 64 + tb + 16 * j;
@@ -467,6 +486,8 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
         rowa[i] += gq;
         colb[j] += gq;
       }
+  const double e2b = block_sum256(e2);
+  if (tid == 0) cd.part[(int64_t)tp * cd.n_holes + hp] = e2b;
   __syncthreads();
   double* sRC = &sYa[0][0];   // row sums [0..63], column sums [64..127]
   if (tid < 128) sRC[tid] = 0.0;
@@ -847,7 +868,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
   if (!YREG)
     for (int t = 0; t < na; ++t) sY[t * 256 + tid] = 0.0;
   const double epsc = d.eps[c];
-  double q = 0.0;
+  double q = 0.0, e2 = 0.0;
   const int64_t S = cd.n_str;
   for (int64_t s0 = 0; s0 < S; s0 += B12C) {
     __syncthreads();
@@ -909,6 +930,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
         const double2 t = make_double2(sg[k].x * w[k], sg[k].y * w[k]);
         sbv[k] = valid ? make_double2(twoN * t.x, twoN * t.y) : make_double2(0.0, 0.0);
         dl[k] = valid ? -oneN * cabs2(t) : 0.0;
+        e2 += valid ? cabs2(sg[k]) * w[k] : 0.0;
         q += dl[k];
       }
       // Xbar_j += sigma-bar conj(D_j)
@@ -955,6 +977,8 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
     for (int t = 0; t < NY; ++t)
       if (t < na) sY[t * 256 + tid] = y[t];
   }
+  const double e2b = block_sum256(e2);
+  if (tid == 0) cd.part[(int64_t)bid.y * nc + c] = e2b;
   // row constants: eps and W of c, a, b
   __syncthreads();
   if (tid < 16) {
@@ -1140,11 +1164,12 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
 
 // sigma of one (string tile t, row (tp, la)) block on MFMA, then in place the
 // adjoint sigma-bar = (2/N) sigma / Delta and dl = Delta-bar = -|sigma|^2 /
-// (N Delta^2), zero outside the valid (string, a < b < n_v) entries.  Ends
-// with a barrier (the MFMA staging's last).
+// (N Delta^2), zero outside the valid (string, a < b < n_v) entries, and adds
+// |sigma|^2 / Delta of the valid entries to e2.  Ends with a barrier (the MFMA
+// staging's last).
 __device__ __forceinline__ void b02_tile(const Dev& d, const ClassDev& cd, int64_t t, int64_t tp, int la,
                                          double2* sA, double2* sB, d4 (&aR)[2][2], d4 (&aI)[2][2],
-                                         double (&dl)[2][2][4]) {
+                                         double (&dl)[2][2][4], double& e2) {
   const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
   const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
   const double2* M = cd.Md + (int64_t)64 * k0;
@@ -1189,6 +1214,7 @@ __device__ __forceinline__ void b02_tile(const Dev& d, const ClassDev& cd, int64
         aR[i][j][r] = twoN * gw * sx;
         aI[i][j][r] = twoN * gw * sy;
         dl[i][j][r] = -oneN * gw * gw * fma(sx, sx, sy * sy);
+        e2 = fma(gw, fma(sx, sx, sy * sy), e2);
       }
     }
 }
@@ -1209,12 +1235,13 @@ __device__ __forceinline__ void b02r_body(const Dev& d, const ClassDev& cd, cons
   const int64_t n = d.n, gv = d.n_fc + d.n_o;
   double2* Abr = g.Ab + tp * 4096 + la * 64;
   double q[2] = {0.0, 0.0};
+  double e2 = 0.0;
   for (int64_t t = 0; t < cd.n_tiles; ++t) {
     const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
     if (K == 0) continue;
     d4 aR[2][2], aI[2][2];
     double dl[2][2][4];
-    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl);
+    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl, e2);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1256,6 +1283,8 @@ __device__ __forceinline__ void b02r_body(const Dev& d, const ClassDev& cd, cons
         }
     }
   }
+  const double e2b = block_sum256(e2);
+  if (tid == 0) cd.part[bid.x] = e2b;
   // row constants: per column b the sum over strings of Delta-bar
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -1346,7 +1375,8 @@ __device__ __forceinline__ void b02s_body(const Dev& d, const ClassDev& cd, cons
     }
     d4 aR[2][2], aI[2][2];
     double dl[2][2][4];
-    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl);
+    double e2u = 0.0;   // E2 is the row pass's
+    b02_tile(d, cd, t, tp, la, sA, sB, aR, aI, dl, e2u);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -250,7 +250,12 @@ mrpt2_status fill_insts(const Plan& P, const mrpt2_inputs* in, const char* pers,
       I->g = make_grad(ip, gw, go, grad_e2 + i, e2 ? e2 + i : nullptr);
       I->d.out_e2 = I->g.scal + 1;
       I->d.out_parts = nullptr;
-      for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cg[k] = make_class_grad(ip, k, gw);
+      for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+        I->cg[k] = make_class_grad(ip, k, gw);
+        // the adjoint's E2 comes from its row passes' block sums
+        I->cls[k].part = (double*)(gw + ip.grad_base + ip.cls[k].off_e2part);
+        I->cls[k].n_part = ip.cls[k].n_e2part;
+      }
     }
   }
   return MRPT2_OK;

@@ -542,7 +542,10 @@ void build_launches(Plan* P) {
     js.push_back(job(i, std::max<int64_t>(1, std::min<int64_t>(cdiv64(n32, 256), 65536)), 1));
   }
   add_launch(P, seq, K_BZERO, ST_BZERO, js);
-  for (const Launch& L : P->energy) seq->push_back(L);
+  // the forward pass without its sigma and E2 kernels: the row passes below
+  // recompute every determinant's term and write E2 per block
+  for (const Launch& L : P->energy)
+    if (!(L.stage >= ST_SIGMA0 && L.stage < ST_SIGMA0 + MRPT2_N_CLASS) && L.kid != K_FINISH) seq->push_back(L);
   js.clear();
   for (int k = 0; k < MRPT2_N_CLASS; ++k)
     for (int i : all) {
@@ -623,6 +626,9 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_B22FIN, ST_BFIN, j22);
     add_launch(P, seq, K_BSFIN, ST_BFIN, js);
   }
+  js.clear();
+  for (int i : all) js.push_back(job(i, 1, 1));
+  add_launch(P, seq, K_FINISH, ST_BFIN, js);   // E2 of the row passes' block sums
   js.clear();
   for (int i : all) {
     const int np = (int)P->inst[i].pstrings.size();
@@ -1160,6 +1166,15 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_ecoef = Gw.take((size_t)cp.n_conn * 16);
       cp.off_wpart = Gw.take(b22 ? (size_t)cp.parts * ((S + kB22Threads - 1) / kB22Threads) * ip.n_v * ip.n_a * 8 : 0);
       cp.off_u2 = Gw.take((cp.kernel_bwd == KERN_E02 && S > 0 && cp.n_rows > 0) ? (size_t)cp.parts * S * ip.n_v * 8 : 0);
+      // E2 share of every block of the class's row pass
+      cp.n_e2part = 0;
+      if (S > 0 && cp.n_rows > 0) {
+        if (cp.kernel_bwd == KERN_E22) cp.n_e2part = cp.n_holes * ip.n_tp;
+        else if (cp.kernel_bwd == KERN_E12) cp.n_e2part = cp.n_holes * 16 * ip.n_tp;
+        else if (cp.kernel_bwd == KERN_E02) cp.n_e2part = 64 * ip.n_tp;
+        else cp.n_e2part = cdiv64(cp.n_rows, 256) * cp.row_split;
+      }
+      cp.off_e2part = Gw.take((size_t)cp.n_e2part * 8);
       // string tables transposed for the generic string-owned pass of the
       // one-virtual classes (lanes = strings)
       const bool pass = S > 0 && cp.n_rows > 0 && cp.kernel_bwd == KERN_GENERIC && cp.v <= 1;

@@ -50,6 +50,8 @@ struct ClassPlan {
   // gradient workspace offsets (adjoint): coupling adjoints, string-pass partials
   size_t off_Xb = 0, off_Tb = 0, off_cbe = 0, off_r1 = 0, off_dbp = 0, off_ecoef = 0, off_wpart = 0;
   size_t off_UvT = 0, off_UcT = 0, off_u2 = 0;
+  size_t off_e2part = 0;               // adjoint: per row-pass block, its share of E2
+  int64_t n_e2part = 0;
   int parts = 1;                       // row parts of the string-owned adjoint pass
   int64_t rows_per_part = 0;           // rows per part (tile pairs per part for the (1,2) kernels)
   int row_split = 1;                   // string chunks of the generic row-owned adjoint pass
