@@ -1030,7 +1030,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
 // and the Uc table of c: W[c][t] += sum_s [t in s] Tbar_part[s].
 // grid (ceil(S/256), n_c * groups), block 256.
 template <int MJ>
-__device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+__device__ __forceinline__ void b12s_wide(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
   __shared__ double2 sX[64][MJ];
   __shared__ double sQ[64];
@@ -1142,6 +1142,140 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
   }
   __syncthreads();
   if (tid < na && sZ[tid] != 0.0) atomicAdd(&g.Wb[(gfc + c) * n + ga + tid], sZ[tid]);
+}
+
+// The same pass when the block's strings couple through at most MQ patterns
+// (the union of their masks, the usual case: strings come ordered by mask):
+// only those patterns' couplings are staged, the coefficients and their
+// adjoints sit compacted in MQ registers, and each coupling read from LDS
+// serves both sigma and the coefficient adjoint of its determinant (one
+// reciprocal per determinant instead of one per four; half the LDS reads).
+template <int MQ>
+__device__ __forceinline__ void b12s_compact(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                             const uint3 bid, uint32_t um) {
+  __shared__ double2 sX[64][MQ];
+  __shared__ double sQ[64];
+  __shared__ double sZ[64];
+  const int tid = threadIdx.x;
+  const int64_t S = cd.n_str;
+  int64_t s = (int64_t)bid.x * 256 + tid;
+  const bool live = s < S;
+  if (!live) s = S - 1;
+  const int part = bid.y;
+  const int ngr = (int)((d.n_tp + cg.rows_per_part - 1) / cg.rows_per_part);
+  const int c = part / ngr;
+  const int64_t tp0 = (int64_t)(part % ngr) * cg.rows_per_part;
+  const int64_t tp1 = min(d.n_tp, tp0 + cg.rows_per_part);
+  const int J = cd.n_pat;
+  const int nv = d.n_v, nc = d.n_c, na = d.n_a;
+  const int64_t n = d.n, gfc = d.n_fc, gv = d.n_fc + d.n_o, ga = d.n_fc + d.n_c;
+  const double N = d.scal[1], oneN = 1.0 / N, twoN = 2.0 / N;
+  // the block's patterns, in order: jl[q], q < nq
+  int jl[MQ];
+  const int nq = __builtin_popcount(um);
+  {
+    uint32_t m = um;
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      jl[q] = m ? __builtin_ctz(m) : 0;
+      m &= m - 1;
+    }
+  }
+  double2 Dc[MQ], Dbc[MQ];
+#pragma unroll
+  for (int q = 0; q < MQ; ++q) {
+    Dc[q] = q < nq ? cd.D[s * J + jl[q]] : make_double2(0.0, 0.0);
+    Dbc[q] = make_double2(0.0, 0.0);
+  }
+  int64_t prq[MQ];   // occupied pair of (c, the pattern's active spinor)
+#pragma unroll
+  for (int q = 0; q < MQ; ++q) prq[q] = q < nq ? occ_pair(c, nc + cd.pat[jl[q]].a0, d.n_o) : 0;
+  const double Gs = cd.T[s] + cd.Uc[s * nc + c] + d.eps[c];
+  const double* Uvs = cd.Uv + s * nv;
+  double tq = 0.0;
+  if (tid < 64) sZ[tid] = 0.0;
+  __syncthreads();
+  for (int64_t tp = tp0; tp < tp1; ++tp) {
+    const int I = d.tile_pairs[2 * tp], Jt = d.tile_pairs[2 * tp + 1];
+    for (int la = 0; la < 64; ++la) {
+      const int a = I * 64 + la;
+      if (a >= nv || Jt * 64 + 63 <= a) break;
+      __syncthreads();
+      for (int e = tid; e < 64 * MQ; e += 256) {
+        const int q = e >> 6, lb = e & 63;
+        const int b = Jt * 64 + lb;
+        double2 v = make_double2(0.0, 0.0);
+        int64_t pr = 0;
+#pragma unroll
+        for (int u = 0; u < MQ; ++u)
+          if (u == q) pr = prq[u];
+        if (q < nq && b > a && b < nv) v = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb];
+        sX[lb][q] = v;
+      }
+      if (tid < 64) {
+        const int b = Jt * 64 + tid;
+        sQ[tid] = (b > a && b < nv) ? -d.eps[d.n_o + a] - d.eps[d.n_o + b] - d.W[(gv + a) * n + gv + b] +
+                                          d.W[(gfc + c) * n + gv + a] + d.W[(gfc + c) * n + gv + b]
+                                    : 0.0;
+      }
+      __syncthreads();
+      const double ga_s = Gs - Uvs[a];
+      const int lb0 = max(0, a + 1 - Jt * 64);
+      const int lb1 = min(64, nv - Jt * 64);
+      for (int l = lb0; l < lb1; ++l) {
+        double2 xv[MQ];
+        double2 sg = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < MQ; ++q)
+          if (q < nq) {
+            xv[q] = sX[l][q];
+            sg = cfma(Dc[q], xv[q], sg);
+          }
+        const double w = rcp_nr(ga_s + sQ[l] - Uvs[Jt * 64 + l]);
+        const double2 t = make_double2(sg.x * w, sg.y * w);
+        const double2 sbv = make_double2(twoN * t.x, twoN * t.y);
+        tq -= oneN * cabs2(t);
+#pragma unroll
+        for (int q = 0; q < MQ; ++q)
+          if (q < nq) {   // Dbar_j += sigma-bar conj(X_j)
+            Dbc[q].x = fma(sbv.x, xv[q].x, fma(sbv.y, xv[q].y, Dbc[q].x));
+            Dbc[q].y = fma(sbv.y, xv[q].x, fma(-sbv.x, xv[q].y, Dbc[q].y));
+          }
+      }
+    }
+  }
+  if (live) {
+    double2* out = cg.dbp + ((int64_t)part * S + s) * J;
+#pragma unroll
+    for (int q = 0; q < MQ; ++q)
+      if (q < nq) out[jl[q]] = Dbc[q];
+    cg.Tb[(int64_t)part * S + s] = tq;
+    uint64_t x = cd.strings[s];
+    while (x) {
+      const int t = __builtin_ctzll(x);
+      x &= x - 1;
+      atomicAdd(&sZ[t], tq);
+    }
+  }
+  __syncthreads();
+  if (tid < na && sZ[tid] != 0.0) atomicAdd(&g.Wb[(gfc + c) * n + ga + tid], sZ[tid]);
+}
+
+// String pass of class (1,2): the compact form when the block's strings couple
+// through at most 12 patterns, else the wide form.
+template <int MJ>
+__device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
+                                          const uint3 bid) {
+  __shared__ uint32_t sUm;
+  const int64_t S = cd.n_str;
+  const int64_t s = (int64_t)bid.x * 256 + threadIdx.x;
+  if (threadIdx.x == 0) sUm = 0u;
+  __syncthreads();
+  if (s < S) atomicOr(&sUm, cd.mask[s]);
+  __syncthreads();
+  const uint32_t um = __builtin_amdgcn_readfirstlane(sUm);
+  if (MJ > 12 && __builtin_popcount(um) > 12) b12s_wide<MJ>(d, cd, g, cg, bid);
+  else b12s_compact<(MJ < 12 ? MJ : 12)>(d, cd, g, cg, bid, um);
 }
 
 // ---- class (0,2) ---------------------------------------------------------------------
