@@ -340,7 +340,9 @@ constexpr int AK = 16;              // complex k per stage
 constexpr int AKP = AK + 1;         // padded LDS row (double2)
 
 __device__ __forceinline__ void abuild128_body(const Dev& d, const uint3 bid) {
-  __shared__ double2 sA[128 * AKP];
+  // A staged as (re, im, -im, re): the lanes of the second k of a pair read the
+  // (-im, re) half, so each MFMA operand comes straight from LDS
+  __shared__ double4 sA[128 * AKP];
   __shared__ double2 sB[128 * AKP];
   const int nvt = d.n_vt, nvt2 = (nvt + 1) >> 1;
   int I2 = 0;
@@ -408,7 +410,8 @@ __device__ __forceinline__ void abuild128_body(const Dev& d, const uint3 bid) {
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 512 * q;
       const double m = (k0 + e % AK) < nl ? 1.0 : -1.0;
-      sA[(e / AK) * AKP + e % AK] = make_double2(rs[q] * ra[q].x, rs[q] * ra[q].y);
+      const double xr = rs[q] * ra[q].x, xi = rs[q] * ra[q].y;
+      sA[(e / AK) * AKP + e % AK] = make_double4(xr, xi, -xi, xr);
       sB[(e / AK) * AKP + e % AK] = make_double2(m * rb[q].x, m * rb[q].y);
     }
     __syncthreads();
@@ -420,15 +423,12 @@ __device__ __forceinline__ void abuild128_body(const Dev& d, const uint3 bid) {
         double ar[4], ai[4], bb[2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double2 v = sA[(rowA + i * 16) * AKP + kc];
-          ar[i] = comp ? -v.y : v.x;
-          ai[i] = comp ? v.x : v.y;
+          const double2 v = ((const double2*)&sA[(rowA + i * 16) * AKP + kc])[comp];
+          ar[i] = v.x;
+          ai[i] = v.y;
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const double2 v = sB[(rowB + j * 16) * AKP + kc];
-          bb[j] = comp ? v.y : v.x;
-        }
+        for (int j = 0; j < 2; ++j) bb[j] = ((const double*)&sB[(rowB + j * 16) * AKP + kc])[comp];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
