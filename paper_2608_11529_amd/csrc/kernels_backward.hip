@@ -1302,7 +1302,7 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
 // |sigma|^2 / Delta of the valid entries to e2.  Ends with a barrier (the MFMA
 // staging's last).
 __device__ __forceinline__ void b02_tile(const Dev& d, const ClassDev& cd, int64_t t, int64_t tp, int la,
-                                         double2* sA, double2* sB, d4 (&aR)[2][2], d4 (&aI)[2][2],
+                                         double4* sA, double2* sB, d4 (&aR)[2][2], d4 (&aI)[2][2],
                                          double (&dl)[2][2][4], double& e2) {
   const int s0 = cd.tile_s0[t], s1 = cd.tile_s0[t + 1];
   const int k0 = cd.tile_k0[t], K = cd.tile_k0[t + 1] - k0;
@@ -1355,7 +1355,7 @@ __device__ __forceinline__ void b02_tile(const Dev& d, const ClassDev& cd, int64
 
 // Row pass.  grid (64 n_tp) (block = tp * 64 + la), block 256.
 __device__ __forceinline__ void b02r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const uint3 bid) {
-  __shared__ double2 sA[64 * KP];
+  __shared__ double4 sA[64 * KP];
   __shared__ double2 sB[64 * KP];
   __shared__ double2 sS[64 * 65];          // sigma-bar [string][b]
   __shared__ double sQ[2][64];
@@ -1445,7 +1445,7 @@ __device__ __forceinline__ void b02r_body(const Dev& d, const ClassDev& cd, cons
 // nkb = the widest tile's support in 64-column blocks; block 256.
 __device__ __forceinline__ void b02s_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid, int nkb) {
-  __shared__ double2 sA[64 * KP];
+  __shared__ double4 sA[64 * KP];
   __shared__ double2 sB[64 * KP];
   __shared__ double2 sS[64 * 65];          // sigma-bar [string][b], at the end Mbar [string][column]
   __shared__ double sRow[2][64];

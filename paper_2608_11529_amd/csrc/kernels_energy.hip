@@ -786,9 +786,11 @@ __device__ __forceinline__ void e02coef_body(const Dev& d, const ClassDev& cd, c
 // 32-term stage; denominators and sums stay FP64.
 template <bool F32, bool LS>
 __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
-  constexpr int SH = F32 ? 64 * KP32 : 2 * 64 * KP;   // float2 slots of each staging buffer
-  __shared__ __align__(16) float2 sA[SH];
-  __shared__ __align__(16) float2 sB[SH];
+  // float2 slots of each staging buffer (the FP64 A operand is staged as
+  // (re, im, -im, re))
+  constexpr int SHA = F32 ? 64 * KP32 : 4 * 64 * KP, SHB = F32 ? 64 * KP32 : 2 * 64 * KP;
+  __shared__ __align__(32) float2 sA[SHA];
+  __shared__ __align__(32) float2 sB[SHB];
   __shared__ double red[256];
   const int64_t t = bid.x;
   const int64_t tp = bid.y >> 6;
@@ -816,7 +818,7 @@ __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* 
     cgemm64_f32c(fa, fb, K, sA, sB, accR, accI);
   } else {
     d4 aR[2][2], aI[2][2];
-    cgemm64<true>(fa, fb, K, (double2*)sA, (double2*)sB, aR, aI);
+    cgemm64<true>(fa, fb, K, (double4*)sA, (double2*)sB, aR, aI);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -166,11 +166,17 @@ constexpr int KP = KC + 1;
 // B[l/16][l%16]; the result D[i][j] sits in lane j + 16 (i%4), register i/4.
 // A complex product uses two real MFMAs per pair of complex k:
 //   Re += [ar, -ai] . [br; bi],   Im += [ai, ar] . [br; bi].
+// TA = double4: the A operand is staged as (re, im, -im, re) per complex k, so
+// that the lanes holding the second real k of a pair read the (-im, re) half
+// and every operand comes straight from LDS (no per-step selects; twice the
+// LDS of the A stage, which costs occupancy where many small blocks run).
+// TA = double2: staged as (re, im), the lanes select their parts.
 // BCOL: b(c, k) is read with c fastest across threads (operands stored k-major).
 // ZERO = false adds to the accumulators instead of starting from zero.
-template <bool BCOL = false, bool ZERO = true, class FA, class FB>
-__device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double2* sB,
+template <bool BCOL = false, bool ZERO = true, class TA, class FA, class FB>
+__device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, TA* sA, double2* sB,
                                         d4 (&accR)[2][2], d4 (&accI)[2][2]) {
+  constexpr bool PAIR = sizeof(TA) == 32;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
   if (ZERO) {
@@ -188,7 +194,9 @@ __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double
     for (int e = tid; e < 64 * KC; e += 256) {
       const int r = e / KC, kk = e % KC;
       const bool in = (k0 + kk) < K;
-      sA[r * KP + kk] = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
+      const double2 v = in ? fa(r, k0 + kk) : make_double2(0.0, 0.0);
+      if constexpr (PAIR) sA[r * KP + kk] = make_double4(v.x, v.y, -v.y, v.x);
+      else sA[r * KP + kk] = v;
       if (!BCOL) sB[r * KP + kk] = in ? fb(r, k0 + kk) : make_double2(0.0, 0.0);
     }
     if (BCOL)
@@ -203,15 +211,18 @@ __device__ __forceinline__ void cgemm64(FA fa, FB fb, int K, double2* sA, double
       double ar[2], ai[2], bb[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const double2 v = sA[(wr + i * 16 + (lane & 15)) * KP + kc];
-        ar[i] = comp ? -v.y : v.x;
-        ai[i] = comp ? v.x : v.y;
+        if constexpr (PAIR) {
+          const double2 v = ((const double2*)&sA[(wr + i * 16 + (lane & 15)) * KP + kc])[comp];
+          ar[i] = v.x;
+          ai[i] = v.y;
+        } else {
+          const double2 v = sA[(wr + i * 16 + (lane & 15)) * KP + kc];
+          ar[i] = comp ? -v.y : v.x;
+          ai[i] = comp ? v.x : v.y;
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const double2 v = sB[(wc + j * 16 + (lane & 15)) * KP + kc];
-        bb[j] = comp ? v.y : v.x;
-      }
+      for (int j = 0; j < 2; ++j) bb[j] = ((const double*)&sB[(wc + j * 16 + (lane & 15)) * KP + kc])[comp];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
