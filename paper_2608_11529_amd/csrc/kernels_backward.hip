@@ -1885,7 +1885,7 @@ __device__ __forceinline__ void bagemm_body(const Dev& d, const GradDev& g, cons
 // blocks are nearly full (large n_v and N_L).
 // grid (ceil(n_l/128), ceil(n_vt/2) * n_o), block 512.
 __device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, const uint3 bid) {
-  __shared__ double2 sA[128 * KP];
+  __shared__ double4 sA[128 * KP];   // (re, im, -im, re): MFMA operands straight from LDS
   __shared__ double2 sB[128 * KP];
   const int nvt = (d.n_v + 63) / 64, nvt2 = (nvt + 1) / 2;
   const int x = bid.y / nvt2;
@@ -1921,7 +1921,7 @@ __device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, c
         const int a = a0 + r, I = a >> 6, bb = b0 + kk;
         double2 v = make_double2(0.0, 0.0);
         if (I <= Jb && a < nv && bb < nv) v = Abp[tpi(I, Jb) * 4096 + (r & 63) * 64 + lb0 + kk];
-        sA[r * KP + kk] = make_double2(sgn * v.x, sgn * v.y);
+        sA[r * KP + kk] = make_double4(sgn * v.x, sgn * v.y, -sgn * v.y, sgn * v.x);
       }
       // B operand: conj(S_y[b][L]), L fastest
       for (int e = tid; e < 128 * KC; e += 512) {
@@ -1937,8 +1937,9 @@ __device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, c
           const int a = a0 + r, I = a >> 6, bb = b0 + kk;
           if (Jb <= I && a < nv && bb < nv) {
             const double2 v = Abp[tpi(Jb, I) * 4096 + (lb0 + kk) * 64 + (r & 63)];
-            const double2 w = sA[r * KP + kk];
-            sA[r * KP + kk] = make_double2(w.x - sgn * v.x, w.y - sgn * v.y);
+            const double4 w = sA[r * KP + kk];
+            const double nx = w.x - sgn * v.x, ny = w.y - sgn * v.y;
+            sA[r * KP + kk] = make_double4(nx, ny, -ny, nx);
           }
         }
         __syncthreads();
@@ -1949,15 +1950,12 @@ __device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, c
         double ar[4], ai[4], bq[2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const double2 v = sA[(rowA + i * 16) * KP + kc];
-          ar[i] = comp ? -v.y : v.x;
-          ai[i] = comp ? v.x : v.y;
+          const double2 v = ((const double2*)&sA[(rowA + i * 16) * KP + kc])[comp];
+          ar[i] = v.x;
+          ai[i] = v.y;
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const double2 v = sB[(rowB + j * 16) * KP + kc];
-          bq[j] = comp ? v.y : v.x;
-        }
+        for (int j = 0; j < 2; ++j) bq[j] = ((const double*)&sB[(rowB + j * 16) * KP + kc])[comp];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
