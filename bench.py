@@ -103,8 +103,9 @@ def roofline(dom, ms, cases, precision):
                    for pb, _ in cases)
         peak = FP32_MFMA_PEAK if mixed else FP64_MFMA_PEAK
         ach = flop / (ms * 1e-3)
-        return {"kernel": "k_b_abuild%s (virtual-pair integrals <ab||xy>, complex %s MFMA)"
-                          % ("_f32" if mixed else "128", "FP32" if mixed else "FP64"),
+        return {"kernel": ("k_b_abuild_f32 (virtual-pair integrals <ab||xy>, complex FP32 MFMA)" if mixed else
+                           "k_b_abuild128 / k_b_abuild (virtual-pair integrals <ab||xy>, complex FP64 MFMA; "
+                           "128 x 128 blocks where they fill, else 64 x 64)"),
                 "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": None}
     if dom == "sigma_22":
