@@ -646,8 +646,10 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
             const int la = e / NB, lb = e % NB;
             const int a = a0 + la, b = b0 + lb;
             const bool ok = (a < b) && (b < nv);
+            // outside a < b < n_v: zero weight and a denominator near -1e30,
+            // whose fraction vanishes (products of four such stay finite)
             sA2[la][lb] = ok ? cabs2(Ablk[(ha + la) * 64 + hb + lb]) : 0.0;
-            sWab[la][lb] = ok ? W[(gv + a) * n + gv + b] : 0.0;
+            sWab[la][lb] = ok ? W[(gv + a) * n + gv + b] : -1e30;
           }
           if (tid < 2 * B22S) {
             const int side = tid / B22S, l = tid % B22S;
@@ -669,14 +671,10 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
 #pragma unroll
             for (int lb = 0; lb < NB; lb += 4) {
               double dd[4], a2[4];
-              // branch-free: the denominator is finite for every (a, b) of the
-              // sub-tile (sA2 = sWab = 0 outside a < b < n_v, yb = 0 beyond
-              // n_v); pairs with a zero weight take 1
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
                 a2[k] = sA2[la][lb + k];
-                const double dv = (base + yb[lb + k]) - sWab[la][lb + k];
-                dd[k] = fma(a2[k] != 0.0 ? 1.0 : 0.0, dv - 1.0, 1.0);
+                dd[k] = (base + yb[lb + k]) - sWab[la][lb + k];
               }
               const double p01 = dd[0] * dd[1], p23 = dd[2] * dd[3];
               const double r = rcp_nr(p01 * p23);

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(SIG_THREADS) k_b_sigma(MRPT2_ARGS) {
 __global__ void __launch_bounds__(256) k_b_finish(MRPT2_ARGS) {
   MRPT2_JOB
   (void)bid;
-  finish_body(I.d, I.cls);
+  finish_body(I.d, I.cls, flag);
 }
 
 // ---- adjoint ----

@@ -892,8 +892,9 @@ __device__ __forceinline__ void e02_body(const Dev& d, const ClassDev& cd, int* 
 
 // Per-class sum of partials (Neumaier-compensated, fixed order) divided by
 // ||C||^2; out[k] for k < 9, out[9] = E2, out[10] = E0 - E_core,
-// out[11] = ||C||^2; e2 receives E2.  One block.
-__device__ __forceinline__ void finish_body(const Dev& d, const ClassDev* cds) {
+// out[11] = ||C||^2; e2 receives E2.  A non-finite E2 (an exactly zero
+// denominator, an overflow) sets the error flag.  One block.
+__device__ __forceinline__ void finish_body(const Dev& d, const ClassDev* cds, int* flag) {
   __shared__ double ss[256], sc[256];
   __shared__ double cls[MRPT2_N_CLASS];
   double* out = d.out_parts;
@@ -932,6 +933,7 @@ __device__ __forceinline__ void finish_body(const Dev& d, const ClassDev* cds) {
       s = t;
     }
     const double tot = s + comp;
+    if (!isfinite(tot)) *flag = 2;
     if (out) {
       for (int k = 0; k < MRPT2_N_CLASS; ++k) out[k] = cls[k];
       out[9] = tot;

@@ -191,9 +191,10 @@ def test_zero_denominator_is_reported():
     two-electron integrals and one virtual orbital energy equal to a core
     orbital energy, so that the single excitation between them has
     E0 - H_KK = 0 exactly (eq. pt2en is undefined there).  Without a level
-    shift the call reports MRPT2_ERR_NUMERIC; with the imaginary level shift
-    of Sec. 2.6 (whose weight Delta^3/(Delta^4 + b^2) vanishes at Delta = 0)
-    the same instance gives a finite energy."""
+    shift the energy and the adjoint call report MRPT2_ERR_NUMERIC; with the
+    imaginary level shift of Sec. 2.6 (whose weight Delta^3/(Delta^4 + b^2)
+    vanishes at Delta = 0) the same instance gives a finite energy, and the
+    adjoint call the same E2."""
     import torch
     import paper_2608_11529_amd as M
     pb = problem("s_single")
@@ -208,6 +209,12 @@ def test_zero_denominator_is_reported():
     with pytest.raises(M.Mrpt2Error) as ei:
         eng.energy([(h, Bs, c)])
     assert ei.value.code == 6
+    # the adjoint call (which forms E2 in its own passes) reports it as well
+    with pytest.raises(M.Mrpt2Error) as ei:
+        eng.backward([(h, Bs, c)])
+    assert ei.value.code == 6
     eng_ls = M.Engine(M.Plan(M.desc_of_problem(pb, level_shift_b=0.5)))
     e2, parts = eng_ls.energy([(h, Bs, c)])
     assert np.isfinite(float(e2[0]))
+    outs, e2b = eng_ls.backward([(h, Bs, c)])
+    assert abs(float(e2b[0]) - float(e2[0])) <= 1e-13 * max(1.0, abs(float(e2[0])))
