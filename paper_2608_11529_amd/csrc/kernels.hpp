@@ -166,6 +166,7 @@ struct GradDev {
 
 struct ClassGrad {
   double2* Xb;         // [n_pat][n_rows] adjoint of X (v < 2)
+  double2* Xbp;        // [row_split][n_pat][n_rows] its private partials per string chunk, or null
   double* Tb;          // [parts][S]  per-part sums of dE2/dDelta over each string
   double2* cbe;        // [parts][n_conn] per-part coefficient adjoints per coupling
   double* r1;          // [parts][S] class (2,2): per-part sums of |A|^2 / Delta per string

@@ -211,6 +211,14 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
   const int64_t chunk = (S + nsc - 1) / nsc;
   const int64_t s_lo = (int64_t)bid.y * chunk, s_hi = min(S, s_lo + chunk);
   const bool shared_rows = nsc > 1;
+  // several string chunks: the chunk's own slice of partials where the plan
+  // gave them (plain adds, summed in order by bxbred_body), else atomics
+  double2* Xbw = Xb;
+  bool atomic = shared_rows;
+  if (V < 2 && shared_rows && cg.Xbp) {
+    Xbw = cg.Xbp + (int64_t)bid.y * cd.n_pat * cd.n_rows;
+    atomic = false;
+  }
   for (int64_t s = s_lo; s < s_hi; ++s) {
     const int e0 = cd.conn_ptr[s], e1 = cd.conn_ptr[s + 1];
     if (e1 == e0) continue;
@@ -232,9 +240,9 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     if (w.valid) {
       e2 = fma(gw, cabs2(sig), e2);
       for (e = e0; e < e1; ++e) {
-        double2* p = Xb + coupling_off<H, V>(d, cd, ek[e], w, rr);
+        double2* p = Xbw + coupling_off<H, V>(d, cd, ek[e], w, rr);
         const double2 v = cmul(sb, cconj(ec[e]));
-        if (shared_rows) catomic(p, v);
+        if (atomic) catomic(p, v);
         else *p = cadd(*p, v);
       }
       q += dl;
@@ -279,6 +287,17 @@ __device__ __forceinline__ void brow_body(const Dev& d, const ClassDev& cd, cons
     if (V >= 1) atomicAdd(&Wb[(gv + w.a) * n + ga + t], -y);
     if (V == 2) atomicAdd(&Wb[(gv + w.b) * n + ga + t], -y);
   }
+}
+
+// Coupling adjoints of a class from the string chunks' private slices, summed
+// in chunk order.  grid (ceil(n_pat n_rows / 256)), block 256.
+__device__ __forceinline__ void bxbred_body(const ClassDev& cd, const ClassGrad& cg, const uint3 bid) {
+  const int64_t i = (int64_t)bid.x * 256 + threadIdx.x;
+  const int64_t m = (int64_t)cd.n_pat * cd.n_rows;
+  if (i >= m) return;
+  double2 v = make_double2(0.0, 0.0);
+  for (int p = 0; p < cg.row_split; ++p) v = cadd(v, cg.Xbp[(int64_t)p * m + i]);
+  cg.Xb[i] = v;
 }
 
 // ---- string pass -------------------------------------------------------------

@@ -196,6 +196,10 @@ __global__ void __launch_bounds__(256) k_b_bxb(MRPT2_ARGS) {
   MRPT2_JOB
   bxbuild_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);
 }
+__global__ void __launch_bounds__(256) k_b_bxbred(MRPT2_ARGS) {
+  MRPT2_JOB
+  bxbred_body(I.cls[jb.arg], I.cg[jb.arg], bid);
+}
 __global__ void __launch_bounds__(512) k_b_bag128(MRPT2_ARGS) {
   MRPT2_JOB
   bagemm128_body(I.d, I.g, bid);

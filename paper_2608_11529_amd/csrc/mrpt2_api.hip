@@ -162,6 +162,7 @@ ClassGrad make_class_grad(const InstancePlan& ip, int k, char* gw) {
   char* G = gw + ip.grad_base;
   ClassGrad c{};
   c.Xb = (double2*)(G + cp.off_Xb);
+  c.Xbp = cp.xb_private ? (double2*)(G + cp.off_Xbp) : nullptr;
   c.Tb = (double*)(G + cp.off_Tb);
   c.cbe = (double2*)(G + cp.off_cbe);
   c.r1 = (double*)(G + cp.off_r1);
@@ -449,6 +450,7 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_BXB: hipLaunchKernelGGL(k_b_bxb, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAG: hipLaunchKernelGGL(k_b_bag, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAG128: hipLaunchKernelGGL(k_b_bag128, g, dim3(512), 0, st, insts, jobs, nj, flag, ka); break;
+      case K_BXBRED: hipLaunchKernelGGL(k_b_bxbred, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BAGF: hipLaunchKernelGGL(k_b_bagf, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BGG: hipLaunchKernelGGL(k_b_bgg, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BFOCK: hipLaunchKernelGGL(k_b_bfock, g, b64, 0, st, insts, jobs, nj, flag, ka); break;

@@ -612,6 +612,15 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_B02S, ST_BSTR0 + k, j02s);
     add_launch(P, seq, K_B02W, ST_BSTR0 + k, j02w, lds02);
     add_launch(P, seq, K_BROW22 + k, ST_BROW0 + k, jr, lds);
+    {
+      std::vector<JobH> jx;
+      for (int i : all) {
+        const ClassPlan& cp = P->inst[i].cls[k];
+        if (cp.xb_private && !cp.strings.empty() && cp.n_rows > 0)
+          jx.push_back(job(i, cdiv64((int64_t)cp.patterns.size() * cp.n_rows, 256), 1, k));
+      }
+      add_launch(P, seq, K_BXBRED, ST_BROW0 + k, jx);
+    }
     add_launch(P, seq, K_BSTR22 + k, ST_BSTR0 + k, jsr);
   }
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
@@ -1158,6 +1167,13 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
         if (rb < 512) cp.row_split = (int)std::min<int64_t>(S, (rt + rb - 1) / rb);
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
+      // with several string chunks per row block the generic row pass writes
+      // each chunk's coupling adjoints into its own slice (plain adds, summed
+      // in order afterwards) where that stays within 4 GiB, else it adds them
+      // atomically into one array
+      const size_t xbp = (size_t)cp.row_split * cp.patterns.size() * (size_t)std::max<int64_t>(cp.n_rows, 0) * 16;
+      cp.xb_private = cp.kernel_bwd == KERN_GENERIC && cp.v < 2 && S > 0 && cp.row_split > 1 && xbp <= (4ull << 30);
+      cp.off_Xbp = Gw.take(cp.xb_private ? xbp : 0);
       cp.off_Tb = Gw.take((size_t)cp.parts * S * 8);
       const bool b22 = cp.kernel_bwd == KERN_E22, b12 = cp.kernel_bwd == KERN_E12;
       cp.off_cbe = Gw.take((b22 || b12) ? 0 : (size_t)cp.parts * cp.n_conn * 16);

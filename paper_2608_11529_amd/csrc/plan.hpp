@@ -51,6 +51,8 @@ struct ClassPlan {
   size_t off_Xb = 0, off_Tb = 0, off_cbe = 0, off_r1 = 0, off_dbp = 0, off_ecoef = 0, off_wpart = 0;
   size_t off_UvT = 0, off_UcT = 0, off_u2 = 0;
   size_t off_e2part = 0;               // adjoint: per row-pass block, its share of E2
+  size_t off_Xbp = 0;                  // private coupling-adjoint partials per string chunk (or 0 bytes)
+  bool xb_private = false;
   int64_t n_e2part = 0;
   int parts = 1;                       // row parts of the string-owned adjoint pass
   int64_t rows_per_part = 0;           // rows per part (tile pairs per part for the (1,2) kernels)
@@ -127,7 +129,7 @@ enum KernelId : int {
   K_FOCKX, K_ABUILD64,
   // class (0,2) adjoint on MFMA: row pass, string pass, Uv tables
   K_B02R, K_B02S, K_B02W,
-  K_BAG128
+  K_BAG128, K_BXBRED
 };
 
 // Timing slots (mrpt2_energy_timed).
