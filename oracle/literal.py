@@ -158,3 +158,45 @@ def e2_literal(space, h, g, C, q_mode=0, H_PP=None, b=0.0):
         terms.setdefault(external_class(space, K), []).append(abs(s) ** 2 * en_weight(d, b) / norm)
     parts = {k: math.fsum(v) for k, v in terms.items()}
     return math.fsum(parts.values()), E0, parts, len(sigma)
+
+
+def denominator_stats(space, h, g, C, thresh, q_mode=0, H_PP=None):
+    """Per excitation class (core holes, virtual electrons): the smallest
+    |E0 - H_KK| over the external determinants K of Q and the number of them
+    with |E0 - H_KK| < thresh (Sec. 2.6: intruder states are the K whose
+    denominator of eq. pt2en comes close to zero).  Q is every determinant one
+    or two replacements away from a reference determinant that is not itself
+    one (Sec. 2.3; q_mode 1 keeps those with a core hole or a virtual
+    electron).  Returns {class: (min |Delta|, count)}."""
+    P = space.p_dets()
+    if H_PP is None:
+        H_PP = reference_hamiltonian(space, h, g)
+    E0 = reference_energy(H_PP, C)
+    Pset = set(P)
+    n = space.n
+    Q = set()
+    for L in P:
+        occ = bits(L)
+        vir = [p for p in range(n) if not L >> p & 1]
+        for q in occ:
+            for p in vir:
+                Q.add(L ^ (1 << q) ^ (1 << p))
+        for q, s in combinations(occ, 2):
+            for p, r in combinations(vir, 2):
+                Q.add(L ^ (1 << q) ^ (1 << s) ^ (1 << p) ^ (1 << r))
+    Q -= Pset
+    if q_mode == 1:
+        Q = {K for K in Q if (K & space.core_mask) != space.core_mask or (K & space.virt_mask)}
+    hd = np.real(np.diag(h)).astype(np.float64)
+    W = np.zeros((n, n))
+    for p in range(n):
+        for q in range(n):
+            if p != q:
+                W[p, q] = (g(p, p, q, q) - g(p, q, q, p)).real
+    out = {}
+    for K in Q:
+        a = abs(E0 - diagonal(K, hd, W))
+        cls = external_class(space, K)
+        m, c = out.get(cls, (math.inf, 0))
+        out[cls] = (min(m, a), c + (1 if a < thresh else 0))
+    return out

@@ -77,6 +77,45 @@ def test_jordan_wigner_bruteforce(case):
     assert abs(e2_cls - e2_bf) < 1e-12 * max(1.0, abs(e2_bf))
 
 
+@pytest.mark.parametrize("case", JW_CASES[:2], ids=[c[0] for c in JW_CASES[:2]])
+@pytest.mark.parametrize("q_mode", [0, 1])
+def test_denominator_stats_bruteforce(case, q_mode):
+    """Smallest |E0 - H_KK| per excitation class and the count below a
+    threshold (Sec. 2.6) against a brute-force pass over every N-electron
+    determinant within two replacements of P, its diagonal taken from the
+    Slater-Condon rule (not from the pair energies the oracle uses)."""
+    name, seed, n_fc, n_c, subs, ne, nv, sets, hops, base = case
+    spec = SP.small(name, seed, n_fc, n_c, subs, ne, nv, sets, max_hops=hops, base=base)
+    h, Bs, ws = tensors(spec)
+    n = h.shape[0]
+    sp = run.space_of(spec)
+    g, gc, H, c = ground(sp, h, Bs, ws)
+    E0 = literal.reference_energy(H, c)
+    P = sp.p_dets()
+    N = bin(P[0]).count("1")
+    deltas = {}
+    for K in range(1 << n):
+        if bin(K).count("1") != N or K in set(P):
+            continue
+        if min(bin(K ^ L).count("1") for L in P) > 4:
+            continue
+        holes = sp.n_c - bin(K & sp.core_mask).count("1")
+        virt = bin(K & sp.virt_mask).count("1")
+        if q_mode == 1 and holes == 0 and virt == 0:
+            continue
+        d = abs(E0 - literal.matrix_element(K, K, h, gc).real)
+        deltas.setdefault((holes, virt), []).append(d)
+    allv = np.sort(np.concatenate([np.array(v) for v in deltas.values()]))
+    k = len(allv) // 3
+    thresh = 0.5 * (allv[k] + allv[k + 1])     # between two values: no tie at the threshold
+    got = literal.denominator_stats(sp, h, gc, c, thresh, q_mode)
+    assert set(got) == set(deltas)
+    for cls, v in deltas.items():
+        m, cnt = got[cls]
+        assert abs(m - min(v)) <= 1e-12 * max(1.0, min(v)), (cls, m, min(v))
+        assert cnt == sum(1 for x in v if x < thresh), cls
+
+
 # ------------------------------------------------------------ level shift
 # Sec. 2.6: 1/Delta -> Re 1/(Delta + i eps) with eps = b/Delta.  The oracle
 # writes the shifted inverse as complex arithmetic; the pins below reach it
