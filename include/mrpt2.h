@@ -61,6 +61,18 @@ typedef enum {
 
 typedef enum { MRPT2_FP64 = 0, MRPT2_MIXED = 1 } mrpt2_precision;
 
+/* Storage of the Cholesky factors B_t[L] (and of their gradients dB_t):
+ *  MRPT2_LAYOUT_FULL    complex [rank_t][n][n], every entry;
+ *  MRPT2_LAYOUT_PACKED  complex [rank_t][n (n + 1) / 2]: the upper triangle
+ *    of each Hermitian B_t[L] by rows, entry (p, q) with p <= q at
+ *    p n - p (p - 1) / 2 + (q - p); the lower triangle is its conjugate and
+ *    the imaginary part of a diagonal entry is ignored.  Halves the factor
+ *    memory and its one HBM pass.  The gradient in this layout is taken with
+ *    respect to the stored entries themselves: 2 P_pq off the diagonal and
+ *    P_pp on it, P being the Hermitian-projected gradient of the full
+ *    layout. */
+typedef enum { MRPT2_LAYOUT_FULL = 0, MRPT2_LAYOUT_PACKED = 1 } mrpt2_layout;
+
 /* Problem description (one instance).  Sec. 2.4: the primary space holds
  * the active occupations whose per-subspace electron counts m_k satisfy
  * sum m_k = n_act_elec and sum_k max(0, m_k - sub_base[k]) <= max_hops
@@ -90,6 +102,7 @@ typedef struct {
                                        eq. pt2 exactly.  A nonzero b runs the
                                        adjoint of every excitation class on the
                                        generic passes (slower). */
+  int32_t layout;                   /* mrpt2_layout of B and dB */
 } mrpt2_desc;
 
 /* Sizes and exact algorithmic work of one instance. */
@@ -124,14 +137,15 @@ typedef struct {
 /* Inputs of one instance (device pointers). */
 typedef struct {
   const double* h;                     /* complex [n][n] */
-  const double* B[MRPT2_MAX_SETS];     /* complex [rank_t][n][n] */
+  const double* B[MRPT2_MAX_SETS];     /* complex [rank_t][n][n], or
+                                          [rank_t][n (n + 1) / 2] packed */
   const double* c;                     /* complex [N_P], plan order */
 } mrpt2_inputs;
 
 /* Gradient outputs of one instance (device pointers, caller-owned, overwritten). */
 typedef struct {
   double* dh;                          /* complex [n][n] */
-  double* dB[MRPT2_MAX_SETS];          /* complex [rank_t][n][n] */
+  double* dB[MRPT2_MAX_SETS];          /* complex, in the layout of B */
   double* dc;                          /* complex [N_P], plan order */
 } mrpt2_grads;
 
@@ -143,7 +157,7 @@ typedef struct mrpt2_plan_s* mrpt2_plan_t;
  * Errors: MRPT2_ERR_ARG for null pointers, n_inst < 1 or a level_shift_b
  * that is not finite, MRPT2_ERR_SHAPE for inconsistent sizes (electrons vs
  * subspaces, more than 64 active spinors, N_P >= 2^24), MRPT2_ERR_UNSUPPORTED
- * for an unknown precision.  On error *out is NULL. */
+ * for an unknown precision or factor layout.  On error *out is NULL. */
 mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* out);
 
 /* Launch shapes of one instance's work decomposition, per excitation class
@@ -318,6 +332,24 @@ mrpt2_status mrpt2_reference_states_direct(mrpt2_plan_t plan, int32_t inst, cons
  * solver; meant for n up to a few hundred.  Errors: MRPT2_ERR_ARG,
  * MRPT2_ERR_NUMERIC for non-finite input. */
 mrpt2_status mrpt2_hermitian_eigh(int32_t n, const double* a, double* w, double* v);
+
+/* Denominator statistics of the external space (Sec. 2.6: an intruder state
+ * is an external determinant K whose E0 - H_KK comes close to zero, where
+ * its term of eq. pt2en blows up and the level shift is meant to act): for
+ * every instance and excitation class, the smallest |E0 - H_KK| over the
+ * class's determinants and the number of them with |E0 - H_KK| < thresh
+ * (the unshifted denominators, whatever the plan's level shift).  Runs the
+ * factor tables, the occupied-block integrals, the reference energy and the
+ * per-string denominator tables on `workspace` (not the pair integrals or
+ * any sigma contraction), then one pass over each class's (row x string)
+ * grid.  in: as mrpt2_energy (c is read for E0).  min_abs_delta: host
+ * double[n_inst][9], class order as in mrpt2_info, +inf for an empty class
+ * (written); n_below: host int64[n_inst][9] or NULL (written).  Synchronises
+ * the stream.  Errors as mrpt2_energy; MRPT2_ERR_ARG for a NULL
+ * min_abs_delta or a thresh that is negative or not finite. */
+mrpt2_status mrpt2_delta_stats(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream, double thresh, double* min_abs_delta,
+                               int64_t* n_below);
 
 /* Bytes of the gradient workspace of mrpt2_energy_backward (256-byte aligned
  * device allocation, caller-owned). */

@@ -14,8 +14,10 @@ from .capi import CLASSES, Mrpt2Error  # noqa: F401
 
 
 def make_desc(n_frozen_core, n_core, n_virt, sub_sizes, sub_base, max_hops, n_act_elec,
-              sets, q_mode=0, precision=0, level_shift_b=0.0):
-    """Fill a descriptor.  sets = [(rank, weight), ...]."""
+              sets, q_mode=0, precision=0, level_shift_b=0.0, layout=0):
+    """Fill a descriptor.  sets = [(rank, weight), ...]; layout 0 passes
+    each factor matrix in full [n][n], 1 as its packed upper triangle
+    [n (n + 1) / 2] (see hermitian_pack)."""
     d = capi.Desc()
     d.n_frozen_core = n_frozen_core
     d.n_core = n_core
@@ -33,14 +35,26 @@ def make_desc(n_frozen_core, n_core, n_virt, sub_sizes, sub_base, max_hops, n_ac
         d.weight[t] = w
     d.precision = precision
     d.level_shift_b = level_shift_b
+    d.layout = layout
     return d
 
 
-def desc_of_problem(pb, precision=0, q_mode=None, level_shift_b=0.0):
+def desc_of_problem(pb, precision=0, q_mode=None, level_shift_b=0.0, layout=0):
     """Descriptor of a synth.problems.Problem."""
     return make_desc(pb.n_fc, pb.n_c, pb.n_v, pb.sub_sizes, pb.base, min(pb.max_hops, 1 << 20),
                      pb.n_elec, pb.sets, pb.q_mode if q_mode is None else q_mode, precision,
-                     level_shift_b)
+                     level_shift_b, layout)
+
+
+def hermitian_pack(B):
+    """Packed layout of Hermitian factor matrices: B [..., n, n] ->
+    [..., n (n + 1) / 2], the upper triangle of each matrix by rows (entry
+    (p, q), p <= q, at p n - p (p - 1) / 2 + (q - p)).  A copy in the
+    caller's tensor library; the library reads the packed tensor directly."""
+    import torch
+    n = B.shape[-1]
+    iu = torch.triu_indices(n, n, device=B.device)
+    return B[..., iu[0], iu[1]].contiguous()
 
 
 class Plan:
@@ -174,9 +188,12 @@ class Engine:
         ranks = [desc.rank[t] for t in range(desc.n_sets)]
         if len(Bs) != len(ranks):
             raise ValueError("instance %d: %d factor sets expected" % (i, len(ranks)))
+        packed = desc.layout == 1
         for t, (B, r) in enumerate(zip(Bs, ranks)):
-            if tuple(B.shape) != (r, n, n) or B.dtype != torch.complex128:
-                raise ValueError("instance %d: B[%d] must be complex128 [%d, %d, %d]" % (i, t, r, n, n))
+            want = (r, n * (n + 1) // 2) if packed else (r, n, n)
+            if tuple(B.shape) != want or B.dtype != torch.complex128:
+                raise ValueError("instance %d: B[%d] must be complex128 %s%s"
+                                 % (i, t, list(want), " (packed layout)" if packed else ""))
         if c is not None and (c.dtype != torch.complex128 or c.dim() not in (1, 2)
                               or c.shape[-1] != info.n_ref or c.numel() == 0):
             raise ValueError("instance %d: c must be complex128 [N_P = %d] (or [n_roots, N_P])" % (i, info.n_ref))
@@ -290,6 +307,22 @@ class Engine:
         capi.check(capi.lib().mrpt2_energy_backward(*args), "mrpt2_energy_backward")
         del keep
         return outs, self.e2
+
+    def delta_stats(self, insts, thresh=0.0):
+        """Smallest |E0 - H_KK| per instance and excitation class and the
+        number of external determinants with |E0 - H_KK| < thresh (host numpy
+        [n_inst, 9] float64 and int64; class order of capi.Info)."""
+        arr, keep = self._inputs(insts)
+        n = self.plan.n_inst
+        mn = np.zeros((n, capi.N_CLASS))
+        cnt = np.zeros((n, capi.N_CLASS), dtype=np.int64)
+        code = capi.lib().mrpt2_delta_stats(self.plan.handle, arr, self.persistent.data_ptr(),
+                                            self.workspace.data_ptr(), self.plan.workspace_bytes, self._sptr(),
+                                            float(thresh), mn.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        capi.check(code, "mrpt2_delta_stats")
+        del keep
+        return mn, cnt
 
     def class_partials(self, cls, inst=0):
         """Block partial sums of class cls from the last energy() (host numpy,

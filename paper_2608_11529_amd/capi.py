@@ -52,6 +52,7 @@ class Desc(ctypes.Structure):
         ("weight", ctypes.c_double * MAX_SETS),
         ("precision", ctypes.c_int32),
         ("level_shift_b", ctypes.c_double),
+        ("layout", ctypes.c_int32),
     ]
 
 
@@ -141,6 +142,9 @@ def lib():
         L.mrpt2_energy_async.restype = st
         L.mrpt2_check.argtypes = [vp, vp, vp]
         L.mrpt2_check.restype = st
+        L.mrpt2_delta_stats.argtypes = [vp, ctypes.POINTER(Inputs), vp, vp, ctypes.c_size_t, vp, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.mrpt2_delta_stats.restype = st
         L.mrpt2_energy_roots.argtypes = [vp, ctypes.POINTER(Inputs), ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                          vp, vp, vp]
         L.mrpt2_energy_roots.restype = st
@@ -210,5 +214,5 @@ EXPORTED = [
     "mrpt2_plan_class_strings", "mrpt2_class_partials", "mrpt2_energy_async", "mrpt2_check",
     "mrpt2_plan_backward_size", "mrpt2_energy_backward", "mrpt2_energy_backward_timed", "mrpt2_plan_tuned",
     "mrpt2_energy_static", "mrpt2_static_workspace_bytes", "mrpt2_reference_sigma",
-    "mrpt2_reference_states_direct_size", "mrpt2_reference_states_direct",
+    "mrpt2_reference_states_direct_size", "mrpt2_reference_states_direct", "mrpt2_delta_stats",
 ]

@@ -71,7 +71,30 @@ struct SetPtrs {
   int rank[4];
   int l0[4];
   int n_sets;
+  int packed;      // 1: each B[L] stored as its upper triangle by rows
 };
+
+// Offset of entry (p, q), p <= q, in a row-major packed upper triangle of an
+// n x n matrix.
+__device__ __forceinline__ int64_t tri_off(int p, int q, int n) {
+  return (int64_t)p * n - (int64_t)p * (p - 1) / 2 + (q - p);
+}
+// Entries per factor matrix in the caller's layout.
+__device__ __forceinline__ int64_t fac_stride(const SetPtrs& sp, int n) {
+  return sp.packed ? (int64_t)n * (n + 1) / 2 : (int64_t)n * n;
+}
+// Factor entry B[L][p][q] of one set (Hermitian; the packed layout keeps the
+// upper triangle, the lower is its conjugate, a diagonal entry is real).
+__device__ __forceinline__ double2 fac_at(const SetPtrs& sp, const double2* B, int L, int p, int q, int n) {
+  if (!sp.packed) return B[((int64_t)L * n + p) * n + q];
+  const double2* M = B + (int64_t)L * ((int64_t)n * (n + 1) / 2);
+  if (p < q) return M[tri_off(p, q, n)];
+  if (p > q) {
+    const double2 v = M[tri_off(q, p, n)];
+    return make_double2(v.x, -v.y);
+  }
+  return make_double2(M[tri_off(p, p, n)].x, 0.0);
+}
 
 struct Dev {
   int n_fc, n_c, n_a, n_v, n_o, n_occ, n_corr, n, n_l, n_p;
@@ -101,6 +124,8 @@ struct Dev {
   double2* sigp;             // [n_p]
   double* scal;              // [0] = E0 - E_core, [1] = ||C||^2
   double ls_b2;              // square of the imaginary level-shift constant b (0: none)
+  double dstat_thresh;       // denominator statistics: count |Delta| below this
+  double2* dstat_out;        // [9] per class (min |Delta|, count below the threshold)
   double* dsum;              // [n_l]
   // inputs and outputs of the current call
   const double2* h;          // [n][n]
@@ -137,6 +162,8 @@ struct ClassDev {
   const int32_t* tile_sup;  // [tile_k0[n_tiles]] occupied-pair index or -1
   const int32_t* ccol;      // [n_conn]
   double2* Md;              // tile t: [64][K_t] at 64 * tile_k0[t]
+  double2* dstat;           // denominator statistics per (row block, string chunk)
+  int64_t n_dstat;
 };
 
 // Adjoint (backward) state of one instance: gradients of E2 with respect to

@@ -2285,6 +2285,9 @@ __device__ __forceinline__ void bdg_body(const Dev& d, const GradDev& g, const u
 //     + [p == q] s dgbar[L][p]                  (diagonals)
 //     + [q occupied type, p correlated] s slabbar[q][p - n_fc][L]
 // written as gradE2 (R(p,q) + conj(R(q,p))) / 2.  32 x 32 tiles through LDS.
+// In the packed layout the stored entry (p, q), p < q, stands for both
+// triangles, so its gradient is gradE2 (R(p,q) + conj(R(q,p))), and a real
+// diagonal entry's is gradE2 Re R(p,p).
 // grid (ceil(n/32), ceil(n/32) * rank), block 256 (32 x 8).
 __device__ __forceinline__ double2 raw_dB(const Dev& d, const GradDev& g, int Lg, int p, int q, double2 b) {
   const double s = d.scale[Lg], sg = d.sign[Lg];
@@ -2309,10 +2312,30 @@ __device__ __forceinline__ void bdB_body(const Dev& d, const GradDev& g, int t, 
   const int L = bid.y / nt;
   const int P0 = (bid.y % nt) * 32, Q0 = bid.x * 32;
   const int Lg = d.sets.l0[t] + L;
-  const double2* B = d.sets.B[t] + (int64_t)L * d.n * d.n;
-  double2* out = g.out_dB[t] + (int64_t)L * d.n * d.n;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t n = d.n;
+  if (d.sets.packed) {
+    if (P0 > Q0 + 31) return;                  // tile entirely below the diagonal
+    double2* out = g.out_dB[t] + (int64_t)L * fac_stride(d.sets, d.n);
+    const double ge = *g.grad_e2;
+    for (int k = ty; k < 32; k += 8) {
+      const int p = P0 + k, q = Q0 + tx;
+      if (p > q || q >= d.n) continue;
+      const double2 b = fac_at(d.sets, d.sets.B[t], L, p, q, d.n);
+      const double2 a = raw_dB(d, g, Lg, p, q, b);
+      double2 v;
+      if (p == q) {
+        v = make_double2(ge * a.x, 0.0);
+      } else {
+        const double2 c = raw_dB(d, g, Lg, q, p, make_double2(b.x, -b.y));
+        v = make_double2(ge * (a.x + c.x), ge * (a.y - c.y));
+      }
+      out[tri_off(p, q, d.n)] = v;
+    }
+    return;
+  }
+  const double2* B = d.sets.B[t] + (int64_t)L * d.n * d.n;
+  double2* out = g.out_dB[t] + (int64_t)L * d.n * d.n;
   // transposed partner: R(q, p) for q in [Q0, Q0+32), p in [P0, P0+32)
   for (int k = ty; k < 32; k += 8) {
     const int q = Q0 + k, p = P0 + tx;

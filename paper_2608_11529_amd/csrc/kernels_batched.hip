@@ -196,6 +196,16 @@ __global__ void __launch_bounds__(256) k_b_bxb(MRPT2_ARGS) {
   MRPT2_JOB
   bxbuild_body(I.d, I.cls[jb.arg], I.g, I.cg[jb.arg], bid);
 }
+template <int H, int V>
+__global__ void __launch_bounds__(256) k_b_dstat(MRPT2_ARGS) {
+  MRPT2_JOB
+  dstat_body<H, V>(I.d, I.cls[jb.arg], jb.gy, bid);
+}
+__global__ void __launch_bounds__(256) k_b_dstatfin(MRPT2_ARGS) {
+  MRPT2_JOB
+  (void)bid;
+  dstatfin_body(I.d, I.cls);
+}
 __global__ void __launch_bounds__(256) k_b_bxbred(MRPT2_ARGS) {
   MRPT2_JOB
   bxbred_body(I.cls[jb.arg], I.cg[jb.arg], bid);

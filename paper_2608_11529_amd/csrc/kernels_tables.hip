@@ -23,7 +23,7 @@ __device__ __forceinline__ void pack_body(const Dev& d, int t, const uint3 bid) 
       const int li = e >> 4, xi = e & 15;
       const int L = Lb + li, x = x0 + xi;
       double2 v = make_double2(0.0, 0.0);
-      if (L < rank && x < d.n_occ) v = B[((int64_t)L * d.n + row) * d.n + x];
+      if (L < rank && x < d.n_occ) v = fac_at(d.sets, B, L, row, x, d.n);
       tile[li][xi] = v;
     }
     __syncthreads();
@@ -53,7 +53,7 @@ __device__ __forceinline__ void diag_body(const Dev& d, int t, const uint3 bid) 
   const int p = bid.x * 256 + threadIdx.x;
   const int L = bid.y;
   if (p >= d.n || L >= rank) return;
-  d.dg[(int64_t)(l0 + L) * d.n + p] = d.scale[l0 + L] * B[((int64_t)L * d.n + p) * d.n + p].x;
+  d.dg[(int64_t)(l0 + L) * d.n + p] = d.scale[l0 + L] * fac_at(d.sets, B, L, p, p, d.n).x;
 }
 
 // Pair energies W_pq = (pp|qq) - (pq|qp) over all spinors, streaming every
@@ -66,8 +66,10 @@ __device__ __forceinline__ void wpass_body(const Dev& d, int* flag, const uint3 
   if (q >= d.n) return;
   double coul = 0.0, exch = 0.0;
   for (int t = 0; t < sp.n_sets; ++t) {
-    const double2* __restrict__ B = sp.B[t] + (int64_t)p * d.n + q;
-    const int64_t stride = (int64_t)d.n * d.n;
+    // |B_pq| is the same from either triangle
+    const double2* __restrict__ B =
+        sp.B[t] + (sp.packed ? (p <= q ? tri_off(p, q, d.n) : tri_off(q, p, d.n)) : (int64_t)p * d.n + q);
+    const int64_t stride = fac_stride(sp, d.n);
     const int l0 = sp.l0[t];
     const int rank = sp.rank[t];
     int L = 0;

@@ -22,6 +22,7 @@
 #include "kernels_tables.hip"
 #include "kernels_energy.hip"
 #include "kernels_backward.hip"
+#include "kernels_stats.hip"
 #include "kernels_batched.hip"
 #include "kernels_davidson.hip"
 
@@ -83,10 +84,12 @@ Dev make_dev(const InstancePlan& ip, const char* pers, char* work, const mrpt2_i
   d.scal = (double*)(W + ip.off_scal);
   d.ls_b2 = ip.d.level_shift_b * ip.d.level_shift_b;
   d.dsum = (double*)(W + ip.off_dsum);
+  d.dstat_out = (double2*)(W + ip.off_dstat_out);
   d.h = (const double2*)in->h;
   d.c = (const double2*)in->c;
   int l0 = 0;
   d.sets.n_sets = ip.d.n_sets;
+  d.sets.packed = ip.d.layout == MRPT2_LAYOUT_PACKED ? 1 : 0;
   for (int t = 0; t < ip.d.n_sets; ++t) {
     d.sets.B[t] = (const double2*)in->B[t];
     d.sets.rank[t] = ip.d.rank[t];
@@ -125,6 +128,8 @@ ClassDev make_class(const InstancePlan& ip, int k, const char* pers, char* work)
   c.tile_sup = (const int32_t*)(P + cp.off_tile_sup);
   c.ccol = (const int32_t*)(P + cp.off_ccol);
   c.Md = (double2*)(W + cp.off_Md);
+  c.dstat = (double2*)(W + cp.off_dstat);
+  c.n_dstat = cp.n_dstat;
   c.part = (double*)(W + ip.off_part_class[k]);
   c.n_part = (cp.strings.empty() || cp.n_rows == 0) ? 0 : cp.n_blocks;
   const int64_t rb = cdiv(cp.n_rows, 256);
@@ -242,6 +247,7 @@ mrpt2_status fill_insts(const Plan& P, const mrpt2_inputs* in, const char* pers,
     I->d.out_e2 = e2 ? e2 + i : nullptr;
     I->d.out_parts = parts ? parts + 12 * i : nullptr;
     I->d.out_hpp = (double2*)hpp_out;
+    I->d.dstat_thresh = P.dstat_thresh;
     for (int k = 0; k < MRPT2_N_CLASS; ++k) I->cls[k] = make_class(ip, k, pers, work);
     if (gw) {
       const mrpt2_grads* go = grads + i;
@@ -380,6 +386,16 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_SIG10: hipLaunchKernelGGL((k_b_sigma<1, 0, 7>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_SIG00: hipLaunchKernelGGL((k_b_sigma<0, 0, 8>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_FINISH: hipLaunchKernelGGL(k_b_finish, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT22: hipLaunchKernelGGL((k_b_dstat<2, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT12: hipLaunchKernelGGL((k_b_dstat<1, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT02: hipLaunchKernelGGL((k_b_dstat<0, 2>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT21: hipLaunchKernelGGL((k_b_dstat<2, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT11: hipLaunchKernelGGL((k_b_dstat<1, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT01: hipLaunchKernelGGL((k_b_dstat<0, 1>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT20: hipLaunchKernelGGL((k_b_dstat<2, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT10: hipLaunchKernelGGL((k_b_dstat<1, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTAT00: hipLaunchKernelGGL((k_b_dstat<0, 0>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_DSTATFIN: hipLaunchKernelGGL(k_b_dstatfin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_BZERO: hipLaunchKernelGGL(k_b_bzero, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
 #define MRPT2_BROW(ID, H, V, K)                                                                    \
   case ID:                                                                                        \
@@ -894,6 +910,35 @@ mrpt2_status mrpt2_energy_timed(mrpt2_plan_t plan, const mrpt2_inputs* in, const
   }
   for (int i = 0; i < 256; ++i) hipEventDestroy(tm.ev[i]);
   return s;
+}
+
+mrpt2_status mrpt2_delta_stats(mrpt2_plan_t plan, const mrpt2_inputs* in, const void* persistent, void* workspace,
+                               size_t workspace_bytes, hipStream_t st, double thresh, double* min_abs_delta,
+                               int64_t* n_below) {
+  if (!plan || !in || !min_abs_delta || !(thresh >= 0.0) || !std::isfinite(thresh)) return MRPT2_ERR_ARG;
+  Plan& P = plan->p;
+  mrpt2_status s = check_regions(P, persistent, workspace, workspace_bytes);
+  if (s != MRPT2_OK) return s;
+  P.dstat_thresh = thresh;
+  s = upload_insts(P, in, (const char*)persistent, (char*)workspace, st, nullptr, nullptr, nullptr, -1);
+  if (s != MRPT2_OK) return s;
+  Timer tm;
+  s = run(P, P.stats, (const char*)persistent, (char*)workspace, st, tm);
+  if (s != MRPT2_OK) return s;
+  s = read_flag(P, workspace, st);
+  if (s != MRPT2_OK) return s;
+  for (size_t i = 0; i < P.inst.size(); ++i) {
+    double2 v[MRPT2_N_CLASS];
+    HIPCHK(hipMemcpyAsync(v, (const char*)workspace + P.inst[i].workspace_base + P.inst[i].off_dstat_out,
+                          sizeof(v), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const bool empty = P.inst[i].cls[k].n_dstat == 0;
+      min_abs_delta[i * MRPT2_N_CLASS + k] = empty ? HUGE_VAL : v[k].x;
+      if (n_below) n_below[i * MRPT2_N_CLASS + k] = empty ? 0 : (int64_t)v[k].y;
+    }
+  }
+  return MRPT2_OK;
 }
 
 mrpt2_status mrpt2_plan_backward_size(mrpt2_plan_t plan, size_t* grad_workspace_bytes) {

@@ -419,6 +419,7 @@ void build_launches(Plan* P) {
   P->jobs.clear();
   P->energy.clear();
   P->backward.clear();
+  P->stats.clear();
   P->reference.clear();
   const int ni = (int)P->inst.size();
   std::vector<int> all(ni);
@@ -533,6 +534,25 @@ void build_launches(Plan* P) {
   js.clear();
   for (int i : all) js.push_back(job(i, 1, 1));
   add_launch(P, seq, K_FINISH, ST_FINISH, js);
+  // denominator statistics: the forward tables up to the per-string
+  // denominator tables (no pair integrals, no sigma), one pass per class,
+  // then the fold per instance
+  seq = &P->stats;
+  for (const Launch& L : P->energy)
+    if (L.stage == ST_NONE || L.stage == ST_TABLES || L.stage == ST_GBUILD || L.stage == ST_REF ||
+        L.kid == K_CTAB)
+      seq->push_back(L);
+  for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+    js.clear();
+    for (int i : all) {
+      const ClassPlan& cp = P->inst[i].cls[k];
+      if (cp.n_dstat > 0) js.push_back(job(i, cdiv64(cp.n_rows, 256), cp.dstat_chunks, k));
+    }
+    add_launch(P, seq, K_DSTAT22 + k, ST_NONE, js);
+  }
+  js.clear();
+  for (int i : all) js.push_back(job(i, 1, 1));
+  add_launch(P, seq, K_DSTATFIN, ST_NONE, js);
   // adjoint: clear the gradient workspace, recompute the forward pass, then
   // the per-class passes and the chain back through the tables
   seq = &P->backward;
@@ -827,6 +847,10 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       *err = "unknown precision";
       return MRPT2_ERR_UNSUPPORTED;
     }
+    if (d.layout != MRPT2_LAYOUT_FULL && d.layout != MRPT2_LAYOUT_PACKED) {
+      *err = "unknown factor layout";
+      return MRPT2_ERR_UNSUPPORTED;
+    }
     if (!std::isfinite(d.level_shift_b)) {
       *err = "level shift b must be finite";
       return MRPT2_ERR_ARG;
@@ -1072,6 +1096,7 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
     ip.off_sigp = W.take(NP * 16);
     ip.off_scal = W.take(16 * 8);
     ip.off_dsum = W.take((size_t)ip.n_l * 8);
+    ip.off_dstat_out = W.take(MRPT2_N_CLASS * 16);
     ip.n_part = 0;
     for (int k = 0; k < MRPT2_N_CLASS; ++k) {
       ClassPlan& cp = ip.cls[k];
@@ -1080,6 +1105,16 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       cp.off_Uc = W.take(cp.h > 0 ? S * ip.n_c * 8 : 0);
       cp.off_Uv = W.take(cp.v > 0 ? S * ip.n_v * 8 : 0);
       cp.off_X = W.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
+      // denominator statistics: row blocks of 256, strings split into enough
+      // chunks for about 4096 blocks
+      cp.dstat_chunks = 1;
+      cp.n_dstat = 0;
+      if (S && cp.n_rows > 0) {
+        const int64_t rb = cdiv64(cp.n_rows, 256);
+        cp.dstat_chunks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)S, cdiv64(4096, rb)));
+        cp.n_dstat = rb * cp.dstat_chunks;
+      }
+      cp.off_dstat = W.take((size_t)cp.n_dstat * 16);
       // a level shift changes every denominator: the dedicated forward
       // kernels have shifted variants, the adjoint then runs on the generic
       // passes (the only ones that carry the shifted weight's derivative)

@@ -72,6 +72,10 @@ struct ClassPlan {
   // launch-shape targets (mrpt2_tuning; 0 = built-in rule)
   int64_t sigma_target = 0, bwd_target = 0, bwd_row_target = 0;
   int64_t n_blocks = 0;                // partial sums written by the class's kernel
+  // denominator statistics: (row block, string chunk) values in the workspace
+  size_t off_dstat = 0;
+  int dstat_chunks = 1;
+  int64_t n_dstat = 0;
 };
 
 struct InstancePlan {
@@ -99,6 +103,7 @@ struct InstancePlan {
   size_t off_fx = 0;
   size_t off_dg = 0, off_slab = 0, off_slab32 = 0, off_W = 0, off_eps = 0, off_f = 0, off_G = 0, off_A = 0;
   size_t off_hpp = 0, off_sigp = 0, off_scal = 0, off_dsum = 0, off_part = 0;
+  size_t off_dstat_out = 0;           // [9] (min |Delta|, count) of mrpt2_delta_stats
   size_t workspace_bytes = 0, workspace_base = 0;
   // gradient workspace layout (adjoint)
   size_t off_gs = 0, off_Wb = 0, off_Wsym = 0, off_epsb = 0, off_fb = 0, off_Gb = 0, off_Ab = 0;
@@ -129,7 +134,10 @@ enum KernelId : int {
   K_FOCKX, K_ABUILD64,
   // class (0,2) adjoint on MFMA: row pass, string pass, Uv tables
   K_B02R, K_B02S, K_B02W,
-  K_BAG128, K_BXBRED
+  K_BAG128, K_BXBRED,
+  // denominator statistics (one per class, same order), then the fold
+  K_DSTAT22, K_DSTAT12, K_DSTAT02, K_DSTAT21, K_DSTAT11, K_DSTAT01, K_DSTAT20, K_DSTAT10, K_DSTAT00,
+  K_DSTATFIN
 };
 
 // Timing slots (mrpt2_energy_timed).
@@ -168,6 +176,8 @@ struct Plan {
   std::vector<JobH> jobs;
   std::vector<Launch> energy;         // launch sequence of mrpt2_energy (all instances)
   std::vector<Launch> backward;       // launch sequence of mrpt2_energy_backward
+  std::vector<Launch> stats;          // launch sequence of mrpt2_delta_stats
+  double dstat_thresh = 0.0;          // threshold of the current mrpt2_delta_stats call
   size_t grad_bytes = 0;              // gradient workspace of mrpt2_energy_backward
   std::vector<std::vector<Launch>> reference;  // per instance: tables + H_PP
   std::vector<std::vector<Launch>> reference_tables;  // per instance: tables only

@@ -1,0 +1,100 @@
+"""Denominator statistics (mrpt2_delta_stats): the smallest |E0 - H_KK| per
+excitation class and the number of external determinants below a threshold
+(Sec. 2.6, the intruder-state measure), against the oracle's enumeration of
+Q (oracle.literal.denominator_stats, pinned by brute force), on the small
+problems, with q_mode 1, under a level shift (which does not enter the
+statistics) and in a batched plan."""
+import numpy as np
+import pytest
+
+import synth.problems as SP
+from oracle import literal, run
+
+from helpers import CLASSES, problem, to_plan_order, oracle_reference
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["s_cas", "s_das", "s_fc", "s_hop0", "s_single", "s_nocore", "s_full"]
+
+
+def oracle_stats(name, q_mode, thresh):
+    pb = problem(name)
+    h, Bs = SP.one_body(pb).numpy(), [B.numpy() for B in SP.factors(pb)]
+    ws = SP.weights(pb)
+    hfc, Bc = run.correlated_inputs(h, Bs, ws, pb.n_fc)
+    _, gc = run.full_eri_callable(Bc, ws)
+    _, _, c_o, P_o = oracle_reference(name)
+    return literal.denominator_stats(run.space_of(pb), hfc, gc, c_o, thresh, q_mode)
+
+
+def stable_thresh(name, q_mode):
+    """A threshold that no |E0 - H_KK| lies within 1e-9 (relative) of, so the
+    counts do not depend on rounding: the smallest class minimum times 4,
+    nudged until the counts just below and above it agree."""
+    t = 4.0 * min(m for m, _ in oracle_stats(name, q_mode, 0.0).values())
+    for _ in range(20):
+        lo = oracle_stats(name, q_mode, t * (1 - 1e-9))
+        hi = oracle_stats(name, q_mode, t * (1 + 1e-9))
+        if all(lo[k][1] == hi[k][1] for k in lo):
+            return t, lo
+        t *= 1.07
+    raise AssertionError("no stable threshold")
+
+
+def gpu_stats(names, q_mode, thresh, level_shift_b=0.0):
+    import torch
+    import paper_2608_11529_amd as M
+    dev = torch.device("cuda:0")
+    descs, ins = [], []
+    for name in names:
+        pb = problem(name)
+        descs.append(M.desc_of_problem(pb, q_mode=q_mode, level_shift_b=level_shift_b))
+    plan = M.Plan(descs)
+    for i, name in enumerate(names):
+        pb = problem(name)
+        _, _, c_o, P_o = oracle_reference(name)
+        c = to_plan_order(c_o, P_o, plan.ref_strings(i), pb.n_c)
+        ins.append((SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)],
+                    torch.from_numpy(np.ascontiguousarray(c)).to(dev)))
+    eng = M.Engine(plan, dev)
+    print("[gpu] delta stats %s q_mode %d b %g" % (names, q_mode, level_shift_b), flush=True)
+    return eng.delta_stats(ins, thresh)
+
+
+def check(mn, cnt, want):
+    for k, cl in enumerate(CLASSES):
+        if cl not in want:
+            assert mn[k] == np.inf and cnt[k] == 0, (cl, mn[k], cnt[k])
+            continue
+        wm, wc = want[cl]
+        assert abs(mn[k] - wm) <= 1e-12 * max(1.0, wm), (cl, mn[k], wm)
+        assert cnt[k] == wc, (cl, cnt[k], wc)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_delta_stats_match_oracle(name):
+    t, want = stable_thresh(name, 0)
+    mn, cnt = gpu_stats([name], 0, t)
+    check(mn[0], cnt[0], want)
+
+
+def test_delta_stats_q_mode_1_level_shift_and_batch():
+    t, want = stable_thresh("s_das", 1)
+    mn, cnt = gpu_stats(["s_das"], 1, t)
+    check(mn[0], cnt[0], want)
+    # the level shift acts on the weights, not on the statistics
+    mn_s, cnt_s = gpu_stats(["s_das"], 1, t, level_shift_b=0.3)
+    assert np.array_equal(mn_s, mn) and np.array_equal(cnt_s, cnt)
+    # two instances in one plan give their single-plan statistics
+    t2, want2 = stable_thresh("s_fc", 0)
+    mb, cb = gpu_stats(["s_fc", "s_cas"], 0, t2)
+    check(mb[0], cb[0], want2)
+    ms, cs = gpu_stats(["s_cas"], 0, t2)
+    assert np.array_equal(mb[1], ms[0]) and np.array_equal(cb[1], cs[0])
+
+
+def test_delta_stats_rejects_bad_threshold():
+    import paper_2608_11529_amd as M
+    with pytest.raises(M.Mrpt2Error) as ei:
+        gpu_stats(["s_cas"], 0, -1.0)
+    assert ei.value.code == 1

@@ -86,6 +86,7 @@ def test_table3_counts_through_the_plan():
 @pytest.mark.parametrize("field,value,code", [
     ("n_sub", 17, 1), ("n_sets", 0, 1), ("q_mode", 2, 1), ("precision", 7, 3),
     ("level_shift_b", float("nan"), 1), ("level_shift_b", float("inf"), 1), ("n_act_elec", 9, 2),
+    ("layout", 2, 3),
 ])
 def test_plan_rejects_bad_descriptors(field, value, code):
     M = lib_module()
@@ -94,6 +95,36 @@ def test_plan_rejects_bad_descriptors(field, value, code):
     with pytest.raises(M.Mrpt2Error) as ei:
         M.Plan(d)
     assert ei.value.code == code
+
+
+def test_packed_layout_offsets_and_shapes():
+    """The packed factor layout: the plan is the same as the full layout's,
+    hermitian_pack puts entry (p, q), p <= q, at the offset the header states
+    (p n - p (p - 1) / 2 + (q - p)), and the binding takes [rank, n (n + 1) / 2]
+    tensors for a packed plan and refuses full ones."""
+    import torch
+    M = lib_module()
+    pb = problem("s_fc")
+    full = M.Plan(M.desc_of_problem(pb)).info()
+    plan = M.Plan(M.desc_of_problem(pb, layout=1))
+    info = plan.info()
+    assert info.n_ext == full.n_ext and list(info.n_ext_class) == list(full.n_ext_class)
+    n = info.n_orb
+    z = SP.complex_normal(5, 77, (3, n, n))
+    B = 0.5 * (z + z.transpose(-1, -2).conj())
+    P = M.hermitian_pack(B)
+    assert tuple(P.shape) == (3, n * (n + 1) // 2)
+    for p in range(n):
+        for q in range(p, n):
+            assert torch.equal(P[:, p * n - p * (p - 1) // 2 + (q - p)], B[:, p, q])
+    eng = M.Engine.__new__(M.Engine)
+    eng.torch, eng.plan = torch, plan
+    h = torch.zeros((n, n), dtype=torch.complex128)
+    c = torch.zeros(info.n_ref, dtype=torch.complex128)
+    packed = [torch.zeros((r, n * (n + 1) // 2), dtype=torch.complex128) for r, _ in pb.sets]
+    eng._check_shapes(0, h, packed, c)
+    with pytest.raises(ValueError, match="packed"):
+        eng._check_shapes(0, h, [torch.zeros((r, n, n), dtype=torch.complex128) for r, _ in pb.sets], c)
 
 
 def test_level_shift_keeps_the_external_space():
