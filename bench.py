@@ -490,6 +490,46 @@ def main():
     if args.level_shift != 0.0:
         guarded("level_shift", measure_level_shift)
 
+    def measure_packed():
+        # the same evaluation with the factors in the Hermitian-packed layout
+        # (upper triangles, half the memory and half the factor pass)
+        dpk = M.desc_of_problem(pb, precision=prec[args.precision], layout=1)
+        epk = M.Engine(M.Plan(dpk, tuning=autotune.tuning_for(dpk)), dev)
+        Bp = [M.hermitian_pack(B) for B in Bs]
+        epk.energy([(h, Bp, c)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e2p, _, pms = epk.energy_timed([(h, Bp, c)])
+        torch.cuda.synchronize()
+        pk_ms = (time.perf_counter() - t0) * 1000.0
+        out["packed_layout"] = {
+            "precision": args.precision, "ms_per_step": pk_ms, "dets_per_s": info.n_ext / (pk_ms * 1e-3),
+            "factor_bytes": sum(int(x.numel()) * 16 for x in Bp), "e2": float(e2p[0].item()),
+            "abs_dE2_vs_full_layout": abs(float(e2p[0].item()) - head["e2"]),
+            "factor_tables_ms": round(pms.get("factor_tables", 0.0), 2),
+            "factor_tables_ms_full_layout": round(stage.get("factor_tables", 0.0), 2),
+        }
+        print("[bench] packed layout: %.1f ms, E2=%.12f" % (pk_ms, out["packed_layout"]["e2"]),
+              file=sys.stderr, flush=True)
+        del epk, Bp
+        torch.cuda.empty_cache()
+
+    guarded("packed_layout", measure_packed)
+
+    def measure_delta_stats():
+        # smallest |E0 - H_KK| per class (intruder measure of Sec. 2.6) and the
+        # determinants within 1 Eh of zero
+        eng = engs[args.precision]
+        t0 = time.perf_counter()
+        mn, cnt = eng.delta_stats(insts, 1.0)
+        ds_ms = (time.perf_counter() - t0) * 1000.0
+        out["delta_stats"] = {"ms": ds_ms, "thresh": 1.0,
+                              "min_abs_delta": {"%d%d" % cl: float(mn[0][k]) for k, cl in enumerate(M.CLASSES)},
+                              "n_below": {"%d%d" % cl: int(cnt[0][k]) for k, cl in enumerate(M.CLASSES)}}
+        print("[bench] delta stats: " + json.dumps(out["delta_stats"]), file=sys.stderr, flush=True)
+
+    guarded("delta_stats", measure_delta_stats)
+
     def measure_davidson():
         # reference states: device block Davidson (H_PP assembled and applied
         # on the GPU) against H_PP copied to the host and ARPACK/LAPACK

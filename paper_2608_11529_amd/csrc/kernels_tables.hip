@@ -57,18 +57,18 @@ __device__ __forceinline__ void diag_body(const Dev& d, int t, const uint3 bid) 
 }
 
 // Pair energies W_pq = (pp|qq) - (pq|qp) over all spinors, streaming every
-// factor once: (pq|qp) = sum_L w_L |B_pq|^2 for Hermitian B.
+// factor once: (pq|qp) = sum_L w_L |B_pq|^2 for Hermitian B.  W is
+// symmetric: with packed factors only q >= p is read (rows of the stored
+// triangle, contiguous in q) and each entry is also written to (q, p).
 // grid (ceil(n/256), n), block 256.  Sets flag on non-finite results.
 __device__ __forceinline__ void wpass_body(const Dev& d, int* flag, const uint3 bid) {
   const SetPtrs& sp = d.sets;
   const int q = bid.x * 256 + threadIdx.x;
   const int p = bid.y;
-  if (q >= d.n) return;
+  if (q >= d.n || (sp.packed && q < p)) return;
   double coul = 0.0, exch = 0.0;
   for (int t = 0; t < sp.n_sets; ++t) {
-    // |B_pq| is the same from either triangle
-    const double2* __restrict__ B =
-        sp.B[t] + (sp.packed ? (p <= q ? tri_off(p, q, d.n) : tri_off(q, p, d.n)) : (int64_t)p * d.n + q);
+    const double2* __restrict__ B = sp.B[t] + (sp.packed ? tri_off(p, q, d.n) : (int64_t)p * d.n + q);
     const int64_t stride = fac_stride(sp, d.n);
     const int l0 = sp.l0[t];
     const int rank = sp.rank[t];
@@ -99,6 +99,7 @@ __device__ __forceinline__ void wpass_body(const Dev& d, int* flag, const uint3 
     w = 0.0;
   }
   d.W[(int64_t)p * d.n + q] = w;
+  if (sp.packed && q != p) d.W[(int64_t)q * d.n + p] = w;
 }
 
 // Orbital energies in the field of the frozen and correlated core:
