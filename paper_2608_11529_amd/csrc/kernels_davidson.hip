@@ -79,13 +79,15 @@ __global__ void __launch_bounds__(256) k_dv_comb(const double2* __restrict__ X, 
 }
 
 // Diagonal-preconditioned residuals, T[t0 + j][i] = R[j][i] / (theta_j - H_ii),
-// with the denominator kept at least 1e-8 in magnitude.  grid (ceil(n/256), nr).
-__global__ void __launch_bounds__(256) k_dv_prec(const double2* __restrict__ H, const double2* __restrict__ R,
+// with the denominator kept at least 1e-8 in magnitude; dg[i] = Re H_ii (the
+// dense solver's diagonal or the direct solver's active-space energies, the
+// latter having no stored H).  grid (ceil(n/256), nr).
+__global__ void __launch_bounds__(256) k_dv_prec(const double* __restrict__ dg, const double2* __restrict__ R,
                                                   const double* __restrict__ theta, double2* T, int t0, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
-  double den = theta[j] - H[(int64_t)i * n + i].x;
+  double den = theta[j] - dg[i];
   if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
   const double2 r = R[(int64_t)j * n + i];
   T[(int64_t)(t0 + j) * n + i] = make_double2(r.x / den, r.y / den);

@@ -665,7 +665,7 @@ mrpt2_status davidson(char* base, const DvLayout& L, int64_t n64, int k, double 
     int acc = 0;
     for (int u = 0; u < nu; ++u) {
       const int row = m + acc;
-      hipLaunchKernelGGL(k_dv_prec, dim3(nb, 1), b256, 0, st, H, R + (size_t)open[u] * n, th + u, V, row, n);
+      hipLaunchKernelGGL(k_dv_prec, dim3(nb, 1), b256, 0, st, dg, R + (size_t)open[u] * n, th + u, V, row, n);
       hipLaunchKernelGGL(k_dv_dots, dim3(1), b256, 0, st, V, row, V, row, 1, n, G);
       HIPCHK(hipGetLastError());
       cd pre;
