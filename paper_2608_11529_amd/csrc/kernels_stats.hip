@@ -27,7 +27,12 @@ __device__ __forceinline__ void block_min_sum256(double& mn, double& cnt) {
 // Delta = E0 - H_KK is the row constant plus the string tables, as in the
 // energy kernels.  Each block writes the smallest |Delta| of its determinants
 // and how many lie below the threshold (counts are exact in a double).
+// Two-virtual classes: the block's 256 rows are one hole tuple, one virtual
+// tile pair, four a and 64 b, so each chunk of strings stages the string
+// parts of Delta (T + Uc, Uv of the four a and of the 64 b) in LDS.
 // grid (ceil(rows / 256), string chunks), block 256.
+constexpr int DSC = 64;   // strings per LDS chunk of the two-virtual statistics pass
+
 template <int H, int V>
 __device__ __forceinline__ void dstat_body(const Dev& d, const ClassDev& cd, int nchunk, const uint3 bid) {
   const int64_t r = (int64_t)bid.x * 256 + threadIdx.x;
@@ -37,7 +42,47 @@ __device__ __forceinline__ void dstat_body(const Dev& d, const ClassDev& cd, int
   const int64_t s0 = (int64_t)bid.y * per, s1 = s0 + per < S ? s0 + per : S;
   const double th = d.dstat_thresh;
   double mn = __builtin_huge_val(), cnt = 0.0;
-  if (w.valid) {
+  if constexpr (V == 2) {
+    __shared__ double sG[DSC], sUa[DSC][4], sUb[DSC][64];
+    const int tid = threadIdx.x, ia = tid >> 6, ib = tid & 63;
+    const int64_t rab0 = ((int64_t)bid.x * 256) % (d.n_tp * 4096);
+    const int64_t tp = rab0 >> 12;
+    const int la0 = (int)((rab0 >> 6) & 63);
+    const int a0 = d.tile_pairs[2 * tp] * 64 + la0, b0 = d.tile_pairs[2 * tp + 1] * 64;
+    const int nv = d.n_v, nc = d.n_c;
+    for (int64_t c0 = s0; c0 < s1; c0 += DSC) {
+      __syncthreads();
+      for (int e = tid; e < DSC * 64; e += 256) {
+        const int sl = e >> 6, l = e & 63;
+        const int64_t s = c0 + sl;
+        sUb[sl][l] = (s < s1 && b0 + l < nv) ? cd.Uv[s * nv + b0 + l] : 0.0;
+      }
+      {
+        const int sl = tid >> 2, l = tid & 3;
+        const int64_t s = c0 + sl;
+        sUa[sl][l] = (s < s1 && a0 + l < nv) ? cd.Uv[s * nv + a0 + l] : 0.0;
+      }
+      if (tid < DSC) {
+        const int64_t s = c0 + tid;
+        double gs = __builtin_huge_val();      // padding: |Delta| = inf counts nowhere
+        if (s < s1) {
+          gs = cd.T[s];
+          if (H >= 1) gs += cd.Uc[s * nc + w.c0];
+          if (H == 2) gs += cd.Uc[s * nc + w.c1];
+        }
+        sG[tid] = gs;
+      }
+      __syncthreads();
+      if (w.valid) {
+        const int ns = (int)(s1 - c0 < DSC ? s1 - c0 : DSC);
+        for (int sl = 0; sl < ns; ++sl) {
+          const double a = fabs(((sG[sl] + qr) - sUa[sl][ia]) - sUb[sl][ib]);
+          mn = fmin(mn, a);
+          cnt += a < th ? 1.0 : 0.0;
+        }
+      }
+    }
+  } else if (w.valid) {
     for (int64_t s = s0; s < s1; ++s) {
       const double a = fabs(string_delta<H, V>(cd, d, s, w) + qr);
       mn = fmin(mn, a);
