@@ -553,6 +553,9 @@ __device__ __forceinline__ void b22a_body(const Dev& d, const ClassDev& cd, cons
 constexpr int B22T = 256;
 constexpr int B22S = 16;
 constexpr int B22HP = 8;                   // at most this many core pairs per part (LDS slab of the Uc sums)
+// Row stride of the per-thread LDS columns: one double of padding puts the 16
+// rows that the contraction reads at once (one per lane group) in distinct banks.
+constexpr int B22P = B22T + 1;
 
 // Contract one B22S-row slab of per-thread values with the string occupations:
 // wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < B22S, t < n_a.
@@ -565,7 +568,7 @@ __device__ __forceinline__ void b22_contract(const double* buf, const uint64_t* 
 #pragma unroll
   for (int m = 0; m < NM; ++m) acc[m] = 0.0;
   for (int l = 0; l < B22T; ++l) {
-    const double v = buf[cx * B22T + l];
+    const double v = buf[cx * B22P + l];
     const uint64_t x = sStr[l] >> tq;
 #pragma unroll
     for (int m = 0; m < NM; ++m) acc[m] += ((x >> (TQ * m)) & 1ull) ? v : 0.0;
@@ -612,7 +615,7 @@ __device__ __forceinline__ void btrans_body(const Dev& d, const ClassDev& cd, co
 
 __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid, int64_t nsblk) {
-  __shared__ double sBuf[B22S * B22T];   // per-thread column: a side, then b side of a sub-tile
+  __shared__ double sBuf[B22S * B22P];   // per-thread column: a side, then b side of a sub-tile
   __shared__ double sA2[B22S][B22S];
   __shared__ double sWab[B22S][B22S];
   __shared__ double sWc[2][B22S];        // W[c][v] + W[c'][v] of the sub-tile's a (0) and b (1)
@@ -649,7 +652,7 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
         const int b0 = J * 64 + hb;
         if (b0 >= nv || b0 + NB - 1 <= a0) continue;
 #pragma unroll
-        for (int la = 0; la < B22S; ++la) sBuf[la * B22T + tid] = 0.0;
+        for (int la = 0; la < B22S; ++la) sBuf[la * B22P + tid] = 0.0;
         double vb[NB], ybs[NB];
 #pragma unroll
         for (int lb = 0; lb < NB; ++lb) {
@@ -712,7 +715,7 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
               }
             }
             q2c += va;
-            sBuf[la * B22T + tid] += cw * va;
+            sBuf[la * B22P + tid] += cw * va;
           }
           T2 += q2c;
           sQ2[hp - hp0][tid] += cw * q2c;   // own column
@@ -722,7 +725,7 @@ __device__ __forceinline__ void b22b_body(const Dev& d, const ClassDev& cd, cons
         b22_contract(sBuf, sStr, wpart, a0, nv, na);
         __syncthreads();
 #pragma unroll
-        for (int lb = 0; lb < NB; ++lb) sBuf[lb * B22T + tid] = cw * vb[lb];
+        for (int lb = 0; lb < NB; ++lb) sBuf[lb * B22P + tid] = cw * vb[lb];
         __syncthreads();
         b22_contract(sBuf, sStr, wpart, b0, nv, na);
         __syncthreads();
