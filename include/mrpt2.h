@@ -171,6 +171,13 @@ mrpt2_status mrpt2_plan(const mrpt2_desc* desc, int32_t n_inst, mrpt2_plan_t* ou
  *   bwd_row_blocks  the generic row-owned adjoint pass when it has fewer than
  *                   512 row blocks: strings split into
  *                   ceil(target / row blocks) chunks (default 2048).
+ * and one per instance:
+ *   pair_tile       edge of the output blocks of the FP64 virtual-pair
+ *                   integral build: 128 (eight waves, four 64 x 64 tiles per
+ *                   block) or 64 (one tile per block); 0 keeps the built-in
+ *                   rule (128 where at least 90 % of the 128 x 128 blocks'
+ *                   tiles lie on or above the diagonal and inside n_virt);
+ *                   the mixed form has one block shape and ignores it.
  * The values change launch grids and partial-sum layouts, never the result
  * beyond summation order.  Tables of them are written by the package's
  * autotuner (timed sweeps per class and size bucket). */
@@ -178,10 +185,12 @@ typedef struct {
   int32_t sigma_blocks[MRPT2_N_CLASS];
   int32_t bwd_blocks[MRPT2_N_CLASS];
   int32_t bwd_row_blocks[MRPT2_N_CLASS];
+  int32_t pair_tile;
 } mrpt2_tuning;
 
 /* mrpt2_plan with launch shapes: tuning is a host array of n_inst entries
- * (or NULL for the built-in rules).  Negative values are MRPT2_ERR_ARG. */
+ * (or NULL for the built-in rules).  Negative values, and a pair_tile other
+ * than 0, 64 or 128, are MRPT2_ERR_ARG. */
 mrpt2_status mrpt2_plan_tuned(const mrpt2_desc* desc, int32_t n_inst, const mrpt2_tuning* tuning,
                               mrpt2_plan_t* out);
 

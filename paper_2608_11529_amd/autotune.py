@@ -3,18 +3,23 @@
 The work decomposition of a plan has three block-count targets per
 excitation class (see mrpt2_tuning in include/mrpt2.h): the string chunks of
 the generic sigma kernel, the row parts of the string-owned adjoint pass and
-the string chunks of the generic row-owned adjoint pass.  tune() times the
-candidates of each target on the GPU (every class's stage is timed separately
-by the library, so one run per candidate serves all classes) and keeps, per
-class, the fastest candidate when it beats the built-in rule by more than
-MIN_GAIN.  Results are stored in a JSON table keyed by size bucket
+the string chunks of the generic row-owned adjoint pass; and one tile shape
+per instance, the edge (64 or 128) of the FP64 pair-integral blocks.  tune()
+times the candidates of each target on the GPU (every class's stage is timed
+separately by the library, so one run per candidate serves all classes) and
+keeps, per class, the fastest candidate when it beats the built-in rule by
+more than MIN_GAIN.  Results are stored in a JSON table keyed by size bucket
 
     "<h><v>/q<floor log2 N_Q>/s<floor log2 strings>"
 
-(class, external determinants and external strings of the class), and
-tuning_for() turns a table into the per-instance capi.Tuning that
-Plan(descs, tuning=...) takes.  Classes whose bucket is not in the table keep
-the built-in rule.
+(class, external determinants and external strings of the class), or for the
+pair-integral blocks
+
+    "pair/vt<64-wide virtual tiles>/l<floor log2 Cholesky vectors>",
+
+and tuning_for() turns a table into the per-instance capi.Tuning that
+Plan(descs, tuning=...) takes.  Classes and instances whose bucket is not in
+the table keep the built-in rule.
 
     python -m paper_2608_11529_amd.autotune c1 c2 c4 c3:0 c3:9 ... --out paper_2608_11529_amd/tuning.json
 """
@@ -34,6 +39,7 @@ CANDIDATES = {
     "bwd_row_blocks": (512, 1024, 4096, 8192, 16384, 32768, 65536),   # swept together with bwd_blocks
 }
 DEFAULTS = {"sigma_blocks": 8192, "bwd_blocks": 2048, "bwd_row_blocks": 2048}
+PAIR_TILES = (64, 128)
 MIN_GAIN = 0.03
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
@@ -45,6 +51,14 @@ def bucket(info, k):
         return None
     h, v = capi.CLASSES[k]
     return "%d%d/q%d/s%d" % (h, v, int(math.log2(nq)), int(math.log2(ns)))
+
+
+def pair_bucket(desc, info):
+    """Size bucket of an instance's FP64 pair-integral build (None without
+    virtual pairs)."""
+    if desc.n_virt < 2:
+        return None
+    return "pair/vt%d/l%d" % ((desc.n_virt + 63) // 64, int(math.log2(max(info.n_chol, 1))))
 
 
 def load_table(table=None):
@@ -75,6 +89,7 @@ def tuning_for(descs, table=None):
             ent = tab.get(bucket(info, k) or "", {})
             for knob in KNOBS:
                 getattr(t, knob)[k] = int(ent.get(knob, 0))
+        t.pair_tile = int(tab.get(pair_bucket(descs[i], info) or "", {}).get("pair_tile", 0))
         out.append(t)
     return out
 
@@ -107,9 +122,10 @@ def _stage_times(desc, inst, tuning, backward, reps):
     return acc
 
 
-def tune(desc, inst, backward=True, reps=2, log=print):
-    """Sweep every target of one instance; returns {bucket: {knob: value}}
-    for the classes where a candidate beat the built-in rule."""
+def tune(desc, inst, backward=True, reps=2, log=print, classes=True):
+    """Sweep every target of one instance (classes=False: only the
+    pair-integral block edge); returns {bucket: {knob: value}} for the
+    classes and instances where a candidate beat the built-in rule."""
     from . import Plan
     info = Plan(desc).info()
     found = {}
@@ -118,8 +134,8 @@ def tune(desc, inst, backward=True, reps=2, log=print):
     # both.  A sweep sets every class at once, so the shared stages carry the
     # effect of all classes: charging it to each class errs on the side of the
     # built-in rule.
-    sweeps = [({"sigma_blocks": ("sigma_%d%d", ("reduce",))}, False)]
-    if backward:
+    sweeps = [({"sigma_blocks": ("sigma_%d%d", ("reduce",))}, False)] if classes else []
+    if backward and classes:
         sweeps.append(({"bwd_blocks": ("bwd_str_%d%d", ("bwd_string_fin",)),
                         "bwd_row_blocks": ("bwd_row_%d%d", ())}, True))
     for knobs, bwd in sweeps:
@@ -146,6 +162,23 @@ def tune(desc, inst, backward=True, reps=2, log=print):
                     found.setdefault(b, {})[knob] = best
                     log("[autotune] class %s bucket %s: %s %d -> %d, %.2f -> %.2f ms"
                         % (cl, b, knob, DEFAULTS[knob], best, t_def, t_best))
+    # block edge of the FP64 pair-integral build (the mixed form has one shape)
+    pb_key = pair_bucket(desc, info)
+    if pb_key is not None:
+        d64 = capi.Desc.from_buffer_copy(desc)
+        d64.precision = 0
+        t_rule = _stage_times(d64, inst, None, False, reps).get("pair_integrals", 0.0)
+        best, t_best = None, t_rule
+        for v in PAIR_TILES:
+            tu = capi.Tuning()
+            tu.pair_tile = v
+            tv = _stage_times(d64, inst, [tu], False, reps).get("pair_integrals", 0.0)
+            log("[autotune] pair_tile = %d: %.2f ms (rule %.2f ms)" % (v, tv, t_rule))
+            if tv < t_best:
+                best, t_best = v, tv
+        if best is not None and t_best < (1.0 - MIN_GAIN) * t_rule:
+            found.setdefault(pb_key, {})["pair_tile"] = best
+            log("[autotune] bucket %s: pair_tile %d, %.2f -> %.2f ms" % (pb_key, best, t_rule, t_best))
     return found
 
 
@@ -157,6 +190,7 @@ def main(argv=None):
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--pair-only", action="store_true", help="sweep only the pair-integral block edge")
     args = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
@@ -175,7 +209,7 @@ def main(argv=None):
         c, _ = ground_state(Engine(Plan(desc_of_problem(pb))), h, Bs)
         print("[autotune] %s: inputs ready" % name, flush=True)
         found = tune(desc, (h, Bs, c), backward=not args.no_backward, reps=args.reps,
-                     log=lambda m: print(m, flush=True))
+                     log=lambda m: print(m, flush=True), classes=not args.pair_only)
         for b, ent in found.items():
             table.setdefault(b, {}).update(ent)
         runs.append(name)
@@ -188,7 +222,8 @@ def main(argv=None):
         made_by, workloads = old.get("made_by", []), old.get("workloads", [])
     made_by.append("python -m paper_2608_11529_amd.autotune " + " ".join(sys.argv[1:] if argv is None else argv))
     with open(args.out, "w") as f:
-        json.dump({"made_by": made_by, "workloads": workloads + runs, "candidates": CANDIDATES,
+        json.dump({"made_by": made_by, "workloads": workloads + runs,
+                   "candidates": dict(CANDIDATES, pair_tile=PAIR_TILES),
                    "defaults": DEFAULTS, "buckets": table}, f, indent=1, sort_keys=True)
     print("[autotune] wrote %s (%d buckets)" % (args.out, len(table)), flush=True)
 

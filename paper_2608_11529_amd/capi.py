@@ -97,6 +97,7 @@ class Tuning(ctypes.Structure):
         ("sigma_blocks", ctypes.c_int32 * N_CLASS),
         ("bwd_blocks", ctypes.c_int32 * N_CLASS),
         ("bwd_row_blocks", ctypes.c_int32 * N_CLASS),
+        ("pair_tile", ctypes.c_int32),
     ]
 
 

@@ -442,14 +442,16 @@ void build_launches(Plan* P) {
   {
     // FP64: 128 x 128 blocks of virtual pairs where at least 90 % of their
     // waves have a tile to compute (n_tp tiles over 4 n2 (n2 + 1) / 2 wave
-    // pairs), else one 64 x 64 tile per block; mixed form: its own kernel
+    // pairs), else one 64 x 64 tile per block, unless the tuning fixes the
+    // block edge; mixed form: its own kernel
     std::vector<JobH> j128, j64, j32;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       if (ip.n_v < 2 || ip.n_pairs == 0) continue;
       const int64_t n2 = (ip.n_vt + 1) / 2, nstp = n2 * (n2 + 1) / 2;
       if (ip.d.precision == MRPT2_MIXED) j32.push_back(job(i, ip.n_tp, ip.n_pairs));
-      else if (10 * ip.n_tp >= 9 * 4 * nstp) j128.push_back(job(i, nstp, ip.n_pairs));
+      else if (ip.pair_tile == 128 || (ip.pair_tile == 0 && 10 * ip.n_tp >= 9 * 4 * nstp))
+        j128.push_back(job(i, nstp, ip.n_pairs));
       else j64.push_back(job(i, ip.n_tp, ip.n_pairs));
     }
     add_launch(P, seq, K_ABUILD, ST_ABUILD, j128);
@@ -944,6 +946,14 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
     // external space by class: level = v + min over P categories of the
     // surplus sum_k max(0, m_k - m'_k) must not exceed 2
     int64_t n_ext = 0;
+    if (tuning) {
+      const int pt = tuning[ii].pair_tile;
+      if (pt != 0 && pt != 64 && pt != 128) {
+        *err = "pair_tile must be 0, 64 or 128";
+        return MRPT2_ERR_ARG;
+      }
+      ip.pair_tile = pt;
+    }
     for (int k = 0; k < MRPT2_N_CLASS; ++k) {
       ClassPlan& cp = ip.cls[k];
       cp.h = kClassH[k];

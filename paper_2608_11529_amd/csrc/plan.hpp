@@ -83,6 +83,7 @@ struct InstancePlan {
   int n_fc = 0, n_c = 0, n_a = 0, n_v = 0, n_e = 0;
   int n = 0, n_corr = 0, n_o = 0, n_occ = 0, n_l = 0;
   int n_vt = 0;                       // virtual tiles
+  int pair_tile = 0;                  // FP64 pair-integral blocks: 64, 128 or 0 (rule)
   int64_t n_tp = 0;                   // virtual tile pairs I <= J
   int64_t n_pairs = 0;                // occupied pairs x < y (core + active)
   std::vector<std::vector<int>> pcats;

@@ -37,6 +37,10 @@ def test_tuned_plans_match_builtin(name):
         e2 = float(eng.energy(ins, parts=False)[0].item())
         (dh, dB, dc), = eng.backward(ins)[0]
         res.append((e2, dh.cpu().numpy(), [x.cpu().numpy() for x in dB], dc.cpu().numpy()))
+    check_same(res)
+
+
+def check_same(res):
     e0, h0, B0, c0 = res[0]
     for e, h, B, c in res[1:]:
         assert abs(e - e0) <= 1e-12 * max(1.0, abs(e0))
@@ -44,3 +48,28 @@ def test_tuned_plans_match_builtin(name):
         assert np.abs(c - c0).max() <= 1e-11 * np.abs(c0).max()
         for x, y in zip(B, B0):
             assert np.abs(x - y).max() <= 1e-11 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("name", ["s_tiles", "c0"])
+def test_pair_tile_shapes_match_rule(name):
+    """Both block edges of the FP64 pair-integral build, forced through the
+    tuning, give the built-in rule's E2 and gradients."""
+    import torch
+    import paper_2608_11529_amd as M
+    pb = problem(name)
+    _, _, c_o, P_o = oracle_reference(name)
+    desc = M.desc_of_problem(pb)
+    res = []
+    for pt in (0, 64, 128):
+        t = capi.Tuning()
+        t.pair_tile = pt
+        plan = M.Plan(desc, tuning=t)
+        eng = M.Engine(plan)
+        dev = eng.device
+        c = torch.from_numpy(np.ascontiguousarray(to_plan_order(c_o, P_o, plan.ref_strings(), pb.n_c))).to(dev)
+        ins = [(SP.one_body(pb).to(dev), [B.to(dev) for B in SP.factors(pb)], c)]
+        print(f"[gpu] pair_tile {pt} {name}", flush=True)
+        e2 = float(eng.energy(ins, parts=False)[0].item())
+        (dh, dB, dc), = eng.backward(ins)[0]
+        res.append((e2, dh.cpu().numpy(), [x.cpu().numpy() for x in dB], dc.cpu().numpy()))
+    check_same(res)

@@ -64,6 +64,23 @@ def test_negative_target_rejected():
     assert e.value.code == 1
     with pytest.raises(ValueError):
         M.Plan([desc, desc], tuning=[capi.Tuning()])
+    t = capi.Tuning()
+    t.pair_tile = 32                                 # only 0, 64 and 128 are block edges
+    with pytest.raises(capi.Mrpt2Error) as e:
+        M.Plan(desc, tuning=t)
+    assert e.value.code == 1
+
+
+def test_pair_tile_bucket_lookup():
+    descs = [M.desc_of_problem(problem(n)) for n in ("s_tiles", "c0")]
+    plan = M.Plan(descs)
+    b = autotune.pair_bucket(descs[0], plan.info(0))
+    assert b == "pair/vt2/l%d" % (int(plan.info(0).n_chol).bit_length() - 1)
+    tu = autotune.tuning_for(descs, {b: {"pair_tile": 128}})
+    assert tu[0].pair_tile == 128
+    if autotune.pair_bucket(descs[1], plan.info(1)) != b:
+        assert tu[1].pair_tile == 0
+    M.Plan(descs, tuning=tu)
 
 
 def test_table_lookup_by_bucket():
