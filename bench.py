@@ -347,6 +347,10 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=2, metavar="K",
                     help="after the c4 measurement also time the 64-instance batch c3 (one batched call "
                          "against 64 one-instance calls, K steps each); 0: skip")
+    ap.add_argument("--no-packed-layout", action="store_true",
+                    help="skip the forward call with the factors in the Hermitian-packed layout")
+    ap.add_argument("--no-delta-stats", action="store_true",
+                    help="skip the denominator statistics (smallest |E0 - H_KK| per class)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers three times (reference for HBM counters)")
     args = ap.parse_args()
@@ -514,7 +518,8 @@ def main():
         del epk, Bp
         torch.cuda.empty_cache()
 
-    guarded("packed_layout", measure_packed)
+    if not args.no_packed_layout:
+        guarded("packed_layout", measure_packed)
 
     def measure_delta_stats():
         # smallest |E0 - H_KK| per class (intruder measure of Sec. 2.6) and the
@@ -528,7 +533,8 @@ def main():
                               "n_below": {"%d%d" % cl: int(cnt[0][k]) for k, cl in enumerate(M.CLASSES)}}
         print("[bench] delta stats: " + json.dumps(out["delta_stats"]), file=sys.stderr, flush=True)
 
-    guarded("delta_stats", measure_delta_stats)
+    if not args.no_delta_stats:
+        guarded("delta_stats", measure_delta_stats)
 
     def measure_davidson():
         # reference states: device block Davidson (H_PP assembled and applied
