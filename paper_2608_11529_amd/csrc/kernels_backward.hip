@@ -849,6 +849,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
   __shared__ double2 sD[B12C][MJ];
   __shared__ uint32_t sM[B12C];
   __shared__ uint64_t sStr[B12C];
+  __shared__ uint64_t sOcc[B12C];           // up to 8 occupied spinors per string, one byte each
   __shared__ double sRow[16], sCol[16];
   const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
   const int tp = tps >> 4, sub = tps & 15;
@@ -908,7 +909,21 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       const int64_t s = s0 + tid;
       sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : 1e30;
       sM[tid] = (s < S) ? cd.mask[s] : 0u;
-      sStr[tid] = (s < S) ? cd.strings[s] : 0ull;
+      const uint64_t str = (s < S) ? cd.strings[s] : 0ull;
+      sStr[tid] = str;
+      // the string's occupied spinors, padded with row n_a of sY (a row that
+      // is never read); all ones marks a string with more than 8
+      uint64_t ol = ~0ull;
+      if (__builtin_popcountll(str) <= 8) {
+        ol = 0;
+        uint64_t x = str;
+        for (int i = 0; i < 8; ++i) {
+          const uint64_t t = x ? (uint64_t)__builtin_ctzll(x) : (uint64_t)na;
+          x &= x - 1;
+          ol |= t << (8 * i);
+        }
+      }
+      sOcc[tid] = ol;
     }
     __syncthreads();
 #pragma unroll 1
@@ -972,11 +987,18 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
           for (int t = 0; t < NY; ++t)
             if ((str >> t) & 1ull) y[t] += dl[k];
         } else {
-          uint64_t x = str;
-          while (x) {
-            const int t = __builtin_ctzll(x);
-            x &= x - 1;
-            atomicAdd(&sY[t * 256 + tid], dl[k]);
+          const uint64_t ol = uniform64(sOcc[sl + k]);
+          if (ol != ~0ull) {
+            // eight adds at addresses taken from the byte list, no bit scan
+#pragma unroll
+            for (int i = 0; i < 8; ++i) atomicAdd(&sY[(int)((ol >> (8 * i)) & 0xff) * 256 + tid], dl[k]);
+          } else {
+            uint64_t x = str;
+            while (x) {
+              const int t = __builtin_ctzll(x);
+              x &= x - 1;
+              atomicAdd(&sY[t * 256 + tid], dl[k]);
+            }
           }
         }
       }

@@ -612,7 +612,7 @@ void build_launches(Plan* P) {
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         const int vs = (J > 16 && J <= 20) ? 4 : v;
         j12r[vs].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
-        lds12 = std::max(lds12, (size_t)ip.n_a * 256 * 8);
+        lds12 = std::max(lds12, (size_t)(ip.n_a + 1) * 256 * 8);   // + a row for padding adds
         j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
