@@ -1073,8 +1073,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
 // grid (ceil(S/256), n_c * groups), block 256.
 template <int MJ>
 __device__ __forceinline__ void b12s_wide(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
-                                          const uint3 bid) {
-  __shared__ double2 sX[64][MJ];
+                                          const uint3 bid, double2 (*sX)[MJ]) {
   __shared__ double sQ[64];
   __shared__ double sZ[64];
   const int tid = threadIdx.x;
@@ -1192,10 +1191,12 @@ __device__ __forceinline__ void b12s_wide(const Dev& d, const ClassDev& cd, cons
 // adjoints sit compacted in MQ registers, and each coupling read from LDS
 // serves both sigma and the coefficient adjoint of its determinant (one
 // reciprocal per determinant instead of one per four; half the LDS reads).
+// Slots beyond the block's nq patterns hold zero coefficients and couplings,
+// so the per-determinant loops run over all MQ slots without branches (MQ is
+// nq rounded up to an even count by the caller).
 template <int MQ>
 __device__ __forceinline__ void b12s_compact(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
-                                             const uint3 bid, uint32_t um) {
-  __shared__ double2 sX[64][MQ];
+                                             const uint3 bid, uint32_t um, double2 (*sX)[MQ]) {
   __shared__ double sQ[64];
   __shared__ double sZ[64];
   const int tid = threadIdx.x;
@@ -1268,21 +1269,19 @@ __device__ __forceinline__ void b12s_compact(const Dev& d, const ClassDev& cd, c
         double2 xv[MQ];
         double2 sg = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < MQ; ++q)
-          if (q < nq) {
-            xv[q] = sX[l][q];
-            sg = cfma(Dc[q], xv[q], sg);
-          }
+        for (int q = 0; q < MQ; ++q) {
+          xv[q] = sX[l][q];
+          sg = cfma(Dc[q], xv[q], sg);
+        }
         const double w = rcp_nr(ga_s + sQ[l] - Uvs[Jt * 64 + l]);
         const double2 t = make_double2(sg.x * w, sg.y * w);
         const double2 sbv = make_double2(twoN * t.x, twoN * t.y);
         tq -= oneN * cabs2(t);
 #pragma unroll
-        for (int q = 0; q < MQ; ++q)
-          if (q < nq) {   // Dbar_j += sigma-bar conj(X_j)
-            Dbc[q].x = fma(sbv.x, xv[q].x, fma(sbv.y, xv[q].y, Dbc[q].x));
-            Dbc[q].y = fma(sbv.y, xv[q].x, fma(-sbv.x, xv[q].y, Dbc[q].y));
-          }
+        for (int q = 0; q < MQ; ++q) {   // Dbar_j += sigma-bar conj(X_j)
+          Dbc[q].x = fma(sbv.x, xv[q].x, fma(sbv.y, xv[q].y, Dbc[q].x));
+          Dbc[q].y = fma(sbv.y, xv[q].x, fma(-sbv.x, xv[q].y, Dbc[q].y));
+        }
       }
     }
   }
@@ -1316,8 +1315,16 @@ __device__ __forceinline__ void b12s_body(const Dev& d, const ClassDev& cd, cons
   if (s < S) atomicOr(&sUm, cd.mask[s]);
   __syncthreads();
   const uint32_t um = __builtin_amdgcn_readfirstlane(sUm);
-  if (MJ > 12 && __builtin_popcount(um) > 12) b12s_wide<MJ>(d, cd, g, cg, bid);
-  else b12s_compact<(MJ < 12 ? MJ : 12)>(d, cd, g, cg, bid, um);
+  // one LDS buffer for whichever form runs
+  constexpr int MB = MJ > 12 ? MJ : 12;
+  __shared__ double2 sXb[64 * MB];
+  const int nq = __builtin_popcount(um);
+  if (MJ > 12 && nq > 12) b12s_wide<MJ>(d, cd, g, cg, bid, (double2(*)[MJ])sXb);
+  else if (nq <= 4) b12s_compact<4>(d, cd, g, cg, bid, um, (double2(*)[4])sXb);
+  else if (nq <= 6) b12s_compact<6>(d, cd, g, cg, bid, um, (double2(*)[6])sXb);
+  else if (MJ <= 8 || nq <= 8) b12s_compact<8>(d, cd, g, cg, bid, um, (double2(*)[8])sXb);
+  else if (nq <= 10) b12s_compact<10>(d, cd, g, cg, bid, um, (double2(*)[10])sXb);
+  else b12s_compact<12>(d, cd, g, cg, bid, um, (double2(*)[12])sXb);
 }
 
 // ---- class (0,2) ---------------------------------------------------------------------
