@@ -818,8 +818,8 @@ __device__ __forceinline__ void b22fin_body(const Dev& d, const ClassDev& cd, co
 // Delta-bar (YREG: in registers, else in its own LDS column; the string's
 // occupation is wave-uniform, so the update loop is scalar); the sums over b
 // (table of a) and over a (table of b) are taken once per block at the end.
-// grid (n_c, 16 n_tp), block 256, dynamic LDS n_a * 256 doubles.
-constexpr int B12C = 32;
+// Strings are staged CH at a time (64 where the LDS holds it, else 32).
+// grid (n_c, 16 n_tp), block 256, dynamic LDS (n_a + 1) * 256 doubles.
 
 __device__ __forceinline__ double xsum16(double v) {   // sum over the 16 lanes sharing tid >> 4
   v += __shfl_xor(v, 1, 64);
@@ -839,17 +839,17 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {   // a wave-uniform 
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <int MJ, int GS, bool YREG>
+template <int MJ, int GS, bool YREG, int CH>
 __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
   extern __shared__ double sY[];            // [n_a][256]
-  __shared__ double sUa[B12C][16];
-  __shared__ double sUb[B12C][16];
-  __shared__ double sG[B12C];
-  __shared__ double2 sD[B12C][MJ];
-  __shared__ uint32_t sM[B12C];
-  __shared__ uint64_t sStr[B12C];
-  __shared__ uint64_t sOcc[B12C];           // up to 8 occupied spinors per string, one byte each
+  __shared__ double sUa[CH][16];
+  __shared__ double sUb[CH][16];
+  __shared__ double sG[CH];
+  __shared__ double2 sD[CH][MJ];
+  __shared__ uint32_t sM[CH];
+  __shared__ uint64_t sStr[CH];
+  __shared__ uint64_t sOcc[CH];           // up to 8 occupied spinors per string, one byte each
   __shared__ double sRow[16], sCol[16];
   const int tps = bid.y;                    // cores fastest: blocks of one sub-tile share its tables
   const int tp = tps >> 4, sub = tps & 15;
@@ -891,21 +891,21 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
   const double epsc = d.eps[c];
   double q = 0.0, e2 = 0.0;
   const int64_t S = cd.n_str;
-  for (int64_t s0 = 0; s0 < S; s0 += B12C) {
+  for (int64_t s0 = 0; s0 < S; s0 += CH) {
     __syncthreads();
-    for (int e = tid; e < B12C * 16; e += 256) {
+    for (int e = tid; e < CH * 16; e += 256) {
       const int sl = e >> 4, l = e & 15;
       const int64_t s = s0 + sl;
       const int aa = I * 64 + sa * 16 + l, bb = Jt * 64 + sb * 16 + l;
       sUa[sl][l] = (s < S && aa < nv) ? cd.Uv[s * nv + aa] : 0.0;
       sUb[sl][l] = (s < S && bb < nv) ? cd.Uv[s * nv + bb] : 0.0;
     }
-    for (int e = tid; e < B12C * MJ; e += 256) {
+    for (int e = tid; e < CH * MJ; e += 256) {
       const int sl = e / MJ, j = e % MJ;
       const int64_t s = s0 + sl;
       sD[sl][j] = (s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
     }
-    if (tid < B12C) {
+    if (tid < CH) {
       const int64_t s = s0 + tid;
       sG[tid] = (s < S) ? cd.T[s] + cd.Uc[s * nc + c] + epsc : 1e30;
       sM[tid] = (s < S) ? cd.mask[s] : 0u;
@@ -927,7 +927,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
     }
     __syncthreads();
 #pragma unroll 1
-    for (int sl = 0; sl < B12C; sl += GS) {
+    for (int sl = 0; sl < CH; sl += GS) {
       uint32_t um = 0;
 #pragma unroll
       for (int k = 0; k < GS; ++k) um |= sM[sl + k];

@@ -160,12 +160,12 @@ __global__ void __launch_bounds__(256) k_b_b22fin(MRPT2_ARGS) {
   MRPT2_JOB
   b22fin_body(I.d, I.cls[0], I.g, I.cg[0], bid);
 }
-template <int MJ>
+template <int MJ, int CH = 32>
 __global__ void __launch_bounds__(256, (MJ == 20 ? 2 : 1)) k_b_b12r(MRPT2_ARGS) {
   MRPT2_JOB
   // four strings per group up to 20 patterns (two beyond: registers); the
   // per-spinor table sums in registers up to 16 patterns, else in LDS
-  b12r_body<MJ, (MJ > 20 ? 2 : 4), (MJ <= 16)>(I.d, I.cls[1], I.g, I.cg[1], bid);
+  b12r_body<MJ, (MJ > 20 ? 2 : 4), (MJ <= 16), CH>(I.d, I.cls[1], I.g, I.cg[1], bid);
 }
 template <int MJ>
 __global__ void __launch_bounds__(256) k_b_b12s(MRPT2_ARGS) {

@@ -443,18 +443,19 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
         break;
       case K_BTRANS: hipLaunchKernelGGL(k_b_btrans, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_B22FIN: hipLaunchKernelGGL(k_b_b22fin, g, b256, 0, st, insts, jobs, nj, flag, ka); break;
-#define MRPT2_B12R(ID, MJ)                                                                         \
+#define MRPT2_B12R(ID, MJ, ...)                                                                    \
   case ID:                                                                                        \
     if (L.dyn_lds > 65536 &&                                                                      \
-        hipFuncSetAttribute((const void*)k_b_b12r<MJ>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            (int)L.dyn_lds) != hipSuccess)                                        \
+        hipFuncSetAttribute((const void*)k_b_b12r<MJ __VA_ARGS__>,                                \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.dyn_lds) != hipSuccess) \
       return MRPT2_ERR_HIP;                                                                       \
-    hipLaunchKernelGGL((k_b_b12r<MJ>), g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka);        \
+    hipLaunchKernelGGL((k_b_b12r<MJ __VA_ARGS__>), g, b256, L.dyn_lds, st, insts, jobs, nj, flag, ka); \
     break;
       MRPT2_B12R(K_B12R_8, 8)
       MRPT2_B12R(K_B12R_16, 16)
       MRPT2_B12R(K_B12R_24, 24)
       MRPT2_B12R(K_B12R_20, 20)
+      MRPT2_B12R(K_B12R_20W, 20, , 64)
       case K_B12S_20: hipLaunchKernelGGL((k_b_b12s<20>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       MRPT2_B12R(K_B12R_32, 32)
 #undef MRPT2_B12R

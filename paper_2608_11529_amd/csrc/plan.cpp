@@ -577,8 +577,8 @@ void build_launches(Plan* P) {
     }
   add_launch(P, seq, K_BECOEF, ST_BZERO, js);
   for (int k = 0; k < MRPT2_N_CLASS; ++k) {
-    std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[5], j12s[5], j02r, j02s, j02w;
-    size_t lds = 0, lds12 = 0, lds02 = 0;
+    std::vector<JobH> jr, jsr, j22a, j22b, j22w, jt, j12r[6], j12s[5], j02r, j02s, j02w;
+    size_t lds = 0, lds12 = 0, lds12w = 0, lds02 = 0;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -611,8 +611,12 @@ void build_launches(Plan* P) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 24 ? 2 : 3;
         const int vs = (J > 16 && J <= 20) ? 4 : v;
-        j12r[vs].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
-        lds12 = std::max(lds12, (size_t)(ip.n_a + 1) * 256 * 8);   // + a row for padding adds
+        // + a row for padding adds; the 20-pattern row pass takes 64-string
+        // chunks (about 40 KB of static LDS) where its spinor sums leave room
+        const size_t ly = (size_t)(ip.n_a + 1) * 256 * 8;
+        const bool wide_chunk = vs == 4 && ly + 40960 <= 160 * 1024;
+        j12r[wide_chunk ? 5 : vs].push_back(job(i, cp.n_holes, ip.n_tp * 16, k));
+        (wide_chunk ? lds12w : lds12) = std::max(wide_chunk ? lds12w : lds12, ly);
         j12s[vs].push_back(job(i, cdiv64((int64_t)cp.strings.size(), 256), cp.parts, k));
         continue;
       }
@@ -629,6 +633,7 @@ void build_launches(Plan* P) {
       add_launch(P, seq, K_B12S_8 + v, ST_BSTR0 + k, j12s[v]);
     }
     add_launch(P, seq, K_B12R_20, ST_BROW0 + k, j12r[4], lds12);
+    add_launch(P, seq, K_B12R_20W, ST_BROW0 + k, j12r[5], lds12w);
     add_launch(P, seq, K_B12S_20, ST_BSTR0 + k, j12s[4]);
     add_launch(P, seq, K_B02R, ST_BROW0 + k, j02r);
     add_launch(P, seq, K_B02S, ST_BSTR0 + k, j02s);

@@ -138,7 +138,8 @@ enum KernelId : int {
   K_BAG128, K_BXBRED,
   // denominator statistics (one per class, same order), then the fold
   K_DSTAT22, K_DSTAT12, K_DSTAT02, K_DSTAT21, K_DSTAT11, K_DSTAT01, K_DSTAT20, K_DSTAT10, K_DSTAT00,
-  K_DSTATFIN
+  K_DSTATFIN,
+  K_B12R_20W                           // the 20-pattern (1,2) row pass with 64-string chunks
 };
 
 // Timing slots (mrpt2_energy_timed).
