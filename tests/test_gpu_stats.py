@@ -14,7 +14,7 @@ from helpers import CLASSES, problem, to_plan_order, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ["s_cas", "s_das", "s_fc", "s_hop0", "s_single", "s_nocore", "s_full"]
+NAMES = ["s_cas", "s_das", "s_fc", "s_hop0", "s_single", "s_nocore", "s_full", "s_tiles", "c0"]
 
 
 def oracle_stats(name, q_mode, thresh):
