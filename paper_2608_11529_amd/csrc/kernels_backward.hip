@@ -559,26 +559,32 @@ constexpr int B22P = B22T + 1;
 
 // Contract one B22S-row slab of per-thread values with the string occupations:
 // wpart[v0 + x][t] += sum_l [t in str_l] buf[x][l], rows x < B22S, t < n_a.
+// A 16 x 256 by 256 x 64 product with a 0/1 right factor, on FP64 MFMA:
+// wave w takes the spinors t = 16 w ... 16 w + 15 (16 x 16 x 4 products over
+// the 256 strings; lane l supplies buf[l % 16][k + l / 16] and the bit of
+// spinor 16 w + l % 16 in string k + l / 16, and holds the result rows
+// l / 16 + 4 r of column l % 16).  No barrier inside.
+static_assert(B22S == 16, "the contraction's MFMA tile has 16 rows");
 __device__ __forceinline__ void b22_contract(const double* buf, const uint64_t* sStr, double* wpart, int v0, int nv,
                                              int na) {
-  constexpr int TQ = B22T / B22S;           // threads per row: spinors t = tq + TQ m
-  constexpr int NM = 64 / TQ;
-  const int tid = threadIdx.x, cx = tid % B22S, tq = tid / B22S;
-  double acc[NM];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) acc[m] = 0.0;
-  for (int l = 0; l < B22T; ++l) {
-    const double v = buf[cx * B22P + l];
-    const uint64_t x = sStr[l] >> tq;
-#pragma unroll
-    for (int m = 0; m < NM; ++m) acc[m] += ((x >> (TQ * m)) & 1ull) ? v : 0.0;
+  typedef double d4c __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, t0 = 16 * (threadIdx.x >> 6);
+  if (t0 >= na) return;                      // wave-uniform
+  const int m = lane & 15, kq = lane >> 4;
+  d4c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int l0 = 0; l0 < B22T; l0 += 4) {
+    const int l = l0 + kq;
+    const double a = buf[m * B22P + l];
+    const double b = ((sStr[l] >> (t0 + m)) & 1ull) ? 1.0 : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  const int vv = v0 + cx;
-  if (vv < nv) {
+  const int t = t0 + m;
+  if (t < na) {
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      const int t = tq + TQ * m;
-      if (t < na) wpart[(int64_t)vv * na + t] += acc[m];
+    for (int r = 0; r < 4; ++r) {
+      const int vv = v0 + kq + 4 * r;
+      if (vv < nv) wpart[(int64_t)vv * na + t] += acc[r];
     }
   }
 }
