@@ -23,15 +23,6 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 
-// Read-only view of device memory in the constant address space: a load with
-// a wave-uniform address through it becomes a scalar load (scalar cache), which
-// leaves the LDS pipe and the vector memory path to the per-lane data.  Only
-// for memory that no kernel writes while the reading kernel runs.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T* kconst(const T* p) {
-  return (const __attribute__((address_space(4))) T*)p;
-}
-
 // Reciprocal: hardware estimate (about 2^-24 relative) refined by one
 // Newton-Raphson step, r1 = r0 (2 - d r0), giving relative error below 2^-47
 // with a one-sided bias, far under the energy tolerances used here.
