@@ -1962,65 +1962,108 @@ __device__ __forceinline__ void bagemm128_body(const Dev& d, const GradDev& g, c
   auto tpi = [&](int i0, int j0) -> int64_t {   // tile pair (i0 <= j0)
     return (int64_t)i0 * nvt - (int64_t)i0 * (i0 - 1) / 2 + (j0 - i0);
   };
-  for (int y = 0; y < no; ++y) {
-    if (y == x) continue;
+  // Stages run over (y != x, b0); the raw operands of the next stage are
+  // fetched into registers while the current stage's products run (one block
+  // per CU: nothing else would hide the fetch), and scaled when stored.
+  // Element e = tid + 512 q (q < 4): term 1 and B at (r, kk) = (e / KC, e % KC),
+  // term 2 at (r, kk) = (e % 128, e / 128) (a fastest, coalesced).
+  double2 f1[4], fbv[4], f2[4];
+  auto fetch = [&](int y, int b0) {
     const int64_t pr = x < y ? occ_pair(x, y, no) : occ_pair(y, x, no);
-    const double sgn = x < y ? 1.0 : -1.0;
     const double2* Sy = d.slab + ((int64_t)(d.n_fc + y) * d.n_corr + no) * nl;
     const double2* Abp = g.Ab + pr * d.n_tp * 4096;
-    for (int b0 = 0; b0 < nv; b0 += KC) {
-      const int Jb = b0 >> 6, lb0 = b0 & 63;    // the 16 b lie in one tile
-      // D term 1: Abar[a][b] from tile (I, Jb), I <= Jb, 16 consecutive b per row
-      for (int e = tid; e < 128 * KC; e += 512) {
+    const int Jb = b0 >> 6, lb0 = b0 & 63;    // the 16 b lie in one tile
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 512 * q;
+      {
         const int r = e / KC, kk = e % KC;
         const int a = a0 + r, I = a >> 6, bb = b0 + kk;
-        double2 v = make_double2(0.0, 0.0);
-        if (I <= Jb && a < nv && bb < nv) v = Abp[tpi(I, Jb) * 4096 + (r & 63) * 64 + lb0 + kk];
-        sA[r * KP + kk] = make_double4(sgn * v.x, sgn * v.y, -sgn * v.y, sgn * v.x);
+        f1[q] = (I <= Jb && a < nv && bb < nv) ? Abp[tpi(I, Jb) * 4096 + (r & 63) * 64 + lb0 + kk]
+                                                : make_double2(0.0, 0.0);
       }
-      // B operand: conj(S_y[b][L]), L fastest
-      for (int e = tid; e < 128 * KC; e += 512) {
+      {
         const int c = e & 127, kk = e >> 7;
         const int L = L0 + c, bb = b0 + kk;
-        sB[c * KP + kk] = (L < nl && bb < nv) ? cconj(Sy[(int64_t)bb * nl + L]) : make_double2(0.0, 0.0);
+        fbv[q] = (L < nl && bb < nv) ? Sy[(int64_t)bb * nl + L] : make_double2(0.0, 0.0);
       }
-      __syncthreads();
-      // D term 2: - Abar[b][a] from tile (Jb, I), Jb <= I, a fastest
-      if (Jb <= 2 * I2 + 1) {
-        for (int e = tid; e < 128 * KC; e += 512) {
-          const int r = e & 127, kk = e >> 7;
-          const int a = a0 + r, I = a >> 6, bb = b0 + kk;
-          if (Jb <= I && a < nv && bb < nv) {
-            const double2 v = Abp[tpi(Jb, I) * 4096 + (lb0 + kk) * 64 + (r & 63)];
-            const double4 w = sA[r * KP + kk];
-            const double nx = w.x - sgn * v.x, ny = w.y - sgn * v.y;
-            sA[r * KP + kk] = make_double4(nx, ny, -ny, nx);
-          }
-        }
-        __syncthreads();
+      {
+        const int r = e & 127, kk = e >> 7;
+        const int a = a0 + r, I = a >> 6, bb = b0 + kk;
+        f2[q] = (Jb <= I && a < nv && bb < nv) ? Abp[tpi(Jb, I) * 4096 + (lb0 + kk) * 64 + (r & 63)]
+                                                : make_double2(0.0, 0.0);
       }
-#pragma unroll 2
-      for (int ks = 0; ks < KC; ks += 2) {
-        const int kc = ks + kcl;
-        double ar[4], ai[4], bq[2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double2 v = ((const double2*)&sA[(rowA + i * 16) * KP + kc])[comp];
-          ar[i] = v.x;
-          ai[i] = v.y;
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) bq[j] = ((const double*)&sB[(rowB + j * 16) * KP + kc])[comp];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bq[j], accR[i][j], 0, 0, 0);
-            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bq[j], accI[i][j], 0, 0, 0);
-          }
-      }
-      __syncthreads();
     }
+  };
+  auto next = [&](int& y, int& b0) {           // the stage after (y, b0); y = no at the end
+    b0 += KC;
+    if (b0 >= nv) {
+      b0 = 0;
+      ++y;
+      if (y == x) ++y;
+    }
+  };
+  int y = x == 0 ? 1 : 0, b0 = 0;
+  if (y < no) fetch(y, b0);
+  while (y < no) {
+    const double sgn = x < y ? 1.0 : -1.0;
+    const int Jb = b0 >> 6;
+    const bool term2 = Jb <= 2 * I2 + 1;
+    __syncthreads();                          // the previous stage's products are done
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 512 * q;
+      {
+        const int r = e / KC, kk = e % KC;
+        const double2 v = f1[q];
+        sA[r * KP + kk] = make_double4(sgn * v.x, sgn * v.y, -sgn * v.y, sgn * v.x);
+      }
+      {
+        const int c = e & 127, kk = e >> 7;
+        sB[c * KP + kk] = cconj(fbv[q]);
+      }
+    }
+    // D term 2: - Abar[b][a] from tile (Jb, I), Jb <= I
+    if (term2) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 512 * q;
+        const int r = e & 127, kk = e >> 7;
+        const double2 v = f2[q];
+        if (v.x != 0.0 || v.y != 0.0) {
+          const double4 w = sA[r * KP + kk];
+          const double nx = w.x - sgn * v.x, ny = w.y - sgn * v.y;
+          sA[r * KP + kk] = make_double4(nx, ny, -ny, nx);
+        }
+      }
+    }
+    __syncthreads();
+    int yn = y, bn = b0;
+    next(yn, bn);
+    if (yn < no) fetch(yn, bn);               // in flight during the products
+#pragma unroll 2
+    for (int ks = 0; ks < KC; ks += 2) {
+      const int kc = ks + kcl;
+      double ar[4], ai[4], bq[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 v = ((const double2*)&sA[(rowA + i * 16) * KP + kc])[comp];
+        ar[i] = v.x;
+        ai[i] = v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bq[j] = ((const double*)&sB[(rowB + j * 16) * KP + kc])[comp];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bq[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bq[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    y = yn;
+    b0 = bn;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
