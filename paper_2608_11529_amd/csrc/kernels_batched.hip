@@ -96,10 +96,10 @@ __global__ void __launch_bounds__(256) k_b_e21(MRPT2_ARGS) {
   MRPT2_JOB
   e21_body<MJ, LS>(I.d, I.cls[3], flag, bid);
 }
-template <int MJ, bool LS>
+template <int MJ, bool LS, bool F32 = false>
 __global__ void __launch_bounds__(256) k_b_e12(MRPT2_ARGS) {
   MRPT2_JOB
-  e12_body<MJ, LS>(I.d, I.cls[1], flag, bid);
+  e12_body<MJ, LS, F32>(I.d, I.cls[1], flag, bid);
 }
 template <bool F32, bool LS>
 __global__ void __launch_bounds__(256) k_b_e02(MRPT2_ARGS) {

@@ -1,5 +1,7 @@
 // Reference-space energy, per-string denominator tables, the sigma
 // contraction with the Epstein-Nesbet epilogue, and the reductions.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -505,14 +507,33 @@ __device__ __forceinline__ void dense_coef_body(const Dev& d, const ClassDev& cd
 // the LDS traffic per determinant (the LDS read bandwidth, not the FP64
 // arithmetic, limited the one-pair form).  Partial sums stay per 16 x 16
 // sub-tile.  grid (n_c, 8 n_tp), block 256.
+// F32 (mixed form): the couplings and coefficients are rounded to FP32 and
+// sigma is summed in FP32 (a few terms per determinant; the mixed form's
+// pair integrals carry FP32 rounding already), which halves the LDS bytes of
+// every coefficient read; |sigma|^2, the denominators and the sums stay FP64.
 constexpr int SC12 = 64;
 
-template <int MJ, bool LS>
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double cabs2_64(double2 a) { return cabs2(a); }
+__device__ __forceinline__ double cabs2_64(float2 a) {
+  const double x = a.x, y = a.y;
+  return fma(x, x, y * y);
+}
+template <class CV>
+__device__ __forceinline__ CV to_cv(double2 v) {
+  if constexpr (sizeof(CV) == 8) return make_float2((float)v.x, (float)v.y);
+  else return v;
+}
+
+template <int MJ, bool LS, bool F32 = false>
 __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
+  typedef typename std::conditional<F32, float2, double2>::type CV;
   __shared__ double sUa[SC12][16];
   __shared__ double sUb[SC12][32];
   __shared__ double sG[SC12];
-  __shared__ double2 sD[SC12][MJ];
+  __shared__ CV sD[SC12][MJ];
   __shared__ uint32_t sM[SC12];
   __shared__ double red[2][256];
   const int tps = bid.y;                    // cores fastest: blocks of one region share its tables
@@ -536,7 +557,7 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
   int lb[2];
   bool valid[2];
   double rowc[2];
-  double2 X[2][MJ];
+  CV X[2][MJ];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     lb[p] = sb2 * 32 + 16 * p + (tid & 15);
@@ -548,10 +569,10 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
               W[(gfc + c) * d.n + gv + b];
 #pragma unroll
     for (int j = 0; j < MJ; ++j) {
-      X[p][j] = make_double2(0.0, 0.0);
+      X[p][j] = to_cv<CV>(make_double2(0.0, 0.0));
       if (j < J) {
         const int64_t pr = occ_pair(c, nc + cd.pat[j].a0, d.n_o);
-        X[p][j] = d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb[p]];
+        X[p][j] = to_cv<CV>(d.A[(pr * d.n_tp + tp) * 4096 + la * 64 + lb[p]]);
       }
     }
   }
@@ -578,7 +599,7 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
     for (int e = tid; e < SC12 * MJ; e += 256) {
       const int sl = e / MJ, j = e % MJ;
       const int64_t s = s0 + sl;
-      sD[sl][j] = (s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0);
+      sD[sl][j] = to_cv<CV>((s < S && j < J) ? cd.D[s * J + j] : make_double2(0.0, 0.0));
     }
     if (tid < SC12) {
       const int64_t s = s0 + tid;
@@ -588,20 +609,20 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
     __syncthreads();
 #pragma unroll 1
     for (int sl = 0; sl < SC12; sl += 4) {
-      double2 sg[2][4];
+      CV sg[2][4];
       // strings are ordered by pattern mask, so the union of four masks is
       // usually a single mask; absent couplings carry zero coefficients
       const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
 #pragma unroll
       for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sg[p][k] = make_double2(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) sg[p][k] = to_cv<CV>(make_double2(0.0, 0.0));
 #pragma unroll
       for (int j = 0; j < MJ; ++j)
         if (um & (1u << j)) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const double2 dv = sD[sl + k][j];
+            const CV dv = sD[sl + k][j];
             sg[0][k] = cfma(dv, X[0][j], sg[0][k]);
             sg[1][k] = cfma(dv, X[1][j], sg[1][k]);
           }
@@ -617,7 +638,7 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
         double w[4], dd[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          w[k] = cabs2(sg[p][k]);
+          w[k] = cabs2_64(sg[p][k]);
           dd[k] = (g4[k] + rowc[p]) - ua[k] - sUb[sl + k][ib + 16 * p];
           if constexpr (LS) {
             const double d2 = dd[k] * dd[k];

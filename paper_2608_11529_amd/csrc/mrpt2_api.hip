@@ -305,6 +305,7 @@ bool depends_on_c(int kid) {
   switch (kid) {
     case K_SIGP: case K_E0: case K_CTAB: case K_DCOEF: case K_E02COEF: case K_E22:
     case K_E12_8: case K_E12_16: case K_E12_20: case K_E12_24: case K_E12_32: case K_E02: case K_E02F:
+    case K_E12F_8: case K_E12F_16: case K_E12F_20: case K_E12F_24: case K_E12F_32:
     case K_E22S: case K_E12S_8: case K_E12S_16: case K_E12S_20: case K_E12S_24: case K_E12S_32: case K_E02S:
     case K_E02FS: case K_E21_8: case K_E21_16: case K_E21_20: case K_E21_24: case K_E21_32: case K_E21S_8:
     case K_E21S_16: case K_E21S_20: case K_E21S_24: case K_E21S_32:
@@ -365,6 +366,11 @@ mrpt2_status run(const Plan& P, const std::vector<Launch>& seq, const char* pers
       case K_E21S_32: hipLaunchKernelGGL((k_b_e21<32, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_24: hipLaunchKernelGGL((k_b_e12<24, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E12_32: hipLaunchKernelGGL((k_b_e12<32, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12F_8: hipLaunchKernelGGL((k_b_e12<8, false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12F_16: hipLaunchKernelGGL((k_b_e12<16, false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12F_20: hipLaunchKernelGGL((k_b_e12<20, false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12F_24: hipLaunchKernelGGL((k_b_e12<24, false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
+      case K_E12F_32: hipLaunchKernelGGL((k_b_e12<32, false, true>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02: hipLaunchKernelGGL((k_b_e02<false, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E02F: hipLaunchKernelGGL((k_b_e02<true, false>), g, b256, 0, st, insts, jobs, nj, flag, ka); break;
       case K_E22S: hipLaunchKernelGGL(k_b_e22<true>, g, b256, 0, st, insts, jobs, nj, flag, ka); break;

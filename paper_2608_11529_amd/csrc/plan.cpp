@@ -489,7 +489,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E02COEF, ST_PREP0 + k, js);
     // sigma: dedicated kernels, then the generic kernel for the rest
     // (index 1 of each pair: the level-shifted variant)
-    std::vector<JobH> e22[2], e12[2][5], e21[2][5], e02[2], e02f[2], gen;
+    std::vector<JobH> e22[2], e12[2][5], e12f[5], e21[2][5], e02[2], e02f[2], gen;
     for (int i : all) {
       const InstancePlan& ip = P->inst[i];
       const ClassPlan& cp = ip.cls[k];
@@ -500,7 +500,7 @@ void build_launches(Plan* P) {
       } else if (cp.kernel == KERN_E12) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 20 ? 4 : J <= 24 ? 2 : 3;
-        e12[ls][v].push_back(job(i, cp.n_holes, ip.n_tp * 8, k));
+        (ip.d.precision == MRPT2_MIXED && !ls ? e12f[v] : e12[ls][v]).push_back(job(i, cp.n_holes, ip.n_tp * 8, k));
       } else if (cp.kernel == KERN_E21) {
         const size_t J = cp.patterns.size();
         const int v = J <= 8 ? 0 : J <= 16 ? 1 : J <= 20 ? 2 : J <= 24 ? 3 : 4;
@@ -517,6 +517,7 @@ void build_launches(Plan* P) {
     add_launch(P, seq, K_E12_24, ST_SIGMA0 + k, e12[0][2]);
     add_launch(P, seq, K_E12_32, ST_SIGMA0 + k, e12[0][3]);
     add_launch(P, seq, K_E12_20, ST_SIGMA0 + k, e12[0][4]);
+    for (int v = 0; v < 5; ++v) add_launch(P, seq, K_E12F_8 + v, ST_SIGMA0 + k, e12f[v]);
     add_launch(P, seq, K_E02, ST_SIGMA0 + k, e02[0]);
     add_launch(P, seq, K_E02F, ST_SIGMA0 + k, e02f[0]);
     add_launch(P, seq, K_E22S, ST_SIGMA0 + k, e22[1]);

@@ -139,7 +139,9 @@ enum KernelId : int {
   // denominator statistics (one per class, same order), then the fold
   K_DSTAT22, K_DSTAT12, K_DSTAT02, K_DSTAT21, K_DSTAT11, K_DSTAT01, K_DSTAT20, K_DSTAT10, K_DSTAT00,
   K_DSTATFIN,
-  K_B12R_20W                           // the 20-pattern (1,2) row pass with 64-string chunks
+  K_B12R_20W,                          // the 20-pattern (1,2) row pass with 64-string chunks
+  // class (1,2) of the mixed form: sigma summed in FP32
+  K_E12F_8, K_E12F_16, K_E12F_24, K_E12F_32, K_E12F_20
 };
 
 // Timing slots (mrpt2_energy_timed).
