@@ -1160,6 +1160,27 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
       ip.off_part_class[k] = W.take(std::max<int64_t>(ip.n_part_class[k], 1) * 8);
     }
     ip.workspace_bytes = W.cur;
+  }
+  // Work of each class's generic adjoint row pass over the whole plan (row
+  // blocks x strings): one launch covers every instance, so a batch shares
+  // the pass's block target among its instances in proportion to their work
+  // instead of giving each instance the whole target.
+  int64_t row_blocks[MRPT2_N_CLASS] = {0}, row_work[MRPT2_N_CLASS] = {0};
+  for (const InstancePlan& ip : out->inst)
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) {
+      const ClassPlan& cp = ip.cls[k];
+      const int64_t S = (int64_t)cp.strings.size();
+      if (S > 0 && cp.n_rows > 0 && cp.kernel_bwd != KERN_E22 && cp.kernel_bwd != KERN_E12 &&
+          cp.kernel_bwd != KERN_E02) {
+        row_blocks[k] += (cp.n_rows + 255) / 256;
+        row_work[k] += (cp.n_rows + 255) / 256 * S;
+      }
+    }
+  for (int ii = 0; ii < n_inst; ++ii) {
+    InstancePlan& ip = out->inst[ii];
+    const size_t NP = ip.pstrings.size();
+    int64_t n_ext = 0;
+    for (int k = 0; k < MRPT2_N_CLASS; ++k) n_ext += ip.cls[k].n_ext;
     // ---- gradient workspace layout (adjoint) ----
     Layout Gw;
     ip.off_gs = Gw.take(16 * 8);
@@ -1212,10 +1233,13 @@ mrpt2_status build_plan(const mrpt2_desc* dd, int n_inst, const mrpt2_tuning* tu
         parts = std::min<int64_t>(parts, std::max<int64_t>(1, (int64_t)((256ull << 20) / (16 * std::max<int64_t>(cp.n_conn, 1)))));
         cp.rows_per_part = (cp.n_rows + parts - 1) / parts;
         cp.parts = (int)((cp.n_rows + cp.rows_per_part - 1) / cp.rows_per_part);
-        // row pass: few rows -> split the strings over blocks as well
-        const int64_t rb = (cp.n_rows + 255) / 256;
+        // row pass: few rows -> split the strings over blocks as well; the
+        // instance takes its share S rb / row_work of the target, so every
+        // block of the launch gets about the same number of (row, string)
+        // items (a single instance: ceil(target / rb) string chunks)
         const int64_t rt = cp.bwd_row_target > 0 ? cp.bwd_row_target : 2048;
-        if (rb < 512) cp.row_split = (int)std::min<int64_t>(S, (rt + rb - 1) / rb);
+        if (row_blocks[k] < 512)
+          cp.row_split = (int)std::min<int64_t>(S, std::max<int64_t>(1, (rt * S + row_work[k] - 1) / row_work[k]));
       }
       cp.off_Xb = Gw.take((cp.v < 2 && S) ? (size_t)cp.patterns.size() * cp.n_rows * 16 : 0);
       // with several string chunks per row block the generic row pass writes

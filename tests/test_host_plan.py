@@ -213,3 +213,19 @@ def test_reference_excitation_lists_count():
                 if i != j and bin(b[i] ^ b[j]).count("1") in (2, 4):
                     n += 1
         assert plan.info().n_ref_couplings == n, (name, plan.info().n_ref_couplings, n)
+
+
+def test_batched_adjoint_workspace_is_shared_over_instances():
+    """One launch of the adjoint's generic row pass covers every instance of a
+    plan, so a batch divides the pass's block target among its instances in
+    proportion to their work instead of giving each the whole target: the
+    64-instance batch's gradient workspace (private coupling-adjoint slices
+    per string chunk among it) stays below 50 GB (124.6 GB when every
+    instance split its strings for the whole device), and a one-instance
+    plan is unchanged by the rule."""
+    import paper_2608_11529_amd as M
+    ds = [M.desc_of_problem(SP.batched_instance(s), precision=1, layout=1) for s in range(64)]
+    plan = M.Plan(ds)
+    assert plan.grad_bytes < 50e9, plan.grad_bytes
+    one = M.Plan(ds[:1])
+    assert one.grad_bytes <= plan.grad_bytes
