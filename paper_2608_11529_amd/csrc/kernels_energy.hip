@@ -527,6 +527,44 @@ __device__ __forceinline__ CV to_cv(double2 v) {
   else return v;
 }
 
+// FP64 multiply-add acc += (+-c_L) x, where c_L is the value c held by lane L
+// of the thread's row of 16 lanes (DPP row broadcast on the first operand):
+// coefficients loaded once per row feed all 64 lanes without an LDS
+// broadcast read per use.  c is written only by loads, never by a vector
+// instruction just before, so the DPP read needs no wait states.
+template <int L, bool NEG>
+__device__ __forceinline__ void fmac_row(double& acc, double c, double x) {
+  if constexpr (NEG)
+    asm("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
+  else
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
+}
+
+// sigma of four strings for the two (a, b) of a thread, pattern j = J0 and
+// every later pattern present in the group's mask um; the coefficient of
+// (string k, pattern j) is entry e = k MJ + j of the group's 4 MJ staged
+// coefficients, held by lane e mod 16 of every row in C[e / 16].  The
+// products run in the order of cfma (same rounding).
+template <int MJ, int J0, int K>
+__device__ __forceinline__ void e12_row_k(const double2 (&C)[MJ / 4], const double2 (&X)[2][MJ],
+                                          double2 (&sg)[2][4]) {
+  constexpr int E = K * MJ + J0, M = E >> 4, L = E & 15;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    fmac_row<L, true>(sg[p][K].x, C[M].y, X[p][J0].y);
+    fmac_row<L, false>(sg[p][K].x, C[M].x, X[p][J0].x);
+    fmac_row<L, false>(sg[p][K].y, C[M].y, X[p][J0].x);
+    fmac_row<L, false>(sg[p][K].y, C[M].x, X[p][J0].y);
+  }
+  if constexpr (K + 1 < 4) e12_row_k<MJ, J0, K + 1>(C, X, sg);
+}
+template <int MJ, int J0>
+__device__ __forceinline__ void e12_row_fmas(uint32_t um, const double2 (&C)[MJ / 4], const double2 (&X)[2][MJ],
+                                             double2 (&sg)[2][4]) {
+  if (um & (1u << J0)) e12_row_k<MJ, J0, 0>(C, X, sg);
+  if constexpr (J0 + 1 < MJ) e12_row_fmas<MJ, J0 + 1>(um, C, X, sg);
+}
+
 template <int MJ, bool LS, bool F32 = false>
 __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* flag, const uint3 bid) {
   typedef typename std::conditional<F32, float2, double2>::type CV;
@@ -617,16 +655,27 @@ __device__ __forceinline__ void e12_body(const Dev& d, const ClassDev& cd, int* 
       for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int k = 0; k < 4; ++k) sg[p][k] = to_cv<CV>(make_double2(0.0, 0.0));
+      if constexpr (F32) {
 #pragma unroll
-      for (int j = 0; j < MJ; ++j)
-        if (um & (1u << j)) {
+        for (int j = 0; j < MJ; ++j)
+          if (um & (1u << j)) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const CV dv = sD[sl + k][j];
-            sg[0][k] = cfma(dv, X[0][j], sg[0][k]);
-            sg[1][k] = cfma(dv, X[1][j], sg[1][k]);
+            for (int k = 0; k < 4; ++k) {
+              const CV dv = sD[sl + k][j];
+              sg[0][k] = cfma(dv, X[0][j], sg[0][k]);
+              sg[1][k] = cfma(dv, X[1][j], sg[1][k]);
+            }
           }
-        }
+      } else {
+        // the group's 4 MJ coefficients are contiguous in sD: lane l of each
+        // row loads entries l, l + 16, ... (MJ is a multiple of 4)
+        static_assert(MJ % 4 == 0, "pattern slots in multiples of four");
+        const double2* cg = &sD[sl][0];
+        double2 C[MJ / 4];
+#pragma unroll
+        for (int m = 0; m < MJ / 4; ++m) C[m] = cg[(tid & 15) + 16 * m];
+        e12_row_fmas<MJ, 0>(um, C, X, sg);
+      }
       double g4[4], ua[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
