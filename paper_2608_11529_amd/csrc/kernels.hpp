@@ -23,6 +23,19 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 
+// FP64 multiply-add acc += (+-c_L) x, where c_L is the value c held by lane L
+// of the thread's row of 16 lanes (DPP row broadcast on the first operand):
+// coefficients loaded once per row feed all 64 lanes without an LDS
+// broadcast read per use.  c is written only by loads, never by a vector
+// instruction just before, so the DPP read needs no wait states.
+template <int L, bool NEG>
+__device__ __forceinline__ void fmac_row(double& acc, double c, double x) {
+  if constexpr (NEG)
+    asm("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
+  else
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
+}
+
 // Reciprocal: hardware estimate (about 2^-24 relative) refined by one
 // Newton-Raphson step, r1 = r0 (2 - d r0), giving relative error below 2^-47
 // with a one-sided bias, far under the energy tolerances used here.

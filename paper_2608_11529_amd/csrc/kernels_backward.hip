@@ -845,6 +845,43 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {   // a wave-uniform 
   return ((uint64_t)hi << 32) | lo;
 }
 
+// The group's GS MJ coefficients (string k, pattern j at entry e = k MJ + j)
+// are held by lane e mod 16 of every row in C[e / 16] and reach the products
+// by DPP row broadcast (fmac_row), in the operand order of the LDS form:
+// sigma_k += D_kj X_j, and Xbar_j += sigma-bar_k conj(D_kj).
+template <int MJ, int GS, int J0, int K>
+__device__ __forceinline__ void b12r_sig_k(const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
+                                           double2 (&sg)[GS]) {
+  constexpr int E = K * MJ + J0, M = E >> 4, L = E & 15;
+  fmac_row<L, true>(sg[K].x, C[M].y, X[J0].y);
+  fmac_row<L, false>(sg[K].x, C[M].x, X[J0].x);
+  fmac_row<L, false>(sg[K].y, C[M].y, X[J0].x);
+  fmac_row<L, false>(sg[K].y, C[M].x, X[J0].y);
+  if constexpr (K + 1 < GS) b12r_sig_k<MJ, GS, J0, K + 1>(C, X, sg);
+}
+template <int MJ, int GS, int J0>
+__device__ __forceinline__ void b12r_sig(uint32_t um, const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
+                                         double2 (&sg)[GS]) {
+  if (um & (1u << J0)) b12r_sig_k<MJ, GS, J0, 0>(C, X, sg);
+  if constexpr (J0 + 1 < MJ) b12r_sig<MJ, GS, J0 + 1>(um, C, X, sg);
+}
+template <int MJ, int GS, int J0, int K>
+__device__ __forceinline__ void b12r_xb_k(const double2 (&C)[GS * MJ / 16], const double2 (&sbv)[GS],
+                                          double2 (&Xb)[MJ]) {
+  constexpr int E = K * MJ + J0, M = E >> 4, L = E & 15;
+  fmac_row<L, false>(Xb[J0].x, C[M].y, sbv[K].y);
+  fmac_row<L, false>(Xb[J0].x, C[M].x, sbv[K].x);
+  fmac_row<L, true>(Xb[J0].y, C[M].y, sbv[K].x);
+  fmac_row<L, false>(Xb[J0].y, C[M].x, sbv[K].y);
+  if constexpr (K + 1 < GS) b12r_xb_k<MJ, GS, J0, K + 1>(C, sbv, Xb);
+}
+template <int MJ, int GS, int J0>
+__device__ __forceinline__ void b12r_xb(uint32_t um, const double2 (&C)[GS * MJ / 16], const double2 (&sbv)[GS],
+                                        double2 (&Xb)[MJ]) {
+  if (um & (1u << J0)) b12r_xb_k<MJ, GS, J0, 0>(C, sbv, Xb);
+  if constexpr (J0 + 1 < MJ) b12r_xb<MJ, GS, J0 + 1>(um, C, sbv, Xb);
+}
+
 template <int MJ, int GS, bool YREG, int CH>
 __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, const GradDev& g, const ClassGrad& cg,
                                           const uint3 bid) {
@@ -941,12 +978,14 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
       double2 sg[GS];
 #pragma unroll
       for (int k = 0; k < GS; ++k) sg[k] = make_double2(0.0, 0.0);
+      static_assert((GS * MJ) % 16 == 0, "a group's coefficients fill whole rows");
+      double2 C[GS * MJ / 16];
+      {
+        const double2* cgrp = &sD[sl][0];    // the group's GS MJ coefficients, contiguous
 #pragma unroll
-      for (int j = 0; j < MJ; ++j)
-        if (um & (1u << j)) {
-#pragma unroll
-          for (int k = 0; k < GS; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
-        }
+        for (int m = 0; m < GS * MJ / 16; ++m) C[m] = cgrp[(tid & 15) + 16 * m];
+      }
+      b12r_sig<MJ, GS, 0>(um, C, X, sg);
       double dd[GS];
 #pragma unroll
       for (int k = 0; k < GS; ++k) dd[k] = valid ? (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib] : 1.0;
@@ -974,17 +1013,16 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
         e2 += valid ? cabs2(sg[k]) * w[k] : 0.0;
         q += dl[k];
       }
-      // Xbar_j += sigma-bar conj(D_j)
+      // Xbar_j += sigma-bar conj(D_j); the coefficients are read again
+      // rather than held through the denominators (the registers are short;
+      // the empty asm with a memory clobber keeps the two reads apart)
+      asm volatile("" ::: "memory");
+      {
+        const double2* cgrp = &sD[sl][0];
 #pragma unroll
-      for (int j = 0; j < MJ; ++j)
-        if (um & (1u << j)) {
-#pragma unroll
-          for (int k = 0; k < GS; ++k) {
-            const double2 dv = sD[sl + k][j];
-            Xb[j].x = fma(sbv[k].x, dv.x, fma(sbv[k].y, dv.y, Xb[j].x));
-            Xb[j].y = fma(sbv[k].y, dv.x, fma(-sbv[k].x, dv.y, Xb[j].y));
-          }
-        }
+        for (int m = 0; m < GS * MJ / 16; ++m) C[m] = cgrp[(tid & 15) + 16 * m];
+      }
+      b12r_xb<MJ, GS, 0>(um, C, sbv, Xb);
 #pragma unroll
       for (int k = 0; k < GS; ++k) {
         const uint64_t str = uniform64(sStr[sl + k]);

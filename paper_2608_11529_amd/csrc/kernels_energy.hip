@@ -527,19 +527,6 @@ __device__ __forceinline__ CV to_cv(double2 v) {
   else return v;
 }
 
-// FP64 multiply-add acc += (+-c_L) x, where c_L is the value c held by lane L
-// of the thread's row of 16 lanes (DPP row broadcast on the first operand):
-// coefficients loaded once per row feed all 64 lanes without an LDS
-// broadcast read per use.  c is written only by loads, never by a vector
-// instruction just before, so the DPP read needs no wait states.
-template <int L, bool NEG>
-__device__ __forceinline__ void fmac_row(double& acc, double c, double x) {
-  if constexpr (NEG)
-    asm("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
-  else
-    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
-}
-
 // sigma of four strings for the two (a, b) of a thread, pattern j = J0 and
 // every later pattern present in the group's mask um; the coefficient of
 // (string k, pattern j) is entry e = k MJ + j of the group's 4 MJ staged
