@@ -33,10 +33,12 @@ HBM_PEAK = 8.0e12              # B/s
 
 def cpu_baseline(pb, seconds=15.0):
     """The oracle (as it stands, single thread) on a bounded sample of the
-    same workload: class (2,2) for the first core pairs, the first 64
-    virtual spinors and every reference string, on the sub-problem of frozen
-    core + core + active + those virtuals (the determinants it covers have the
-    same terms as in the full problem)."""
+    same workload, extrapolated to its class mix: classes (2,2) and (1,2) for
+    the first core pairs (cores), the first 64 virtual spinors and every
+    string, on the sub-problem of frozen core + core + active + those
+    virtuals, with a one-hot reference vector on the lowest-diagonal
+    reference determinant (the oracle's cost per external determinant does
+    not depend on the vector's values)."""
     import numpy as np
     import torch
     from threadpoolctl import threadpool_limits
@@ -86,8 +88,9 @@ def cpu_baseline(pb, seconds=15.0):
     return {
         "value": value, "unit": "dets/s", "cores": 1, "kind": "oracle",
         "sample": "classes (2,2) and (1,2) (%.0f%% of N_Q): %d core pairs and %d cores, each x C(%d,2) virtual "
-                  "pairs x all strings (%d and %d external determinants in %.1f s and %.1f s), rates "
-                  "combined with the workload's class mix; single-threaded numpy oracle"
+                  "pairs x all strings (%d and %d external determinants in %.1f s and %.1f s), one-hot reference "
+                  "vector; rates extrapolated to the whole workload with its class mix; single-threaded "
+                  "numpy oracle"
                   % (100.0 * sum(nq.values()) / info.n_ext, samples[(2, 2)][0], samples[(1, 2)][0], n_keep_v,
                      samples[(2, 2)][1], samples[(1, 2)][1], samples[(2, 2)][2], samples[(1, 2)][2]),
     }
