@@ -26,8 +26,9 @@ __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * 
 // FP64 multiply-add acc += (+-c_L) x, where c_L is the value c held by lane L
 // of the thread's row of 16 lanes (DPP row broadcast on the first operand):
 // coefficients loaded once per row feed all 64 lanes without an LDS
-// broadcast read per use.  c is written only by loads, never by a vector
-// instruction just before, so the DPP read needs no wait states.
+// broadcast read per use.  Callers pass c straight from a memory load: a
+// vector instruction writing c shortly before would need wait states ahead
+// of the DPP read, which the inline assembly does not insert.
 template <int L, bool NEG>
 __device__ __forceinline__ void fmac_row(double& acc, double c, double x) {
   if constexpr (NEG)
