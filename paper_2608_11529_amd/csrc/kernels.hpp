@@ -37,6 +37,27 @@ __device__ __forceinline__ void fmac_row(double& acc, double c, double x) {
     asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(c), "v"(x), "n"(L));
 }
 
+// sigma_k += D_kj X_j for the GS strings of a group and one row of couplings
+// X (patterns J0 and later present in the group's mask um): coefficient
+// (string k, pattern j), entry e = k MJ + j of the group's GS MJ, is held by
+// lane e mod 16 of every row in C[e / 16] and reaches the products by DPP
+// row broadcast (fmac_row), in the order of cfma.
+template <int MJ, int GS, int J0, int K>
+__device__ __forceinline__ void row_sig_k(const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
+                                           double2 (&sg)[GS]) {
+  constexpr int E = K * MJ + J0, M = E >> 4, L = E & 15;
+  fmac_row<L, true>(sg[K].x, C[M].y, X[J0].y);
+  fmac_row<L, false>(sg[K].x, C[M].x, X[J0].x);
+  fmac_row<L, false>(sg[K].y, C[M].y, X[J0].x);
+  fmac_row<L, false>(sg[K].y, C[M].x, X[J0].y);
+  if constexpr (K + 1 < GS) row_sig_k<MJ, GS, J0, K + 1>(C, X, sg);
+}
+template <int MJ, int GS, int J0>
+__device__ __forceinline__ void row_sig(uint32_t um, const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
+                                         double2 (&sg)[GS]) {
+  if (um & (1u << J0)) row_sig_k<MJ, GS, J0, 0>(C, X, sg);
+  if constexpr (J0 + 1 < MJ) row_sig<MJ, GS, J0 + 1>(um, C, X, sg);
+}
 // Reciprocal: hardware estimate (about 2^-24 relative) refined by one
 // Newton-Raphson step, r1 = r0 (2 - d r0), giving relative error below 2^-47
 // with a one-sided bias, far under the energy tolerances used here.

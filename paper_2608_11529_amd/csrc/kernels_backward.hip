@@ -845,26 +845,8 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {   // a wave-uniform 
   return ((uint64_t)hi << 32) | lo;
 }
 
-// The group's GS MJ coefficients (string k, pattern j at entry e = k MJ + j)
-// are held by lane e mod 16 of every row in C[e / 16] and reach the products
-// by DPP row broadcast (fmac_row), in the operand order of the LDS form:
-// sigma_k += D_kj X_j, and Xbar_j += sigma-bar_k conj(D_kj).
-template <int MJ, int GS, int J0, int K>
-__device__ __forceinline__ void b12r_sig_k(const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
-                                           double2 (&sg)[GS]) {
-  constexpr int E = K * MJ + J0, M = E >> 4, L = E & 15;
-  fmac_row<L, true>(sg[K].x, C[M].y, X[J0].y);
-  fmac_row<L, false>(sg[K].x, C[M].x, X[J0].x);
-  fmac_row<L, false>(sg[K].y, C[M].y, X[J0].x);
-  fmac_row<L, false>(sg[K].y, C[M].x, X[J0].y);
-  if constexpr (K + 1 < GS) b12r_sig_k<MJ, GS, J0, K + 1>(C, X, sg);
-}
-template <int MJ, int GS, int J0>
-__device__ __forceinline__ void b12r_sig(uint32_t um, const double2 (&C)[GS * MJ / 16], const double2 (&X)[MJ],
-                                         double2 (&sg)[GS]) {
-  if (um & (1u << J0)) b12r_sig_k<MJ, GS, J0, 0>(C, X, sg);
-  if constexpr (J0 + 1 < MJ) b12r_sig<MJ, GS, J0 + 1>(um, C, X, sg);
-}
+// Xbar_j += sigma-bar_k conj(D_kj) with the group's coefficients held as for
+// row_sig (kernels.hpp), in the operand order of the LDS form.
 template <int MJ, int GS, int J0, int K>
 __device__ __forceinline__ void b12r_xb_k(const double2 (&C)[GS * MJ / 16], const double2 (&sbv)[GS],
                                           double2 (&Xb)[MJ]) {
@@ -985,7 +967,7 @@ __device__ __forceinline__ void b12r_body(const Dev& d, const ClassDev& cd, cons
 #pragma unroll
         for (int m = 0; m < GS * MJ / 16; ++m) C[m] = cgrp[(tid & 15) + 16 * m];
       }
-      b12r_sig<MJ, GS, 0>(um, C, X, sg);
+      row_sig<MJ, GS, 0>(um, C, X, sg);
       double dd[GS];
 #pragma unroll
       for (int k = 0; k < GS; ++k) dd[k] = valid ? (sG[sl + k] + rowc) - sUa[sl + k][ia] - sUb[sl + k][ib] : 1.0;

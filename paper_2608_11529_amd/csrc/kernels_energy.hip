@@ -772,12 +772,15 @@ __device__ __forceinline__ void e21_body(const Dev& d, const ClassDev& cd, int* 
       const uint32_t um = sM[sl] | sM[sl + 1] | sM[sl + 2] | sM[sl + 3];
 #pragma unroll
       for (int k = 0; k < 4; ++k) sg[k] = make_double2(0.0, 0.0);
+      // the group's 4 MJ coefficients, contiguous in sD: lane l of each row
+      // loads entries l, l + 16, ..., the products take them by row broadcast
+      double2 C[MJ / 4];
+      {
+        const double2* cg = &sD[sl][0];
 #pragma unroll
-      for (int j = 0; j < MJ; ++j)
-        if (um & (1u << j)) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) sg[k] = cfma(sD[sl + k][j], X[j], sg[k]);
-        }
+        for (int m = 0; m < MJ / 4; ++m) C[m] = cg[(tid & 15) + 16 * m];
+      }
+      row_sig<MJ, 4, 0>(um, C, X, sg);
       double w[4], dd[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
