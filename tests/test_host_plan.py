@@ -229,3 +229,8 @@ def test_batched_adjoint_workspace_is_shared_over_instances():
     assert plan.grad_bytes < 50e9, plan.grad_bytes
     one = M.Plan(ds[:1])
     assert one.grad_bytes <= plan.grad_bytes
+    # the forward recomputation and adjoint of all 64 instances on one GPU
+    # (288 GB): packed factors and their gradients, both workspaces
+    fac = sum(16 * pb.n_l * pb.n * (pb.n + 1) // 2 for pb in map(SP.batched_instance, range(64)))
+    total = 2 * fac + plan.workspace_bytes + plan.grad_bytes
+    assert total < 240e9, total / 1e9
